@@ -1,0 +1,251 @@
+"""FP64 CPU oracle for the MS-GWaM-3D ray-volume hot path -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the package smoke check and the benchmark's CPU-baseline
+leg may import this package.  It is a ctypes wrapper around ``orc.c`` (plain
+C, double precision, one ray at a time) plus the numpy reference of the
+column surrogate in ``mlp.py``.  It shares no code with the GPU library and
+never imports it.
+
+Parity status: see ``orc.h``; every oracle function is pinned by the
+``-m "not gpu"`` tests except the choice of merge partners (a reading),
+which is "parity unpinned" beyond its conserved sums.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+
+ACTIVE, GONE_TOP, GONE_BOTTOM, GONE_POLE, INVALID, MERGED, CAPPED = range(7)
+RAY_FIELDS = ("x", "y", "z", "k", "l", "m", "dx", "dy", "dz", "px", "py", "pz", "n")
+
+
+def build(force: bool = True) -> str:
+    """Compile orc.c into liborc.so (gcc, -ffp-contract=off, OpenMP)."""
+    src = os.path.join(_HERE, "orc.c")
+    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(src):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+           "-shared", "-Wall", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Bg(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("x0", C.c_double), ("y0", C.c_double), ("a", C.c_double)] + \
+               [(n, C.c_void_p) for n in ("U", "V", "N2", "f2", "rho", "Ux", "Uy", "Uz", "Vx", "Vy", "Vz",
+                                           "N2x", "N2y", "N2z", "f2y")]
+
+
+class _Rays(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in RAY_FIELDS + ("id", "state", "col")]
+
+
+class Tally(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_active", "n_top", "n_bottom", "n_pole", "n_invalid",
+                                         "n_merged", "n_capped", "n_split")] + \
+               [(n, C.c_double) for n in ("sum_W", "sum_kW", "sum_lW", "sum_mW", "removed_W")]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        L.orc_prepare.argtypes = [P]
+        L.orc_interp.argtypes = [P, C.c_double, C.c_double, C.c_double, P]
+        L.orc_dispersion.argtypes = [C.c_double] * 5 + [P]
+        L.orc_rhs.argtypes = [P, P, P]
+        L.orc_step.argtypes = [P, P, C.c_int64, C.c_double, P]
+        L.orc_keys.argtypes = [P, P, C.c_int64]
+        L.orc_deposit.argtypes = [P, P, C.c_int64, P]
+        L.orc_drag.argtypes = [P, P, P]
+        L.orc_split.argtypes = [P, P, C.c_int64, C.c_int64, C.c_double, P, P]
+        L.orc_split.restype = C.c_int64
+        L.orc_merge.argtypes = [P, P, C.c_int64, C.c_int32, P]
+        L.orc_cap.argtypes = [P, P, C.c_int64, C.c_int32, P]
+        L.orc_stats.argtypes = [P, C.c_int64, P]
+        L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+class Background:
+    """A grid plus resolved fields U, V, N2 [nz][ny][nx], Coriolis parameter
+    f [ny] and reference density rho [nz]; gradients are filled on creation."""
+
+    def __init__(self, geometry, nx, ny, nz, dx, dy, dz, x0, y0, a, U, V, N2, f, rho):
+        c = lambda v: np.ascontiguousarray(v, dtype=np.float64)
+        self.U, self.V, self.N2 = c(U), c(V), c(N2)
+        f = c(f)
+        self.f2 = c(f * f)
+        self.rho = c(rho)
+        shape = (nz, ny, nx)
+        for arr in (self.U, self.V, self.N2):
+            assert arr.shape == shape
+        assert self.f2.shape == (ny,) and self.rho.shape == (nz,)
+        self.grads = {n: np.zeros(shape) for n in ("Ux", "Uy", "Uz", "Vx", "Vy", "Vz", "N2x", "N2y", "N2z")}
+        self.f2y = np.zeros(ny)
+        b = _Bg()
+        b.geometry, b.nx, b.ny, b.nz = geometry, nx, ny, nz
+        b.dx, b.dy, b.dz, b.x0, b.y0, b.a = dx, dy, dz, x0, y0, a
+        b.U, b.V, b.N2, b.f2, b.rho = (_ptr(v) for v in (self.U, self.V, self.N2, self.f2, self.rho))
+        for n, v in self.grads.items():
+            setattr(b, n, _ptr(v))
+        b.f2y = _ptr(self.f2y)
+        self._b = b
+        self.geometry, self.nx, self.ny, self.nz = geometry, nx, ny, nz
+        self.dx, self.dy, self.dz, self.x0, self.y0, self.a = dx, dy, dz, x0, y0, a
+        lib().orc_prepare(C.byref(b))
+
+    @classmethod
+    def from_workload(cls, w) -> "Background":
+        return cls(w.geometry, w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.x0, w.y0, w.a, w.U, w.V, w.N2, w.f, w.rho)
+
+    @property
+    def ref(self):
+        return C.byref(self._b)
+
+    def interp(self, x, y, z) -> np.ndarray:
+        out = np.zeros(14)
+        lib().orc_interp(self.ref, float(x), float(y), float(z), _ptr(out))
+        return out
+
+    def rhs(self, Y) -> np.ndarray:
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        F = np.zeros(9)
+        lib().orc_rhs(self.ref, _ptr(Y), _ptr(F))
+        return F
+
+
+def dispersion(N2, f2, k, l, m) -> np.ndarray:
+    """(omega_hat, cg_x, cg_y, cg_z) intrinsic."""
+    out = np.zeros(4)
+    lib().orc_dispersion(float(N2), float(f2), float(k), float(l), float(m), _ptr(out))
+    return out
+
+
+class RaySet:
+    """SoA ray volumes with spare capacity for splitting.  Arrays are kept in
+    ascending id order (splitting appends larger ids at the end)."""
+
+    def __init__(self, rays: Dict[str, np.ndarray], capacity: Optional[int] = None):
+        n = int(rays["x"].shape[0])
+        cap = max(int(capacity or n), n, 1)
+        self.cap = cap
+        self.n = n
+        self.a = {}
+        for f in RAY_FIELDS:
+            arr = np.zeros(cap)
+            arr[:n] = rays[f]
+            self.a[f] = arr
+        self.a["id"] = np.zeros(cap, np.int64)
+        self.a["id"][:n] = rays["id"]
+        self.a["state"] = np.full(cap, 255, np.uint8)
+        self.a["state"][:n] = ACTIVE
+        self.a["col"] = np.full(cap, -1, np.int32)
+        s = _Rays()
+        for f in RAY_FIELDS + ("id", "state", "col"):
+            setattr(s, f, _ptr(self.a[f]))
+        self._s = s
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    def __getitem__(self, f):
+        return self.a[f][: self.n]
+
+    def active(self) -> np.ndarray:
+        return self.a["state"][: self.n] == ACTIVE
+
+    def snapshot(self, only_active: bool = True) -> Dict[str, np.ndarray]:
+        sel = self.active() if only_active else slice(None)
+        return {f: self.a[f][: self.n][sel].copy() for f in RAY_FIELDS + ("id", "state", "col")}
+
+
+def step(bg: Background, rs: RaySet, dt: float) -> dict:
+    t = Tally()
+    lib().orc_step(bg.ref, rs.ref, rs.n, float(dt), C.byref(t))
+    return t.as_dict()
+
+
+def keys(bg: Background, rs: RaySet) -> None:
+    lib().orc_keys(bg.ref, rs.ref, rs.n)
+
+
+def deposit(bg: Background, rs: RaySet) -> np.ndarray:
+    """Flux fields [6][nz+1][ny][nx]; computes column keys first."""
+    keys(bg, rs)
+    flux = np.zeros((6, bg.nz + 1, bg.ny, bg.nx))
+    lib().orc_deposit(bg.ref, rs.ref, rs.n, _ptr(flux))
+    return flux
+
+
+def drag(bg: Background, flux: np.ndarray) -> np.ndarray:
+    flux = np.ascontiguousarray(flux, dtype=np.float64)
+    assert flux.shape == (6, bg.nz + 1, bg.ny, bg.nx)
+    out = np.zeros((2, bg.nz, bg.ny, bg.nx))
+    lib().orc_drag(bg.ref, _ptr(flux), _ptr(out))
+    return out
+
+
+def split(bg: Background, rs: RaySet, alpha: float, next_id: Optional[int] = None) -> dict:
+    t = Tally()
+    nid = C.c_int64(int(rs.a["id"][: rs.n].max()) + 1 if next_id is None and rs.n else (next_id or 0))
+    out = lib().orc_split(bg.ref, rs.ref, rs.n, rs.cap, float(alpha), C.byref(nid), C.byref(t))
+    if out < 0:
+        raise RuntimeError("split exceeds capacity")
+    rs.n = int(out)
+    d = t.as_dict()
+    d["next_id"] = nid.value
+    return d
+
+
+def merge(bg: Background, rs: RaySet, n_max: int) -> dict:
+    t = Tally()
+    lib().orc_merge(bg.ref, rs.ref, rs.n, int(n_max), C.byref(t))
+    return t.as_dict()
+
+
+def cap(bg: Background, rs: RaySet, n_max: int) -> dict:
+    t = Tally()
+    lib().orc_cap(bg.ref, rs.ref, rs.n, int(n_max), C.byref(t))
+    return t.as_dict()
+
+
+def stats(rs: RaySet) -> dict:
+    t = Tally()
+    lib().orc_stats(rs.ref, rs.n, C.byref(t))
+    return t.as_dict()
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
