@@ -1,0 +1,178 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) ray-volume tracer for the MS-GWaM-3D
+ * gravity-wave parameterization (Voelker et al., arXiv 2309.11257).
+ *
+ * The library advances phase-space ray volumes (carrier position, carrier
+ * wavevector, physical extents; wave-action density and phase-space areas
+ * fixed) with a low-storage three-stage Runge-Kutta scheme through a
+ * resolved background wind (U, V) and stratification N^2 with rotation f, and
+ * projects their pseudo-momentum fluxes onto the grid to form the wave drag.
+ *
+ * Conventions shared by every entry point
+ *  - Status codes: every function returns RT_OK (0) or a positive error.
+ *    Argument, state and capacity errors are detected before any device work
+ *    and leave the context unchanged; rt_last_error() describes the last one.
+ *  - Asynchrony: calls enqueue work on the context's stream and return,
+ *    except where a host copy or a count is needed (stated per function).
+ *  - Memory: every pointer argument is owned by the caller and is not kept
+ *    after the call returns.  `where` says whether a pointer is host memory
+ *    (RT_HOST) or device memory on the context's GPU (RT_DEVICE); device
+ *    pointers must stay valid until the stream has passed the call.  The
+ *    context's own device memory comes from the config's alloc/free callback
+ *    pair (e.g. a PyTorch caching allocator) or, if alloc is NULL, from
+ *    hipMalloc.
+ *  - Grid: cell-centred, layout [nz][ny][nx] (x fastest).  Cartesian: a
+ *    periodic f-plane box, coordinates in metres from (x0, y0) = (0, 0).
+ *    Spherical: longitude (periodic, rad), latitude (rad, from y0 = -pi/2),
+ *    height above the surface r - a (m).  Levels are uniform, z in [0, nz dz].
+ *  - Threads: a context is not thread-safe; separate contexts are independent.
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rt_ctx_s *rt_ctx;
+typedef int32_t rt_status;
+
+enum {
+    RT_OK = 0,
+    RT_E_ARG = 1,         /* bad argument (NULL pointer, size, non-positive N^2, ...) */
+    RT_E_STATE = 2,       /* call out of order (e.g. step before background) */
+    RT_E_NOMEM = 3,       /* device allocation failed */
+    RT_E_CAPACITY = 4,    /* ray count would exceed the configured capacity */
+    RT_E_DEVICE = 5,      /* a HIP runtime call failed */
+    RT_E_NUMERIC = 6,     /* reserved: numeric failure reported by the device */
+    RT_E_UNSUPPORTED = 7  /* valid request that this build does not handle */
+};
+enum { RT_CARTESIAN = 0, RT_SPHERICAL = 1 };
+enum { RT_FP64 = 0, RT_FP32 = 1 };
+enum { RT_HOST = 0, RT_DEVICE = 1 };
+enum { RT_STEP_DEPOSIT = 1 };
+enum { RT_MERGE = 0, RT_CAP = 1, RT_SPLIT_ONLY = 2 };
+
+typedef struct {
+    int32_t geometry;   /* RT_CARTESIAN or RT_SPHERICAL */
+    int32_t precision;  /* RT_FP64: double state, bit-reproducible steps.
+                           RT_FP32: single-precision state and integration,
+                           positions held as (cell, offset in cell), wave
+                           action and all flux sums in double */
+    int32_t nx, ny, nz; /* grid cells; nx*ny < 2^31 - 8 */
+    int32_t reserved;
+    double dx, dy, dz;  /* spacing: m (Cartesian) or rad, rad, m (spherical) */
+    double a;           /* planetary radius (spherical), m */
+    int64_t capacity;   /* maximum number of ray volumes, including split children */
+    void *(*alloc)(size_t bytes, void *user); /* device allocator, or NULL */
+    void (*free)(void *ptr, void *user);
+    void *user;
+    void *stream;       /* hipStream_t to run on; NULL = the null stream */
+} rt_config;
+
+/* One ray volume per index; structure of arrays, all double except id.
+ *   x, y, z      carrier position (see Grid above)
+ *   k, l, m      carrier wavevector (rad/m): zonal, meridional, vertical
+ *   dx, dy, dz   physical extents in coordinate units (m, or rad, rad, m)
+ *   px, py, pz   phase-space areas: metric extent times wavenumber extent
+ *                (Dx Dk, Dy Dl, Dz Dm; on the sphere Dx = (a+z) cos(phi)
+ *                Dlambda and Dy = (a+z) Dphi), conserved while the volume
+ *                deforms (Section 3a, eq. vpvol_cons_cart and eq. dkxdkl)
+ *   n            phase-space wave-action density N, constant in the volume
+ *   id           unique label, returned unchanged                         */
+typedef struct {
+    double *x, *y, *z, *k, *l, *m, *dx, *dy, *dz, *px, *py, *pz, *n;
+    int64_t *id;
+} rt_rays;
+
+typedef struct {
+    int64_t n_active;                     /* ray volumes in the domain */
+    int64_t n_top, n_bottom, n_pole;      /* removed at the domain edges (cumulative) */
+    int64_t n_invalid;                    /* removed as non-finite / degenerate (cumulative) */
+    int64_t n_split, n_merged, n_capped;  /* cumulative counts */
+    double sum_W, sum_kW, sum_lW, sum_mW; /* wave action and pseudo-momentum of the active set */
+    double removed_W;                     /* wave action removed at the edges and by the cap */
+    int64_t steps;                        /* steps taken */
+} rt_stats;
+
+/* Create a context on the current HIP device.  The grid and precision are
+   fixed for the context's lifetime.  Errors: RT_E_ARG for bad sizes. */
+rt_status rt_create(const rt_config *cfg, rt_ctx *out);
+
+/* Release all device memory of the context (synchronises its stream). */
+rt_status rt_destroy(rt_ctx ctx);
+
+/* Install the resolved background (Section 3b: the mean fields and their
+ * gradients are interpolated to the ray-volume centre and faces).
+ *   U, V, N2   [nz][ny][nx] double, cell centres; N2 > 0 everywhere
+ *   f          [ny] Coriolis parameter per latitude row (NULL = all zero)
+ *   rho        [nz] reference density per level (> 0), used by the drag
+ * The gradient fields are formed on the device by centred differences,
+ * periodic in x (and y on the box), one-sided at the vertical ends and at the
+ * first and last latitude rows.  An RT_FP32 context rounds every field to
+ * single precision once, round-to-nearest-even.  Host inputs are copied
+ * before return; RT_E_ARG if N2 <= 0 or rho <= 0 anywhere (host inputs only;
+ * device inputs are trusted). */
+rt_status rt_init_background(rt_ctx ctx, const double *U, const double *V, const double *N2,
+                             const double *f, const double *rho, int32_t where);
+
+/* Load n ray volumes (replacing any current set).  n may be 0.  Volumes
+ * outside the vertical domain, with non-finite state or non-positive extents
+ * are counted as removed at load.  RT_E_CAPACITY if n > capacity. */
+rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int32_t where);
+
+/* Copy out the active ray volumes in the library's internal order (grouped
+ * by column).  *n_inout: in = length of the caller's arrays, out = number
+ * written.  Synchronises.  RT_E_ARG if the arrays are too short (then
+ * *n_inout is set to the number needed and nothing is written). */
+rt_status rt_get_rays(rt_ctx ctx, rt_rays *rays, int64_t *n_inout, int32_t where);
+
+/* Advance every active ray volume by one RK3 step of length dt (Appendix B:
+ * Williamson's low-storage third-order scheme; Section 3a: carrier moved by
+ * the mean and extents by the difference of the face group velocities,
+ * wavevector by the refraction equations eq. eikonal-sphere 1-3 with
+ * Gamma = 0).  Afterwards volumes are wrapped periodically, those leaving
+ * through the top or bottom or within 0.5 degree of a pole are removed, and
+ * the set is regrouped by parent column (Appendix B, horizontal propagation).
+ * With RT_STEP_DEPOSIT the fluxes and drag are also formed into the
+ * context's own buffers (read them with rt_deposit_flux(ctx, NULL, ...) --
+ * see there).  No synchronisation. */
+rt_status rt_step(rt_ctx ctx, double dt, int32_t flags);
+
+/* Project the current ray volumes onto the grid (Section 3b and App. A:
+ * pseudo-momentum flux, integral of cg_hat k_h N d^3k; vertical fluxes on the
+ * staggered interfaces, horizontal fluxes as cell means of the volumes whose
+ * carrier is in the column) and form the drag du, dv = -(1/rho) div F.
+ *   flux  [6][nz+1][ny][nx] double: Fxk, Fxl, Fyk, Fyl (levels, slot nz = 0),
+ *         Fzk, Fzl (interfaces 0..nz); may be NULL
+ *   drag  [2][nz][ny][nx] double: du, dv; may be NULL
+ * Sums are deterministic (bitwise identical between runs).  No
+ * synchronisation unless where == RT_HOST. */
+rt_status rt_deposit_flux(rt_ctx ctx, double *flux, double *drag, int32_t where);
+
+/* Vertical splitting (Appendix B, ray volume splitting): every volume taller
+ * than alpha_split * dz is halved (repeatedly, up to 64 pieces) into
+ * volumes with the same wavevector and density.  Then, with mode RT_MERGE,
+ * any grid cell holding more than n_max_per_cell volumes has adjacent pairs
+ * of similar wavevector merged (conserving wave action and pseudo-momentum);
+ * with RT_CAP any column holding more than n_max_per_cell volumes loses those
+ * of lowest wave energy (Appendix B, computational performance);
+ * RT_SPLIT_ONLY skips both.  alpha_split <= 0 skips splitting.  Synchronises
+ * (the new count is needed); fills *out if not NULL.  RT_E_CAPACITY (nothing
+ * changed) if the split children do not fit. */
+rt_status rt_split_merge(rt_ctx ctx, double alpha_split, int32_t n_max_per_cell, int32_t mode,
+                         rt_stats *out);
+
+/* Current diagnostics (deterministic sums).  Synchronises. */
+rt_status rt_get_stats(rt_ctx ctx, rt_stats *out);
+
+/* Human-readable description of the last error on this context ("" if none). */
+const char *rt_last_error(rt_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_H */

@@ -1,0 +1,241 @@
+"""ctypes binding of the C ABI in include/rt.h (argument marshalling only).
+
+Every step of the tracer runs in the HIP library librt.so; this module only
+passes pointers, sizes and the stream.  Device memory for the library comes
+from PyTorch's caching allocator through the rt_config alloc/free callbacks.
+Importing this module fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librt.so")
+
+RT_OK, RT_E_ARG, RT_E_STATE, RT_E_NOMEM, RT_E_CAPACITY, RT_E_DEVICE, RT_E_NUMERIC, RT_E_UNSUPPORTED = range(8)
+RT_CARTESIAN, RT_SPHERICAL = 0, 1
+RT_FP64, RT_FP32 = 0, 1
+RT_HOST, RT_DEVICE = 0, 1
+RT_STEP_DEPOSIT = 1
+RT_MERGE, RT_CAP, RT_SPLIT_ONLY = 0, 1, 2
+
+RAY_FIELDS = ("x", "y", "z", "k", "l", "m", "dx", "dy", "dz", "px", "py", "pz", "n")
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Config(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("precision", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("nz", C.c_int32), ("reserved", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
+                ("dz", C.c_double), ("a", C.c_double), ("capacity", C.c_int64), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("user", C.c_void_p), ("stream", C.c_void_p)]
+
+
+class Rays(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in RAY_FIELDS] + [("id", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_active", "n_top", "n_bottom", "n_pole", "n_invalid", "n_split",
+                                         "n_merged", "n_capped")] + \
+               [(n, C.c_double) for n in ("sum_W", "sum_kW", "sum_lW", "sum_mW", "removed_W")] + \
+               [("steps", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class RTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rt error {code}: {msg}")
+        self.code = code
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python paper_2309_11257_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.rt_create.argtypes = [C.POINTER(Config), C.POINTER(P)]
+        L.rt_destroy.argtypes = [P]
+        L.rt_init_background.argtypes = [P, P, P, P, P, P, I32]
+        L.rt_set_rays.argtypes = [P, C.POINTER(Rays), I64, I32]
+        L.rt_get_rays.argtypes = [P, C.POINTER(Rays), C.POINTER(I64), I32]
+        L.rt_step.argtypes = [P, D, I32]
+        L.rt_deposit_flux.argtypes = [P, P, P, I32]
+        L.rt_split_merge.argtypes = [P, D, I32, I32, C.POINTER(Stats)]
+        L.rt_get_stats.argtypes = [P, C.POINTER(Stats)]
+        L.rt_last_error.argtypes = [P]
+        L.rt_last_error.restype = C.c_char_p
+        for name in ("rt_create", "rt_destroy", "rt_init_background", "rt_set_rays", "rt_get_rays", "rt_step",
+                     "rt_deposit_flux", "rt_split_merge", "rt_get_stats"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Tracer:
+    """One library context on one GPU (cuda:0 unless given) and torch's
+    current stream.  Inputs may be numpy arrays (host) or CUDA tensors."""
+
+    def __init__(self, geometry: int, precision: int, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float,
+                 capacity: int, a: float = 6.371e6, device: str = "cuda:0"):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.precision = precision
+        self._mem: Dict[int, object] = {}
+
+        def _alloc(nbytes, user):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            p = t.data_ptr()
+            self._mem[p] = t
+            return p
+
+        def _free(ptr, user):
+            self._mem.pop(int(ptr), None)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device)
+            cfg = Config(geometry, precision, nx, ny, nz, 0, dx, dy, dz, a, int(capacity), self._alloc_cb,
+                         self._free_cb, None, C.c_void_p(stream.cuda_stream))
+            h = C.c_void_p()
+            st = lib().rt_create(C.byref(cfg), C.byref(h))
+            if st != RT_OK:
+                raise RTError(st, "rt_create failed")
+        self.h = h
+        self.stream = stream
+
+    @classmethod
+    def for_workload(cls, w, precision: int, capacity: Optional[int] = None, device: str = "cuda:0") -> "Tracer":
+        cap = capacity if capacity is not None else max(w.n_rays, 1)
+        return cls(w.geometry, precision, w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, cap, a=w.a, device=device)
+
+    def _check(self, st: int):
+        if st != RT_OK:
+            raise RTError(st, lib().rt_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().rt_destroy(self.h)
+            self.h = None
+            self._mem.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- marshalling helpers -------------------------------------------------
+    def _ptr_where(self, arrs):
+        """Returns (pointers, where, keepalive) for a list of arrays that are
+        either all numpy (host) or all CUDA tensors (device)."""
+        torch = self.torch
+        if all(isinstance(a, torch.Tensor) for a in arrs):
+            keep = [a.contiguous() for a in arrs]
+            for a in keep:
+                assert a.device.type == "cuda"
+            return [a.data_ptr() for a in keep], RT_DEVICE, keep
+        keep = [np.ascontiguousarray(a) for a in arrs]
+        return [a.ctypes.data for a in keep], RT_HOST, keep
+
+    # -- API -------------------------------------------------------------------
+    def init_background(self, U, V, N2, f, rho):
+        arrs = [U, V, N2, rho] + ([f] if f is not None else [])
+        torch = self.torch
+        if all(isinstance(a, torch.Tensor) for a in arrs):
+            arrs = [a.to(self.device, torch.float64) for a in arrs]
+        else:
+            arrs = [np.asarray(a, dtype=np.float64) for a in arrs]
+        ptrs, where, keep = self._ptr_where(arrs)
+        fp = ptrs[4] if f is not None else None
+        self._check(lib().rt_init_background(self.h, ptrs[0], ptrs[1], ptrs[2], fp, ptrs[3], where))
+        if where == RT_DEVICE:
+            self._bg_keep = keep
+
+    def init_background_from(self, w):
+        self.init_background(w.U, w.V, w.N2, w.f, w.rho)
+
+    def set_rays(self, rays: Dict[str, object]):
+        torch = self.torch
+        n = int(rays["x"].shape[0])
+        if isinstance(rays["x"], torch.Tensor):
+            arrs = [rays[f].to(self.device, torch.float64) for f in RAY_FIELDS] + [rays["id"].to(self.device, torch.int64)]
+        else:
+            arrs = [np.asarray(rays[f], dtype=np.float64) for f in RAY_FIELDS] + [np.asarray(rays["id"], dtype=np.int64)]
+        ptrs, where, keep = self._ptr_where(arrs)
+        r = Rays(*ptrs)
+        self._check(lib().rt_set_rays(self.h, C.byref(r), n, where))
+        if where == RT_DEVICE:
+            self.stream.synchronize()
+
+    def get_rays(self, device: bool = False) -> Dict[str, object]:
+        n = C.c_int64(0)
+        st = lib().rt_get_rays(self.h, None, C.byref(n), RT_HOST)
+        if st not in (RT_OK, RT_E_ARG):
+            self._check(st)
+        cnt = n.value
+        torch = self.torch
+        if device:
+            out = {f: torch.empty(max(cnt, 1), dtype=torch.float64, device=self.device) for f in RAY_FIELDS}
+            out["id"] = torch.empty(max(cnt, 1), dtype=torch.int64, device=self.device)
+            r = Rays(*[out[f].data_ptr() for f in RAY_FIELDS], out["id"].data_ptr())
+            where = RT_DEVICE
+        else:
+            out = {f: np.empty(max(cnt, 1)) for f in RAY_FIELDS}
+            out["id"] = np.empty(max(cnt, 1), dtype=np.int64)
+            r = Rays(*[out[f].ctypes.data for f in RAY_FIELDS], out["id"].ctypes.data)
+            where = RT_HOST
+        n2 = C.c_int64(cnt)
+        self._check(lib().rt_get_rays(self.h, C.byref(r), C.byref(n2), where))
+        return {k: v[: n2.value] for k, v in out.items()}
+
+    def step(self, dt: float, deposit: bool = False):
+        self._check(lib().rt_step(self.h, float(dt), RT_STEP_DEPOSIT if deposit else 0))
+
+    def deposit(self, flux=None, drag=None, host: bool = False):
+        """Returns (flux [6, nz+1, ny, nx], drag [2, nz, ny, nx]) float64: CUDA
+        tensors by default, numpy arrays with host=True."""
+        torch = self.torch
+        nz, ny, nx = self.nz, self.ny, self.nx
+        if host:
+            flux = np.zeros((6, nz + 1, ny, nx)) if flux is None else flux
+            drag = np.zeros((2, nz, ny, nx)) if drag is None else drag
+            self._check(lib().rt_deposit_flux(self.h, flux.ctypes.data, drag.ctypes.data, RT_HOST))
+            return flux, drag
+        if flux is None:
+            flux = torch.empty((6, nz + 1, ny, nx), dtype=torch.float64, device=self.device)
+        if drag is None:
+            drag = torch.empty((2, nz, ny, nx), dtype=torch.float64, device=self.device)
+        self._check(lib().rt_deposit_flux(self.h, flux.data_ptr(), drag.data_ptr(), RT_DEVICE))
+        return flux, drag
+
+    def split_merge(self, alpha: float, n_max: int = 0, mode: int = RT_SPLIT_ONLY) -> dict:
+        s = Stats()
+        self._check(lib().rt_split_merge(self.h, float(alpha), int(n_max), int(mode), C.byref(s)))
+        return s.as_dict()
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(lib().rt_get_stats(self.h, C.byref(s)))
+        return s.as_dict()

@@ -1,0 +1,460 @@
+// Host side of the C ABI declared in include/rt.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+
+#include "rt_internal.h"
+
+rt_status rt_fail(rt_ctx c, rt_status s, const char *fmt, ...)
+{
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof(c->err), fmt, ap);
+        va_end(ap);
+    }
+    return s;
+}
+
+static void *ctx_alloc(rt_ctx c, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (c->nallocs >= (int)(sizeof(c->allocs) / sizeof(c->allocs[0]))) return nullptr;
+    if (c->cfg.alloc) {
+        p = c->cfg.alloc(bytes, c->cfg.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) c->allocs[c->nallocs++] = p;
+    return p;
+}
+
+static void ctx_release(rt_ctx c)
+{
+    for (int i = 0; i < c->nallocs; i++) {
+        if (c->cfg.free)
+            c->cfg.free(c->allocs[i], c->cfg.user);
+        else if (!c->cfg.alloc)
+            (void)hipFree(c->allocs[i]);
+    }
+    c->nallocs = 0;
+}
+
+#define ALLOC(ptr, type, count)                                       \
+    do {                                                              \
+        ptr = (type *)ctx_alloc(ctx, sizeof(type) * (size_t)(count)); \
+        if (!ptr) {                                                   \
+            ctx_release(ctx);                                         \
+            delete ctx;                                               \
+            return RT_E_NOMEM;                                        \
+        }                                                             \
+    } while (0)
+
+extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
+{
+    if (!out) return RT_E_ARG;
+    *out = nullptr;
+    if (!cfg) return RT_E_ARG;
+    if (cfg->geometry != RT_CARTESIAN && cfg->geometry != RT_SPHERICAL) return RT_E_ARG;
+    if (cfg->precision != RT_FP64 && cfg->precision != RT_FP32) return RT_E_ARG;
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return RT_E_ARG;
+    if ((int64_t)cfg->nx * cfg->ny > (int64_t)0x7ffffff0) return RT_E_ARG;
+    if ((int64_t)cfg->nx * cfg->ny * cfg->nz > (int64_t)0x7ffffff0) return RT_E_ARG;
+    if (cfg->nz > 1024) return RT_E_UNSUPPORTED;
+    if (!(cfg->dx > 0 && cfg->dy > 0 && cfg->dz > 0)) return RT_E_ARG;
+    if (cfg->geometry == RT_SPHERICAL && !(cfg->a > 0)) return RT_E_ARG;
+    if (cfg->capacity < 0 || cfg->capacity > (int64_t)0xffffff00) return RT_E_ARG;
+    if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return RT_E_ARG;
+
+    rt_ctx ctx = new rt_ctx_s();
+    memset(ctx, 0, sizeof(*ctx));
+    ctx->cfg = *cfg;
+    ctx->stream = (hipStream_t)cfg->stream;
+    ctx->precision = cfg->precision;
+    Grid &g = ctx->g;
+    g.geometry = cfg->geometry;
+    g.nx = cfg->nx;
+    g.ny = cfg->ny;
+    g.nz = cfg->nz;
+    g.ncol = cfg->nx * cfg->ny;
+    g.dx = cfg->dx;
+    g.dy = cfg->dy;
+    g.dz = cfg->dz;
+    g.x0 = 0.0;
+    g.y0 = cfg->geometry == RT_SPHERICAL ? -0.5 * M_PI : 0.0;
+    g.a = cfg->a;
+    g.Lx = (double)g.nx * g.dx;
+    g.Ly = (double)g.ny * g.dy;
+    g.Lz = (double)g.nz * g.dz;
+    g.pole = 89.5 * (3.14159265358979323846 / 180.0);
+
+    const int64_t cells = (int64_t)g.ncol * g.nz;
+    const int64_t cap = cfg->capacity > 0 ? cfg->capacity : 1;
+    ctx->cap = cfg->capacity;
+
+    // background (double always; single copies for an FP32 context)
+    double *bgd;
+    ALLOC(bgd, double, 12 * cells + 2 * (int64_t)g.ny + g.nz);
+    Bg<double> &b = ctx->bg64;
+    b.U = bgd;
+    b.V = bgd + cells;
+    b.N2 = bgd + 2 * cells;
+    b.Ux = bgd + 3 * cells;
+    b.Uy = bgd + 4 * cells;
+    b.Uz = bgd + 5 * cells;
+    b.Vx = bgd + 6 * cells;
+    b.Vy = bgd + 7 * cells;
+    b.Vz = bgd + 8 * cells;
+    b.N2x = bgd + 9 * cells;
+    b.N2y = bgd + 10 * cells;
+    b.N2z = bgd + 11 * cells;
+    b.f2 = bgd + 12 * cells;
+    b.f2y = bgd + 12 * cells + g.ny;
+    ctx->rho = bgd + 12 * cells + 2 * g.ny;
+    b.rho = ctx->rho;
+    if (ctx->precision == RT_FP32) {
+        float *bgf;
+        ALLOC(bgf, float, 12 * cells + 2 * (int64_t)g.ny);
+        Bg<float> &h = ctx->bg32;
+        const float **dst[12] = {&h.U, &h.V, &h.N2, &h.Ux, &h.Uy, &h.Uz, &h.Vx, &h.Vy, &h.Vz, &h.N2x, &h.N2y, &h.N2z};
+        for (int q = 0; q < 12; q++) *dst[q] = bgf + q * cells;
+        h.f2 = bgf + 12 * cells;
+        h.f2y = bgf + 12 * cells + g.ny;
+        h.rho = ctx->rho;
+    }
+    // ray state, two buffers
+    for (int buf = 0; buf < 2; buf++) {
+        if (ctx->precision == RT_FP64) {
+            double *m;
+            ALLOC(m, double, 13 * cap);
+            S64 &s = ctx->s64[buf];
+            double **f[13] = {&s.x, &s.y, &s.z, &s.k, &s.l, &s.m, &s.dx, &s.dy, &s.dz, &s.px, &s.py, &s.pz, &s.n};
+            for (int q = 0; q < 13; q++) *f[q] = m + q * cap;
+            ALLOC(s.id, int64_t, cap);
+        } else {
+            float *m;
+            ALLOC(m, float, 12 * cap);
+            S32 &s = ctx->s32[buf];
+            float **f[12] = {&s.xi, &s.eta, &s.z, &s.k, &s.l, &s.m, &s.dxi, &s.deta, &s.dz, &s.px, &s.py, &s.pz};
+            for (int q = 0; q < 12; q++) *f[q] = m + q * cap;
+            ALLOC(s.col, uint32_t, cap);
+            ALLOC(s.W, double, cap);
+            ALLOC(s.id, int64_t, cap);
+        }
+        ALLOC(ctx->key[buf], uint32_t, cap);
+    }
+    ALLOC(ctx->perm, uint32_t, cap);
+    ALLOC(ctx->skeys, uint32_t, cap);
+    ALLOC(ctx->tk, uint32_t, cap);
+    ALLOC(ctx->tv, uint32_t, cap);
+    ctx->hist_len = radix_hist_len(cap);
+    ALLOC(ctx->hist, uint32_t, ctx->hist_len);
+    ALLOC(ctx->colstart, uint32_t, (int64_t)g.ncol + 1);
+    ALLOC(ctx->flux, double, (int64_t)6 * (g.nz + 1) * g.ncol);
+    ALLOC(ctx->drag, double, 2 * cells);
+    ALLOC(ctx->dc, DevCounters, 1);
+    ALLOC(ctx->red, double, 8 + 4 * (cap / 256 + 2));
+    ALLOC(ctx->ired, int64_t, 8 + 2 * cap);
+    if (hipMemsetAsync(ctx->dc, 0, sizeof(DevCounters), ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->colstart, 0, sizeof(uint32_t) * ((size_t)g.ncol + 1), ctx->stream) != hipSuccess) {
+        ctx_release(ctx);
+        delete ctx;
+        return RT_E_DEVICE;
+    }
+    ctx->cur = 0;
+    *out = ctx;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_destroy(rt_ctx ctx)
+{
+    if (!ctx) return RT_E_ARG;
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx_release(ctx);
+    delete ctx;
+    return RT_OK;
+}
+
+extern "C" const char *rt_last_error(rt_ctx ctx) { return ctx ? ctx->err : "null context"; }
+
+static int key_bits(int ncol)
+{
+    const uint32_t maxkey = (uint32_t)ncol + RK_NREASON;
+    int b = 0;
+    while ((1ull << b) <= maxkey) b++;
+    return b;
+}
+
+// sort the current buffer's keys -> skeys/perm, column offsets, removal tallies
+static rt_status sort_current(rt_ctx ctx)
+{
+    const int64_t bound = ctx->n_bound;
+    radix_sort(ctx->key[ctx->cur], nullptr, ctx->skeys, ctx->perm, ctx->tk, ctx->tv, ctx->hist, &ctx->dc->n_sorted,
+               bound, key_bits(ctx->g.ncol), ctx->stream);
+    launch_colstart(ctx->skeys, ctx->dc, ctx->colstart, ctx->g.ncol, ctx->stream);
+    if (ctx->precision == RT_FP64)
+        launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->red, ctx->stream);
+    else
+        launch_tally32(ctx->g, ctx->s32[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->red, ctx->stream);
+    HIP_OK(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status rt_init_background(rt_ctx ctx, const double *U, const double *V, const double *N2, const double *f,
+                                        const double *rho, int32_t where)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!U || !V || !N2 || !rho) return rt_fail(ctx, RT_E_ARG, "U, V, N2 and rho are required");
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    const Grid &g = ctx->g;
+    const int64_t cells = (int64_t)g.ncol * g.nz;
+    if (where == RT_HOST) {
+        for (int64_t i = 0; i < cells; i++)
+            if (!(N2[i] > 0.0) || !std::isfinite(N2[i]) || !std::isfinite(U[i]) || !std::isfinite(V[i]))
+                return rt_fail(ctx, RT_E_ARG, "background cell %lld: N2 must be positive and fields finite",
+                               (long long)i);
+        for (int k = 0; k < g.nz; k++)
+            if (!(rho[k] > 0.0)) return rt_fail(ctx, RT_E_ARG, "rho[%d] must be positive", k);
+    }
+    const hipMemcpyKind kind = where == RT_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    double *bgd = (double *)ctx->bg64.U;
+    HIP_OK(hipMemcpyAsync(bgd, U, sizeof(double) * cells, kind, ctx->stream));
+    HIP_OK(hipMemcpyAsync(bgd + cells, V, sizeof(double) * cells, kind, ctx->stream));
+    HIP_OK(hipMemcpyAsync(bgd + 2 * cells, N2, sizeof(double) * cells, kind, ctx->stream));
+    HIP_OK(hipMemcpyAsync(ctx->rho, rho, sizeof(double) * g.nz, kind, ctx->stream));
+    // f is staged in the flux scratch (ncol*(nz+1)*6 >= ny doubles)
+    double *fstage = nullptr;
+    if (f) {
+        fstage = ctx->flux;
+        HIP_OK(hipMemcpyAsync(fstage, f, sizeof(double) * g.ny, kind, ctx->stream));
+    }
+    launch_gradients64(g, ctx->bg64.U, ctx->bg64.V, ctx->bg64.N2, fstage, bgd + 3 * cells, (double *)ctx->bg64.f2,
+                       (double *)ctx->bg64.f2y, ctx->stream);
+    if (ctx->precision == RT_FP32) {
+        float *bgf = (float *)ctx->bg32.U;
+        launch_round32(bgd, bgf, 12 * cells + 2 * (int64_t)g.ny, ctx->stream);
+    }
+    HIP_OK(hipGetLastError());
+    if (where == RT_HOST) HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->have_bg = true;
+    return RT_OK;
+}
+
+static rt_status check_rays(rt_ctx ctx, const rt_rays *r)
+{
+    if (!r || !r->x || !r->y || !r->z || !r->k || !r->l || !r->m || !r->dx || !r->dy || !r->dz || !r->px || !r->py ||
+        !r->pz || !r->n || !r->id)
+        return rt_fail(ctx, RT_E_ARG, "all ray arrays are required");
+    return RT_OK;
+}
+
+// device staging for host ray arrays (allocated on first use)
+static rt_status stage_rays(rt_ctx ctx, rt_rays *dev, int64_t n)
+{
+    static const int nf = 13;
+    double *m = (double *)ctx_alloc(ctx, sizeof(double) * (size_t)(nf * (n > 0 ? n : 1)) + sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!m) return rt_fail(ctx, RT_E_NOMEM, "staging allocation failed");
+    double **f[13] = {&dev->x, &dev->y, &dev->z, &dev->k, &dev->l, &dev->m, &dev->dx, &dev->dy, &dev->dz,
+                      &dev->px, &dev->py, &dev->pz, &dev->n};
+    for (int q = 0; q < nf; q++) *f[q] = m + (int64_t)q * (n > 0 ? n : 1);
+    dev->id = (int64_t *)(m + (int64_t)nf * (n > 0 ? n : 1));
+    return RT_OK;
+}
+
+static void unstage(rt_ctx ctx, void *p)
+{
+    // release the most recent staging allocation
+    if (ctx->nallocs > 0 && ctx->allocs[ctx->nallocs - 1] == p) {
+        ctx->nallocs--;
+        if (ctx->cfg.free)
+            ctx->cfg.free(p, ctx->cfg.user);
+        else if (!ctx->cfg.alloc)
+            (void)hipFree(p);
+    }
+}
+
+extern "C" rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int32_t where)
+{
+    if (!ctx) return RT_E_ARG;
+    if (n < 0) return rt_fail(ctx, RT_E_ARG, "negative ray count");
+    if (n > ctx->cap) return rt_fail(ctx, RT_E_CAPACITY, "%lld ray volumes exceed capacity %lld", (long long)n,
+                                     (long long)ctx->cap);
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    if (n > 0) {
+        rt_status st = check_rays(ctx, rays);
+        if (st) return st;
+    }
+    rt_rays src = {};
+    void *staged = nullptr;
+    if (n > 0) {
+        if (where == RT_HOST) {
+            rt_status st = stage_rays(ctx, &src, n);
+            if (st) return st;
+            staged = src.x;
+            const double *hs[13] = {rays->x, rays->y, rays->z, rays->k, rays->l, rays->m, rays->dx,
+                                    rays->dy, rays->dz, rays->px, rays->py, rays->pz, rays->n};
+            double *ds[13] = {src.x, src.y, src.z, src.k, src.l, src.m, src.dx, src.dy, src.dz, src.px, src.py, src.pz, src.n};
+            for (int q = 0; q < 13; q++)
+                HIP_OK(hipMemcpyAsync(ds[q], hs[q], sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+            HIP_OK(hipMemcpyAsync(src.id, rays->id, sizeof(int64_t) * n, hipMemcpyHostToDevice, ctx->stream));
+        } else {
+            src = *rays;
+        }
+    }
+    HIP_OK(hipMemsetAsync(ctx->dc, 0, sizeof(DevCounters), ctx->stream));
+    ctx->cur = 0;
+    if (ctx->precision == RT_FP64)
+        launch_load64(ctx->g, src, n, ctx->s64[0], ctx->key[0], ctx->stream);
+    else
+        launch_load32(ctx->g, src, n, ctx->s32[0], ctx->key[0], ctx->stream);
+    launch_set_sorted(ctx->dc, n, ctx->stream);
+    ctx->n_bound = n;
+    rt_status st = sort_current(ctx);
+    if (st) return st;
+    if (staged) {
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        unstage(ctx, staged);
+    }
+    ctx->have_rays = true;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!ctx->have_bg) return rt_fail(ctx, RT_E_STATE, "rt_init_background has not been called");
+    if (!ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "rt_set_rays has not been called");
+    if (!std::isfinite(dt)) return rt_fail(ctx, RT_E_ARG, "dt must be finite");
+    const int nxt = 1 - ctx->cur;
+    if (ctx->precision == RT_FP64)
+        launch_step64(ctx->g, ctx->bg64, ctx->s64[ctx->cur], ctx->s64[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
+                      ctx->n_bound, dt, ctx->stream);
+    else
+        launch_step32(ctx->g, ctx->bg32, ctx->s32[ctx->cur], ctx->s32[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
+                      ctx->n_bound, dt, ctx->stream);
+    launch_sorted_from_active(ctx->dc, ctx->stream);
+    ctx->cur = nxt;
+    rt_status st = sort_current(ctx);
+    if (st) return st;
+    if (flags & RT_STEP_DEPOSIT) return rt_deposit_flux(ctx, nullptr, nullptr, RT_DEVICE);
+    return RT_OK;
+}
+
+extern "C" rt_status rt_deposit_flux(rt_ctx ctx, double *flux, double *drag, int32_t where)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    const Grid &g = ctx->g;
+    double *fdst = (where == RT_DEVICE && flux) ? flux : ctx->flux;
+    double *ddst = (where == RT_DEVICE && drag) ? drag : ctx->drag;
+    if (ctx->precision == RT_FP64)
+        launch_deposit64(g, ctx->bg64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
+    else
+        launch_deposit32(g, ctx->bg32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
+    launch_drag(g, ctx->rho, fdst, ddst, ctx->stream);
+    HIP_OK(hipGetLastError());
+    if (where == RT_HOST) {
+        const size_t nf = (size_t)6 * (g.nz + 1) * g.ncol, nd = (size_t)2 * g.nz * g.ncol;
+        if (flux) HIP_OK(hipMemcpyAsync(flux, fdst, sizeof(double) * nf, hipMemcpyDeviceToHost, ctx->stream));
+        if (drag) HIP_OK(hipMemcpyAsync(drag, ddst, sizeof(double) * nd, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+    }
+    return RT_OK;
+}
+
+static rt_status read_counters(rt_ctx ctx, DevCounters *h)
+{
+    HIP_OK(hipMemcpyAsync(h, ctx->dc, sizeof(DevCounters), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_get_rays(rt_ctx ctx, rt_rays *rays, int64_t *n_inout, int32_t where)
+{
+    if (!ctx || !n_inout) return rt_fail(ctx, RT_E_ARG, "n_inout is required");
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    if (!ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "no rays loaded");
+    DevCounters h;
+    rt_status st = read_counters(ctx, &h);
+    if (st) return st;
+    const int64_t n = h.n_active;
+    if (*n_inout < n) {
+        const long long have = (long long)*n_inout;
+        *n_inout = n;
+        return rt_fail(ctx, RT_E_ARG, "output arrays hold %lld, need %lld", have, (long long)n);
+    }
+    *n_inout = n;
+    if (n == 0) return RT_OK;
+    st = check_rays(ctx, rays);
+    if (st) return st;
+    rt_rays dst = *rays;
+    void *staged = nullptr;
+    if (where == RT_HOST) {
+        st = stage_rays(ctx, &dst, n);
+        if (st) return st;
+        staged = dst.x;
+    }
+    if (ctx->precision == RT_FP64)
+        launch_store64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->dc, dst, n, ctx->stream);
+    else
+        launch_store32(ctx->g, ctx->s32[ctx->cur], ctx->perm, ctx->dc, dst, n, ctx->stream);
+    HIP_OK(hipGetLastError());
+    if (where == RT_HOST) {
+        double *hs[13] = {rays->x, rays->y, rays->z, rays->k, rays->l, rays->m, rays->dx,
+                          rays->dy, rays->dz, rays->px, rays->py, rays->pz, rays->n};
+        const double *ds[13] = {dst.x, dst.y, dst.z, dst.k, dst.l, dst.m, dst.dx, dst.dy, dst.dz, dst.px, dst.py, dst.pz, dst.n};
+        for (int q = 0; q < 13; q++)
+            HIP_OK(hipMemcpyAsync(hs[q], ds[q], sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipMemcpyAsync(rays->id, dst.id, sizeof(int64_t) * n, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    if (staged) unstage(ctx, staged);
+    return RT_OK;
+}
+
+extern "C" rt_status rt_get_stats(rt_ctx ctx, rt_stats *out)
+{
+    if (!ctx || !out) return rt_fail(ctx, RT_E_ARG, "out is required");
+    memset(out, 0, sizeof(*out));
+    if (ctx->have_rays) {
+        if (ctx->precision == RT_FP64)
+            launch_stats64(ctx->s64[ctx->cur], ctx->perm, ctx->dc, ctx->red, ctx->n_bound, ctx->stream);
+        else
+            launch_stats32(ctx->s32[ctx->cur], ctx->perm, ctx->dc, ctx->red, ctx->n_bound, ctx->stream);
+        HIP_OK(hipGetLastError());
+        double sums[4];
+        HIP_OK(hipMemcpyAsync(sums, ctx->red, sizeof(sums), hipMemcpyDeviceToHost, ctx->stream));
+        DevCounters h;
+        rt_status st = read_counters(ctx, &h);
+        if (st) return st;
+        out->n_active = h.n_active;
+        out->n_top = h.removed[RK_TOP];
+        out->n_bottom = h.removed[RK_BOTTOM];
+        out->n_pole = h.removed[RK_POLE];
+        out->n_invalid = h.removed[RK_INVALID];
+        out->n_capped = h.removed[RK_CAPPED];
+        out->n_merged = h.n_merged;
+        out->n_split = h.n_split;
+        out->sum_W = sums[0];
+        out->sum_kW = sums[1];
+        out->sum_lW = sums[2];
+        out->sum_mW = sums[3];
+        out->removed_W = h.removed_W;
+        out->steps = h.steps;
+    }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_split_merge(rt_ctx ctx, double alpha_split, int32_t n_max_per_cell, int32_t mode, rt_stats *out)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
+    if (mode != RT_MERGE && mode != RT_CAP && mode != RT_SPLIT_ONLY) return rt_fail(ctx, RT_E_ARG, "bad mode");
+    if (mode != RT_SPLIT_ONLY && n_max_per_cell < 1) return rt_fail(ctx, RT_E_ARG, "n_max_per_cell must be >= 1");
+    return do_split_merge(ctx, alpha_split, n_max_per_cell, mode, out);
+}

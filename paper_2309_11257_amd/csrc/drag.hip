@@ -1,0 +1,62 @@
+// Wave drag from the deposited fluxes (eq. mean-flow-impact with the
+// pseudo-momentum flux of Appendix A): du = -(1/rho) div(Fk), dv likewise with
+// Fl.  Horizontal divergence by centred differences of the cell-mean fluxes
+// (periodic; on the sphere (1/(r cos phi)) [d_lambda Fx + d_phi(cos phi Fy)]
+// with one-sided differences at the first and last rows), vertical
+// divergence as the difference of the interface fluxes across the level.
+// One thread per cell; HBM-bound stencil.  Built with -ffp-contract=off.
+#include "rt_internal.h"
+
+__global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__ rho, const double *__restrict__ flux,
+                                              double *__restrict__ drag)
+{
+    const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const int i = (int)(c % g.nx);
+    const int j = (int)((c / g.nx) % g.ny);
+    const int k = (int)(c / ((int64_t)g.nx * g.ny));
+    const int64_t plane = (int64_t)(g.nz + 1) * g.ncol;
+    const int64_t row = g.nx;
+    const int64_t at = (int64_t)k * g.ncol + (int64_t)j * g.nx + i;
+    const int ip = (i + 1) % g.nx, im = (i + g.nx - 1) % g.nx;
+    for (int comp = 0; comp < 2; comp++) {
+        const double *Fx = flux + (int64_t)(0 + comp) * plane;
+        const double *Fy = flux + (int64_t)(2 + comp) * plane;
+        const double *Fz = flux + (int64_t)(4 + comp) * plane;
+        const double divz = (Fz[at + g.ncol] - Fz[at]) / g.dz;
+        double divx, divy;
+        if (g.geometry == RT_CARTESIAN) {
+            const int jp = (j + 1) % g.ny, jm = (j + g.ny - 1) % g.ny;
+            divx = (Fx[at - i + ip] - Fx[at - i + im]) / (2.0 * g.dx);
+            divy = (Fy[at + (jp - j) * row] - Fy[at + (jm - j) * row]) / (2.0 * g.dy);
+        } else {
+            const double r = g.a + ((double)k + 0.5) * g.dz;
+            const double cj = cos(g.y0 + ((double)j + 0.5) * g.dy);
+            const double rc = r * cj;
+            double dphi;
+            divx = ((Fx[at - i + ip] - Fx[at - i + im]) / (2.0 * g.dx)) / rc;
+            if (g.ny == 1) {
+                dphi = 0.0;
+            } else if (j == 0) {
+                const double c1 = cos(g.y0 + 1.5 * g.dy);
+                dphi = (c1 * Fy[at + row] - cj * Fy[at]) / g.dy;
+            } else if (j == g.ny - 1) {
+                const double cm = cos(g.y0 + ((double)j - 0.5) * g.dy);
+                dphi = (cj * Fy[at] - cm * Fy[at - row]) / g.dy;
+            } else {
+                const double cp = cos(g.y0 + ((double)j + 1.5) * g.dy);
+                const double cm = cos(g.y0 + ((double)j - 0.5) * g.dy);
+                dphi = (cp * Fy[at + row] - cm * Fy[at - row]) / (2.0 * g.dy);
+            }
+            divy = dphi / rc;
+        }
+        drag[(int64_t)comp * cells + c] = -((divx + divy) + divz) / rho[k];
+    }
+}
+
+void launch_drag(const Grid &g, const double *rho, const double *flux, double *drag, hipStream_t s)
+{
+    const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+    k_drag<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, rho, flux, drag);
+}

@@ -1,0 +1,542 @@
+// Single-precision kernels: RK3 step on the FP32 state, load/store between the
+// double-precision interface and the FP32 layout, removal tallies,
+// diagnostics and the deposition payload.
+//
+// FP32 layout.  A horizontal position is held as the index of its column plus
+// an offset in cell units, so its resolution is a fixed fraction of a cell
+// (about 1e-7 cell) everywhere in the domain instead of degrading with the
+// distance from the origin; this keeps the column assignment of the FP32
+// path as sharp as the FP64 one.  Extents Dx, Dy are in cell units too.  The
+// wave action W = N Px Py Pz is formed once in double at load and kept in
+// double, and every flux sum is accumulated in double.
+#include "dev64.h"
+#include "deposit_common.h"
+
+namespace f32 {
+
+struct G32 {
+    int geometry, nx, ny, nz, ncol;
+    float dz, inv_dz, Lz, a;
+    float inv_dx, inv_dy;  // Cartesian: 1/dx, 1/dy in 1/m; spherical: 1/dlambda, 1/dphi
+    float y0, dyr;         // spherical: latitude origin and spacing (rad)
+    float pole;
+};
+
+__host__ __device__ inline G32 make_g32(const Grid &g)
+{
+    G32 h;
+    h.geometry = g.geometry;
+    h.nx = g.nx;
+    h.ny = g.ny;
+    h.nz = g.nz;
+    h.ncol = g.ncol;
+    h.dz = (float)g.dz;
+    h.inv_dz = (float)(1.0 / g.dz);
+    h.Lz = (float)g.Lz;
+    h.a = (float)g.a;
+    h.inv_dx = (float)(1.0 / g.dx);
+    h.inv_dy = (float)(1.0 / g.dy);
+    h.y0 = (float)g.y0;
+    h.dyr = (float)g.dy;
+    h.pole = (float)g.pole;
+    return h;
+}
+
+// periodic axis: base cell ic, offset u in cell units
+__device__ inline void axis_per(int ic, float u, int n, int &i0, int &i1, float &w)
+{
+    const float t = u - 0.5f;
+    if (!(fabsf(t) < 1.0e6f)) {
+        i0 = 0;
+        i1 = 0;
+        w = t - t;
+        return;
+    }
+    const float fl = floorf(t);
+    w = t - fl;
+    int ii = ic + (int)fl;
+    if (ii < 0 || ii >= n) {
+        ii %= n;
+        if (ii < 0) ii += n;
+    }
+    i0 = ii;
+    i1 = (ii + 1 == n) ? 0 : ii + 1;
+}
+
+// clamped axis (latitude rows, levels): value held beyond the end centres
+__device__ inline void axis_clamp(int ic, float u, int n, int &i0, int &i1, float &w)
+{
+    const float t = u - 0.5f;
+    if (!(fabsf(t) < 1.0e6f)) {
+        i0 = 0;
+        i1 = 0;
+        w = t - t;
+        return;
+    }
+    const float fl = floorf(t);
+    const int j0 = ic + (int)fl;
+    if (j0 < 0) {
+        i0 = 0;
+        i1 = 0;
+        w = 0.0f;
+    } else if (j0 >= n - 1) {
+        i0 = n - 1;
+        i1 = n - 1;
+        w = 0.0f;
+    } else {
+        i0 = j0;
+        i1 = j0 + 1;
+        w = t - fl;
+    }
+}
+
+struct Cell {
+    int a00, a10, a01, a11, i0, i1, j0, j1;
+    float wx, wy, wz;
+};
+
+__device__ inline void locate(const G32 &g, int ic, int jc, float xi, float eta, float z, Cell &c)
+{
+    int k0, k1;
+    axis_per(ic, xi, g.nx, c.i0, c.i1, c.wx);
+    if (g.geometry == RT_CARTESIAN)
+        axis_per(jc, eta, g.ny, c.j0, c.j1, c.wy);
+    else
+        axis_clamp(jc, eta, g.ny, c.j0, c.j1, c.wy);
+    axis_clamp(0, z * g.inv_dz, g.nz, k0, k1, c.wz);
+    c.a00 = (k0 * g.ny + c.j0) * g.nx;
+    c.a10 = (k0 * g.ny + c.j1) * g.nx;
+    c.a01 = (k1 * g.ny + c.j0) * g.nx;
+    c.a11 = (k1 * g.ny + c.j1) * g.nx;
+}
+
+__device__ inline float tri(const float *__restrict__ F, const Cell &c)
+{
+    const float a0 = F[c.a00 + c.i0], a1 = F[c.a00 + c.i1];
+    const float b0 = F[c.a10 + c.i0], b1 = F[c.a10 + c.i1];
+    const float d0 = F[c.a01 + c.i0], d1 = F[c.a01 + c.i1];
+    const float e0 = F[c.a11 + c.i0], e1 = F[c.a11 + c.i1];
+    const float c00 = a0 + c.wx * (a1 - a0);
+    const float c10 = b0 + c.wx * (b1 - b0);
+    const float c01 = d0 + c.wx * (d1 - d0);
+    const float c11 = e0 + c.wx * (e1 - e0);
+    const float c0 = c00 + c.wy * (c10 - c00);
+    const float c1 = c01 + c.wy * (c11 - c01);
+    return c0 + c.wz * (c1 - c0);
+}
+
+__device__ inline float row(const float *__restrict__ F, const Cell &c)
+{
+    return F[c.j0] + c.wy * (F[c.j1] - F[c.j0]);
+}
+
+// group velocity component along one axis at a face: background wind (if
+// any) plus the intrinsic part from the dispersion relation
+__device__ inline float face_cg(const Bg<float> &b, const Cell &f, int axis, float k, float l, float m, float kh2,
+                                float m2, float K2, float invK4)
+{
+    const float N2 = tri(b.N2, f);
+    const float f2 = row(b.f2, f);
+    const float om = sqrtf((N2 * kh2 + f2 * m2) / K2);
+    const float s = (N2 - f2) * invK4 / om;
+    if (axis == 0) return tri(b.U, f) + k * m2 * s;
+    if (axis == 1) return tri(b.V, f) + l * m2 * s;
+    return -m * kh2 * s;
+}
+
+// RK stage right-hand side in cell units: Y = (xi, eta, z, k, l, m, Dxi, Deta, Dz)
+template <bool SPH>
+__device__ inline void rhs(const G32 &g, const Bg<float> &b, int ic, int jc, float phi0, const float *Y, float *F)
+{
+    const float xi = Y[0], eta = Y[1], z = Y[2], k = Y[3], l = Y[4], m = Y[5];
+    const float kh2 = k * k + l * l;
+    const float m2 = m * m;
+    const float K2 = kh2 + m2;
+    const float invK4 = 1.0f / (K2 * K2);
+    Cell c;
+    locate(g, ic, jc, xi, eta, z, c);
+    const float N2c = tri(b.N2, c);
+    const float f2c = row(b.f2, c);
+    const float om = sqrtf((N2c * kh2 + f2c * m2) / K2);
+    const float h = 0.5f / (om * K2);
+    const float q = kh2 * h;
+    const float qf = m2 * h;
+    const float gk = k * tri(b.Ux, c) + l * tri(b.Vx, c) + q * tri(b.N2x, c);
+    const float gl = k * tri(b.Uy, c) + l * tri(b.Vy, c) + q * tri(b.N2y, c) + qf * row(b.f2y, c);
+    const float gm = k * tri(b.Uz, c) + l * tri(b.Vz, c) + q * tri(b.N2z, c);
+    Cell f;
+    locate(g, ic, jc, xi + 0.5f * Y[6], eta, z, f);
+    const float cxp = face_cg(b, f, 0, k, l, m, kh2, m2, K2, invK4);
+    locate(g, ic, jc, xi - 0.5f * Y[6], eta, z, f);
+    const float cxm = face_cg(b, f, 0, k, l, m, kh2, m2, K2, invK4);
+    locate(g, ic, jc, xi, eta + 0.5f * Y[7], z, f);
+    const float cyp = face_cg(b, f, 1, k, l, m, kh2, m2, K2, invK4);
+    locate(g, ic, jc, xi, eta - 0.5f * Y[7], z, f);
+    const float cym = face_cg(b, f, 1, k, l, m, kh2, m2, K2, invK4);
+    locate(g, ic, jc, xi, eta, z + 0.5f * Y[8], f);
+    const float czp = face_cg(b, f, 2, k, l, m, kh2, m2, K2, invK4);
+    locate(g, ic, jc, xi, eta, z - 0.5f * Y[8], f);
+    const float czm = face_cg(b, f, 2, k, l, m, kh2, m2, K2, invK4);
+    if (!SPH) {
+        F[0] = 0.5f * (cxp + cxm) * g.inv_dx;
+        F[1] = 0.5f * (cyp + cym) * g.inv_dy;
+        F[2] = 0.5f * (czp + czm);
+        F[3] = -gk;
+        F[4] = -gl;
+        F[5] = -gm;
+        F[6] = (cxp - cxm) * g.inv_dx;
+        F[7] = (cyp - cym) * g.inv_dy;
+        F[8] = czp - czm;
+    } else {
+        const float r = g.a + z;
+        const float ir = 1.0f / r;
+        float sphi, cphi;
+        sincosf(phi0 + eta * g.dyr, &sphi, &cphi);
+        const float tphi = sphi / cphi;
+        const float irc = ir / cphi;
+        const float uc = 0.5f * (cxp + cxm);
+        const float vc = 0.5f * (cyp + cym);
+        const float wc = 0.5f * (czp + czm);
+        F[0] = uc * irc * g.inv_dx;
+        F[1] = vc * ir * g.inv_dy;
+        F[2] = wc;
+        F[3] = -gk * irc - k * wc * ir + k * tphi * vc * ir;
+        F[4] = -gl * ir - l * wc * ir - k * tphi * uc * ir;
+        F[5] = -gm + k * uc * ir + l * vc * ir;
+        F[6] = (cxp - cxm) * irc * g.inv_dx;
+        F[7] = (cyp - cym) * ir * g.inv_dy;
+        F[8] = czp - czm;
+    }
+}
+
+// move a periodic (cell, offset) pair back to offset in [0, 1)
+__device__ inline void renorm_periodic(int &ic, float &u, int n)
+{
+    const float fl = floorf(u);
+    int ii = ic + (int)fl;
+    u = u - fl;
+    if (u >= 1.0f) {
+        u = 0.0f;
+        ii += 1;
+    }
+    if (ii < 0 || ii >= n) {
+        ii %= n;
+        if (ii < 0) ii += n;
+    }
+    ic = ii;
+}
+
+}  // namespace f32
+
+using f32::G32;
+
+template <bool SPH>
+__global__ __launch_bounds__(256) void k_step32(G32 g, Bg<float> b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
+                                                uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc,
+                                                float dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dc->n_active) return;
+    const uint32_t s = perm[i];
+    const uint32_t col = src.col[s];
+    int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
+    float Y[9] = {src.xi[s], src.eta[s], src.z[s], src.k[s], src.l[s], src.m[s], src.dxi[s], src.deta[s], src.dz[s]};
+    float Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float F[9];
+    const float A[3] = {0.0f, -5.0f / 9.0f, -153.0f / 128.0f};
+    const float B[3] = {1.0f / 3.0f, 15.0f / 16.0f, 8.0f / 15.0f};
+    const float phi0 = g.y0 + (float)jc * g.dyr;
+#pragma unroll 1
+    for (int st = 0; st < 3; st++) {
+        f32::rhs<SPH>(g, b, ic, jc, phi0, Y, F);
+#pragma unroll
+        for (int c = 0; c < 9; c++) {
+            Q[c] = A[st] * Q[c] + dt * F[c];
+            Y[c] = Y[c] + B[st] * Q[c];
+        }
+    }
+    // post-step: validity, wrap, removal, column key
+    uint32_t key;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 9; c++) ok = ok && isfinite(Y[c]);
+    ok = ok && Y[6] > 0.0f && Y[7] > 0.0f && Y[8] > 0.0f && (Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) > 0.0f;
+    ok = ok && fabsf(Y[0]) < 1.0e6f && fabsf(Y[1]) < 1.0e6f;
+    if (!ok) {
+        key = (uint32_t)(g.ncol + RK_INVALID);
+    } else {
+        f32::renorm_periodic(ic, Y[0], g.nx);
+        key = 0;
+        if (SPH) {
+            const float phi = phi0 + Y[1] * g.dyr;
+            if (fabsf(phi) >= g.pole) key = (uint32_t)(g.ncol + RK_POLE);
+            const float fl = floorf(Y[1]);
+            int jj = jc + (int)fl;
+            Y[1] = Y[1] - fl;
+            if (Y[1] >= 1.0f) {
+                Y[1] = 0.0f;
+                jj += 1;
+            }
+            if (jj < 0) {
+                jj = 0;
+                Y[1] = 0.0f;
+            }
+            if (jj > g.ny - 1) {
+                jj = g.ny - 1;
+                Y[1] = 0.999999940395f;
+            }
+            jc = jj;
+        } else {
+            f32::renorm_periodic(jc, Y[1], g.ny);
+        }
+        if (key == 0) {
+            if (Y[2] < 0.0f)
+                key = (uint32_t)(g.ncol + RK_BOTTOM);
+            else if (Y[2] > g.Lz)
+                key = (uint32_t)(g.ncol + RK_TOP);
+            else
+                key = (uint32_t)(jc * g.nx + ic);
+        }
+    }
+    dst.col[i] = (uint32_t)(jc * g.nx + ic);
+    dst.xi[i] = Y[0];
+    dst.eta[i] = Y[1];
+    dst.z[i] = Y[2];
+    dst.k[i] = Y[3];
+    dst.l[i] = Y[4];
+    dst.m[i] = Y[5];
+    dst.dxi[i] = Y[6];
+    dst.deta[i] = Y[7];
+    dst.dz[i] = Y[8];
+    dst.px[i] = src.px[s];
+    dst.py[i] = src.py[s];
+    dst.pz[i] = src.pz[s];
+    dst.W[i] = src.W[s];
+    dst.id[i] = src.id[s];
+    key_out[i] = key;
+}
+
+void launch_step32(const Grid &g, const Bg<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
+                   const DevCounters *dc, int64_t bound, double dt, hipStream_t s)
+{
+    if (bound <= 0) return;
+    const unsigned nb = (unsigned)((bound + 255) / 256);
+    const G32 h = f32::make_g32(g);
+    if (g.geometry == RT_SPHERICAL)
+        k_step32<true><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt);
+    else
+        k_step32<false><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt);
+}
+
+// ---------------------------------------------------------------------------
+// conversions
+// ---------------------------------------------------------------------------
+__global__ void k_round32(const double *in, float *out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+void launch_round32(const double *in, float *out, int64_t n, hipStream_t s)
+{
+    if (n > 0) k_round32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, out, n);
+}
+
+__global__ void k_load32(Grid g, rt_rays in, int64_t n, S32 d, uint32_t *key)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double Y[9] = {in.x[i], in.y[i], in.z[i], in.k[i], in.l[i], in.m[i], in.dx[i], in.dy[i], in.dz[i]};
+    const uint32_t kk = d64::post_step(g, Y);
+    uint32_t col = 0;
+    float xi = 0.0f, eta = 0.0f;
+    if (kk < (uint32_t)g.ncol) {
+        col = kk;
+        const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
+        xi = (float)((Y[0] - g.x0) / g.dx - (double)ic);
+        eta = (float)((Y[1] - g.y0) / g.dy - (double)jc);
+        if (xi >= 1.0f) xi = 0.99999994f;
+        if (eta >= 1.0f) eta = 0.99999994f;
+    }
+    d.col[i] = col;
+    d.xi[i] = xi;
+    d.eta[i] = eta;
+    d.z[i] = (float)Y[2];
+    d.k[i] = (float)Y[3];
+    d.l[i] = (float)Y[4];
+    d.m[i] = (float)Y[5];
+    d.dxi[i] = (float)(Y[6] / g.dx);
+    d.deta[i] = (float)(Y[7] / g.dy);
+    d.dz[i] = (float)Y[8];
+    d.px[i] = (float)in.px[i];
+    d.py[i] = (float)in.py[i];
+    d.pz[i] = (float)in.pz[i];
+    d.W[i] = ((in.n[i] * in.px[i]) * in.py[i]) * in.pz[i];
+    d.id[i] = in.id[i];
+    key[i] = kk;
+}
+
+void launch_load32(const Grid &g, const rt_rays &in, int64_t n, S32 dst, uint32_t *key, hipStream_t s)
+{
+    if (n > 0) k_load32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, in, n, dst, key);
+}
+
+__global__ void k_store32(Grid g, S32 st, const uint32_t *perm, const DevCounters *dc, rt_rays o)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dc->n_active) return;
+    const uint32_t s = perm[i];
+    const uint32_t col = st.col[s];
+    const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
+    o.x[i] = g.x0 + ((double)ic + (double)st.xi[s]) * g.dx;
+    o.y[i] = g.y0 + ((double)jc + (double)st.eta[s]) * g.dy;
+    o.z[i] = st.z[s];
+    o.k[i] = st.k[s];
+    o.l[i] = st.l[s];
+    o.m[i] = st.m[s];
+    o.dx[i] = (double)st.dxi[s] * g.dx;
+    o.dy[i] = (double)st.deta[s] * g.dy;
+    o.dz[i] = st.dz[s];
+    const double px = st.px[s], py = st.py[s], pz = st.pz[s];
+    o.px[i] = px;
+    o.py[i] = py;
+    o.pz[i] = pz;
+    o.n[i] = st.W[s] / ((px * py) * pz);
+    o.id[i] = st.id[s];
+}
+
+void launch_store32(const Grid &g, S32 src, const uint32_t *perm, const DevCounters *dc, rt_rays out, int64_t bound,
+                    hipStream_t s)
+{
+    if (bound > 0) k_store32<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(g, src, perm, dc, out);
+}
+
+// ---------------------------------------------------------------------------
+// tallies and diagnostics (deterministic, see kern64.hip)
+// ---------------------------------------------------------------------------
+__global__ void k_tally32(Grid g, S32 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc)
+{
+    __shared__ double sw[256];
+    __shared__ int cnt[RK_NREASON];
+    const int tid = threadIdx.x;
+    if (tid < RK_NREASON) cnt[tid] = 0;
+    __syncthreads();
+    const int64_t a = dc->n_active, e = dc->n_sorted;
+    double w = 0.0;
+    for (int64_t i = a + tid; i < e; i += 256) {
+        const int reason = (int)(skeys[i] - (uint32_t)g.ncol);
+        if (reason >= 0 && reason < RK_NREASON) atomicAdd(&cnt[reason], 1);
+        if (reason != RK_INVALID) w += st.W[perm[i]];
+    }
+    sw[tid] = w;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) sw[tid] += sw[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) dc->removed_W += sw[0];
+    if (tid < RK_NREASON) dc->removed[tid] += cnt[tid];
+}
+
+void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc, double *red,
+                    hipStream_t s)
+{
+    (void)red;
+    k_tally32<<<1, 256, 0, s>>>(g, st, perm, skeys, dc);
+}
+
+__global__ void k_stats32_part(S32 st, const uint32_t *perm, const DevCounters *dc, double *part)
+{
+    __shared__ double sh[4][256];
+    const int tid = threadIdx.x;
+    const int64_t n = dc->n_active;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    double v[4] = {0, 0, 0, 0};
+    if (i < n) {
+        const uint32_t s = perm[i];
+        const double W = st.W[s];
+        v[0] = W;
+        v[1] = (double)st.k[s] * W;
+        v[2] = (double)st.l[s] * W;
+        v[3] = (double)st.m[s] * W;
+    }
+    for (int q = 0; q < 4; q++) sh[q][tid] = v[q];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off)
+            for (int q = 0; q < 4; q++) sh[q][tid] += sh[q][tid + off];
+        __syncthreads();
+    }
+    if (tid < 4) part[4 + (int64_t)blockIdx.x * 4 + tid] = sh[tid][0];
+}
+
+__global__ void k_stats32_final(double *part, int64_t nblocks)
+{
+    __shared__ double sh[4][256];
+    const int tid = threadIdx.x;
+    double v[4] = {0, 0, 0, 0};
+    for (int64_t b = tid; b < nblocks; b += 256)
+        for (int q = 0; q < 4; q++) v[q] += part[4 + b * 4 + q];
+    for (int q = 0; q < 4; q++) sh[q][tid] = v[q];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off)
+            for (int q = 0; q < 4; q++) sh[q][tid] += sh[q][tid + off];
+        __syncthreads();
+    }
+    if (tid < 4) part[tid] = sh[tid][0];
+}
+
+void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s)
+{
+    const int64_t nb = bound > 0 ? (bound + 255) / 256 : 0;
+    if (nb > 0) k_stats32_part<<<(unsigned)nb, 256, 0, s>>>(st, perm, dc, red);
+    k_stats32_final<<<1, 256, 0, s>>>(red, nb);
+}
+
+// ---------------------------------------------------------------------------
+// deposition payload: single-precision dispersion at the carrier, wave action
+// and the flux densities in double
+// ---------------------------------------------------------------------------
+struct Pay32 {
+    G32 g;
+    Bg<float> b;
+    S32 st;
+    __device__ void load(uint32_t s, double &zb, double &zt, double *bv) const
+    {
+        const uint32_t col = st.col[s];
+        const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
+        const float z = st.z[s];
+        const float k = st.k[s], l = st.l[s], m = st.m[s];
+        const float Dz = st.dz[s];
+        f32::Cell c;
+        f32::locate(g, ic, jc, st.xi[s], st.eta[s], z, c);
+        const float N2 = f32::tri(b.N2, c);
+        const float f2 = f32::row(b.f2, c);
+        const float kh2 = k * k + l * l;
+        const float m2 = m * m;
+        const float K2 = kh2 + m2;
+        const float om = sqrtf((N2 * kh2 + f2 * m2) / K2);
+        const float sc = (N2 - f2) / (K2 * K2) / om;
+        const double cx = (double)(k * m2 * sc);
+        const double cy = (double)(l * m2 * sc);
+        const double cz = (double)(-m * kh2 * sc);
+        const double sW = st.W[s] / (double)Dz;
+        const double kd = k, ld = l;
+        bv[0] = (cx * kd) * sW;
+        bv[1] = (cx * ld) * sW;
+        bv[2] = (cy * kd) * sW;
+        bv[3] = (cy * ld) * sW;
+        bv[4] = (cz * kd) * sW;
+        bv[5] = (cz * ld) * sW;
+        zb = (double)z - 0.5 * (double)Dz;
+        zt = (double)z + 0.5 * (double)Dz;
+    }
+};
+
+void launch_deposit32(const Grid &g, const Bg<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+                      double *flux, hipStream_t s)
+{
+    Pay32 p{f32::make_g32(g), b, st};
+    k_deposit<Pay32><<<(unsigned)g.ncol, 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
+}

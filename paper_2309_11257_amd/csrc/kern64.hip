@@ -1,0 +1,335 @@
+// Double-precision kernels: background gradients, load/store, the RK3 step,
+// removal tallies, diagnostics and the per-ray deposition payload.
+// Built with -ffp-contract=off (see dev64.h).
+#include "deposit_common.h"
+#include "dev64.h"
+
+// ---------------------------------------------------------------------------
+// background: centred-difference gradients (periodic in x, and in y on the
+// box; one-sided at the vertical ends and the first/last latitude rows)
+// ---------------------------------------------------------------------------
+__global__ void k_gradients(Grid g, const double *U, const double *V, const double *N2, double *out)
+{
+    const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const int i = (int)(c % g.nx);
+    const int j = (int)((c / g.nx) % g.ny);
+    const int k = (int)(c / ((int64_t)g.nx * g.ny));
+    const double *F[3] = {U, V, N2};
+    const int ip = (i + 1) % g.nx, im = (i + g.nx - 1) % g.nx;
+    const int64_t row = (int64_t)g.nx;
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    for (int f = 0; f < 3; f++) {
+        const double *A = F[f];
+        const double gx = (A[c - i + ip] - A[c - i + im]) / (2.0 * g.dx);
+        double gy, gz;
+        if (g.geometry == RT_CARTESIAN) {
+            const int jp = (j + 1) % g.ny, jm = (j + g.ny - 1) % g.ny;
+            gy = (A[c + (jp - j) * row] - A[c + (jm - j) * row]) / (2.0 * g.dy);
+        } else if (g.ny == 1) {
+            gy = 0.0;
+        } else if (j == 0) {
+            gy = (A[c + row] - A[c]) / g.dy;
+        } else if (j == g.ny - 1) {
+            gy = (A[c] - A[c - row]) / g.dy;
+        } else {
+            gy = (A[c + row] - A[c - row]) / (2.0 * g.dy);
+        }
+        if (g.nz == 1) {
+            gz = 0.0;
+        } else if (k == 0) {
+            gz = (A[c + plane] - A[c]) / g.dz;
+        } else if (k == g.nz - 1) {
+            gz = (A[c] - A[c - plane]) / g.dz;
+        } else {
+            gz = (A[c + plane] - A[c - plane]) / (2.0 * g.dz);
+        }
+        out[(3 * f + 0) * cells + c] = gx;
+        out[(3 * f + 1) * cells + c] = gy;
+        out[(3 * f + 2) * cells + c] = gz;
+    }
+}
+
+__global__ void k_f2(Grid g, const double *f, double *f2, double *f2y)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.ny) return;
+    // f^2 per row, then its meridional centred difference
+    auto sq = [&](int jj) { const double v = f ? f[jj] : 0.0; return v * v; };
+    f2[j] = sq(j);
+    double d;
+    if (g.geometry == RT_CARTESIAN) {
+        const int jp = (j + 1) % g.ny, jm = (j + g.ny - 1) % g.ny;
+        d = (sq(jp) - sq(jm)) / (2.0 * g.dy);
+    } else if (g.ny == 1) {
+        d = 0.0;
+    } else if (j == 0) {
+        d = (sq(1) - sq(0)) / g.dy;
+    } else if (j == g.ny - 1) {
+        d = (sq(j) - sq(j - 1)) / g.dy;
+    } else {
+        d = (sq(j + 1) - sq(j - 1)) / (2.0 * g.dy);
+    }
+    f2y[j] = d;
+}
+
+void launch_gradients64(const Grid &g, const double *U, const double *V, const double *N2, const double *f,
+                        double *out12, double *f2, double *f2y, hipStream_t s)
+{
+    const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+    k_gradients<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, U, V, N2, out12);
+    k_f2<<<(unsigned)((g.ny + 255) / 256), 256, 0, s>>>(g, f, f2, f2y);
+}
+
+// ---------------------------------------------------------------------------
+// load / store
+// ---------------------------------------------------------------------------
+__global__ void k_load64(Grid g, rt_rays in, int64_t n, S64 d, uint32_t *key)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double Y[9] = {in.x[i], in.y[i], in.z[i], in.k[i], in.l[i], in.m[i], in.dx[i], in.dy[i], in.dz[i]};
+    const uint32_t kk = d64::post_step(g, Y);
+    d.x[i] = Y[0];
+    d.y[i] = Y[1];
+    d.z[i] = Y[2];
+    d.k[i] = Y[3];
+    d.l[i] = Y[4];
+    d.m[i] = Y[5];
+    d.dx[i] = Y[6];
+    d.dy[i] = Y[7];
+    d.dz[i] = Y[8];
+    d.px[i] = in.px[i];
+    d.py[i] = in.py[i];
+    d.pz[i] = in.pz[i];
+    d.n[i] = in.n[i];
+    d.id[i] = in.id[i];
+    key[i] = kk;
+}
+
+void launch_load64(const Grid &g, const rt_rays &in, int64_t n, S64 dst, uint32_t *key, hipStream_t s)
+{
+    if (n > 0) k_load64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, in, n, dst, key);
+}
+
+__global__ void k_store64(S64 st, const uint32_t *perm, const DevCounters *dc, rt_rays o)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dc->n_active) return;
+    const uint32_t s = perm[i];
+    o.x[i] = st.x[s];
+    o.y[i] = st.y[s];
+    o.z[i] = st.z[s];
+    o.k[i] = st.k[s];
+    o.l[i] = st.l[s];
+    o.m[i] = st.m[s];
+    o.dx[i] = st.dx[s];
+    o.dy[i] = st.dy[s];
+    o.dz[i] = st.dz[s];
+    o.px[i] = st.px[s];
+    o.py[i] = st.py[s];
+    o.pz[i] = st.pz[s];
+    o.n[i] = st.n[s];
+    o.id[i] = st.id[s];
+}
+
+void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCounters *dc, rt_rays out, int64_t bound,
+                    hipStream_t s)
+{
+    (void)g;
+    if (bound > 0) k_store64<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(src, perm, dc, out);
+}
+
+// ---------------------------------------------------------------------------
+// RK3 step (Appendix B: Williamson's low-storage three-stage scheme)
+// Reads the current set in sorted order through perm, writes the next
+// buffer contiguously, so the state stays grouped by column.
+// ---------------------------------------------------------------------------
+template <bool SPH>
+__global__ __launch_bounds__(256) void k_step64(Grid g, Bg<double> b, S64 src, S64 dst, const uint32_t *__restrict__ perm,
+                                                uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc, double dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dc->n_active) return;
+    const uint32_t s = perm[i];
+    double Y[9] = {src.x[s], src.y[s], src.z[s], src.k[s], src.l[s], src.m[s], src.dx[s], src.dy[s], src.dz[s]};
+    double Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double F[9];
+    const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+    const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+#pragma unroll 1
+    for (int st = 0; st < 3; st++) {
+        d64::rhs<SPH>(g, b, Y, F);
+#pragma unroll
+        for (int c = 0; c < 9; c++) {
+            Q[c] = A[st] * Q[c] + dt * F[c];
+            Y[c] = Y[c] + B[st] * Q[c];
+        }
+    }
+    const uint32_t key = d64::post_step(g, Y);
+    dst.x[i] = Y[0];
+    dst.y[i] = Y[1];
+    dst.z[i] = Y[2];
+    dst.k[i] = Y[3];
+    dst.l[i] = Y[4];
+    dst.m[i] = Y[5];
+    dst.dx[i] = Y[6];
+    dst.dy[i] = Y[7];
+    dst.dz[i] = Y[8];
+    dst.px[i] = src.px[s];
+    dst.py[i] = src.py[s];
+    dst.pz[i] = src.pz[s];
+    dst.n[i] = src.n[s];
+    dst.id[i] = src.id[s];
+    key_out[i] = key;
+}
+
+void launch_step64(const Grid &g, const Bg<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
+                   const DevCounters *dc, int64_t bound, double dt, hipStream_t s)
+{
+    if (bound <= 0) return;
+    const unsigned nb = (unsigned)((bound + 255) / 256);
+    if (g.geometry == RT_SPHERICAL)
+        k_step64<true><<<nb, 256, 0, s>>>(g, b, src, dst, perm, key_out, dc, dt);
+    else
+        k_step64<false><<<nb, 256, 0, s>>>(g, b, src, dst, perm, key_out, dc, dt);
+}
+
+// ---------------------------------------------------------------------------
+// tallies of volumes removed by the last step (sorted to the end, key =
+// ncol + reason) and diagnostics.  One block, fixed assignment and a fixed
+// reduction tree: deterministic.
+// ---------------------------------------------------------------------------
+__device__ inline double W64(const S64 &st, uint32_t s)
+{
+    return ((st.n[s] * st.px[s]) * st.py[s]) * st.pz[s];
+}
+
+__global__ void k_tally64(Grid g, S64 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc)
+{
+    __shared__ double sw[256];
+    __shared__ int cnt[RK_NREASON];
+    const int tid = threadIdx.x;
+    if (tid < RK_NREASON) cnt[tid] = 0;
+    __syncthreads();
+    const int64_t a = dc->n_active, e = dc->n_sorted;
+    double w = 0.0;
+    for (int64_t i = a + tid; i < e; i += 256) {
+        const int reason = (int)(skeys[i] - (uint32_t)g.ncol);
+        if (reason >= 0 && reason < RK_NREASON) atomicAdd(&cnt[reason], 1);
+        if (reason != RK_INVALID) w += W64(st, perm[i]);
+    }
+    sw[tid] = w;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) sw[tid] += sw[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) dc->removed_W += sw[0];
+    if (tid < RK_NREASON) dc->removed[tid] += cnt[tid];
+}
+
+void launch_tally64(const Grid &g, S64 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc, double *red,
+                    hipStream_t s)
+{
+    (void)red;
+    k_tally64<<<1, 256, 0, s>>>(g, st, perm, skeys, dc);
+}
+
+// sums of W, kW, lW, mW over the active set: per-block partials, then one
+// block adds them in order
+__global__ void k_stats64_part(S64 st, const uint32_t *perm, const DevCounters *dc, double *part)
+{
+    __shared__ double sh[4][256];
+    const int tid = threadIdx.x;
+    const int64_t n = dc->n_active;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    double v[4] = {0, 0, 0, 0};
+    if (i < n) {
+        const uint32_t s = perm[i];
+        const double W = W64(st, s);
+        v[0] = W;
+        v[1] = st.k[s] * W;
+        v[2] = st.l[s] * W;
+        v[3] = st.m[s] * W;
+    }
+    for (int q = 0; q < 4; q++) sh[q][tid] = v[q];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off)
+            for (int q = 0; q < 4; q++) sh[q][tid] += sh[q][tid + off];
+        __syncthreads();
+    }
+    if (tid < 4) part[4 + (int64_t)blockIdx.x * 4 + tid] = sh[tid][0];
+}
+
+__global__ void k_stats_final(double *part, int64_t nblocks)
+{
+    __shared__ double sh[4][256];
+    const int tid = threadIdx.x;
+    double v[4] = {0, 0, 0, 0};
+    for (int64_t b = tid; b < nblocks; b += 256)
+        for (int q = 0; q < 4; q++) v[q] += part[4 + b * 4 + q];
+    for (int q = 0; q < 4; q++) sh[q][tid] = v[q];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off)
+            for (int q = 0; q < 4; q++) sh[q][tid] += sh[q][tid + off];
+        __syncthreads();
+    }
+    if (tid < 4) part[tid] = sh[tid][0];
+}
+
+void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s)
+{
+    const int64_t nb = bound > 0 ? (bound + 255) / 256 : 0;
+    if (nb > 0) k_stats64_part<<<(unsigned)nb, 256, 0, s>>>(st, perm, dc, red);
+    k_stats_final<<<1, 256, 0, s>>>(red, nb);
+}
+
+// ---------------------------------------------------------------------------
+// deposition payload: wave action W = N Px Py Pz, intrinsic group velocity at
+// the carrier from the dispersion relation (N^2 and f^2 interpolated there)
+// ---------------------------------------------------------------------------
+struct Pay64 {
+    Grid g;
+    Bg<double> b;
+    S64 st;
+    __device__ void load(uint32_t s, double &zb, double &zt, double *bv) const
+    {
+        const double x = st.x[s], y = st.y[s], z = st.z[s];
+        const double k = st.k[s], l = st.l[s], m = st.m[s], Dz = st.dz[s];
+        const double W = W64(st, s);
+        d64::Cell c;
+        d64::locate(g, x, y, z, c);
+        const double N2 = d64::tri(b.N2, c);
+        const double f2 = d64::row(b.f2, c);
+        const double kh2 = k * k + l * l;
+        const double m2 = m * m;
+        const double K2 = kh2 + m2;
+        const double K4 = K2 * K2;
+        const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
+        const double d = N2 - f2;
+        const double den = om * K4;
+        const double cx = ((k * m2) * d) / den;
+        const double cy = ((l * m2) * d) / den;
+        const double cz = -(((m * kh2) * d) / den);
+        const double sW = W / Dz;
+        bv[0] = (cx * k) * sW;
+        bv[1] = (cx * l) * sW;
+        bv[2] = (cy * k) * sW;
+        bv[3] = (cy * l) * sW;
+        bv[4] = (cz * k) * sW;
+        bv[5] = (cz * l) * sW;
+        zb = z - 0.5 * Dz;
+        zt = z + 0.5 * Dz;
+    }
+};
+
+void launch_deposit64(const Grid &g, const Bg<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+                      double *flux, hipStream_t s)
+{
+    Pay64 p{g, b, st};
+    k_deposit<Pay64><<<(unsigned)g.ncol, 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
+}

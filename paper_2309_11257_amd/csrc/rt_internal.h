@@ -1,0 +1,141 @@
+// Internal declarations of the gfx950 ray-volume tracer library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rt.h"
+
+// Keys of removed ray volumes sort after every column key: ncol + reason.
+enum { RK_TOP = 0, RK_BOTTOM = 1, RK_POLE = 2, RK_INVALID = 3, RK_MERGED = 4, RK_CAPPED = 5, RK_NREASON = 6 };
+
+struct Grid {
+    int geometry, nx, ny, nz;
+    int ncol;
+    double dx, dy, dz, x0, y0, a;
+    double Lx, Ly, Lz;
+    double pole;  // latitude beyond which ray volumes are removed (rad)
+};
+
+template <typename T>
+struct Bg {
+    const T *U, *V, *N2;
+    const T *Ux, *Uy, *Uz, *Vx, *Vy, *Vz, *N2x, *N2y, *N2z;
+    const T *f2, *f2y;   // [ny]
+    const double *rho;   // [nz]
+};
+
+// double-precision state: absolute coordinates, as the public interface
+struct S64 {
+    double *x, *y, *z, *k, *l, *m, *dx, *dy, *dz, *px, *py, *pz, *n;
+    int64_t *id;
+};
+
+// single-precision state: horizontal position as column index + offset in
+// cell units; extents Dx, Dy in cell units; wave action W in double
+struct S32 {
+    uint32_t *col;
+    float *xi, *eta, *z, *k, *l, *m, *dxi, *deta, *dz, *px, *py, *pz;
+    double *W;
+    int64_t *id;
+};
+
+// device-side counters (one instance per context)
+struct DevCounters {
+    int64_t n_sorted;   // keys in the last sort (slots in the current buffer)
+    int64_t n_active;   // sorted keys that name a column
+    int64_t removed[RK_NREASON];
+    double removed_W;
+    int64_t n_split, n_merged;
+    int64_t split_extra;
+    int64_t next_id;
+    int64_t steps;
+};
+
+struct rt_ctx_s {
+    rt_config cfg;
+    Grid g;
+    hipStream_t stream;
+    char err[512];
+    int precision;
+    // background
+    bool have_bg;
+    Bg<double> bg64;
+    Bg<float> bg32;
+    double *rho;
+    // state: double buffers
+    S64 s64[2];
+    S32 s32[2];
+    uint32_t *key[2];
+    int cur;
+    int64_t cap;
+    int64_t n_bound;  // host-side upper bound of active count (the device holds the exact one)
+    bool have_rays;
+    // sorted view of the current buffer
+    uint32_t *perm, *skeys;
+    uint32_t *colstart;  // [ncol + 1]
+    // sort scratch
+    uint32_t *tk, *tv, *hist;
+    int64_t hist_len;
+    // flux scratch
+    double *flux, *drag;
+    // counters
+    DevCounters *dc;
+    double *red;      // reduction scratch
+    int64_t *ired;    // integer scratch
+    // allocation bookkeeping
+    void *allocs[96];
+    int nallocs;
+};
+
+// error helpers
+rt_status rt_fail(rt_ctx c, rt_status s, const char *fmt, ...);
+
+#define HIP_OK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) return rt_fail(ctx, RT_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// launchers (implemented in the kernel translation units)
+void launch_gradients64(const Grid &g, const double *U, const double *V, const double *N2, const double *f,
+                        double *out12, double *f2, double *f2y, hipStream_t s);
+void launch_round32(const double *in, float *out, int64_t n, hipStream_t s);
+
+void launch_load64(const Grid &g, const rt_rays &in, int64_t n, S64 dst, uint32_t *key, hipStream_t s);
+void launch_load32(const Grid &g, const rt_rays &in, int64_t n, S32 dst, uint32_t *key, hipStream_t s);
+void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCounters *dc, rt_rays out,
+                    int64_t bound, hipStream_t s);
+void launch_store32(const Grid &g, S32 src, const uint32_t *perm, const DevCounters *dc, rt_rays out,
+                    int64_t bound, hipStream_t s);
+
+void launch_step64(const Grid &g, const Bg<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
+                   const DevCounters *dc, int64_t bound, double dt, hipStream_t s);
+void launch_step32(const Grid &g, const Bg<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
+                   const DevCounters *dc, int64_t bound, double dt, hipStream_t s);
+
+// stable LSD radix sort of keys[0..*n) with 32-bit payload (identity if vals == NULL)
+void radix_sort(const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out, uint32_t *vals_out,
+                uint32_t *tk, uint32_t *tv, uint32_t *hist, const int64_t *n_dev, int64_t bound, int nbits,
+                hipStream_t s);
+int64_t radix_hist_len(int64_t bound);
+void launch_colstart(const uint32_t *skeys, DevCounters *dc, uint32_t *colstart, int ncol, hipStream_t s);
+
+void launch_tally64(const Grid &g, S64 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc,
+                    double *red, hipStream_t s);
+void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc,
+                    double *red, hipStream_t s);
+void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
+void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
+
+void launch_deposit64(const Grid &g, const Bg<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+                      double *flux, hipStream_t s);
+void launch_deposit32(const Grid &g, const Bg<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+                      double *flux, hipStream_t s);
+void launch_drag(const Grid &g, const double *rho, const double *flux, double *drag, hipStream_t s);
+
+void launch_copy_n(const uint32_t *src, uint32_t *dst, const DevCounters *dc, int64_t bound, hipStream_t s);
+void launch_set_sorted(DevCounters *dc, int64_t n, hipStream_t s);
+void launch_sorted_from_active(DevCounters *dc, hipStream_t s);
+
+// split / merge / cap
+rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, rt_stats *out);

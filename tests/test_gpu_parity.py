@@ -1,0 +1,239 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+inputs, element by element.  Double precision on the Cartesian box must be
+bit-exact for positions, wavevectors, extents and column keys; fluxes and
+drag within 1e-12; the single-precision path within 1e-5 (relative L2) on the
+drag after one step."""
+import numpy as np
+import pytest
+
+from paper_2309_11257_amd import workloads as W
+from helpers import EVOLVING, FIELDS, assert_flux_close, by_id, gpu_tracer, oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_11257_amd import _rt
+    _rt.lib()
+    return _rt
+
+
+def c2_small(n_cols=500, seed=2):
+    cols = np.sort(np.random.default_rng(seed).choice(128 * 128, n_cols, replace=False))
+    return W.make_c2(cols=cols)
+
+
+def c3_small(n_rays=120_000):
+    return W.make_c3(n_rays=n_rays)
+
+
+def compare_state(orc_rs, gpu, exact=True, rtol=0.0, fields=EVOLVING):
+    o = by_id(orc_rs.snapshot())
+    g = by_id(gpu)
+    assert np.array_equal(o["id"], g["id"]), "active sets differ"
+    for f in fields:
+        if exact:
+            bad = np.nonzero(o[f] != g[f])[0]
+            assert bad.size == 0, f"{f}: {bad.size} differ, e.g. id {o['id'][bad[0]]}: {o[f][bad[0]]!r} vs {g[f][bad[0]]!r}"
+        else:
+            assert np.allclose(g[f], o[f], rtol=rtol, atol=0), f
+
+
+# ---------------------------------------------------------------------------
+def test_fp64_box_one_step_bitwise(rt, orc):
+    w = W.make_c1()
+    _, rs, _ = oracle_run(orc, w, 1)
+    tr = gpu_tracer(w, rt.RT_FP64)
+    tr.step(w.dt)
+    g = tr.get_rays()
+    compare_state(rs, g)
+    compare_state(rs, g, fields=("px", "py", "pz", "n"))
+    # internal order is grouped by the oracle's column key, ascending
+    col_of = dict(zip(rs["id"], rs["col"]))
+    cols = np.array([col_of[i] for i in g["id"]])
+    assert (np.diff(cols) >= 0).all()
+
+
+def test_fp64_box_100_steps_bitwise_and_drag(rt, orc):
+    w = W.make_c1()
+    bg = orc.Background.from_workload(w)
+    rs = orc.RaySet(w.rays)
+    tr = gpu_tracer(w, rt.RT_FP64)
+    for s in range(w.steps):
+        orc.step(bg, rs, w.dt)
+        tr.step(w.dt)
+        if s in (0, 9, 49, 99):
+            ref = orc.deposit(bg, rs)
+            dref = orc.drag(bg, ref)
+            flux, drag = tr.deposit(host=True)
+            assert_flux_close(flux, ref, 1e-12, f"flux step {s}")
+            assert rel_l2(drag, dref) <= 1e-12
+            assert_flux_close(drag, dref, 1e-11, f"drag step {s}")
+    compare_state(rs, tr.get_rays())
+
+
+def test_fp64_jet_box_bitwise(rt, orc):
+    w = c2_small()
+    _, rs, _ = oracle_run(orc, w, 12)
+    tr = gpu_tracer(w, rt.RT_FP64)
+    for _ in range(12):
+        tr.step(w.dt)
+    compare_state(rs, tr.get_rays())
+    bg = orc.Background.from_workload(w)
+    ref = orc.deposit(bg, rs)
+    flux, drag = tr.deposit(host=True)
+    assert_flux_close(flux, ref, 1e-12, "flux")
+    assert rel_l2(drag, orc.drag(bg, ref)) <= 1e-12
+
+
+def test_fp64_sphere_close(rt, orc):
+    """On the sphere the step calls cos and tan, whose last bit may differ
+    between the host's libm and the device library: positions must agree to
+    a few ulp and the fluxes to 1e-12."""
+    w = c3_small()
+    _, rs, _ = oracle_run(orc, w, 5)
+    tr = gpu_tracer(w, rt.RT_FP64)
+    for _ in range(5):
+        tr.step(w.dt)
+    g = by_id(tr.get_rays())
+    o = by_id(rs.snapshot())
+    assert np.array_equal(o["id"], g["id"])
+    for f in EVOLVING:
+        scale = np.abs(o[f]) + 1e-300
+        assert (np.abs(g[f] - o[f]) / scale).max() <= 1e-13, f
+    bg = orc.Background.from_workload(w)
+    ref = orc.deposit(bg, rs)
+    flux, drag = tr.deposit(host=True)
+    assert_flux_close(flux, ref, 1e-12, "flux")
+    assert rel_l2(drag, orc.drag(bg, ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["box", "sphere"])
+def test_fp32_drag_within_1e5(rt, orc, name):
+    w = c2_small() if name == "box" else c3_small()
+    bg = orc.Background.from_workload(w)
+    rs = orc.RaySet(w.rays)
+    tr = gpu_tracer(w, rt.RT_FP32)
+    # at load: fluxes from FP32-rounded state
+    flux, drag = tr.deposit(host=True)
+    ref = orc.deposit(bg, rs)
+    assert rel_l2(drag, orc.drag(bg, ref)) <= 1e-5
+    orc.step(bg, rs, w.dt)
+    tr.step(w.dt)
+    ref = orc.deposit(bg, rs)
+    dref = orc.drag(bg, ref)
+    flux, drag = tr.deposit(host=True)
+    err = rel_l2(drag, dref)
+    assert err <= 1e-5, err
+    for c in range(6):
+        assert rel_l2(flux[c], ref[c]) <= 1e-5, c
+    # state after one step
+    g = by_id(tr.get_rays())
+    o = by_id(rs.snapshot())
+    assert np.array_equal(o["id"], g["id"])
+    for f in ("z", "k", "l", "m", "dz"):
+        assert rel_l2(g[f], o[f]) <= 1e-6, f
+    span = (w.dx, w.dy)
+    for f, d in zip(("x", "y"), span):
+        assert np.abs(g[f] - o[f]).max() <= 1e-5 * d, f
+
+
+def test_deposit_is_deterministic(rt):
+    w = c2_small(300)
+    for prec in (rt.RT_FP64, rt.RT_FP32):
+        outs = []
+        for _ in range(2):
+            tr = gpu_tracer(w, prec)
+            for _ in range(3):
+                tr.step(w.dt)
+            f, d = tr.deposit(host=True)
+            outs.append((f, d))
+            tr.close()
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("n", [0, 1, 255, 257, 4097])
+def test_ragged_and_empty(rt, orc, n):
+    w = W.make_c1(n_rays=max(n, 1))
+    rays = {k: v[:n].copy() for k, v in w.rays.items()}
+    _, rs, _ = oracle_run(orc, w, 3, rays=rays)
+    tr = gpu_tracer(w, rt.RT_FP64, rays=rays, capacity=max(n, 1))
+    for _ in range(3):
+        tr.step(w.dt)
+    g = tr.get_rays()
+    assert len(g["id"]) == int(rs.active().sum())
+    if n:
+        compare_state(rs, g)
+    flux, drag = tr.deposit(host=True)
+    bg = orc.Background.from_workload(w)
+    ref = orc.deposit(bg, rs)
+    if n == 0:
+        assert not flux.any() and not drag.any()
+    else:
+        assert_flux_close(flux, ref, 1e-12)
+
+
+def test_removal_tallies_match_oracle(rt, orc):
+    w = W.make_c1(n_rays=2000)
+    w.rays["z"][:] = np.linspace(-100.0, 63.9e3, 2000)  # some start outside, many near the top
+    bg = orc.Background.from_workload(w)
+    rs = orc.RaySet(w.rays)
+    orc.keys(bg, rs)
+    # the oracle counts the volumes outside the domain at load like the library
+    z = w.rays["z"]
+    pre_bottom = int((z < 0).sum())
+    rs.a["state"][: rs.n][z < 0] = orc.GONE_BOTTOM
+    tr = gpu_tracer(w, rt.RT_FP64)
+    removed_W = 0.0
+    tops = 0
+    for _ in range(30):
+        t = orc.step(bg, rs, w.dt)
+        removed_W += t["removed_W"]
+        tops += t["n_top"]
+        tr.step(w.dt)
+    s = tr.stats()
+    so = orc.stats(rs)
+    assert s["n_active"] == so["n_active"]
+    assert s["n_top"] == tops and tops > 0
+    assert s["n_bottom"] == pre_bottom
+    assert s["steps"] == 30
+    Wpre = (w.rays["n"] * w.rays["px"] * w.rays["py"] * w.rays["pz"])[z < 0].sum()
+    assert s["removed_W"] == pytest.approx(removed_W + Wpre, rel=1e-13)
+    for key in ("sum_W", "sum_kW", "sum_lW", "sum_mW"):
+        assert s[key] == pytest.approx(so[key], rel=1e-13)
+
+
+def test_load_order_is_stable_column_sort(rt, orc):
+    w = c2_small(64)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(w.n_rays)
+    rays = {k: v[perm].copy() for k, v in w.rays.items()}
+    tr = gpu_tracer(w, rt.RT_FP64, rays=rays)
+    g = tr.get_rays()
+    bg = orc.Background.from_workload(w)
+    rs = orc.RaySet(rays)
+    orc.keys(bg, rs)
+    expect = np.argsort(rs["col"], kind="stable")
+    assert np.array_equal(g["id"], rays["id"][expect])
+
+
+def test_api_errors(rt):
+    w = W.make_c1(n_rays=10)
+    tr = rt.Tracer.for_workload(w, rt.RT_FP64, capacity=10)
+    with pytest.raises(rt.RTError) as e:
+        tr.step(60.0)
+    assert e.value.code == rt.RT_E_STATE
+    bad = w.N2.copy()
+    bad[3, 2, 1] = -1.0
+    with pytest.raises(rt.RTError) as e:
+        tr.init_background(w.U, w.V, bad, w.f, w.rho)
+    assert e.value.code == rt.RT_E_ARG
+    tr.init_background_from(w)
+    big = W.make_c1(n_rays=11)
+    with pytest.raises(rt.RTError) as e:
+        tr.set_rays(big.rays)
+    assert e.value.code == rt.RT_E_CAPACITY
