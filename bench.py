@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Benchmark of the ray-volume tracer hot path on one MI355X.
+
+A step is one pass of the whole hot path over the ray set: the RK3 step of
+every active ray volume (interpolation, dispersion, refraction, face group
+velocities, low-storage update, wrap/removal/column keys), the regrouping
+sort, the flux deposition and the drag.  Inputs are resident in HBM before
+the timed region starts.
+
+Default workload: the global 1x1 degree lat-lon grid, 120 levels to 100 km,
+20,000,000 ray volumes (a latitude-dependent background source plus
+clustered convective sources with 10x the mean count in 5 % of the columns),
+dt = 20 s.  The single-precision path is the headline value; the
+double-precision path is timed on the same inputs.  The drag error of both
+against the CPU oracle is measured after one step from identical inputs,
+and the oracle's own speed on that step is the CPU baseline.
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ray-volume updates/s (RK3+deposit) FP32 vs FP64 at stated drag error"
+UNIT = "ray-volume updates/s"
+
+# algorithmic work per ray volume and step (measurement):
+# state read 13 words, written 9 words
+STEP_BYTES = {"fp32": 88, "fp64": 176}
+# flops of one RK3 step of one ray volume (three stages of: centre
+# interpolation of 12 fields, 6 face interpolations, 7 dispersion
+# evaluations, refraction, update), Cartesian count; spherical adds the
+# metric terms
+STEP_FLOPS = {"cartesian": 2200, "spherical": 2300}
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+KERNEL_SOURCES = {"step": ["paper_2309_11257_amd/csrc/kern32.hip"],
+                  "deposit": ["paper_2309_11257_amd/csrc/deposit_common.h", "paper_2309_11257_amd/csrc/kern32.hip"]}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def rel_l2(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.sqrt(((a - b) ** 2).sum() / max((b * b).sum(), 1e-300)))
+
+
+def time_path(w, precision, steps, warmup):
+    import torch
+
+    from paper_2309_11257_amd import _rt
+    tr = _rt.Tracer.for_workload(w, precision)
+    tr.init_background_from(w)
+    # one step from the initial state, for the drag error
+    tr.set_rays(w.rays)
+    tr.step(w.dt)
+    _, drag1 = tr.deposit(host=True)
+    ids1 = tr.get_rays()["id"]
+    cols1 = tr.get_columns()
+    tr.set_rays(w.rays)
+    flux = torch.empty((6, w.nz + 1, w.ny, w.nx), dtype=torch.float64, device="cuda")
+    drag = torch.empty((2, w.nz, w.ny, w.nx), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        tr.step(w.dt)
+        tr.deposit(flux, drag)
+    torch.cuda.synchronize()
+    n0 = tr.stats()["n_active"]
+    tr.profile(True)
+    tr.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        tr.step(w.dt)
+        tr.deposit(flux, drag)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    prof = tr.profile_read()
+    tr.profile(False)
+    n1 = tr.stats()["n_active"]
+    tr.close()
+    del flux, drag
+    torch.cuda.empty_cache()
+    ms_per_step = ms / steps
+    updates = 0.5 * (n0 + n1) * steps
+    return dict(ms_per_step=ms_per_step, wall_s=wall, value=updates / (ms * 1e-3), n_active=(n0, n1),
+                kernels={k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / max(v[1], 1)} for k, v in prof.items()},
+                drag1=drag1, ids1=ids1, cols1=cols1)
+
+
+def cpu_baseline(w):
+    """The oracle as it stands, timed on the host's cores on one full step of
+    the workload (its own step, deposition and drag).  Returns the baseline
+    record and the oracle objects for the error measurement."""
+    import oracle
+    bg = oracle.Background.from_workload(w)
+    rs = oracle.RaySet(w.rays)
+    t0 = time.perf_counter()
+    oracle.step(bg, rs, w.dt)
+    flux = oracle.deposit(bg, rs)
+    drag = oracle.drag(bg, flux)
+    t = time.perf_counter() - t0
+    n = w.n_rays
+    rec = dict(value=n / t, unit=UNIT, cores=oracle.num_threads(), kind="oracle",
+               sample=f"one full RK3 step + deposition + drag of all {n} ray volumes of the timed workload "
+                      f"({t:.1f} s)")
+    return rec, (oracle, bg, rs, drag)
+
+
+def drag_errors(orc_state, run):
+    """Relative L2 drag error of a GPU path after one step against the oracle:
+    raw, and with the oracle taking the kernel's integer decisions (active
+    set, parent column) where rounding put a ray on the other side of a cell
+    face; plus the number of such flipped decisions."""
+    import numpy as np
+    orc, bg, rs, drag_ref = orc_state
+    raw = rel_l2(run["drag1"], drag_ref)
+    ids = rs["id"]
+    active = rs.active()
+    o = np.argsort(run["ids1"], kind="stable")
+    gs, gc = run["ids1"][o], run["cols1"].astype(np.int64)[o]
+    p = np.clip(np.searchsorted(gs, ids), 0, max(gs.size - 1, 0))
+    found = gs[p] == ids if gs.size else np.zeros(ids.size, bool)
+    cols = np.where(found & active, gc[p], -1)
+    flips = int(((cols != rs["col"]) & (cols >= 0)).sum())
+    nset = int((found != active).sum())
+    save = rs.a["state"][: rs.n].copy()
+    savec = rs.a["col"][: rs.n].copy()
+    rs.a["state"][: rs.n][active & ~found] = orc.INVALID
+    flux = orc.deposit(bg, rs, cols=cols)
+    aligned = rel_l2(run["drag1"], orc.drag(bg, flux))
+    rs.a["state"][: rs.n] = save
+    rs.a["col"][: rs.n] = savec
+    return {"aligned": aligned, "raw": raw, "column_flips": flips, "active_set_flips": nset}
+
+
+def load_traffic(kernel, rays):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))[kernel]
+    except (KeyError, ValueError):
+        return None
+    if d.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]) or d.get("rays") != rays:
+        return None
+    return float(d["bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rays", type=int, default=20_000_000, help="ray volumes (default: the full workload)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and the oracle drag error")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
+              "ray set is a design in DESIGN.md, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4}))
+        return
+
+    from paper_2309_11257_amd import _rt
+    from paper_2309_11257_amd import workloads as W
+
+    t = time.perf_counter()
+    w = W.make_c3(n_rays=args.rays)
+    log(f"workload: {w.n_rays} ray volumes on {w.nx}x{w.ny}x{w.nz} ({time.perf_counter() - t:.1f} s)")
+
+    r32 = time_path(w, _rt.RT_FP32, args.steps, args.warmup)
+    log(f"fp32: {r32['ms_per_step']:.3f} ms/step, {r32['value'] / 1e9:.2f} G upd/s, kernels {r32['kernels']}")
+    r64 = None
+    if not args.no_fp64:
+        r64 = time_path(w, _rt.RT_FP64, args.steps, args.warmup)
+        log(f"fp64: {r64['ms_per_step']:.3f} ms/step, {r64['value'] / 1e9:.2f} G upd/s, kernels {r64['kernels']}")
+
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        cpu, orc_state = cpu_baseline(w)
+        log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M upd/s on {cpu['cores']} threads")
+        errs["fp32"] = drag_errors(orc_state, r32)
+        if r64:
+            errs["fp64"] = drag_errors(orc_state, r64)
+        log(f"drag rel L2 error vs oracle after one step: {errs}")
+
+    # roofline of the dominant kernel of the FP32 path
+    kern = max(r32["kernels"].items(), key=lambda kv: kv[1]["ms_total"])
+    name, kd = kern
+    nray = 0.5 * (r32["n_active"][0] + r32["n_active"][1])
+    avg_s = kd["ms_avg"] * 1e-3
+    geom = "spherical" if w.geometry == W.SPHERICAL else "cartesian"
+    if name == "step":
+        gbs = STEP_BYTES["fp32"] * nray / avg_s / 1e9
+        tflops = STEP_FLOPS[geom] * nray / avg_s / 1e12
+        hbm_frac = gbs / PEAK_HBM_GBS
+        alu_frac = tflops / PEAK_FP32_TFLOPS
+        traffic = load_traffic("step", w.n_rays)
+        if alu_frac >= hbm_frac:
+            roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(alu_frac, 4), "traffic": traffic, "kernel": "k_step32",
+                    "hbm_achieved_GBs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4)}
+        else:
+            roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(hbm_frac, 4), "traffic": traffic, "kernel": "k_step32",
+                    "alu_achieved_TFLOPs": round(tflops, 3), "alu_frac": round(alu_frac, 4)}
+    else:
+        # deposition / sort / drag are HBM work: algorithmic bytes per ray
+        per = {"deposit": 36 + 0, "sort": 40, "drag": 0}[name] if name in ("deposit", "sort", "drag") else 0
+        gbs = per * nray / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": load_traffic(name, w.n_rays), "kernel": name}
+    roof["kernel_ms_avg"] = round(kd["ms_avg"], 4)
+
+    out = {
+        "metric": METRIC,
+        "value": round(r32["value"], 1),
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"global lat-lon 360x180x120 (0-100 km), {w.n_rays} ray volumes "
+                               f"(background source + clustered convection), RK3 dt={w.dt:g} s + deposition + drag",
+                   "rays": w.n_rays, "grid": [w.nx, w.ny, w.nz], "dt": w.dt, "geometry": "spherical"},
+        "drag_rel_l2_vs_oracle_1step": errs or None,
+        "fp64": None if r64 is None else {"value": round(r64["value"], 1), "ms_per_step": round(r64["ms_per_step"], 4),
+                                          "dtype": "f64"},
+        "kernels_ms_avg": {k: round(v["ms_avg"], 4) for k, v in r32["kernels"].items()},
+        "kernels_ms_avg_fp64": None if r64 is None else {k: round(v["ms_avg"], 4) for k, v in r64["kernels"].items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -130,6 +130,11 @@ rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int32_t where)
  * *n_inout is set to the number needed and nothing is written). */
 rt_status rt_get_rays(rt_ctx ctx, rt_rays *rays, int64_t *n_inout, int32_t where);
 
+/* Column key (j*nx + i) of each active ray volume's parent column, in the
+ * same order as rt_get_rays returns them.  *n_inout as for rt_get_rays.
+ * Synchronises. */
+rt_status rt_get_columns(rt_ctx ctx, uint32_t *cols, int64_t *n_inout, int32_t where);
+
 /* Advance every active ray volume by one RK3 step of length dt (Appendix B:
  * Williamson's low-storage third-order scheme; Section 3a: carrier moved by
  * the mean and extents by the difference of the face group velocities,
@@ -168,6 +173,16 @@ rt_status rt_split_merge(rt_ctx ctx, double alpha_split, int32_t n_max_per_cell,
 
 /* Current diagnostics (deterministic sums).  Synchronises. */
 rt_status rt_get_stats(rt_ctx ctx, rt_stats *out);
+
+/* Kernel timing for benchmarks.  While on, the library brackets each group of
+ * launches with HIP events on the context's stream, by class:
+ *   0 RK3 step, 1 sort + column offsets + removal tallies, 2 deposition,
+ *   3 drag, 4 split/merge/cap, 5 diagnostics.
+ * rt_profile_read synchronises, returns the summed milliseconds and the
+ * number of timed groups per class since the last read (arrays of 8), and
+ * resets them.  Recording events does not change the work done. */
+rt_status rt_profile(rt_ctx ctx, int32_t on);
+rt_status rt_profile_read(rt_ctx ctx, double *ms, int64_t *groups);
 
 /* Human-readable description of the last error on this context ("" if none). */
 const char *rt_last_error(rt_ctx ctx);

@@ -197,9 +197,18 @@ def keys(bg: Background, rs: RaySet) -> None:
     lib().orc_keys(bg.ref, rs.ref, rs.n)
 
 
-def deposit(bg: Background, rs: RaySet) -> np.ndarray:
-    """Flux fields [6][nz+1][ny][nx]; computes column keys first."""
-    keys(bg, rs)
+def deposit(bg: Background, rs: RaySet, cols: Optional[np.ndarray] = None) -> np.ndarray:
+    """Flux fields [6][nz+1][ny][nx].  The parent column of each active ray
+    is computed from its position unless `cols` (one per ray of the set, -1
+    for inactive) supplies that integer decision from elsewhere -- used to
+    compare a lower-precision path whose rounding put a ray a hair's breadth
+    across a cell face: both sides then take the same decision."""
+    if cols is None:
+        keys(bg, rs)
+    else:
+        cols = np.asarray(cols, dtype=np.int32)
+        assert cols.shape == (rs.n,)
+        rs.a["col"][: rs.n] = cols
     flux = np.zeros((6, bg.nz + 1, bg.ny, bg.nx))
     lib().orc_deposit(bg.ref, rs.ref, rs.n, _ptr(flux))
     return flux

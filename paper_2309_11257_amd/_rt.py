@@ -76,10 +76,13 @@ def lib() -> C.CDLL:
         L.rt_deposit_flux.argtypes = [P, P, P, I32]
         L.rt_split_merge.argtypes = [P, D, I32, I32, C.POINTER(Stats)]
         L.rt_get_stats.argtypes = [P, C.POINTER(Stats)]
+        L.rt_get_columns.argtypes = [P, P, C.POINTER(I64), I32]
+        L.rt_profile.argtypes = [P, I32]
+        L.rt_profile_read.argtypes = [P, P, P]
         L.rt_last_error.argtypes = [P]
         L.rt_last_error.restype = C.c_char_p
         for name in ("rt_create", "rt_destroy", "rt_init_background", "rt_set_rays", "rt_get_rays", "rt_step",
-                     "rt_deposit_flux", "rt_split_merge", "rt_get_stats"):
+                     "rt_deposit_flux", "rt_split_merge", "rt_get_stats", "rt_profile", "rt_profile_read", "rt_get_columns"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -210,6 +213,17 @@ class Tracer:
         self._check(lib().rt_get_rays(self.h, C.byref(r), C.byref(n2), where))
         return {k: v[: n2.value] for k, v in out.items()}
 
+    def get_columns(self) -> np.ndarray:
+        """Parent-column key of each active ray, in get_rays() order."""
+        n = C.c_int64(0)
+        st = lib().rt_get_columns(self.h, None, C.byref(n), RT_HOST)
+        if st not in (RT_OK, RT_E_ARG):
+            self._check(st)
+        out = np.empty(max(n.value, 1), dtype=np.uint32)
+        n2 = C.c_int64(n.value)
+        self._check(lib().rt_get_columns(self.h, out.ctypes.data, C.byref(n2), RT_HOST))
+        return out[: n2.value]
+
     def step(self, dt: float, deposit: bool = False):
         self._check(lib().rt_step(self.h, float(dt), RT_STEP_DEPOSIT if deposit else 0))
 
@@ -234,6 +248,17 @@ class Tracer:
         s = Stats()
         self._check(lib().rt_split_merge(self.h, float(alpha), int(n_max), int(mode), C.byref(s)))
         return s.as_dict()
+
+    PROFILE_CLASSES = ("step", "sort", "deposit", "drag", "split_merge", "stats", "c6", "c7")
+
+    def profile(self, on: bool = True):
+        self._check(lib().rt_profile(self.h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(8)
+        n = np.zeros(8, dtype=np.int64)
+        self._check(lib().rt_profile_read(self.h, ms.ctypes.data, n.ctypes.data))
+        return {c: (float(ms[i]), int(n[i])) for i, c in enumerate(self.PROFILE_CLASSES) if n[i]}
 
     def stats(self) -> dict:
         s = Stats()

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <vector>
 
 #include "rt_internal.h"
 
@@ -33,8 +34,100 @@ static void *ctx_alloc(rt_ctx c, size_t bytes)
     return p;
 }
 
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+};
+struct Prof {
+    std::vector<ProfRec> recs;
+    size_t used = 0;
+    double ms[PC_N] = {0};
+    int64_t n[PC_N] = {0};
+};
+
+static void prof_fold(rt_ctx c)
+{
+    Prof *p = (Prof *)c->prof;
+    if (!p || p->used == 0) return;
+    (void)hipEventSynchronize(p->recs[p->used - 1].b);
+    for (size_t i = 0; i < p->used; i++) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, p->recs[i].a, p->recs[i].b) == hipSuccess) {
+            p->ms[p->recs[i].cls] += t;
+            p->n[p->recs[i].cls] += 1;
+        }
+    }
+    p->used = 0;
+}
+
+void prof_begin(rt_ctx c, int cls)
+{
+    if (!c->prof_on) return;
+    Prof *p = (Prof *)c->prof;
+    if (p->used == 4096) prof_fold(c);
+    if (p->used == p->recs.size()) {
+        ProfRec r;
+        r.cls = cls;
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+        p->recs.push_back(r);
+    }
+    p->recs[p->used].cls = cls;
+    (void)hipEventRecord(p->recs[p->used].a, c->stream);
+    c->prof_class = cls;
+}
+
+void prof_end(rt_ctx c)
+{
+    if (!c->prof_on) return;
+    Prof *p = (Prof *)c->prof;
+    if (p->used < p->recs.size()) {
+        (void)hipEventRecord(p->recs[p->used].b, c->stream);
+        p->used++;
+    }
+}
+
+static void prof_destroy(rt_ctx c)
+{
+    Prof *p = (Prof *)c->prof;
+    if (!p) return;
+    for (auto &r : p->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    delete p;
+    c->prof = nullptr;
+}
+
+extern "C" rt_status rt_profile(rt_ctx ctx, int32_t on)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!ctx->prof) ctx->prof = new Prof();
+    ctx->prof_on = on != 0;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_profile_read(rt_ctx ctx, double *ms, int64_t *groups)
+{
+    if (!ctx || !ms || !groups) return rt_fail(ctx, RT_E_ARG, "ms and groups are required");
+    for (int i = 0; i < PC_N; i++) {
+        ms[i] = 0.0;
+        groups[i] = 0;
+    }
+    Prof *p = (Prof *)ctx->prof;
+    if (!p) return RT_OK;
+    prof_fold(ctx);
+    for (int i = 0; i < PC_N; i++) {
+        ms[i] = p->ms[i];
+        groups[i] = p->n[i];
+        p->ms[i] = 0.0;
+        p->n[i] = 0;
+    }
+    return RT_OK;
+}
+
 static void ctx_release(rt_ctx c)
 {
+    prof_destroy(c);
     for (int i = 0; i < c->nallocs; i++) {
         if (c->cfg.free)
             c->cfg.free(c->allocs[i], c->cfg.user);
@@ -116,6 +209,17 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     b.f2y = bgd + 12 * cells + g.ny;
     ctx->rho = bgd + 12 * cells + 2 * g.ny;
     b.rho = ctx->rho;
+    if (ctx->precision == RT_FP64) {
+        double4 *pa;
+        ALLOC(pa, double4, 4 * cells);
+        ctx->bp64.A = pa;
+        ctx->bp64.G = pa + cells;
+    } else {
+        float4 *pa;
+        ALLOC(pa, float4, 4 * cells);
+        ctx->bp32.A = pa;
+        ctx->bp32.G = pa + cells;
+    }
     if (ctx->precision == RT_FP32) {
         float *bgf;
         ALLOC(bgf, float, 12 * cells + 2 * (int64_t)g.ny);
@@ -193,6 +297,7 @@ static int key_bits(int ncol)
 static rt_status sort_current(rt_ctx ctx)
 {
     const int64_t bound = ctx->n_bound;
+    prof_begin(ctx, PC_SORT);
     radix_sort(ctx->key[ctx->cur], nullptr, ctx->skeys, ctx->perm, ctx->tk, ctx->tv, ctx->hist, &ctx->dc->n_sorted,
                bound, key_bits(ctx->g.ncol), ctx->stream);
     launch_colstart(ctx->skeys, ctx->dc, ctx->colstart, ctx->g.ncol, ctx->stream);
@@ -200,6 +305,7 @@ static rt_status sort_current(rt_ctx ctx)
         launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->red, ctx->stream);
     else
         launch_tally32(ctx->g, ctx->s32[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->red, ctx->stream);
+    prof_end(ctx);
     HIP_OK(hipGetLastError());
     return RT_OK;
 }
@@ -237,6 +343,9 @@ extern "C" rt_status rt_init_background(rt_ctx ctx, const double *U, const doubl
     if (ctx->precision == RT_FP32) {
         float *bgf = (float *)ctx->bg32.U;
         launch_round32(bgd, bgf, 12 * cells + 2 * (int64_t)g.ny, ctx->stream);
+        launch_pack32(g, ctx->bg64, (float4 *)ctx->bp32.A, (float4 *)ctx->bp32.G, ctx->stream);
+    } else {
+        launch_pack64(g, ctx->bg64, (double4 *)ctx->bp64.A, (double4 *)ctx->bp64.G, ctx->stream);
     }
     HIP_OK(hipGetLastError());
     if (where == RT_HOST) HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -330,12 +439,14 @@ extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
     if (!ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "rt_set_rays has not been called");
     if (!std::isfinite(dt)) return rt_fail(ctx, RT_E_ARG, "dt must be finite");
     const int nxt = 1 - ctx->cur;
+    prof_begin(ctx, PC_STEP);
     if (ctx->precision == RT_FP64)
-        launch_step64(ctx->g, ctx->bg64, ctx->s64[ctx->cur], ctx->s64[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
+        launch_step64(ctx->g, ctx->bp64, ctx->s64[ctx->cur], ctx->s64[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
                       ctx->n_bound, dt, ctx->stream);
     else
-        launch_step32(ctx->g, ctx->bg32, ctx->s32[ctx->cur], ctx->s32[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
+        launch_step32(ctx->g, ctx->bp32, ctx->s32[ctx->cur], ctx->s32[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
                       ctx->n_bound, dt, ctx->stream);
+    prof_end(ctx);
     launch_sorted_from_active(ctx->dc, ctx->stream);
     ctx->cur = nxt;
     rt_status st = sort_current(ctx);
@@ -352,11 +463,15 @@ extern "C" rt_status rt_deposit_flux(rt_ctx ctx, double *flux, double *drag, int
     const Grid &g = ctx->g;
     double *fdst = (where == RT_DEVICE && flux) ? flux : ctx->flux;
     double *ddst = (where == RT_DEVICE && drag) ? drag : ctx->drag;
+    prof_begin(ctx, PC_DEPOSIT);
     if (ctx->precision == RT_FP64)
-        launch_deposit64(g, ctx->bg64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
+        launch_deposit64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
     else
-        launch_deposit32(g, ctx->bg32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
+        launch_deposit32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
+    prof_end(ctx);
+    prof_begin(ctx, PC_DRAG);
     launch_drag(g, ctx->rho, fdst, ddst, ctx->stream);
+    prof_end(ctx);
     HIP_OK(hipGetLastError());
     if (where == RT_HOST) {
         const size_t nf = (size_t)6 * (g.nz + 1) * g.ncol, nd = (size_t)2 * g.nz * g.ncol;
@@ -414,6 +529,30 @@ extern "C" rt_status rt_get_rays(rt_ctx ctx, rt_rays *rays, int64_t *n_inout, in
     }
     HIP_OK(hipStreamSynchronize(ctx->stream));
     if (staged) unstage(ctx, staged);
+    return RT_OK;
+}
+
+extern "C" rt_status rt_get_columns(rt_ctx ctx, uint32_t *cols, int64_t *n_inout, int32_t where)
+{
+    if (!ctx || !n_inout) return rt_fail(ctx, RT_E_ARG, "n_inout is required");
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    if (!ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "no rays loaded");
+    DevCounters h;
+    rt_status st = read_counters(ctx, &h);
+    if (st) return st;
+    const int64_t n = h.n_active;
+    if (*n_inout < n) {
+        const long long have = (long long)*n_inout;
+        *n_inout = n;
+        return rt_fail(ctx, RT_E_ARG, "output array holds %lld, need %lld", have, (long long)n);
+    }
+    *n_inout = n;
+    if (n == 0) return RT_OK;
+    if (!cols) return rt_fail(ctx, RT_E_ARG, "cols is required");
+    // the sorted keys of the active set are the columns in internal order
+    HIP_OK(hipMemcpyAsync(cols, ctx->skeys, sizeof(uint32_t) * n,
+                          where == RT_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
     return RT_OK;
 }
 

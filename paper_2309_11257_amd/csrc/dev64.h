@@ -54,46 +54,55 @@ __device__ inline void axis_clamped(double p, double origin, double d, int n, in
     }
 }
 
+// The eight corners of the interpolation cell: column indices of the four
+// (j, i) corners and the two levels, plus the weights.
 struct Cell {
-    int a00, a10, a01, a11;  // row offsets (j,k) combos: (j0,k0) (j1,k0) (j0,k1) (j1,k1)
-    int i0, i1, j0, j1;
+    int c00, c01, c10, c11;  // columns (j0,i0) (j0,i1) (j1,i0) (j1,i1), times nz
+    int k0, k1;
     double wx, wy, wz;
 };
 
 __device__ inline void locate(const Grid &g, double x, double y, double z, Cell &c)
 {
-    int k0, k1;
-    axis_periodic(x, g.x0, g.dx, g.nx, c.i0, c.i1, c.wx);
+    int i0, i1, j0, j1;
+    axis_periodic(x, g.x0, g.dx, g.nx, i0, i1, c.wx);
     if (g.geometry == RT_CARTESIAN)
-        axis_periodic(y, g.y0, g.dy, g.ny, c.j0, c.j1, c.wy);
+        axis_periodic(y, g.y0, g.dy, g.ny, j0, j1, c.wy);
     else
-        axis_clamped(y, g.y0, g.dy, g.ny, c.j0, c.j1, c.wy);
-    axis_clamped(z, 0.0, g.dz, g.nz, k0, k1, c.wz);
-    c.a00 = (k0 * g.ny + c.j0) * g.nx;
-    c.a10 = (k0 * g.ny + c.j1) * g.nx;
-    c.a01 = (k1 * g.ny + c.j0) * g.nx;
-    c.a11 = (k1 * g.ny + c.j1) * g.nx;
+        axis_clamped(y, g.y0, g.dy, g.ny, j0, j1, c.wy);
+    axis_clamped(z, 0.0, g.dz, g.nz, c.k0, c.k1, c.wz);
+    c.c00 = (j0 * g.nx + i0) * g.nz;
+    c.c01 = (j0 * g.nx + i1) * g.nz;
+    c.c10 = (j1 * g.nx + i0) * g.nz;
+    c.c11 = (j1 * g.nx + i1) * g.nz;
 }
 
-// x on the four corner rows, then y, then z
-__device__ inline double tri(const double *__restrict__ F, const Cell &c)
+// Trilinear interpolation of a packed 4-vector record, component by
+// component: x on the four corner rows, then y, then z.  R = records per cell.
+template <int R>
+__device__ inline double4 tri4(const double4 *__restrict__ F, const Cell &c, int r)
 {
-    double a0 = F[c.a00 + c.i0], a1 = F[c.a00 + c.i1];
-    double b0 = F[c.a10 + c.i0], b1 = F[c.a10 + c.i1];
-    double d0 = F[c.a01 + c.i0], d1 = F[c.a01 + c.i1];
-    double e0 = F[c.a11 + c.i0], e1 = F[c.a11 + c.i1];
-    double c00 = a0 + c.wx * (a1 - a0);
-    double c10 = b0 + c.wx * (b1 - b0);
-    double c01 = d0 + c.wx * (d1 - d0);
-    double c11 = e0 + c.wx * (e1 - e0);
-    double c0 = c00 + c.wy * (c10 - c00);
-    double c1 = c01 + c.wy * (c11 - c01);
-    return c0 + c.wz * (c1 - c0);
-}
-
-__device__ inline double row(const double *__restrict__ F, const Cell &c)
-{
-    return F[c.j0] + c.wy * (F[c.j1] - F[c.j0]);
+    const double4 a0 = F[(c.c00 + c.k0) * R + r], a1 = F[(c.c01 + c.k0) * R + r];
+    const double4 b0 = F[(c.c10 + c.k0) * R + r], b1 = F[(c.c11 + c.k0) * R + r];
+    const double4 d0 = F[(c.c00 + c.k1) * R + r], d1 = F[(c.c01 + c.k1) * R + r];
+    const double4 e0 = F[(c.c10 + c.k1) * R + r], e1 = F[(c.c11 + c.k1) * R + r];
+    double4 o;
+#define TRI_(q)                                               \
+    {                                                         \
+        const double c00 = a0.q + c.wx * (a1.q - a0.q);      \
+        const double c10 = b0.q + c.wx * (b1.q - b0.q);      \
+        const double c01 = d0.q + c.wx * (d1.q - d0.q);      \
+        const double c11 = e0.q + c.wx * (e1.q - e0.q);      \
+        const double c0 = c00 + c.wy * (c10 - c00);           \
+        const double c1 = c01 + c.wy * (c11 - c01);           \
+        o.q = c0 + c.wz * (c1 - c0);                          \
+    }
+    TRI_(x)
+    TRI_(y)
+    TRI_(z)
+    TRI_(w)
+#undef TRI_
+    return o;
 }
 
 // omega_hat^2 = (N^2 kh^2 + f^2 m^2)/K^2 (eq. dispersion, Gamma = 0)
@@ -108,7 +117,7 @@ __device__ inline double omega_hat(double N2, double f2, double kh2, double m2, 
 // and extent rates from the group velocities at the opposing face centres
 // (Section 3a, Appendix B).
 template <bool SPH>
-__device__ inline void rhs(const Grid &g, const Bg<double> &b, const double *Y, double *F)
+__device__ inline void rhs(const Grid &g, const BgP<double> &b, const double *Y, double *F)
 {
     const double x = Y[0], y = Y[1], z = Y[2], k = Y[3], l = Y[4], m = Y[5];
     const double Dx = Y[6], Dy = Y[7], Dz = Y[8];
@@ -118,49 +127,56 @@ __device__ inline void rhs(const Grid &g, const Bg<double> &b, const double *Y, 
     const double K4 = K2 * K2;
     Cell c;
     locate(g, x, y, z, c);
-    const double N2c = tri(b.N2, c);
-    const double f2c = row(b.f2, c);
-    const double om = omega_hat(N2c, f2c, kh2, m2, K2);
+    const double4 Ac = tri4<1>(b.A, c, 0);   // U V N2 f2
+    const double om = omega_hat(Ac.z, Ac.w, kh2, m2, K2);
     const double q = kh2 / ((2.0 * om) * K2);
     const double qf = m2 / ((2.0 * om) * K2);
-    const double gk = (k * tri(b.Ux, c) + l * tri(b.Vx, c)) + q * tri(b.N2x, c);
-    const double gl = ((k * tri(b.Uy, c) + l * tri(b.Vy, c)) + q * tri(b.N2y, c)) + qf * row(b.f2y, c);
-    const double gm = (k * tri(b.Uz, c) + l * tri(b.Vz, c)) + q * tri(b.N2z, c);
+    // gradient records one at a time: (Ux Uy Uz Vx) (Vy Vz N2x N2y) (N2z f2y)
+    double Ux = 0, Uy = 0, Uz = 0, Vx = 0, Vy = 0, Vz = 0, N2x = 0, N2y = 0, N2z = 0, f2y = 0;
+#pragma unroll 1
+    for (int r = 0; r < 3; r++) {
+        const double4 Gr = tri4<3>(b.G, c, r);
+        Ux = r == 0 ? Gr.x : Ux;
+        Uy = r == 0 ? Gr.y : Uy;
+        Uz = r == 0 ? Gr.z : Uz;
+        Vx = r == 0 ? Gr.w : Vx;
+        Vy = r == 1 ? Gr.x : Vy;
+        Vz = r == 1 ? Gr.y : Vz;
+        N2x = r == 1 ? Gr.z : N2x;
+        N2y = r == 1 ? Gr.w : N2y;
+        N2z = r == 2 ? Gr.x : N2z;
+        f2y = r == 2 ? Gr.y : f2y;
+    }
+    const double gk = (k * Ux + l * Vx) + q * N2x;
+    const double gl = ((k * Uy + l * Vy) + q * N2y) + qf * f2y;
+    const double gm = (k * Uz + l * Vz) + q * N2z;
 
-    double cxp, cxm, cyp, cym, czp, czm;
-    {
+    // faces: +x, -x, +y, -y, +z, -z, one at a time (bounded register use)
+    double cxp = 0.0, cxm = 0.0, cyp = 0.0, cym = 0.0, czp = 0.0, czm = 0.0;
+#pragma unroll 1
+    for (int fc = 0; fc < 6; fc++) {
+        const int ax = fc >> 1;
+        const double sg = (fc & 1) ? -0.5 : 0.5;
+        double px = x, py = y, pz = z;
+        if (ax == 0)
+            px = x + sg * Dx;
+        else if (ax == 1)
+            py = y + sg * Dy;
+        else
+            pz = z + sg * Dz;
         Cell f;
-        double N2f, f2f, omf;
-        locate(g, x + 0.5 * Dx, y, z, f);
-        N2f = tri(b.N2, f);
-        f2f = row(b.f2, f);
-        omf = omega_hat(N2f, f2f, kh2, m2, K2);
-        cxp = tri(b.U, f) + ((k * m2) * (N2f - f2f)) / (omf * K4);
-        locate(g, x - 0.5 * Dx, y, z, f);
-        N2f = tri(b.N2, f);
-        f2f = row(b.f2, f);
-        omf = omega_hat(N2f, f2f, kh2, m2, K2);
-        cxm = tri(b.U, f) + ((k * m2) * (N2f - f2f)) / (omf * K4);
-        locate(g, x, y + 0.5 * Dy, z, f);
-        N2f = tri(b.N2, f);
-        f2f = row(b.f2, f);
-        omf = omega_hat(N2f, f2f, kh2, m2, K2);
-        cyp = tri(b.V, f) + ((l * m2) * (N2f - f2f)) / (omf * K4);
-        locate(g, x, y - 0.5 * Dy, z, f);
-        N2f = tri(b.N2, f);
-        f2f = row(b.f2, f);
-        omf = omega_hat(N2f, f2f, kh2, m2, K2);
-        cym = tri(b.V, f) + ((l * m2) * (N2f - f2f)) / (omf * K4);
-        locate(g, x, y, z + 0.5 * Dz, f);
-        N2f = tri(b.N2, f);
-        f2f = row(b.f2, f);
-        omf = omega_hat(N2f, f2f, kh2, m2, K2);
-        czp = -(((m * kh2) * (N2f - f2f)) / (omf * K4));
-        locate(g, x, y, z - 0.5 * Dz, f);
-        N2f = tri(b.N2, f);
-        f2f = row(b.f2, f);
-        omf = omega_hat(N2f, f2f, kh2, m2, K2);
-        czm = -(((m * kh2) * (N2f - f2f)) / (omf * K4));
+        locate(g, px, py, pz, f);
+        const double4 Af = tri4<1>(b.A, f, 0);
+        const double omf = omega_hat(Af.z, Af.w, kh2, m2, K2);
+        const double num = ax == 0 ? k * m2 : (ax == 1 ? l * m2 : m * kh2);
+        const double t = (num * (Af.z - Af.w)) / (omf * K4);
+        const double v = ax == 0 ? Af.x + t : (ax == 1 ? Af.y + t : -t);
+        cxp = fc == 0 ? v : cxp;
+        cxm = fc == 1 ? v : cxm;
+        cyp = fc == 2 ? v : cyp;
+        cym = fc == 3 ? v : cym;
+        czp = fc == 4 ? v : czp;
+        czm = fc == 5 ? v : czm;
     }
     if (!SPH) {
         F[0] = 0.5 * (cxp + cxm);

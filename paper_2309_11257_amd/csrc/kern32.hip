@@ -91,31 +91,29 @@ __device__ inline void axis_clamp(int ic, float u, int n, int &i0, int &i1, floa
 }
 
 struct Cell {
-    int a00, a10, a01, a11, i0, i1, j0, j1;
+    int c00, c01, c10, c11;  // columns (j0,i0) (j0,i1) (j1,i0) (j1,i1), times nz
+    int k0, k1;
     float wx, wy, wz;
 };
 
 __device__ inline void locate(const G32 &g, int ic, int jc, float xi, float eta, float z, Cell &c)
 {
-    int k0, k1;
-    axis_per(ic, xi, g.nx, c.i0, c.i1, c.wx);
+    int i0, i1, j0, j1;
+    axis_per(ic, xi, g.nx, i0, i1, c.wx);
     if (g.geometry == RT_CARTESIAN)
-        axis_per(jc, eta, g.ny, c.j0, c.j1, c.wy);
+        axis_per(jc, eta, g.ny, j0, j1, c.wy);
     else
-        axis_clamp(jc, eta, g.ny, c.j0, c.j1, c.wy);
-    axis_clamp(0, z * g.inv_dz, g.nz, k0, k1, c.wz);
-    c.a00 = (k0 * g.ny + c.j0) * g.nx;
-    c.a10 = (k0 * g.ny + c.j1) * g.nx;
-    c.a01 = (k1 * g.ny + c.j0) * g.nx;
-    c.a11 = (k1 * g.ny + c.j1) * g.nx;
+        axis_clamp(jc, eta, g.ny, j0, j1, c.wy);
+    axis_clamp(0, z * g.inv_dz, g.nz, c.k0, c.k1, c.wz);
+    c.c00 = (j0 * g.nx + i0) * g.nz;
+    c.c01 = (j0 * g.nx + i1) * g.nz;
+    c.c10 = (j1 * g.nx + i0) * g.nz;
+    c.c11 = (j1 * g.nx + i1) * g.nz;
 }
 
-__device__ inline float tri(const float *__restrict__ F, const Cell &c)
+__device__ inline float lerp3(float a0, float a1, float b0, float b1, float d0, float d1, float e0, float e1,
+                              const Cell &c)
 {
-    const float a0 = F[c.a00 + c.i0], a1 = F[c.a00 + c.i1];
-    const float b0 = F[c.a10 + c.i0], b1 = F[c.a10 + c.i1];
-    const float d0 = F[c.a01 + c.i0], d1 = F[c.a01 + c.i1];
-    const float e0 = F[c.a11 + c.i0], e1 = F[c.a11 + c.i1];
     const float c00 = a0 + c.wx * (a1 - a0);
     const float c10 = b0 + c.wx * (b1 - b0);
     const float c01 = d0 + c.wx * (d1 - d0);
@@ -125,58 +123,99 @@ __device__ inline float tri(const float *__restrict__ F, const Cell &c)
     return c0 + c.wz * (c1 - c0);
 }
 
-__device__ inline float row(const float *__restrict__ F, const Cell &c)
+// trilinear interpolation of a packed float4 record (R records per cell)
+template <int R>
+__device__ inline float4 tri4(const float4 *__restrict__ F, const Cell &c, int r)
 {
-    return F[c.j0] + c.wy * (F[c.j1] - F[c.j0]);
+    const float4 a0 = F[(c.c00 + c.k0) * R + r], a1 = F[(c.c01 + c.k0) * R + r];
+    const float4 b0 = F[(c.c10 + c.k0) * R + r], b1 = F[(c.c11 + c.k0) * R + r];
+    const float4 d0 = F[(c.c00 + c.k1) * R + r], d1 = F[(c.c01 + c.k1) * R + r];
+    const float4 e0 = F[(c.c10 + c.k1) * R + r], e1 = F[(c.c11 + c.k1) * R + r];
+    float4 o;
+    o.x = lerp3(a0.x, a1.x, b0.x, b1.x, d0.x, d1.x, e0.x, e1.x, c);
+    o.y = lerp3(a0.y, a1.y, b0.y, b1.y, d0.y, d1.y, e0.y, e1.y, c);
+    o.z = lerp3(a0.z, a1.z, b0.z, b1.z, d0.z, d1.z, e0.z, e1.z, c);
+    o.w = lerp3(a0.w, a1.w, b0.w, b1.w, d0.w, d1.w, e0.w, e1.w, c);
+    return o;
 }
 
 // group velocity component along one axis at a face: background wind (if
 // any) plus the intrinsic part from the dispersion relation
-__device__ inline float face_cg(const Bg<float> &b, const Cell &f, int axis, float k, float l, float m, float kh2,
-                                float m2, float K2, float invK4)
+__device__ inline float face_cg(const BgP<float> &b, const Cell &f, int axis, float k, float l, float m, float kh2,
+                                float m2, float invK2, float invK4)
 {
-    const float N2 = tri(b.N2, f);
-    const float f2 = row(b.f2, f);
-    const float om = sqrtf((N2 * kh2 + f2 * m2) / K2);
-    const float s = (N2 - f2) * invK4 / om;
-    if (axis == 0) return tri(b.U, f) + k * m2 * s;
-    if (axis == 1) return tri(b.V, f) + l * m2 * s;
+    const float4 A = tri4<1>(b.A, f, 0);
+    const float om = sqrtf((A.z * kh2 + A.w * m2) * invK2);
+    const float s = (A.z - A.w) * invK4 / om;
+    if (axis == 0) return A.x + k * m2 * s;
+    if (axis == 1) return A.y + l * m2 * s;
     return -m * kh2 * s;
 }
 
 // RK stage right-hand side in cell units: Y = (xi, eta, z, k, l, m, Dxi, Deta, Dz)
 template <bool SPH>
-__device__ inline void rhs(const G32 &g, const Bg<float> &b, int ic, int jc, float phi0, const float *Y, float *F)
+__device__ inline void rhs(const G32 &g, const BgP<float> &b, int ic, int jc, float phi0, const float *Y, float *F)
 {
     const float xi = Y[0], eta = Y[1], z = Y[2], k = Y[3], l = Y[4], m = Y[5];
     const float kh2 = k * k + l * l;
     const float m2 = m * m;
     const float K2 = kh2 + m2;
-    const float invK4 = 1.0f / (K2 * K2);
+    const float invK2 = 1.0f / K2;
+    const float invK4 = invK2 * invK2;
     Cell c;
     locate(g, ic, jc, xi, eta, z, c);
-    const float N2c = tri(b.N2, c);
-    const float f2c = row(b.f2, c);
-    const float om = sqrtf((N2c * kh2 + f2c * m2) / K2);
-    const float h = 0.5f / (om * K2);
+    const float4 Ac = tri4<1>(b.A, c, 0);  // U V N2 f2
+    const float om = sqrtf((Ac.z * kh2 + Ac.w * m2) * invK2);
+    const float h = 0.5f * invK2 / om;
     const float q = kh2 * h;
     const float qf = m2 * h;
-    const float gk = k * tri(b.Ux, c) + l * tri(b.Vx, c) + q * tri(b.N2x, c);
-    const float gl = k * tri(b.Uy, c) + l * tri(b.Vy, c) + q * tri(b.N2y, c) + qf * row(b.f2y, c);
-    const float gm = k * tri(b.Uz, c) + l * tri(b.Vz, c) + q * tri(b.N2z, c);
-    Cell f;
-    locate(g, ic, jc, xi + 0.5f * Y[6], eta, z, f);
-    const float cxp = face_cg(b, f, 0, k, l, m, kh2, m2, K2, invK4);
-    locate(g, ic, jc, xi - 0.5f * Y[6], eta, z, f);
-    const float cxm = face_cg(b, f, 0, k, l, m, kh2, m2, K2, invK4);
-    locate(g, ic, jc, xi, eta + 0.5f * Y[7], z, f);
-    const float cyp = face_cg(b, f, 1, k, l, m, kh2, m2, K2, invK4);
-    locate(g, ic, jc, xi, eta - 0.5f * Y[7], z, f);
-    const float cym = face_cg(b, f, 1, k, l, m, kh2, m2, K2, invK4);
-    locate(g, ic, jc, xi, eta, z + 0.5f * Y[8], f);
-    const float czp = face_cg(b, f, 2, k, l, m, kh2, m2, K2, invK4);
-    locate(g, ic, jc, xi, eta, z - 0.5f * Y[8], f);
-    const float czm = face_cg(b, f, 2, k, l, m, kh2, m2, K2, invK4);
+    // gradient records one at a time: (Ux Uy Uz Vx) (Vy Vz N2x N2y) (N2z f2y)
+    float gk = 0.0f, gl = 0.0f, gm = 0.0f;
+#pragma unroll 1
+    for (int r = 0; r < 3; r++) {
+        const float4 Gr = tri4<3>(b.G, c, r);
+        // r=0: k*Ux -> gk, k*Uy -> gl, k*Uz -> gm, l*Vx -> gk
+        // r=1: l*Vy -> gl, l*Vz -> gm, q*N2x -> gk, q*N2y -> gl
+        // r=2: q*N2z -> gm, qf*f2y -> gl
+        if (r == 0) {
+            gk += k * Gr.x + l * Gr.w;
+            gl += k * Gr.y;
+            gm += k * Gr.z;
+        } else if (r == 1) {
+            gl += l * Gr.x + q * Gr.w;
+            gm += l * Gr.y;
+            gk += q * Gr.z;
+        } else {
+            gm += q * Gr.x;
+            gl += qf * Gr.y;
+        }
+    }
+    // faces +x, -x, +y, -y, +z, -z, one at a time (bounded register use)
+    float cxp = 0.0f, cxm = 0.0f, cyp = 0.0f, cym = 0.0f, czp = 0.0f, czm = 0.0f;
+#pragma unroll 1
+    for (int fc = 0; fc < 6; fc++) {
+        const int ax = fc >> 1;
+        const float sg = (fc & 1) ? -0.5f : 0.5f;
+        float px = xi, py = eta, pz = z;
+        if (ax == 0)
+            px += sg * Y[6];
+        else if (ax == 1)
+            py += sg * Y[7];
+        else
+            pz += sg * Y[8];
+        Cell f;
+        locate(g, ic, jc, px, py, pz, f);
+        const float4 A = tri4<1>(b.A, f, 0);
+        const float omf = sqrtf((A.z * kh2 + A.w * m2) * invK2);
+        const float sc = (A.z - A.w) * invK4 / omf;
+        const float v = ax == 0 ? A.x + k * m2 * sc : (ax == 1 ? A.y + l * m2 * sc : -m * kh2 * sc);
+        cxp = fc == 0 ? v : cxp;
+        cxm = fc == 1 ? v : cxm;
+        cyp = fc == 2 ? v : cyp;
+        cym = fc == 3 ? v : cym;
+        czp = fc == 4 ? v : czp;
+        czm = fc == 5 ? v : czm;
+    }
     if (!SPH) {
         F[0] = 0.5f * (cxp + cxm) * g.inv_dx;
         F[1] = 0.5f * (cyp + cym) * g.inv_dy;
@@ -231,11 +270,11 @@ __device__ inline void renorm_periodic(int &ic, float &u, int n)
 using f32::G32;
 
 template <bool SPH>
-__global__ __launch_bounds__(256) void k_step32(G32 g, Bg<float> b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
-                                                uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc,
-                                                float dt)
+__global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
+                                                   uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc,
+                                                   float dt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= dc->n_active) return;
     const uint32_t s = perm[i];
     const uint32_t col = src.col[s];
@@ -316,7 +355,7 @@ __global__ __launch_bounds__(256) void k_step32(G32 g, Bg<float> b, S32 src, S32
     key_out[i] = key;
 }
 
-void launch_step32(const Grid &g, const Bg<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
+void launch_step32(const Grid &g, const BgP<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, hipStream_t s)
 {
     if (bound <= 0) return;
@@ -500,7 +539,7 @@ void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double 
 // ---------------------------------------------------------------------------
 struct Pay32 {
     G32 g;
-    Bg<float> b;
+    BgP<float> b;
     S32 st;
     __device__ void load(uint32_t s, double &zb, double &zt, double *bv) const
     {
@@ -511,8 +550,9 @@ struct Pay32 {
         const float Dz = st.dz[s];
         f32::Cell c;
         f32::locate(g, ic, jc, st.xi[s], st.eta[s], z, c);
-        const float N2 = f32::tri(b.N2, c);
-        const float f2 = f32::row(b.f2, c);
+        const float4 Ac = f32::tri4<1>(b.A, c, 0);
+        const float N2 = Ac.z;
+        const float f2 = Ac.w;
         const float kh2 = k * k + l * l;
         const float m2 = m * m;
         const float K2 = kh2 + m2;
@@ -534,7 +574,7 @@ struct Pay32 {
     }
 };
 
-void launch_deposit32(const Grid &g, const Bg<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_deposit32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s)
 {
     Pay32 p{f32::make_g32(g), b, st};

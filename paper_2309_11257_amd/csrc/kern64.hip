@@ -82,6 +82,51 @@ void launch_gradients64(const Grid &g, const double *U, const double *V, const d
     k_f2<<<(unsigned)((g.ny + 255) / 256), 256, 0, s>>>(g, f, f2, f2y);
 }
 
+// packed column-major records (see rt_internal.h) from the [nz][ny][nx] fields
+template <typename T, typename V>
+__global__ void k_pack(Grid g, Bg<double> b, V *A, V *G)
+{
+    const int64_t cells = (int64_t)g.ncol * g.nz;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // packed index col*nz + k
+    if (e >= cells) return;
+    const int64_t col = e / g.nz, k = e % g.nz;
+    const int64_t s = k * g.ncol + col;  // source index
+    const int j = (int)(col / g.nx);
+    V a, g0, g1, g2;
+    a.x = (T)b.U[s];
+    a.y = (T)b.V[s];
+    a.z = (T)b.N2[s];
+    a.w = (T)b.f2[j];
+    g0.x = (T)b.Ux[s];
+    g0.y = (T)b.Uy[s];
+    g0.z = (T)b.Uz[s];
+    g0.w = (T)b.Vx[s];
+    g1.x = (T)b.Vy[s];
+    g1.y = (T)b.Vz[s];
+    g1.z = (T)b.N2x[s];
+    g1.w = (T)b.N2y[s];
+    g2.x = (T)b.N2z[s];
+    g2.y = (T)b.f2y[j];
+    g2.z = (T)0;
+    g2.w = (T)0;
+    A[e] = a;
+    G[3 * e + 0] = g0;
+    G[3 * e + 1] = g1;
+    G[3 * e + 2] = g2;
+}
+
+void launch_pack64(const Grid &g, const Bg<double> &b, double4 *A, double4 *G, hipStream_t s)
+{
+    const int64_t cells = (int64_t)g.ncol * g.nz;
+    k_pack<double, double4><<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, b, A, G);
+}
+
+void launch_pack32(const Grid &g, const Bg<double> &b, float4 *A, float4 *G, hipStream_t s)
+{
+    const int64_t cells = (int64_t)g.ncol * g.nz;
+    k_pack<float, float4><<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, b, A, G);
+}
+
 // ---------------------------------------------------------------------------
 // load / store
 // ---------------------------------------------------------------------------
@@ -147,10 +192,10 @@ void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCount
 // buffer contiguously, so the state stays grouped by column.
 // ---------------------------------------------------------------------------
 template <bool SPH>
-__global__ __launch_bounds__(256) void k_step64(Grid g, Bg<double> b, S64 src, S64 dst, const uint32_t *__restrict__ perm,
+__global__ __launch_bounds__(256, 2) void k_step64(Grid g, BgP<double> b, S64 src, S64 dst, const uint32_t *__restrict__ perm,
                                                 uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc, double dt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= dc->n_active) return;
     const uint32_t s = perm[i];
     double Y[9] = {src.x[s], src.y[s], src.z[s], src.k[s], src.l[s], src.m[s], src.dx[s], src.dy[s], src.dz[s]};
@@ -185,7 +230,7 @@ __global__ __launch_bounds__(256) void k_step64(Grid g, Bg<double> b, S64 src, S
     key_out[i] = key;
 }
 
-void launch_step64(const Grid &g, const Bg<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
+void launch_step64(const Grid &g, const BgP<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, hipStream_t s)
 {
     if (bound <= 0) return;
@@ -294,7 +339,7 @@ void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double 
 // ---------------------------------------------------------------------------
 struct Pay64 {
     Grid g;
-    Bg<double> b;
+    BgP<double> b;
     S64 st;
     __device__ void load(uint32_t s, double &zb, double &zt, double *bv) const
     {
@@ -303,8 +348,9 @@ struct Pay64 {
         const double W = W64(st, s);
         d64::Cell c;
         d64::locate(g, x, y, z, c);
-        const double N2 = d64::tri(b.N2, c);
-        const double f2 = d64::row(b.f2, c);
+        const double4 Ac = d64::tri4<1>(b.A, c, 0);
+        const double N2 = Ac.z;
+        const double f2 = Ac.w;
         const double kh2 = k * k + l * l;
         const double m2 = m * m;
         const double K2 = kh2 + m2;
@@ -327,7 +373,7 @@ struct Pay64 {
     }
 };
 
-void launch_deposit64(const Grid &g, const Bg<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_deposit64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s)
 {
     Pay64 p{g, b, st};

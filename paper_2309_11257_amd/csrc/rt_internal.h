@@ -24,6 +24,29 @@ struct Bg {
     const double *rho;   // [nz]
 };
 
+// Packed, column-major background used by the step and deposition kernels:
+// for cell (column c, level k) at index c*nz + k
+//   A = (U, V, N2, f^2)
+//   G = (Ux, Uy, Uz, Vx), (Vy, Vz, N2x, N2y), (N2z, (f^2)_y, 0, 0)
+// so a column's levels are contiguous and one trilinear corner costs one
+// 16/32-byte load per record.
+template <typename T>
+struct V4T;
+template <>
+struct V4T<float> {
+    typedef float4 type;
+};
+template <>
+struct V4T<double> {
+    typedef double4 type;
+};
+
+template <typename T>
+struct BgP {
+    const typename V4T<T>::type *A;  // [ncol*nz]
+    const typename V4T<T>::type *G;  // [ncol*nz*3]
+};
+
 // double-precision state: absolute coordinates, as the public interface
 struct S64 {
     double *x, *y, *z, *k, *l, *m, *dx, *dy, *dz, *px, *py, *pz, *n;
@@ -61,6 +84,8 @@ struct rt_ctx_s {
     bool have_bg;
     Bg<double> bg64;
     Bg<float> bg32;
+    BgP<double> bp64;
+    BgP<float> bp32;
     double *rho;
     // state: double buffers
     S64 s64[2];
@@ -85,7 +110,28 @@ struct rt_ctx_s {
     // allocation bookkeeping
     void *allocs[96];
     int nallocs;
+    // profiling (event pairs by kernel class)
+    bool prof_on;
+    int prof_class;
+    void *prof;  // std::vector of records, owned by api.hip
 };
+
+enum { PC_STEP = 0, PC_SORT = 1, PC_DEPOSIT = 2, PC_DRAG = 3, PC_SPLIT = 4, PC_STATS = 5, PC_N = 8 };
+void prof_begin(rt_ctx ctx, int cls);
+void prof_end(rt_ctx ctx);
+
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2);
+// remap so that each XCD walks a contiguous range of blocks -- for kernels
+// over column-sorted rays this keeps the background columns an XCD touches
+// in its own L2.
+__device__ inline int64_t xcd_block(int64_t nb)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t per = (nb + 7) / 8;
+    const int64_t x = b & 7, q = b >> 3;
+    const int64_t full = nb - (per - 1) * 8;  // XCDs that get `per` blocks
+    return x < full ? x * per + q : full * per + (x - full) * (per - 1) + q;
+}
 
 // error helpers
 rt_status rt_fail(rt_ctx c, rt_status s, const char *fmt, ...);
@@ -100,6 +146,8 @@ rt_status rt_fail(rt_ctx c, rt_status s, const char *fmt, ...);
 void launch_gradients64(const Grid &g, const double *U, const double *V, const double *N2, const double *f,
                         double *out12, double *f2, double *f2y, hipStream_t s);
 void launch_round32(const double *in, float *out, int64_t n, hipStream_t s);
+void launch_pack64(const Grid &g, const Bg<double> &b, double4 *A, double4 *G, hipStream_t s);
+void launch_pack32(const Grid &g, const Bg<double> &b, float4 *A, float4 *G, hipStream_t s);
 
 void launch_load64(const Grid &g, const rt_rays &in, int64_t n, S64 dst, uint32_t *key, hipStream_t s);
 void launch_load32(const Grid &g, const rt_rays &in, int64_t n, S32 dst, uint32_t *key, hipStream_t s);
@@ -108,9 +156,9 @@ void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCount
 void launch_store32(const Grid &g, S32 src, const uint32_t *perm, const DevCounters *dc, rt_rays out,
                     int64_t bound, hipStream_t s);
 
-void launch_step64(const Grid &g, const Bg<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
+void launch_step64(const Grid &g, const BgP<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, hipStream_t s);
-void launch_step32(const Grid &g, const Bg<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
+void launch_step32(const Grid &g, const BgP<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, hipStream_t s);
 
 // stable LSD radix sort of keys[0..*n) with 32-bit payload (identity if vals == NULL)
@@ -127,9 +175,9 @@ void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t 
 void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 
-void launch_deposit64(const Grid &g, const Bg<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_deposit64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s);
-void launch_deposit32(const Grid &g, const Bg<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_deposit32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s);
 void launch_drag(const Grid &g, const double *rho, const double *flux, double *drag, hipStream_t s);
 

@@ -39,3 +39,28 @@ def assert_flux_close(got, ref, rtol, what=""):
     scale = np.abs(ref).max()
     err = np.abs(got - ref).max()
     assert err <= rtol * max(scale, 1e-300), f"{what}: max abs err {err:.3e} vs scale {scale:.3e}"
+
+
+def oracle_deposit_with_kernel_decisions(orc, bg, rs, gpu_rays, gpu_cols):
+    """Oracle fluxes of the oracle's own ray states, with the integer
+    decisions (which rays are active, which column each belongs to) taken
+    from the kernel's output.  Returns (flux, n_column_flips, n_set_flips)."""
+    ids = rs["id"]
+    active = rs.active()
+    gid = np.asarray(gpu_rays["id"])
+    o = np.argsort(gid, kind="stable")
+    gs, gc = gid[o], np.asarray(gpu_cols).astype(np.int64)[o]
+    if gs.size:
+        p = np.clip(np.searchsorted(gs, ids), 0, gs.size - 1)
+        found = gs[p] == ids
+    else:
+        p = np.zeros(ids.size, dtype=np.int64)
+        found = np.zeros(ids.size, dtype=bool)
+    cols = np.where(found & active, gc[p] if gs.size else -1, -1)
+    n_set = int((found != active).sum())
+    flips = int(((cols != rs["col"]) & (cols >= 0)).sum())
+    save = rs.a["state"][: rs.n].copy()
+    rs.a["state"][: rs.n][active & ~found] = orc.INVALID
+    flux = orc.deposit(bg, rs, cols=cols)
+    rs.a["state"][: rs.n] = save
+    return flux, flips, n_set
