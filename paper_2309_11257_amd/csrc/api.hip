@@ -161,6 +161,9 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     if (!(cfg->dx > 0 && cfg->dy > 0 && cfg->dz > 0)) return RT_E_ARG;
     if (cfg->geometry == RT_SPHERICAL && !(cfg->a > 0)) return RT_E_ARG;
     if (cfg->capacity < 0 || cfg->capacity > (int64_t)0xffffff00) return RT_E_ARG;
+    // single-precision lookups address the background with 32-bit indices
+    if (cfg->precision == RT_FP32 && (int64_t)cfg->nx * cfg->ny * cfg->nz * 3 >= ((int64_t)1 << 31))
+        return RT_E_UNSUPPORTED;
     if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return RT_E_ARG;
 
     rt_ctx ctx = new rt_ctx_s();
@@ -243,9 +246,10 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
             float *m;
             ALLOC(m, float, 12 * cap);
             S32 &s = ctx->s32[buf];
-            float **f[12] = {&s.xi, &s.eta, &s.z, &s.k, &s.l, &s.m, &s.dxi, &s.deta, &s.dz, &s.px, &s.py, &s.pz};
+            float **f[12] = {&s.xi, &s.eta, &s.zeta, &s.k, &s.l, &s.m, &s.dxi, &s.deta, &s.dz, &s.px, &s.py, &s.pz};
             for (int q = 0; q < 12; q++) *f[q] = m + q * cap;
             ALLOC(s.col, uint32_t, cap);
+            ALLOC(s.lev, int32_t, cap);
             ALLOC(s.W, double, cap);
             ALLOC(s.id, int64_t, cap);
         }

@@ -3,10 +3,12 @@
 // diagnostics and the deposition payload.
 //
 // FP32 layout.  A horizontal position is held as the index of its column plus
-// an offset in cell units, so its resolution is a fixed fraction of a cell
+// an offset in cell units, and the height as the index of its level plus an
+// offset in level units, so the resolution is a fixed fraction of a cell
 // (about 1e-7 cell) everywhere in the domain instead of degrading with the
-// distance from the origin; this keeps the column assignment of the FP32
-// path as sharp as the FP64 one.  Extents Dx, Dy are in cell units too.  The
+// distance from the origin; this keeps the column assignment and the
+// vertical overlaps of the FP32 path as sharp as the FP64 ones.  Extents
+// Dx, Dy are in cell units, Dz in metres.  The
 // wave action W = N Px Py Pz is formed once in double at load and kept in
 // double, and every flux sum is accumulated in double.
 #include "dev64.h"
@@ -96,7 +98,7 @@ struct Cell {
     float wx, wy, wz;
 };
 
-__device__ inline void locate(const G32 &g, int ic, int jc, float xi, float eta, float z, Cell &c)
+__device__ inline void locate(const G32 &g, int ic, int jc, int kc, float xi, float eta, float zeta, Cell &c)
 {
     int i0, i1, j0, j1;
     axis_per(ic, xi, g.nx, i0, i1, c.wx);
@@ -104,7 +106,7 @@ __device__ inline void locate(const G32 &g, int ic, int jc, float xi, float eta,
         axis_per(jc, eta, g.ny, j0, j1, c.wy);
     else
         axis_clamp(jc, eta, g.ny, j0, j1, c.wy);
-    axis_clamp(0, z * g.inv_dz, g.nz, c.k0, c.k1, c.wz);
+    axis_clamp(kc, zeta, g.nz, c.k0, c.k1, c.wz);
     c.c00 = (j0 * g.nx + i0) * g.nz;
     c.c01 = (j0 * g.nx + i1) * g.nz;
     c.c10 = (j1 * g.nx + i0) * g.nz;
@@ -152,18 +154,20 @@ __device__ inline float face_cg(const BgP<float> &b, const Cell &f, int axis, fl
     return -m * kh2 * s;
 }
 
-// RK stage right-hand side in cell units: Y = (xi, eta, z, k, l, m, Dxi, Deta, Dz)
+// RK stage right-hand side in cell units: Y = (xi, eta, zeta, k, l, m, Dxi,
+// Deta, Dz), offsets relative to the base cell (ic, jc, kc), Dz in metres
 template <bool SPH>
-__device__ inline void rhs(const G32 &g, const BgP<float> &b, int ic, int jc, float phi0, const float *Y, float *F)
+__device__ inline void rhs(const G32 &g, const BgP<float> &b, int ic, int jc, int kc, float phi0, const float *Y,
+                           float *F)
 {
-    const float xi = Y[0], eta = Y[1], z = Y[2], k = Y[3], l = Y[4], m = Y[5];
+    const float xi = Y[0], eta = Y[1], zeta = Y[2], k = Y[3], l = Y[4], m = Y[5];
     const float kh2 = k * k + l * l;
     const float m2 = m * m;
     const float K2 = kh2 + m2;
     const float invK2 = 1.0f / K2;
     const float invK4 = invK2 * invK2;
     Cell c;
-    locate(g, ic, jc, xi, eta, z, c);
+    locate(g, ic, jc, kc, xi, eta, zeta, c);
     const float4 Ac = tri4<1>(b.A, c, 0);  // U V N2 f2
     const float om = sqrtf((Ac.z * kh2 + Ac.w * m2) * invK2);
     const float h = 0.5f * invK2 / om;
@@ -196,15 +200,15 @@ __device__ inline void rhs(const G32 &g, const BgP<float> &b, int ic, int jc, fl
     for (int fc = 0; fc < 6; fc++) {
         const int ax = fc >> 1;
         const float sg = (fc & 1) ? -0.5f : 0.5f;
-        float px = xi, py = eta, pz = z;
+        float px = xi, py = eta, pz = zeta;
         if (ax == 0)
             px += sg * Y[6];
         else if (ax == 1)
             py += sg * Y[7];
         else
-            pz += sg * Y[8];
+            pz += sg * (Y[8] * g.inv_dz);
         Cell f;
-        locate(g, ic, jc, px, py, pz, f);
+        locate(g, ic, jc, kc, px, py, pz, f);
         const float4 A = tri4<1>(b.A, f, 0);
         const float omf = sqrtf((A.z * kh2 + A.w * m2) * invK2);
         const float sc = (A.z - A.w) * invK4 / omf;
@@ -219,7 +223,7 @@ __device__ inline void rhs(const G32 &g, const BgP<float> &b, int ic, int jc, fl
     if (!SPH) {
         F[0] = 0.5f * (cxp + cxm) * g.inv_dx;
         F[1] = 0.5f * (cyp + cym) * g.inv_dy;
-        F[2] = 0.5f * (czp + czm);
+        F[2] = 0.5f * (czp + czm) * g.inv_dz;
         F[3] = -gk;
         F[4] = -gl;
         F[5] = -gm;
@@ -227,7 +231,7 @@ __device__ inline void rhs(const G32 &g, const BgP<float> &b, int ic, int jc, fl
         F[7] = (cyp - cym) * g.inv_dy;
         F[8] = czp - czm;
     } else {
-        const float r = g.a + z;
+        const float r = g.a + ((float)kc + zeta) * g.dz;
         const float ir = 1.0f / r;
         float sphi, cphi;
         sincosf(phi0 + eta * g.dyr, &sphi, &cphi);
@@ -238,7 +242,7 @@ __device__ inline void rhs(const G32 &g, const BgP<float> &b, int ic, int jc, fl
         const float wc = 0.5f * (czp + czm);
         F[0] = uc * irc * g.inv_dx;
         F[1] = vc * ir * g.inv_dy;
-        F[2] = wc;
+        F[2] = wc * g.inv_dz;
         F[3] = -gk * irc - k * wc * ir + k * tphi * vc * ir;
         F[4] = -gl * ir - l * wc * ir - k * tphi * uc * ir;
         F[5] = -gm + k * uc * ir + l * vc * ir;
@@ -279,7 +283,8 @@ __global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src,
     const uint32_t s = perm[i];
     const uint32_t col = src.col[s];
     int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
-    float Y[9] = {src.xi[s], src.eta[s], src.z[s], src.k[s], src.l[s], src.m[s], src.dxi[s], src.deta[s], src.dz[s]};
+    const int kc0 = src.lev[s];
+    float Y[9] = {src.xi[s], src.eta[s], src.zeta[s], src.k[s], src.l[s], src.m[s], src.dxi[s], src.deta[s], src.dz[s]};
     float Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float F[9];
     const float A[3] = {0.0f, -5.0f / 9.0f, -153.0f / 128.0f};
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src,
     const float phi0 = g.y0 + (float)jc * g.dyr;
 #pragma unroll 1
     for (int st = 0; st < 3; st++) {
-        f32::rhs<SPH>(g, b, ic, jc, phi0, Y, F);
+        f32::rhs<SPH>(g, b, ic, jc, kc0, phi0, Y, F);
 #pragma unroll
         for (int c = 0; c < 9; c++) {
             Q[c] = A[st] * Q[c] + dt * F[c];
@@ -296,11 +301,12 @@ __global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src,
     }
     // post-step: validity, wrap, removal, column key
     uint32_t key;
+    int kc = kc0;
     bool ok = true;
 #pragma unroll
     for (int c = 0; c < 9; c++) ok = ok && isfinite(Y[c]);
     ok = ok && Y[6] > 0.0f && Y[7] > 0.0f && Y[8] > 0.0f && (Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) > 0.0f;
-    ok = ok && fabsf(Y[0]) < 1.0e6f && fabsf(Y[1]) < 1.0e6f;
+    ok = ok && fabsf(Y[0]) < 1.0e6f && fabsf(Y[1]) < 1.0e6f && fabsf(Y[2]) < 1.0e6f;
     if (!ok) {
         key = (uint32_t)(g.ncol + RK_INVALID);
     } else {
@@ -328,19 +334,30 @@ __global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src,
         } else {
             f32::renorm_periodic(jc, Y[1], g.ny);
         }
+        {
+            // level index + offset in [0, 1)
+            const float fl = floorf(Y[2]);
+            kc = kc0 + (int)fl;
+            Y[2] = Y[2] - fl;
+            if (Y[2] >= 1.0f) {
+                Y[2] = 0.0f;
+                kc += 1;
+            }
+        }
         if (key == 0) {
-            if (Y[2] < 0.0f)
+            if (kc < 0)
                 key = (uint32_t)(g.ncol + RK_BOTTOM);
-            else if (Y[2] > g.Lz)
+            else if (kc > g.nz || (kc == g.nz && Y[2] > 0.0f))
                 key = (uint32_t)(g.ncol + RK_TOP);
             else
                 key = (uint32_t)(jc * g.nx + ic);
         }
     }
     dst.col[i] = (uint32_t)(jc * g.nx + ic);
+    dst.lev[i] = kc;
     dst.xi[i] = Y[0];
     dst.eta[i] = Y[1];
-    dst.z[i] = Y[2];
+    dst.zeta[i] = Y[2];
     dst.k[i] = Y[3];
     dst.l[i] = Y[4];
     dst.m[i] = Y[5];
@@ -397,10 +414,18 @@ __global__ void k_load32(Grid g, rt_rays in, int64_t n, S32 d, uint32_t *key)
         if (xi >= 1.0f) xi = 0.99999994f;
         if (eta >= 1.0f) eta = 0.99999994f;
     }
+    // height as level index + offset in level units
+    const double gz = Y[2] / g.dz;
+    double fk = floor(gz);
+    if (!(fk >= 0.0)) fk = 0.0;
+    if (fk > (double)g.nz) fk = (double)g.nz;
+    float zeta = (float)(gz - fk);
+    if (zeta >= 1.0f) zeta = 0.99999994f;
     d.col[i] = col;
+    d.lev[i] = (int32_t)fk;
     d.xi[i] = xi;
     d.eta[i] = eta;
-    d.z[i] = (float)Y[2];
+    d.zeta[i] = zeta;
     d.k[i] = (float)Y[3];
     d.l[i] = (float)Y[4];
     d.m[i] = (float)Y[5];
@@ -429,7 +454,7 @@ __global__ void k_store32(Grid g, S32 st, const uint32_t *perm, const DevCounter
     const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
     o.x[i] = g.x0 + ((double)ic + (double)st.xi[s]) * g.dx;
     o.y[i] = g.y0 + ((double)jc + (double)st.eta[s]) * g.dy;
-    o.z[i] = st.z[s];
+    o.z[i] = ((double)st.lev[s] + (double)st.zeta[s]) * g.dz;
     o.k[i] = st.k[s];
     o.l[i] = st.l[s];
     o.m[i] = st.m[s];
@@ -541,15 +566,17 @@ struct Pay32 {
     G32 g;
     BgP<float> b;
     S32 st;
+    double zdz;  // level spacing in double
     __device__ void load(uint32_t s, double &zb, double &zt, double *bv) const
     {
         const uint32_t col = st.col[s];
         const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
-        const float z = st.z[s];
+        const int kc = st.lev[s];
+        const float zeta = st.zeta[s];
         const float k = st.k[s], l = st.l[s], m = st.m[s];
         const float Dz = st.dz[s];
         f32::Cell c;
-        f32::locate(g, ic, jc, st.xi[s], st.eta[s], z, c);
+        f32::locate(g, ic, jc, kc, st.xi[s], st.eta[s], zeta, c);
         const float4 Ac = f32::tri4<1>(b.A, c, 0);
         const float N2 = Ac.z;
         const float f2 = Ac.w;
@@ -569,14 +596,15 @@ struct Pay32 {
         bv[3] = (cy * ld) * sW;
         bv[4] = (cz * kd) * sW;
         bv[5] = (cz * ld) * sW;
-        zb = (double)z - 0.5 * (double)Dz;
-        zt = (double)z + 0.5 * (double)Dz;
+        const double zc = ((double)kc + (double)zeta) * zdz;
+        zb = zc - 0.5 * (double)Dz;
+        zt = zc + 0.5 * (double)Dz;
     }
 };
 
 void launch_deposit32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s)
 {
-    Pay32 p{f32::make_g32(g), b, st};
+    Pay32 p{f32::make_g32(g), b, st, g.dz};
     k_deposit<Pay32><<<(unsigned)g.ncol, 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
 }

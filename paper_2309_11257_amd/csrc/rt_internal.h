@@ -54,10 +54,12 @@ struct S64 {
 };
 
 // single-precision state: horizontal position as column index + offset in
-// cell units; extents Dx, Dy in cell units; wave action W in double
+// cell units, height as level index + offset in level units; extents Dx, Dy
+// in cell units, Dz in metres; wave action W in double
 struct S32 {
     uint32_t *col;
-    float *xi, *eta, *z, *k, *l, *m, *dxi, *deta, *dz, *px, *py, *pz;
+    int32_t *lev;
+    float *xi, *eta, *zeta, *k, *l, *m, *dxi, *deta, *dz, *px, *py, *pz;
     double *W;
     int64_t *id;
 };

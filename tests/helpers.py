@@ -64,3 +64,27 @@ def oracle_deposit_with_kernel_decisions(orc, bg, rs, gpu_rays, gpu_cols):
     flux = orc.deposit(bg, rs, cols=cols)
     rs.a["state"][: rs.n] = save
     return flux, flips, n_set
+
+
+def fp32_representable(w, rays):
+    """The ray set rounded to what the single-precision state can hold
+    exactly: wavenumbers, extents and phase-space areas to float32, horizontal
+    positions to (cell + float32 offset) and heights to (level + float32
+    offset).  Feeding these to both the oracle and the FP32 path isolates the
+    error made inside the steps from the rounding of the inputs."""
+    f32 = lambda a: np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+    r = {k: np.array(v, copy=True) for k, v in rays.items()}
+    for f in ("k", "l", "m", "dz", "px", "py", "pz"):
+        r[f] = f32(r[f])
+    gx = (r["x"] - w.x0) / w.dx
+    i = np.clip(np.floor(gx), 0, w.nx - 1)
+    r["x"] = w.x0 + (i + f32(gx - i)) * w.dx
+    gy = (r["y"] - w.y0) / w.dy
+    j = np.clip(np.floor(gy), 0, w.ny - 1)
+    r["y"] = w.y0 + (j + f32(gy - j)) * w.dy
+    gz = r["z"] / w.dz
+    kz = np.clip(np.floor(gz), 0, w.nz)
+    r["z"] = (kz + f32(gz - kz)) * w.dz
+    r["dx"] = f32(r["dx"] / w.dx) * w.dx
+    r["dy"] = f32(r["dy"] / w.dy) * w.dy
+    return r
