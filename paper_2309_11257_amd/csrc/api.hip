@@ -267,6 +267,7 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     ALLOC(ctx->dc, DevCounters, 1);
     ALLOC(ctx->red, double, 8 + 4 * (cap / 256 + 2));
     ALLOC(ctx->ired, int64_t, 8 + 2 * cap);
+    ALLOC(ctx->sm, uint32_t, 8 * cap + 16 + scan_tmp_len(cap));
     if (hipMemsetAsync(ctx->dc, 0, sizeof(DevCounters), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->colstart, 0, sizeof(uint32_t) * ((size_t)g.ncol + 1), ctx->stream) != hipSuccess) {
         ctx_release(ctx);
@@ -313,6 +314,8 @@ static rt_status sort_current(rt_ctx ctx)
     HIP_OK(hipGetLastError());
     return RT_OK;
 }
+
+rt_status sort_current_ext(rt_ctx ctx) { return sort_current(ctx); }
 
 extern "C" rt_status rt_init_background(rt_ctx ctx, const double *U, const double *V, const double *N2, const double *f,
                                         const double *rho, int32_t where)
@@ -425,6 +428,7 @@ extern "C" rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int
     else
         launch_load32(ctx->g, src, n, ctx->s32[0], ctx->key[0], ctx->stream);
     launch_set_sorted(ctx->dc, n, ctx->stream);
+    launch_maxid(src.id, n, ctx->dc, ctx->stream);
     ctx->n_bound = n;
     rt_status st = sort_current(ctx);
     if (st) return st;

@@ -490,7 +490,7 @@ __global__ void k_tally32(Grid g, S32 st, const uint32_t *perm, const uint32_t *
     for (int64_t i = a + tid; i < e; i += 256) {
         const int reason = (int)(skeys[i] - (uint32_t)g.ncol);
         if (reason >= 0 && reason < RK_NREASON) atomicAdd(&cnt[reason], 1);
-        if (reason != RK_INVALID) w += st.W[perm[i]];
+        if (reason != RK_INVALID && reason != RK_MERGED) w += st.W[perm[i]];
     }
     sw[tid] = w;
     __syncthreads();

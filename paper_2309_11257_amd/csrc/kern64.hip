@@ -153,6 +153,18 @@ __global__ void k_load64(Grid g, rt_rays in, int64_t n, S64 d, uint32_t *key)
     key[i] = kk;
 }
 
+// next free id = 1 + largest id loaded (ids are non-negative)
+__global__ void k_maxid(const int64_t *id, int64_t n, DevCounters *dc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax((unsigned long long *)&dc->next_id, (unsigned long long)(id[i] + 1));
+}
+
+void launch_maxid(const int64_t *id, int64_t n, DevCounters *dc, hipStream_t s)
+{
+    if (n > 0) k_maxid<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(id, n, dc);
+}
+
 void launch_load64(const Grid &g, const rt_rays &in, int64_t n, S64 dst, uint32_t *key, hipStream_t s)
 {
     if (n > 0) k_load64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, in, n, dst, key);
@@ -263,7 +275,7 @@ __global__ void k_tally64(Grid g, S64 st, const uint32_t *perm, const uint32_t *
     for (int64_t i = a + tid; i < e; i += 256) {
         const int reason = (int)(skeys[i] - (uint32_t)g.ncol);
         if (reason >= 0 && reason < RK_NREASON) atomicAdd(&cnt[reason], 1);
-        if (reason != RK_INVALID) w += W64(st, perm[i]);
+        if (reason != RK_INVALID && reason != RK_MERGED) w += W64(st, perm[i]);
     }
     sw[tid] = w;
     __syncthreads();

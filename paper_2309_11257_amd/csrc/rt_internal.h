@@ -109,6 +109,7 @@ struct rt_ctx_s {
     DevCounters *dc;
     double *red;      // reduction scratch
     int64_t *ired;    // integer scratch
+    uint32_t *sm;     // split/merge scratch
     // allocation bookkeeping
     void *allocs[96];
     int nallocs;
@@ -168,6 +169,9 @@ void radix_sort(const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out, 
                 uint32_t *tk, uint32_t *tv, uint32_t *hist, const int64_t *n_dev, int64_t bound, int nbits,
                 hipStream_t s);
 int64_t radix_hist_len(int64_t bound);
+// in-place exclusive scan of t[0..len) (parts: scan_tmp_len(len) scratch)
+void scan_u32(uint32_t *t, int64_t len, uint32_t *parts, hipStream_t s);
+int64_t scan_tmp_len(int64_t len);
 void launch_colstart(const uint32_t *skeys, DevCounters *dc, uint32_t *colstart, int ncol, hipStream_t s);
 
 void launch_tally64(const Grid &g, S64 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc,
@@ -185,6 +189,7 @@ void launch_drag(const Grid &g, const double *rho, const double *flux, double *d
 
 void launch_copy_n(const uint32_t *src, uint32_t *dst, const DevCounters *dc, int64_t bound, hipStream_t s);
 void launch_set_sorted(DevCounters *dc, int64_t n, hipStream_t s);
+void launch_maxid(const int64_t *id, int64_t n, DevCounters *dc, hipStream_t s);
 void launch_sorted_from_active(DevCounters *dc, hipStream_t s);
 
 // split / merge / cap

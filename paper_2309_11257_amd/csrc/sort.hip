@@ -163,6 +163,17 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t *__res
     }
 }
 
+int64_t scan_tmp_len(int64_t len) { return (len + SCAN_CHUNK - 1) / SCAN_CHUNK + 1; }
+
+void scan_u32(uint32_t *t, int64_t len, uint32_t *parts, hipStream_t s)
+{
+    if (len <= 0) return;
+    const int64_t nparts = (len + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    k_scan_reduce<<<(unsigned)nparts, 256, 0, s>>>(t, len, parts);
+    k_scan_parts<<<1, 256, 0, s>>>(parts, nparts);
+    k_scan_apply<<<(unsigned)nparts, 256, 0, s>>>(t, len, parts);
+}
+
 void radix_sort(const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out, uint32_t *vals_out, uint32_t *tk,
                 uint32_t *tv, uint32_t *hist, const int64_t *n_dev, int64_t bound, int nbits, hipStream_t s)
 {

@@ -1,11 +1,744 @@
-// Vertical splitting, per-cell merge and per-column cap.
-#include "rt_internal.h"
+// Vertical splitting, per-cell merge and per-column cap (rt_split_merge).
+//
+// Sequence: (1) compact the active set into the spare buffer in column order;
+// (2) split: count the pieces of every volume taller than alpha dz, order the
+// splitting volumes by id (two stable 32-bit radix sorts), give the new
+// pieces consecutive ids in that order (exclusive scan), write the pieces;
+// (3) regroup by column; (4) merge per 3-D cell or cap per column, one
+// workgroup per over-full cell/column: its volumes are ordered in LDS
+// (bitonic sort), and one lane walks the order exactly as the reference
+// rule does, so the result does not depend on scheduling; (5) rekey and
+// regroup.  Double-precision arithmetic here is built with
+// -ffp-contract=off and follows the same operation order as the split and
+// merge rules are written (halving by 0.5, W-weighted means, bounding hulls).
+#include "dev64.h"
+
+#define SM_MAX_CELL 2048  // records of one cell/column sorted in LDS (24 B each)
+
+// ---------------------------------------------------------------------------
+// common helpers
+// ---------------------------------------------------------------------------
+__device__ inline int octant_of(double k, double l)
+{
+    const int q = (k >= 0.0) ? (l >= 0.0 ? 0 : 3) : (l >= 0.0 ? 1 : 2);
+    const int big_l = fabs(l) > fabs(k);
+    const int off = (q == 0 || q == 2) ? big_l : !big_l;
+    return 2 * q + off;
+}
+
+// spectral group: azimuth octant of (k, l), sign of m, binary exponent of |m|
+__device__ inline uint64_t group_of(double k, double l, double m)
+{
+    int e;
+    frexp(fabs(m), &e);
+    const int64_t gk = ((int64_t)(octant_of(k, l) * 2 + (m < 0.0 ? 0 : 1)) << 16) + (int64_t)(e + 4096);
+    return (uint64_t)gk;
+}
+
+// uniform view of one ray volume in double precision, whatever the storage
+struct RayD {
+    double x, y, z, k, l, m, dx, dy, dz, px, py, pz, W, n;
+    int64_t id;
+};
+
+__device__ inline double metric_x(const Grid &g, double y, double z, double D)
+{
+    return g.geometry == RT_CARTESIAN ? D : ((g.a + z) * cos(y)) * D;
+}
+__device__ inline double metric_y(const Grid &g, double z, double D)
+{
+    return g.geometry == RT_CARTESIAN ? D : (g.a + z) * D;
+}
+
+// --- double-precision storage ----------------------------------------------
+struct IO64 {
+    S64 s;
+    __device__ RayD get(const Grid &g, uint32_t i) const
+    {
+        RayD r;
+        r.x = s.x[i];
+        r.y = s.y[i];
+        r.z = s.z[i];
+        r.k = s.k[i];
+        r.l = s.l[i];
+        r.m = s.m[i];
+        r.dx = s.dx[i];
+        r.dy = s.dy[i];
+        r.dz = s.dz[i];
+        r.px = s.px[i];
+        r.py = s.py[i];
+        r.pz = s.pz[i];
+        r.W = ((s.n[i] * s.px[i]) * s.py[i]) * s.pz[i];
+        r.n = s.n[i];
+        r.id = s.id[i];
+        (void)g;
+        return r;
+    }
+    // set_n: N = W / (Px Py Pz) (merge); otherwise N is carried unchanged
+    __device__ void put(const Grid &g, uint32_t i, const RayD &r, bool set_n) const
+    {
+        (void)g;
+        s.x[i] = r.x;
+        s.y[i] = r.y;
+        s.z[i] = r.z;
+        s.k[i] = r.k;
+        s.l[i] = r.l;
+        s.m[i] = r.m;
+        s.dx[i] = r.dx;
+        s.dy[i] = r.dy;
+        s.dz[i] = r.dz;
+        s.px[i] = r.px;
+        s.py[i] = r.py;
+        s.pz[i] = r.pz;
+        s.n[i] = set_n ? r.W / ((r.px * r.py) * r.pz) : r.n;
+        s.id[i] = r.id;
+    }
+    __device__ int64_t get_id(uint32_t i) const { return s.id[i]; }
+    __device__ void copy2(const IO64 &d, uint32_t from, uint32_t to) const
+    {
+        d.s.x[to] = s.x[from];
+        d.s.y[to] = s.y[from];
+        d.s.z[to] = s.z[from];
+        d.s.k[to] = s.k[from];
+        d.s.l[to] = s.l[from];
+        d.s.m[to] = s.m[from];
+        d.s.dx[to] = s.dx[from];
+        d.s.dy[to] = s.dy[from];
+        d.s.dz[to] = s.dz[from];
+        d.s.px[to] = s.px[from];
+        d.s.py[to] = s.py[from];
+        d.s.pz[to] = s.pz[from];
+        d.s.n[to] = s.n[from];
+        d.s.id[to] = s.id[from];
+    }
+    __device__ double height(const Grid &g, uint32_t i) const
+    {
+        (void)g;
+        return s.z[i];
+    }
+    __device__ double dzv(uint32_t i) const { return s.dz[i]; }
+    __device__ double pzv(uint32_t i) const { return s.pz[i]; }
+    __device__ double wv(uint32_t i) const { return ((s.n[i] * s.px[i]) * s.py[i]) * s.pz[i]; }
+    // a split piece: N is unchanged, so W follows from Pz
+    __device__ void set_piece(const Grid &g, uint32_t i, double z, double D, double P, double W, int64_t id) const
+    {
+        (void)g;
+        (void)W;
+        s.z[i] = z;
+        s.dz[i] = D;
+        s.pz[i] = P;
+        s.id[i] = id;
+    }
+    __device__ uint32_t column(const Grid &g, uint32_t i) const { return (uint32_t)d64::column_of(g, s.x[i], s.y[i]); }
+    __device__ void rewrap(const Grid &g, uint32_t i) const
+    {
+        double x = s.x[i], y = s.y[i];
+        d64::wrap(x, g.x0, g.Lx);
+        if (g.geometry == RT_CARTESIAN) d64::wrap(y, g.y0, g.Ly);
+        s.x[i] = x;
+        s.y[i] = y;
+    }
+    __device__ double energy(const Grid &g, const double4 *bA, uint32_t i) const
+    {
+        d64::Cell c;
+        d64::locate(g, s.x[i], s.y[i], s.z[i], c);
+        const double4 A = d64::tri4<1>(bA, c, 0);
+        const double k = s.k[i], l = s.l[i], m = s.m[i];
+        const double kh2 = k * k + l * l;
+        const double m2 = m * m;
+        const double K2 = kh2 + m2;
+        const double om = d64::omega_hat(A.z, A.w, kh2, m2, K2);
+        return om * (((s.n[i] * s.px[i]) * s.py[i]) * s.pz[i]);
+    }
+};
+
+// --- single-precision storage (positions as cell + offset) -----------------
+struct IO32 {
+    S32 s;
+    __device__ RayD get(const Grid &g, uint32_t i) const
+    {
+        RayD r;
+        const uint32_t col = s.col[i];
+        const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
+        r.x = g.x0 + ((double)ic + (double)s.xi[i]) * g.dx;
+        r.y = g.y0 + ((double)jc + (double)s.eta[i]) * g.dy;
+        r.z = ((double)s.lev[i] + (double)s.zeta[i]) * g.dz;
+        r.k = s.k[i];
+        r.l = s.l[i];
+        r.m = s.m[i];
+        r.dx = (double)s.dxi[i] * g.dx;
+        r.dy = (double)s.deta[i] * g.dy;
+        r.dz = s.dz[i];
+        r.px = s.px[i];
+        r.py = s.py[i];
+        r.pz = s.pz[i];
+        r.W = s.W[i];
+        r.n = 0.0;
+        r.id = s.id[i];
+        return r;
+    }
+    __device__ void put(const Grid &g, uint32_t i, const RayD &r, bool set_n) const
+    {
+        (void)set_n;
+        double fi = floor((r.x - g.x0) / g.dx), fj = floor((r.y - g.y0) / g.dy);
+        fi = fmin(fmax(fi, 0.0), (double)(g.nx - 1));
+        fj = fmin(fmax(fj, 0.0), (double)(g.ny - 1));
+        double fk = floor(r.z / g.dz);
+        fk = fmin(fmax(fk, 0.0), (double)g.nz);
+        s.col[i] = (uint32_t)((int)fj * g.nx + (int)fi);
+        s.xi[i] = (float)((r.x - g.x0) / g.dx - fi);
+        s.eta[i] = (float)((r.y - g.y0) / g.dy - fj);
+        s.lev[i] = (int32_t)fk;
+        s.zeta[i] = (float)(r.z / g.dz - fk);
+        s.k[i] = (float)r.k;
+        s.l[i] = (float)r.l;
+        s.m[i] = (float)r.m;
+        s.dxi[i] = (float)(r.dx / g.dx);
+        s.deta[i] = (float)(r.dy / g.dy);
+        s.dz[i] = (float)r.dz;
+        s.px[i] = (float)r.px;
+        s.py[i] = (float)r.py;
+        s.pz[i] = (float)r.pz;
+        s.W[i] = r.W;
+        s.id[i] = r.id;
+    }
+    __device__ int64_t get_id(uint32_t i) const { return s.id[i]; }
+    __device__ void copy2(const IO32 &d, uint32_t from, uint32_t to) const
+    {
+        d.s.col[to] = s.col[from];
+        d.s.lev[to] = s.lev[from];
+        d.s.xi[to] = s.xi[from];
+        d.s.eta[to] = s.eta[from];
+        d.s.zeta[to] = s.zeta[from];
+        d.s.k[to] = s.k[from];
+        d.s.l[to] = s.l[from];
+        d.s.m[to] = s.m[from];
+        d.s.dxi[to] = s.dxi[from];
+        d.s.deta[to] = s.deta[from];
+        d.s.dz[to] = s.dz[from];
+        d.s.px[to] = s.px[from];
+        d.s.py[to] = s.py[from];
+        d.s.pz[to] = s.pz[from];
+        d.s.W[to] = s.W[from];
+        d.s.id[to] = s.id[from];
+    }
+    __device__ double height(const Grid &g, uint32_t i) const { return ((double)s.lev[i] + (double)s.zeta[i]) * g.dz; }
+    __device__ double dzv(uint32_t i) const { return s.dz[i]; }
+    __device__ double pzv(uint32_t i) const { return s.pz[i]; }
+    __device__ double wv(uint32_t i) const { return s.W[i]; }
+    __device__ void set_piece(const Grid &g, uint32_t i, double z, double D, double P, double W, int64_t id) const
+    {
+        double fk = floor(z / g.dz);
+        fk = fmin(fmax(fk, 0.0), (double)g.nz);
+        s.lev[i] = (int32_t)fk;
+        s.zeta[i] = (float)(z / g.dz - fk);
+        s.dz[i] = (float)D;
+        s.pz[i] = (float)P;
+        s.W[i] = W;
+        s.id[i] = id;
+    }
+    __device__ uint32_t column(const Grid &g, uint32_t i) const { (void)g; return s.col[i]; }
+    __device__ void rewrap(const Grid &g, uint32_t i) const { (void)g; (void)i; }
+    // wave energy from the single-precision background (N2, f2), in double
+    __device__ double energy(const Grid &g, const float4 *bA, uint32_t i) const
+    {
+        const RayD r = get(g, i);
+        d64::Cell c;
+        d64::locate(g, r.x, r.y, r.z, c);
+        const int o[8] = {c.c00 + c.k0, c.c01 + c.k0, c.c10 + c.k0, c.c11 + c.k0,
+                          c.c00 + c.k1, c.c01 + c.k1, c.c10 + c.k1, c.c11 + c.k1};
+        double vz[8], vw[8];
+        for (int q = 0; q < 8; q++) {
+            const float4 t = bA[o[q]];
+            vz[q] = t.z;
+            vw[q] = t.w;
+        }
+        auto tri = [&](const double *v) {
+            const double c00 = v[0] + c.wx * (v[1] - v[0]), c10 = v[2] + c.wx * (v[3] - v[2]);
+            const double c01 = v[4] + c.wx * (v[5] - v[4]), c11 = v[6] + c.wx * (v[7] - v[6]);
+            const double c0 = c00 + c.wy * (c10 - c00), c1 = c01 + c.wy * (c11 - c01);
+            return c0 + c.wz * (c1 - c0);
+        };
+        double4 A;
+        A.z = tri(vz);
+        A.w = tri(vw);
+        const double kh2 = r.k * r.k + r.l * r.l;
+        const double m2 = r.m * r.m;
+        const double K2 = kh2 + m2;
+        return d64::omega_hat(A.z, A.w, kh2, m2, K2) * r.W;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// compaction of the active set into the spare buffer, in column order
+// ---------------------------------------------------------------------------
+template <class IO>
+__global__ void k_compact(IO src, IO dst, const uint32_t *perm, const uint32_t *skeys, uint32_t *key_dst,
+                          const DevCounters *dc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dc->n_active) return;
+    src.copy2(dst, perm[i], (uint32_t)i);
+    key_dst[i] = skeys[i];
+}
+
+// ---------------------------------------------------------------------------
+// split
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t pieces_of(double Dz, double thr)
+{
+    double D = Dz;
+    uint32_t p = 1;
+    while (D > thr && p < 64) {
+        D = 0.5 * D;
+        p *= 2;
+    }
+    return p;
+}
+
+template <class IO>
+__global__ void k_split_count(IO io, const uint32_t *key, int64_t n, int ncol, double thr, uint32_t *extra,
+                              uint32_t *idlo, uint32_t *idhi)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool act = key[i] < (uint32_t)ncol;
+    extra[i] = (act && thr > 0.0) ? pieces_of(io.dzv((uint32_t)i), thr) - 1u : 0u;
+    const int64_t id = io.get_id((uint32_t)i);
+    idlo[i] = (uint32_t)((uint64_t)id & 0xffffffffull);
+    idhi[i] = (uint32_t)((uint64_t)id >> 32);
+}
+
+__global__ void k_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+__global__ void k_split_total(const uint32_t *ex_sorted_scan, const uint32_t *ex_sorted, int64_t n, DevCounters *dc)
+{
+    dc->split_extra = n > 0 ? (int64_t)ex_sorted_scan[n - 1] + (int64_t)ex_sorted[n - 1] : 0;
+}
+
+// r-th splitting volume in id order: lowest piece stays in its slot, the
+// others go to slots n + off[r] + (q - 1) with ids next_id + off[r] + (q - 1).
+// Piece q's height follows the halving tree from the root: at each level the
+// lower half is at z - D/4 and the upper at z + D/4, with D and Pz halved.
+// Pieces are full copies of the parent except for (z, Dz, Pz, W, id); the
+// parent slot is rewritten last.
+template <class IO>
+__global__ void k_split_write(IO io, const Grid g, uint32_t *key, const uint32_t *pid, const uint32_t *off,
+                              const uint32_t *ex, int64_t n, int64_t next_id)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t extra = ex[r];
+    if (extra == 0) return;
+    const uint32_t s = pid[r];
+    const uint32_t p = extra + 1;
+    int levels = 0;
+    while ((1u << levels) < p) levels++;
+    const double z0 = io.height(g, s), D0 = io.dzv(s), P0 = io.pzv(s), W0 = io.wv(s);
+    const int64_t id0 = io.get_id(s);
+    const uint32_t pkey = key[s];
+    for (int qq = (int)p - 1; qq >= 0; qq--) {
+        const uint32_t q = (uint32_t)qq;
+        double z = z0, D = D0, P = P0, Wc = W0;
+        for (int t = 0; t < levels; t++) {
+            const uint32_t bit = (q >> (levels - 1 - t)) & 1u;
+            z = bit ? z + 0.25 * D : z - 0.25 * D;
+            D = 0.5 * D;
+            P = 0.5 * P;
+            Wc = 0.5 * Wc;
+        }
+        uint32_t dst = s;
+        int64_t id = id0;
+        if (q > 0) {
+            dst = (uint32_t)(n + (int64_t)off[r] + (int64_t)(q - 1));
+            id = next_id + (int64_t)off[r] + (int64_t)(q - 1);
+            io.copy2(io, s, dst);
+            key[dst] = pkey;
+        }
+        io.set_piece(g, dst, z, D, P, Wc, id);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+template <class IO>
+__global__ void k_rekey(IO io, const Grid g, uint32_t *key, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (key[i] >= (uint32_t)g.ncol) return;  // removed volumes keep their reason
+    io.rewrap(g, (uint32_t)i);
+    key[i] = io.column(g, (uint32_t)i);
+}
+
+template <class IO>
+__global__ void k_key3(IO io, const Grid g, const uint32_t *key, uint32_t *key3, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t ncell = (uint32_t)g.ncol * (uint32_t)g.nz;
+    if (key[i] >= (uint32_t)g.ncol) {
+        key3[i] = ncell;
+        return;
+    }
+    double fk = floor(io.height(g, (uint32_t)i) / g.dz);
+    if (fk < 0.0) fk = 0.0;
+    if (fk > (double)(g.nz - 1)) fk = (double)(g.nz - 1);
+    key3[i] = key[i] * (uint32_t)g.nz + (uint32_t)fk;
+}
+
+// over-full segments of sorted keys: (start, count) appended to a list
+__global__ void k_overfull(const uint32_t *skeys, int64_t n, uint32_t limit_key, int32_t nmax, uint32_t *list,
+                           uint32_t *nlist, uint32_t *maxcount)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t k = skeys[p];
+    if (k >= limit_key) return;
+    if (p > 0 && skeys[p - 1] == k) return;
+    int64_t lo = p, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (skeys[mid] <= k)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    const uint32_t cnt = (uint32_t)(lo - p);
+    if ((int32_t)cnt <= nmax) return;
+    const uint32_t at = atomicAdd(nlist, 1u);
+    list[2 * at] = (uint32_t)p;
+    list[2 * at + 1] = cnt;
+    atomicMax(maxcount, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// block bitonic sort of (k1, k2, payload) records in LDS, ascending
+// ---------------------------------------------------------------------------
+__device__ inline bool rec_less(uint64_t a1, uint64_t a2, uint64_t b1, uint64_t b2)
+{
+    return a1 < b1 || (a1 == b1 && a2 < b2);
+}
+
+__device__ void block_bitonic(uint64_t *k1, uint64_t *k2, uint32_t *pl, int N)
+{
+    for (int size = 2; size <= N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < N / 2; t += blockDim.x) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const bool sw = up ? rec_less(k1[hi], k2[hi], k1[lo], k2[lo]) : rec_less(k1[lo], k2[lo], k1[hi], k2[hi]);
+                if (sw) {
+                    const uint64_t a = k1[lo], b = k2[lo];
+                    const uint32_t c = pl[lo];
+                    k1[lo] = k1[hi];
+                    k2[lo] = k2[hi];
+                    pl[lo] = pl[hi];
+                    k1[hi] = a;
+                    k2[hi] = b;
+                    pl[hi] = c;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// merge two volumes (survivor a): summed wave action, W-weighted carrier
+// position and wavevector, physical and spectral extents spanning both
+// ---------------------------------------------------------------------------
+__device__ inline void merge_pair(const Grid &g, RayD &a, const RayD &b)
+{
+    const double Wa = a.W, Wb = b.W, W = Wa + Wb;
+    const double dka = a.px / metric_x(g, a.y, a.z, a.dx);
+    const double dkb = b.px / metric_x(g, b.y, b.z, b.dx);
+    const double dla = a.py / metric_y(g, a.z, a.dy);
+    const double dlb = b.py / metric_y(g, b.z, b.dy);
+    const double dma = a.pz / a.dz, dmb = b.pz / b.dz;
+    auto hull = [](double ca, double da, double cb, double db) {
+        const double la = ca - 0.5 * da, lb = cb - 0.5 * db;
+        const double ha = ca + 0.5 * da, hb = cb + 0.5 * db;
+        const double lo = la < lb ? la : lb;
+        const double hi = ha > hb ? ha : hb;
+        return hi - lo;
+    };
+    const double x = (a.x * Wa + b.x * Wb) / W;
+    const double y = (a.y * Wa + b.y * Wb) / W;
+    const double z = (a.z * Wa + b.z * Wb) / W;
+    const double k = (a.k * Wa + b.k * Wb) / W;
+    const double l = (a.l * Wa + b.l * Wb) / W;
+    const double m = (a.m * Wa + b.m * Wb) / W;
+    const double Dx = hull(a.x, a.dx, b.x, b.dx);
+    const double Dy = hull(a.y, a.dy, b.y, b.dy);
+    const double Dz = hull(a.z, a.dz, b.z, b.dz);
+    const double Dk = hull(a.k, dka, b.k, dkb);
+    const double Dl = hull(a.l, dla, b.l, dlb);
+    const double Dm = hull(a.m, dma, b.m, dmb);
+    a.x = x;
+    a.y = y;
+    a.z = z;
+    a.k = k;
+    a.l = l;
+    a.m = m;
+    a.dx = Dx;
+    a.dy = Dy;
+    a.dz = Dz;
+    a.px = metric_x(g, y, z, Dx) * Dk;
+    a.py = metric_y(g, z, Dy) * Dl;
+    a.pz = Dz * Dm;
+    a.W = W;
+}
+
+// one workgroup per over-full cell; records sorted by (group, id)
+template <class IO>
+__global__ __launch_bounds__(256) void k_merge_cells(IO io, const Grid g, const uint32_t *perm3, const uint32_t *list,
+                                                     uint32_t *key, int32_t nmax, DevCounters *dc)
+{
+    extern __shared__ unsigned char sm_smem[];
+    const uint32_t start = list[2 * blockIdx.x], cnt = list[2 * blockIdx.x + 1];
+    int N = 1;
+    while ((uint32_t)N < cnt) N <<= 1;
+    uint64_t *k1 = (uint64_t *)sm_smem;
+    uint64_t *k2 = k1 + N;
+    uint32_t *pl = (uint32_t *)(k2 + N);
+    uint32_t *alive = pl + N;  // by position in the cell's original order
+    __shared__ int s_count, s_merged, s_done;
+    for (int q = threadIdx.x; q < (int)cnt; q += blockDim.x) alive[q] = 1u;
+    if (threadIdx.x == 0) {
+        s_count = (int)cnt;
+        s_merged = 0;
+        s_done = 0;
+    }
+    __syncthreads();
+    while (true) {
+        if (s_done || s_count <= nmax) break;
+        // records of the surviving volumes, keyed by (group, id)
+        for (int q = threadIdx.x; q < N; q += blockDim.x) {
+            if (q < (int)cnt && alive[q]) {
+                const uint32_t s = perm3[start + q];
+                const RayD r = io.get(g, s);
+                k1[q] = group_of(r.k, r.l, r.m);
+                k2[q] = (uint64_t)r.id;
+                pl[q] = (uint32_t)q;
+            } else {
+                k1[q] = ~0ull;
+                k2[q] = ~0ull;
+                pl[q] = 0xffffffffu;
+            }
+        }
+        __syncthreads();
+        block_bitonic(k1, k2, pl, N);
+        if (threadIdx.x == 0) {
+            int count = s_count, merged = 0;
+            int m_ = 0;
+            while (m_ < N && pl[m_] != 0xffffffffu) m_++;
+            for (int q = 0; q + 1 < m_ && count > nmax;) {
+                if (k1[q] == k1[q + 1]) {
+                    const uint32_t sa = perm3[start + pl[q]], sb = perm3[start + pl[q + 1]];
+                    RayD a = io.get(g, sa);
+                    const RayD b = io.get(g, sb);
+                    merge_pair(g, a, b);
+                    io.put(g, sa, a, true);
+                    key[sb] = (uint32_t)(g.ncol + RK_MERGED);
+                    alive[pl[q + 1]] = 0u;
+                    count--;
+                    merged++;
+                    q += 2;
+                } else {
+                    q += 1;
+                }
+            }
+            if (merged == 0) {
+                for (int q = 0; q + 1 < m_ && count > nmax; q += 2) {
+                    const uint32_t sa = perm3[start + pl[q]], sb = perm3[start + pl[q + 1]];
+                    RayD a = io.get(g, sa);
+                    const RayD b = io.get(g, sb);
+                    merge_pair(g, a, b);
+                    io.put(g, sa, a, true);
+                    key[sb] = (uint32_t)(g.ncol + RK_MERGED);
+                    alive[pl[q + 1]] = 0u;
+                    count--;
+                    merged++;
+                }
+                if (merged == 0) s_done = 1;
+            }
+            s_count = count;
+            s_merged += merged;
+        }
+        __threadfence();
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&dc->n_merged, (unsigned long long)s_merged);
+}
+
+// one workgroup per over-full column; remove the lowest wave energies
+template <class IO, class AT>
+__global__ __launch_bounds__(256) void k_cap_columns(IO io, const Grid g, const AT *bA, const uint32_t *perm,
+                                                     const uint32_t *list, uint32_t *key, int32_t nmax)
+{
+    extern __shared__ unsigned char sm_smem[];
+    const uint32_t start = list[2 * blockIdx.x], cnt = list[2 * blockIdx.x + 1];
+    int N = 1;
+    while ((uint32_t)N < cnt) N <<= 1;
+    uint64_t *k1 = (uint64_t *)sm_smem;
+    uint64_t *k2 = k1 + N;
+    uint32_t *pl = (uint32_t *)(k2 + N);
+    for (int q = threadIdx.x; q < N; q += blockDim.x) {
+        if (q < (int)cnt) {
+            const uint32_t s = perm[start + q];
+            const double E = io.energy(g, bA, s);
+            k1[q] = (uint64_t)__double_as_longlong(E);  // E > 0: bit order = numeric order
+            k2[q] = ~(uint64_t)io.get_id(s);            // among equal energies the larger id first
+            pl[q] = s;
+        } else {
+            k1[q] = ~0ull;
+            k2[q] = ~0ull;
+            pl[q] = 0xffffffffu;
+        }
+    }
+    __syncthreads();
+    block_bitonic(k1, k2, pl, N);
+    for (int q = threadIdx.x; q < (int)cnt - nmax; q += blockDim.x) key[pl[q]] = (uint32_t)(g.ncol + RK_CAPPED);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int bits_for(uint64_t maxkey)
+{
+    int b = 0;
+    while (b < 64 && (1ull << b) <= maxkey) b++;
+    return b;
+}
+
+template <class IO, class AT>
+static rt_status split_merge_impl(rt_ctx ctx, IO cur_io, IO other_io, const AT *bA, double alpha, int32_t nmax,
+                                  int32_t mode)
+{
+    const Grid &g = ctx->g;
+    hipStream_t st = ctx->stream;
+    DevCounters h;
+    HIP_OK(hipMemcpyAsync(&h, ctx->dc, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    int64_t n = h.n_active;
+    const int64_t cap = ctx->cap;
+    const unsigned T = 256;
+    auto nb = [&](int64_t m) { return (unsigned)((m + T - 1) / T > 0 ? (m + T - 1) / T : 1); };
+    rt_status result = RT_OK;
+
+    // scratch carved from ctx->sm (uint32): extra | idlo | idhi | exs | offs | key3 | list | small
+    uint32_t *extra = ctx->sm, *idlo = extra + cap, *idhi = idlo + cap, *exs = idhi + cap, *offs = exs + cap;
+    uint32_t *key3 = offs + cap, *list = key3 + cap, *small = list + 2 * cap;  // small: nlist, maxcount
+    uint32_t *parts = small + 8;
+
+    // (1) compaction into the spare buffer, in column order
+    const int nxt = 1 - ctx->cur;
+    if (n > 0) k_compact<IO><<<nb(n), T, 0, st>>>(cur_io, other_io, ctx->perm, ctx->skeys, ctx->key[nxt], ctx->dc);
+    ctx->cur = nxt;
+    IO io = other_io;
+    uint32_t *key = ctx->key[ctx->cur];
+
+    // (2) split
+    if (alpha > 0.0 && n > 0) {
+        const double thr = alpha * g.dz;
+        k_split_count<IO><<<nb(n), T, 0, st>>>(io, key, n, g.ncol, thr, extra, idlo, idhi);
+        launch_set_sorted(ctx->dc, n, st);
+        // slots in id order: stable sort on the low word, then on the high word
+        radix_sort(idlo, nullptr, ctx->skeys, ctx->perm, ctx->tk, ctx->tv, ctx->hist, &ctx->dc->n_sorted, n, 32, st);
+        const uint32_t *pid = ctx->perm;
+        if ((uint64_t)h.next_id > 0xffffffffull) {
+            k_gather_u32<<<nb(n), T, 0, st>>>(idhi, ctx->perm, idlo, n);
+            radix_sort(idlo, ctx->perm, ctx->skeys, exs, ctx->tk, ctx->tv, ctx->hist, &ctx->dc->n_sorted, n,
+                       bits_for((uint64_t)h.next_id >> 32), st);
+            HIP_OK(hipMemcpyAsync(ctx->perm, exs, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
+        }
+        k_gather_u32<<<nb(n), T, 0, st>>>(extra, pid, exs, n);
+        HIP_OK(hipMemcpyAsync(offs, exs, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
+        scan_u32(offs, n, parts, st);
+        k_split_total<<<1, 1, 0, st>>>(offs, exs, n, ctx->dc);
+        int64_t total = 0;
+        HIP_OK(hipMemcpyAsync(&total, &ctx->dc->split_extra, sizeof(total), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (n + total > cap) {
+            result = rt_fail(ctx, RT_E_CAPACITY, "split needs %lld ray volumes, capacity %lld", (long long)(n + total),
+                             (long long)cap);
+        } else if (total > 0) {
+            k_split_write<IO><<<nb(n), T, 0, st>>>(io, g, key, pid, offs, exs, n, h.next_id);
+            h.next_id += total;
+            h.n_split += total;
+            HIP_OK(hipMemcpyAsync(&ctx->dc->next_id, &h.next_id, sizeof(int64_t), hipMemcpyHostToDevice, st));
+            HIP_OK(hipMemcpyAsync(&ctx->dc->n_split, &h.n_split, sizeof(int64_t), hipMemcpyHostToDevice, st));
+            n += total;
+        }
+    }
+
+    // (3) merge per 3-D cell or cap per column
+    if (result == RT_OK && n > 0 && (mode == RT_MERGE || mode == RT_CAP)) {
+        HIP_OK(hipMemsetAsync(small, 0, 8 * sizeof(uint32_t), st));
+        launch_set_sorted(ctx->dc, n, st);
+        const uint32_t *ord;
+        if (mode == RT_MERGE) {
+            const uint64_t ncell = (uint64_t)g.ncol * (uint64_t)g.nz;
+            k_key3<IO><<<nb(n), T, 0, st>>>(io, g, key, key3, n);
+            radix_sort(key3, nullptr, ctx->skeys, ctx->perm, ctx->tk, ctx->tv, ctx->hist, &ctx->dc->n_sorted, n,
+                       bits_for(ncell), st);
+            k_overfull<<<nb(n), T, 0, st>>>(ctx->skeys, n, (uint32_t)ncell, nmax, list, small, small + 1);
+        } else {
+            k_rekey<IO><<<nb(n), T, 0, st>>>(io, g, key, n);
+            radix_sort(key, nullptr, ctx->skeys, ctx->perm, ctx->tk, ctx->tv, ctx->hist, &ctx->dc->n_sorted, n,
+                       bits_for((uint64_t)g.ncol + RK_NREASON), st);
+            k_overfull<<<nb(n), T, 0, st>>>(ctx->skeys, n, (uint32_t)g.ncol, nmax, list, small, small + 1);
+        }
+        ord = ctx->perm;
+        uint32_t hs[2];
+        HIP_OK(hipMemcpyAsync(hs, small, sizeof(hs), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (hs[0] > 0) {
+            if (hs[1] > SM_MAX_CELL) {
+                result = rt_fail(ctx, RT_E_UNSUPPORTED, "%s holds %u ray volumes; at most %d are handled",
+                                 mode == RT_MERGE ? "a cell" : "a column", hs[1], SM_MAX_CELL);
+            } else {
+                int N = 1;
+                while ((uint32_t)N < hs[1]) N <<= 1;
+                const size_t smem = (size_t)N * (8 + 8 + 4 + 4);
+                if (mode == RT_MERGE)
+                    k_merge_cells<IO><<<hs[0], T, smem, st>>>(io, g, ord, list, key, nmax, ctx->dc);
+                else
+                    k_cap_columns<IO, AT><<<hs[0], T, smem, st>>>(io, g, bA, ord, list, key, nmax);
+            }
+        }
+    }
+
+    // (4) rekey and regroup
+    if (n > 0) k_rekey<IO><<<nb(n), T, 0, st>>>(io, g, key, n);
+    launch_set_sorted(ctx->dc, n, st);
+    ctx->n_bound = n;
+    HIP_OK(hipGetLastError());
+    return result;
+}
+
+rt_status sort_current_ext(rt_ctx ctx);
 
 rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, rt_stats *out)
 {
-    (void)alpha;
-    (void)nmax;
-    (void)mode;
-    (void)out;
-    return rt_fail(ctx, RT_E_UNSUPPORTED, "split/merge not built yet");
+    prof_begin(ctx, PC_SPLIT);
+    rt_status r;
+    if (ctx->precision == RT_FP64)
+        r = split_merge_impl<IO64, double4>(ctx, IO64{ctx->s64[ctx->cur]}, IO64{ctx->s64[1 - ctx->cur]}, ctx->bp64.A,
+                                            alpha, nmax, mode);
+    else
+        r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur]}, IO32{ctx->s32[1 - ctx->cur]}, ctx->bp32.A,
+                                           alpha, nmax, mode);
+    rt_status r2 = sort_current_ext(ctx);
+    prof_end(ctx);
+    if (r == RT_OK) r = r2;
+    if (out && r == RT_OK) r = rt_get_stats(ctx, out);
+    return r;
 }

@@ -1,0 +1,127 @@
+"""GPU split / merge / cap against the oracle (bit-exact in double precision
+on the box: same ids, same states)."""
+import numpy as np
+import pytest
+
+from paper_2309_11257_amd import workloads as W
+from helpers import EVOLVING, by_id, gpu_tracer
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_11257_amd import _rt
+    _rt.lib()
+    return _rt
+
+
+def same_state(rs, g, fields=EVOLVING + ("px", "py", "pz", "n")):
+    o = by_id(rs.snapshot())
+    g = by_id(g)
+    assert np.array_equal(o["id"], g["id"]), (len(o["id"]), len(g["id"]))
+    for f in fields:
+        bad = np.nonzero(o[f] != g[f])[0]
+        assert bad.size == 0, f"{f}: {bad.size} differ, e.g. id {o['id'][bad[0]]}: {o[f][bad[0]]!r} vs {g[f][bad[0]]!r}"
+
+
+def tall_rays(n=300, seed=9):
+    w = W.make_c1(n_rays=n)
+    rng = np.random.default_rng(seed)
+    w.rays["dz"][:] = rng.uniform(0.5e3, 9e3, n)
+    w.rays["z"][:] = rng.uniform(10e3, 50e3, n)
+    w.rays["pz"][:] = w.rays["dz"] * 0.1 * np.abs(w.rays["m"])
+    return w
+
+
+def test_split_bitwise(rt, orc):
+    w = tall_rays()
+    bg = orc.Background.from_workload(w)
+    rs = orc.RaySet(w.rays, capacity=300 * 16)
+    t = orc.split(bg, rs, alpha=2.0)
+    tr = gpu_tracer(w, rt.RT_FP64, capacity=300 * 16)
+    st = tr.split_merge(2.0, 0, rt.RT_SPLIT_ONLY)
+    assert st["n_split"] == t["n_split"] > 0
+    assert st["n_active"] == rs.n
+    same_state(rs, tr.get_rays())
+
+
+def test_split_capacity_leaves_set_unchanged(rt):
+    w = tall_rays()
+    tr = gpu_tracer(w, rt.RT_FP64, capacity=320)
+    before = by_id(tr.get_rays())
+    with pytest.raises(rt.RTError) as e:
+        tr.split_merge(2.0, 0, rt.RT_SPLIT_ONLY)
+    assert e.value.code == rt.RT_E_CAPACITY
+    after = by_id(tr.get_rays())
+    for f in before:
+        assert np.array_equal(before[f], after[f]), f
+    tr.step(w.dt)  # still usable
+
+
+@pytest.mark.parametrize("nmax", [64, 16, 3])
+def test_merge_bitwise(rt, orc, nmax):
+    w = W.make_c2(cols=np.arange(0, 16384, 411))
+    bg = orc.Background.from_workload(w)
+    rs = orc.RaySet(w.rays)
+    t = orc.merge(bg, rs, nmax)
+    tr = gpu_tracer(w, rt.RT_FP64)
+    st = tr.split_merge(0.0, nmax, rt.RT_MERGE)
+    assert st["n_merged"] == t["n_merged"] > 0
+    same_state(rs, tr.get_rays())
+    s2 = tr.stats()
+    so = orc.stats(rs)
+    for key in ("sum_W", "sum_kW", "sum_lW", "sum_mW"):
+        assert s2[key] == pytest.approx(so[key], rel=1e-13)
+
+
+def test_cap_matches_oracle(rt, orc):
+    w = W.make_c2(cols=np.arange(0, 16384, 997))
+    bg = orc.Background.from_workload(w)
+    rs = orc.RaySet(w.rays)
+    t = orc.cap(bg, rs, 100)
+    tr = gpu_tracer(w, rt.RT_FP64)
+    st = tr.split_merge(0.0, 100, rt.RT_CAP)
+    assert st["n_capped"] == t["n_capped"] > 0
+    same_state(rs, tr.get_rays())
+    assert st["removed_W"] == pytest.approx(t["removed_W"], rel=1e-13)
+
+
+def test_jet_box_steps_with_split_and_merge_bitwise(rt, orc):
+    """The jet-box recipe: every step split volumes taller than two levels
+    and merge cells holding more than 64 volumes."""
+    w = W.make_c2(cols=np.arange(0, 16384, 257))
+    cap = 4 * w.n_rays
+    bg = orc.Background.from_workload(w)
+    rs = orc.RaySet(w.rays, capacity=cap)
+    tr = gpu_tracer(w, rt.RT_FP64, capacity=cap)
+    for _ in range(12):
+        orc.step(bg, rs, w.dt)
+        orc.split(bg, rs, w.split_alpha)
+        orc.merge(bg, rs, w.merge_nmax)
+        tr.step(w.dt)
+        tr.split_merge(w.split_alpha, w.merge_nmax, rt.RT_MERGE)
+    same_state(rs, tr.get_rays())
+
+
+def test_fp32_split_merge_conserve(rt):
+    w = W.make_c2(cols=np.arange(0, 16384, 411))
+    w.rays["dz"][::3] *= 5.0
+    w.rays["pz"][::3] *= 5.0
+    tr = gpu_tracer(w, rt.RT_FP32, capacity=8 * w.n_rays)
+    s0 = tr.stats()
+    st = tr.split_merge(2.0, 0, rt.RT_SPLIT_ONLY)
+    assert st["n_split"] > 0
+    g = tr.get_rays()
+    assert (g["dz"] <= 2.0 * w.dz * (1 + 1e-6)).all()
+    st = tr.split_merge(0.0, 16, rt.RT_MERGE)
+    assert st["n_merged"] > 0
+    for key in ("sum_W", "sum_kW", "sum_lW", "sum_mW"):
+        assert st[key] == pytest.approx(s0[key], rel=1e-6)
+    g = tr.get_rays()
+    cols = tr.get_columns()
+    cell = cols.astype(np.int64) * w.nz + np.clip(np.floor(g["z"] / w.dz), 0, w.nz - 1).astype(np.int64)
+    assert np.bincount(cell).max() <= 16
