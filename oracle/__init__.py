@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
         L.orc_merge.argtypes = [P, P, C.c_int64, C.c_int32, P]
         L.orc_cap.argtypes = [P, P, C.c_int64, C.c_int32, P]
         L.orc_stats.argtypes = [P, C.c_int64, P]
+        L.orc_features.argtypes = [P, P, C.c_int64, P]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -250,6 +251,21 @@ def stats(rs: RaySet) -> dict:
     t = Tally()
     lib().orc_stats(rs.ref, rs.n, C.byref(t))
     return t.as_dict()
+
+
+def features(bg: Background, rs: RaySet, cols: Optional[np.ndarray] = None) -> np.ndarray:
+    """Surrogate input features [nx*ny][3*nz + 32] of the current state
+    (background profiles and per-sector ray-spectrum moments, see
+    orc_features).  `cols` as in deposit()."""
+    if cols is None:
+        keys(bg, rs)
+    else:
+        cols = np.asarray(cols, dtype=np.int32)
+        assert cols.shape == (rs.n,)
+        rs.a["col"][: rs.n] = cols
+    X = np.zeros((bg.nx * bg.ny, 3 * bg.nz + 32))
+    lib().orc_features(bg.ref, rs.ref, rs.n, _ptr(X))
+    return X
 
 
 def set_threads(n: int) -> None:

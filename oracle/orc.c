@@ -1005,3 +1005,72 @@ void orc_stats(const orc_rays *r, int64_t n, orc_tally *t)
         t->sum_mW += r->m[i] * W;
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Column features of the surrogate (no counterpart in the paper; they
+ * summarise the ray-volume state that the flux projection of Section 3b
+ * reads).  Row c =
+ * j*nx + i of X [ncol][3*nz + 32]:
+ *   U, V, N2 at the column's cell centres, levels 0..nz-1;
+ *   for each of 8 azimuth sectors s (centred on the directions s*45 degrees
+ *   of the horizontal wavevector, boundaries at 22.5 + 45 n degrees):
+ *   sum W, sum |cg_z| k_h W, W-weighted mean log10 k_h, W-weighted mean
+ *   log10 |m|  (means 0 for an empty sector),
+ * over the active rays whose carrier lies in the column (col[] must hold the
+ * keys), summed in ascending index.  cg_z is the intrinsic vertical group
+ * velocity at the carrier (Section 2a), W = N Px Py Pz the wave action of
+ * the volume (Section 3a).
+ * The sector test compares |l| with tan(22.5 deg) |k| and vice versa, so no
+ * arctangent decides an integer.
+ * ------------------------------------------------------------------------ */
+static int azimuth_sector(double k, double l)
+{
+    const double t = 0.41421356237309503; /* tan(pi/8) = sqrt(2) - 1 */
+    double ak = fabs(k), al = fabs(l);
+    if (al <= t * ak) return k > 0.0 ? 0 : 4;
+    if (ak <= t * al) return l > 0.0 ? 2 : 6;
+    if (k > 0.0) return l > 0.0 ? 1 : 7;
+    return l > 0.0 ? 3 : 5;
+}
+
+void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X)
+{
+    int ncol = g->nx * g->ny, nf = 3 * g->nz + 32;
+    int c, k, s;
+    int64_t i;
+    memset(X, 0, sizeof(double) * (size_t)ncol * (size_t)nf);
+    for (c = 0; c < ncol; c++) {
+        int ci = c % g->nx, cj = c / g->nx;
+        double *row = X + (size_t)c * (size_t)nf;
+        for (k = 0; k < g->nz; k++) {
+            row[k] = g->U[IDX(g, ci, cj, k)];
+            row[g->nz + k] = g->V[IDX(g, ci, cj, k)];
+            row[2 * g->nz + k] = g->N2[IDX(g, ci, cj, k)];
+        }
+    }
+    for (i = 0; i < n; i++) {
+        double B[14], D[4], W, kh, *mom;
+        if (r->state[i] != ORC_ACTIVE) continue;
+        orc_interp(g, r->x[i], r->y[i], r->z[i], B);
+        orc_dispersion(B[2], B[12], r->k[i], r->l[i], r->m[i], D);
+        W = ray_W(r, i);
+        kh = sqrt(r->k[i] * r->k[i] + r->l[i] * r->l[i]);
+        s = azimuth_sector(r->k[i], r->l[i]);
+        mom = X + (size_t)r->col[i] * (size_t)nf + 3 * g->nz + 4 * s;
+        mom[0] += W;
+        mom[1] += fabs(D[3]) * kh * W;
+        mom[2] += W * log10(kh);
+        mom[3] += W * log10(fabs(r->m[i]));
+    }
+    for (c = 0; c < ncol; c++)
+        for (s = 0; s < 8; s++) {
+            double *mom = X + (size_t)c * (size_t)nf + 3 * g->nz + 4 * s;
+            if (mom[0] > 0.0) {
+                mom[2] = mom[2] / mom[0];
+                mom[3] = mom[3] / mom[0];
+            } else {
+                mom[2] = 0.0;
+                mom[3] = 0.0;
+            }
+        }
+}

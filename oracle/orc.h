@@ -79,6 +79,7 @@ int64_t orc_split(const orc_bg *g, orc_rays *r, int64_t n, int64_t capacity,
 void orc_merge(const orc_bg *g, orc_rays *r, int64_t n, int32_t n_max, orc_tally *t);
 void orc_cap(const orc_bg *g, orc_rays *r, int64_t n, int32_t n_max, orc_tally *t);
 void orc_stats(const orc_rays *r, int64_t n, orc_tally *t);
+void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X);
 int orc_num_threads(void);
 void orc_set_threads(int n);
 
