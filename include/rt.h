@@ -53,7 +53,7 @@ enum {
 enum { RT_CARTESIAN = 0, RT_SPHERICAL = 1 };
 enum { RT_FP64 = 0, RT_FP32 = 1 };
 enum { RT_HOST = 0, RT_DEVICE = 1 };
-enum { RT_STEP_DEPOSIT = 1 };
+enum { RT_STEP_DEPOSIT = 1, RT_STEP_SURROGATE = 2 };
 enum { RT_MERGE = 0, RT_CAP = 1, RT_SPLIT_ONLY = 2 };
 
 typedef struct {
@@ -144,8 +144,30 @@ rt_status rt_get_columns(rt_ctx ctx, uint32_t *cols, int64_t *n_inout, int32_t w
  * the set is regrouped by parent column (Appendix B, horizontal propagation).
  * With RT_STEP_DEPOSIT the fluxes and drag are also formed into the
  * context's own buffers (read them with rt_deposit_flux(ctx, NULL, ...) --
- * see there).  No synchronisation. */
+ * see there).  With RT_STEP_SURROGATE the volumes whose parent column is
+ * flagged by rt_set_frozen_columns keep their state unchanged for this step
+ * (the column surrogate supplies that column's drag; RT_E_STATE if no flags
+ * were set).  No synchronisation. */
 rt_status rt_step(rt_ctx ctx, double dt, int32_t flags);
+
+/* Column flags for RT_STEP_SURROGATE: mask [ny*nx] uint8 (column j*nx + i),
+ * 1 = frozen.  NULL clears all flags.  Copied on the stream (synchronises
+ * for RT_HOST). */
+rt_status rt_set_frozen_columns(rt_ctx ctx, const uint8_t *mask, int32_t where);
+
+/* Input features of the column surrogate from the current state (the
+ * quantities the flux projection of Section 3b reads, summarised per column):
+ *   X [ny*nx][3*nz + 32] float32, row j*nx + i:
+ *     U, V, N2 at the column's cell centres (levels 0..nz-1);
+ *     for each azimuth sector s = 0..7 of the horizontal wavevector (sector s
+ *     centred on azimuth 45 s degrees, boundaries at 22.5 + 45 n degrees,
+ *     decided by comparing |l| with tan(22.5 deg) |k| and |k| with
+ *     tan(22.5 deg) |l|): sum of W, sum of |cg_z| k_h W (cg_z the intrinsic
+ *     vertical group velocity at the carrier, Section 2a), W-weighted mean of
+ *     log10 k_h and of log10 |m| (0 for an empty sector); W = N Px Py Pz.
+ * Sums are accumulated in double in a fixed order.  No synchronisation
+ * unless where == RT_HOST. */
+rt_status rt_features(rt_ctx ctx, float *X, int32_t where);
 
 /* Project the current ray volumes onto the grid (Section 3b and App. A:
  * pseudo-momentum flux, integral of cg_hat k_h N d^3k; vertical fluxes on the

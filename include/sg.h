@@ -80,8 +80,8 @@ rt_status sg_gradient(sg_net net, int32_t member, const uint16_t *X, const float
                       int32_t where);
 
 /* Trust gate over columns.  A column is trusted (mask 1) when the ensemble's
- * spread -- the root-mean-square over outputs of the members' standard
- * deviation -- is at most tau and every feature lies within [fmin, fmax] of
+ * spread -- the root-mean-square over outputs of the members' sample standard
+ * deviation (n - 1 normalisation; 0 for one member) -- is at most tau and every feature lies within [fmin, fmax] of
  * the training data; otherwise it goes back to the ray tracer (mask 0).
  *   Yens  [n_members][n_cols][n_out] float32 (from sg_forward, member = -1)
  *   Xraw  [n_cols][n_in] float32 unstandardised features
@@ -90,6 +90,24 @@ rt_status sg_gradient(sg_net net, int32_t member, const uint16_t *X, const float
  * All device pointers. */
 rt_status sg_gate(sg_net net, const float *Yens, const float *Xraw, const float *fmin, const float *fmax,
                   int32_t n_cols, float tau, float *spread, uint8_t *mask);
+
+/* Network input from raw features: X[c][f] = bf16((T(x) - mean[f]) / std[f])
+ * with T(x) = log10(max(x + logfloor[f], 1e-30)) where logfloor[f] > 0 and
+ * T(x) = x where logfloor[f] == 0.
+ *   Xraw [n_cols][n_in] float32; mean, std, logfloor [n_in] float32;
+ *   X [n_cols][n_in] bfloat16 output.  All device pointers. */
+rt_status sg_standardize(sg_net net, const float *Xraw, const float *mean, const float *std, const float *logfloor,
+                         int32_t n_cols, uint16_t *X);
+
+/* Replace the tracer's drag in trusted columns by the surrogate's: for every
+ * column c with mask[c] = 1 and output o = comp*nz + k (n_out must equal
+ * 2*nz), drag[o][c] = mean over members of (Yens[m][c][o] * std[o] + mean[o]).
+ * Untrusted columns are left as they are.
+ *   Yens [n_members][n_cols][n_out] float32; mean, std [n_out] float32;
+ *   mask [n_cols] uint8; drag [2][nz][n_cols] float64 (the layout of
+ *   rt_deposit_flux's drag, columns j*nx + i).  All device pointers. */
+rt_status sg_apply_drag(sg_net net, const float *Yens, const float *mean, const float *std, const uint8_t *mask,
+                        int32_t n_cols, int32_t nz, double *drag);
 
 /* Message of the last failed call on this net (static storage of the net). */
 const char *sg_last_error(sg_net net);

@@ -149,9 +149,19 @@ def gate(Yens, Xraw, fmin, fmax, tau: float):
 
 
 def standardize(Xraw, mean, std, logfloor):
-    """Network input: (T(x) - mean) / std with T(x) = log10(x + floor) where
-    floor > 0, identity where floor == 0."""
+    """Network input: (T(x) - mean) / std with T(x) = log10(max(x + floor,
+    1e-30)) where floor > 0, identity where floor == 0."""
     X = np.asarray(Xraw, dtype=np.float64)
     fl = np.asarray(logfloor, dtype=np.float64)
-    T = np.where(fl > 0, np.log10(np.maximum(X + fl, 1e-300)), X)
+    T = np.where(fl > 0, np.log10(np.maximum(X + fl, 1e-30)), X)
     return (T - mean) / std
+
+
+def apply_drag(Yens, mean, std, mask, drag):
+    """drag [2*nz][n_cols] with trusted columns replaced by the ensemble mean
+    of Y * std + mean (outputs o = comp*nz + k)."""
+    Y = np.asarray(Yens, dtype=np.float64) * np.asarray(std, np.float64) + np.asarray(mean, np.float64)
+    out = np.array(drag, dtype=np.float64, copy=True)
+    sel = np.asarray(mask).astype(bool)
+    out[:, sel] = Y.mean(axis=0)[sel].T
+    return out

@@ -20,7 +20,7 @@ RT_OK, RT_E_ARG, RT_E_STATE, RT_E_NOMEM, RT_E_CAPACITY, RT_E_DEVICE, RT_E_NUMERI
 RT_CARTESIAN, RT_SPHERICAL = 0, 1
 RT_FP64, RT_FP32 = 0, 1
 RT_HOST, RT_DEVICE = 0, 1
-RT_STEP_DEPOSIT = 1
+RT_STEP_DEPOSIT, RT_STEP_SURROGATE = 1, 2
 RT_MERGE, RT_CAP, RT_SPLIT_ONLY = 0, 1, 2
 
 RAY_FIELDS = ("x", "y", "z", "k", "l", "m", "dx", "dy", "dz", "px", "py", "pz", "n")
@@ -79,10 +79,13 @@ def lib() -> C.CDLL:
         L.rt_get_columns.argtypes = [P, P, C.POINTER(I64), I32]
         L.rt_profile.argtypes = [P, I32]
         L.rt_profile_read.argtypes = [P, P, P]
+        L.rt_features.argtypes = [P, P, I32]
+        L.rt_set_frozen_columns.argtypes = [P, P, I32]
         L.rt_last_error.argtypes = [P]
         L.rt_last_error.restype = C.c_char_p
         for name in ("rt_create", "rt_destroy", "rt_init_background", "rt_set_rays", "rt_get_rays", "rt_step",
-                     "rt_deposit_flux", "rt_split_merge", "rt_get_stats", "rt_profile", "rt_profile_read", "rt_get_columns"):
+                     "rt_deposit_flux", "rt_split_merge", "rt_get_stats", "rt_profile", "rt_profile_read", "rt_get_columns",
+                     "rt_features", "rt_set_frozen_columns"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -224,8 +227,38 @@ class Tracer:
         self._check(lib().rt_get_columns(self.h, out.ctypes.data, C.byref(n2), RT_HOST))
         return out[: n2.value]
 
-    def step(self, dt: float, deposit: bool = False):
-        self._check(lib().rt_step(self.h, float(dt), RT_STEP_DEPOSIT if deposit else 0))
+    def step(self, dt: float, deposit: bool = False, surrogate: bool = False):
+        flags = (RT_STEP_DEPOSIT if deposit else 0) | (RT_STEP_SURROGATE if surrogate else 0)
+        self._check(lib().rt_step(self.h, float(dt), flags))
+
+    def set_frozen_columns(self, mask=None):
+        """Column flags [ny*nx] (uint8, 1 = frozen) for step(surrogate=True):
+        a numpy array or a CUDA tensor; None clears them."""
+        torch = self.torch
+        if mask is None:
+            self._check(lib().rt_set_frozen_columns(self.h, None, RT_DEVICE))
+        elif isinstance(mask, torch.Tensor):
+            m = mask.to(device=self.device, dtype=torch.uint8).contiguous()
+            assert m.numel() == self.nx * self.ny
+            self._check(lib().rt_set_frozen_columns(self.h, m.data_ptr(), RT_DEVICE))
+            self._frozen_ref = m  # alive until the stream has copied it
+        else:
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            assert m.size == self.nx * self.ny
+            self._check(lib().rt_set_frozen_columns(self.h, m.ctypes.data, RT_HOST))
+
+    def features(self, out=None, host: bool = False):
+        """Surrogate input features [ny*nx][3*nz + 32] float32 of the current
+        state: a CUDA tensor, or a numpy array with host=True."""
+        torch = self.torch
+        shape = (self.nx * self.ny, 3 * self.nz + 32)
+        if host:
+            X = np.zeros(shape, np.float32) if out is None else out
+            self._check(lib().rt_features(self.h, X.ctypes.data, RT_HOST))
+            return X
+        X = torch.empty(shape, dtype=torch.float32, device=self.device) if out is None else out
+        self._check(lib().rt_features(self.h, X.data_ptr(), RT_DEVICE))
+        return X
 
     def deposit(self, flux=None, drag=None, host: bool = False):
         """Returns (flux [6, nz+1, ny, nx], drag [2, nz, ny, nx]) float64: CUDA

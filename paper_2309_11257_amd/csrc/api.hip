@@ -264,6 +264,7 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     ALLOC(ctx->colstart, uint32_t, (int64_t)g.ncol + 1);
     ALLOC(ctx->flux, double, (int64_t)6 * (g.nz + 1) * g.ncol);
     ALLOC(ctx->drag, double, 2 * cells);
+    ALLOC(ctx->frozen, uint8_t, g.ncol);
     ALLOC(ctx->dc, DevCounters, 1);
     ALLOC(ctx->red, double, 8 + 4 * (cap / 256 + 2));
     ALLOC(ctx->ired, int64_t, 8 + 2 * cap);
@@ -446,20 +447,68 @@ extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
     if (!ctx->have_bg) return rt_fail(ctx, RT_E_STATE, "rt_init_background has not been called");
     if (!ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "rt_set_rays has not been called");
     if (!std::isfinite(dt)) return rt_fail(ctx, RT_E_ARG, "dt must be finite");
+    if (flags & ~(RT_STEP_DEPOSIT | RT_STEP_SURROGATE)) return rt_fail(ctx, RT_E_ARG, "unknown rt_step flags");
+    if ((flags & RT_STEP_SURROGATE) && !ctx->have_frozen)
+        return rt_fail(ctx, RT_E_STATE, "RT_STEP_SURROGATE needs rt_set_frozen_columns first");
+    const uint8_t *frozen = (flags & RT_STEP_SURROGATE) ? ctx->frozen : nullptr;
     const int nxt = 1 - ctx->cur;
     prof_begin(ctx, PC_STEP);
     if (ctx->precision == RT_FP64)
         launch_step64(ctx->g, ctx->bp64, ctx->s64[ctx->cur], ctx->s64[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
-                      ctx->n_bound, dt, ctx->stream);
+                      ctx->n_bound, dt, frozen, ctx->skeys, ctx->stream);
     else
         launch_step32(ctx->g, ctx->bp32, ctx->s32[ctx->cur], ctx->s32[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
-                      ctx->n_bound, dt, ctx->stream);
+                      ctx->n_bound, dt, frozen, ctx->skeys, ctx->stream);
     prof_end(ctx);
     launch_sorted_from_active(ctx->dc, ctx->stream);
     ctx->cur = nxt;
     rt_status st = sort_current(ctx);
     if (st) return st;
     if (flags & RT_STEP_DEPOSIT) return rt_deposit_flux(ctx, nullptr, nullptr, RT_DEVICE);
+    return RT_OK;
+}
+
+extern "C" rt_status rt_features(rt_ctx ctx, float *X, int32_t where)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!X) return rt_fail(ctx, RT_E_ARG, "X is required");
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
+    const Grid &g = ctx->g;
+    const size_t n = (size_t)g.ncol * (size_t)(3 * g.nz + 32);
+    float *dst = X;
+    void *staged = nullptr;
+    if (where == RT_HOST) {
+        staged = ctx_alloc(ctx, sizeof(float) * n);
+        if (!staged) return rt_fail(ctx, RT_E_NOMEM, "no device memory for the feature matrix");
+        dst = (float *)staged;
+    }
+    if (ctx->precision == RT_FP64)
+        launch_features64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, dst, ctx->stream);
+    else
+        launch_features32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, dst, ctx->stream);
+    HIP_OK(hipGetLastError());
+    if (staged) {
+        HIP_OK(hipMemcpyAsync(X, dst, sizeof(float) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        unstage(ctx, staged);
+    }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_set_frozen_columns(rt_ctx ctx, const uint8_t *mask, int32_t where)
+{
+    if (!ctx) return RT_E_ARG;
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    const size_t n = (size_t)ctx->g.ncol;
+    if (!mask) {
+        HIP_OK(hipMemsetAsync(ctx->frozen, 0, n, ctx->stream));
+    } else {
+        HIP_OK(hipMemcpyAsync(ctx->frozen, mask, n, where == RT_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                              ctx->stream));
+        if (where == RT_HOST) HIP_OK(hipStreamSynchronize(ctx->stream));
+    }
+    ctx->have_frozen = true;
     return RT_OK;
 }
 

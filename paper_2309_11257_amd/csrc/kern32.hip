@@ -13,6 +13,7 @@
 // double, and every flux sum is accumulated in double.
 #include "dev64.h"
 #include "deposit_common.h"
+#include "features_common.h"
 
 namespace f32 {
 
@@ -276,7 +277,8 @@ using f32::G32;
 template <bool SPH>
 __global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
                                                    uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc,
-                                                   float dt)
+                                                   float dt, const uint8_t *__restrict__ frozen,
+                                                   const uint32_t *__restrict__ skeys)
 {
     const int64_t i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= dc->n_active) return;
@@ -290,8 +292,10 @@ __global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src,
     const float A[3] = {0.0f, -5.0f / 9.0f, -153.0f / 128.0f};
     const float B[3] = {1.0f / 3.0f, 15.0f / 16.0f, 8.0f / 15.0f};
     const float phi0 = g.y0 + (float)jc * g.dyr;
+    // volumes in columns handed to the surrogate keep their state this step
+    const int nst = (frozen && frozen[skeys[i]]) ? 0 : 3;
 #pragma unroll 1
-    for (int st = 0; st < 3; st++) {
+    for (int st = 0; st < nst; st++) {
         f32::rhs<SPH>(g, b, ic, jc, kc0, phi0, Y, F);
 #pragma unroll
         for (int c = 0; c < 9; c++) {
@@ -373,15 +377,16 @@ __global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src,
 }
 
 void launch_step32(const Grid &g, const BgP<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
-                   const DevCounters *dc, int64_t bound, double dt, hipStream_t s)
+                   const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
+                   hipStream_t s)
 {
     if (bound <= 0) return;
     const unsigned nb = (unsigned)((bound + 255) / 256);
     const G32 h = f32::make_g32(g);
     if (g.geometry == RT_SPHERICAL)
-        k_step32<true><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt);
+        k_step32<true><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
     else
-        k_step32<false><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt);
+        k_step32<false><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
 }
 
 // ---------------------------------------------------------------------------
@@ -600,6 +605,34 @@ struct Pay32 {
         zb = zc - 0.5 * (double)Dz;
         zt = zc + 0.5 * (double)Dz;
     }
+    // spectral state, wave action and intrinsic vertical group velocity at
+    // the carrier (surrogate features)
+    __device__ void spec(uint32_t s, double &kd, double &ld, double &md, double &W, double &cgz) const
+    {
+        const uint32_t col = st.col[s];
+        const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
+        f32::Cell c;
+        f32::locate(g, ic, jc, st.lev[s], st.xi[s], st.eta[s], st.zeta[s], c);
+        const float4 Ac = f32::tri4<1>(b.A, c, 0);
+        const float k = st.k[s], l = st.l[s], m = st.m[s];
+        const float kh2 = k * k + l * l;
+        const float m2 = m * m;
+        const float K2 = kh2 + m2;
+        const float om = sqrtf((Ac.z * kh2 + Ac.w * m2) / K2);
+        const float sc = (Ac.z - Ac.w) / (K2 * K2) / om;
+        kd = k;
+        ld = l;
+        md = m;
+        W = st.W[s];
+        cgz = (double)(-m * kh2 * sc);
+    }
+    __device__ void profile(int col, int k, double &u, double &v, double &n2) const
+    {
+        const float4 a = b.A[(int64_t)col * g.nz + k];
+        u = a.x;
+        v = a.y;
+        n2 = a.z;
+    }
 };
 
 void launch_deposit32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
@@ -607,4 +640,11 @@ void launch_deposit32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t
 {
     Pay32 p{f32::make_g32(g), b, st, g.dz};
     k_deposit<Pay32><<<(unsigned)g.ncol, 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
+}
+
+void launch_features32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+                       float *X, hipStream_t s)
+{
+    Pay32 p{f32::make_g32(g), b, st, g.dz};
+    k_features<Pay32><<<(unsigned)g.ncol, 256, 0, s>>>(g, p, perm, colstart, X);
 }

@@ -2,6 +2,7 @@
 // removal tallies, diagnostics and the per-ray deposition payload.
 // Built with -ffp-contract=off (see dev64.h).
 #include "deposit_common.h"
+#include "features_common.h"
 #include "dev64.h"
 
 // ---------------------------------------------------------------------------
@@ -205,7 +206,8 @@ void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCount
 // ---------------------------------------------------------------------------
 template <bool SPH>
 __global__ __launch_bounds__(256, 2) void k_step64(Grid g, BgP<double> b, S64 src, S64 dst, const uint32_t *__restrict__ perm,
-                                                uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc, double dt)
+                                                uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc, double dt,
+                                                const uint8_t *__restrict__ frozen, const uint32_t *__restrict__ skeys)
 {
     const int64_t i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= dc->n_active) return;
@@ -215,8 +217,10 @@ __global__ __launch_bounds__(256, 2) void k_step64(Grid g, BgP<double> b, S64 sr
     double F[9];
     const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
     const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    // volumes in columns handed to the surrogate keep their state this step
+    const int nst = (frozen && frozen[skeys[i]]) ? 0 : 3;
 #pragma unroll 1
-    for (int st = 0; st < 3; st++) {
+    for (int st = 0; st < nst; st++) {
         d64::rhs<SPH>(g, b, Y, F);
 #pragma unroll
         for (int c = 0; c < 9; c++) {
@@ -243,14 +247,15 @@ __global__ __launch_bounds__(256, 2) void k_step64(Grid g, BgP<double> b, S64 sr
 }
 
 void launch_step64(const Grid &g, const BgP<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
-                   const DevCounters *dc, int64_t bound, double dt, hipStream_t s)
+                   const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
+                   hipStream_t s)
 {
     if (bound <= 0) return;
     const unsigned nb = (unsigned)((bound + 255) / 256);
     if (g.geometry == RT_SPHERICAL)
-        k_step64<true><<<nb, 256, 0, s>>>(g, b, src, dst, perm, key_out, dc, dt);
+        k_step64<true><<<nb, 256, 0, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
     else
-        k_step64<false><<<nb, 256, 0, s>>>(g, b, src, dst, perm, key_out, dc, dt);
+        k_step64<false><<<nb, 256, 0, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
 }
 
 // ---------------------------------------------------------------------------
@@ -383,6 +388,31 @@ struct Pay64 {
         zb = z - 0.5 * Dz;
         zt = z + 0.5 * Dz;
     }
+    // spectral state, wave action and intrinsic vertical group velocity at
+    // the carrier (surrogate features)
+    __device__ void spec(uint32_t s, double &k, double &l, double &m, double &W, double &cgz) const
+    {
+        k = st.k[s];
+        l = st.l[s];
+        m = st.m[s];
+        W = W64(st, s);
+        d64::Cell c;
+        d64::locate(g, st.x[s], st.y[s], st.z[s], c);
+        const double4 Ac = d64::tri4<1>(b.A, c, 0);
+        const double N2 = Ac.z, f2 = Ac.w;
+        const double kh2 = k * k + l * l;
+        const double m2 = m * m;
+        const double K2 = kh2 + m2;
+        const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
+        cgz = -(((m * kh2) * (N2 - f2)) / (om * (K2 * K2)));
+    }
+    __device__ void profile(int col, int k, double &u, double &v, double &n2) const
+    {
+        const double4 a = b.A[(int64_t)col * g.nz + k];
+        u = a.x;
+        v = a.y;
+        n2 = a.z;
+    }
 };
 
 void launch_deposit64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
@@ -390,4 +420,11 @@ void launch_deposit64(const Grid &g, const BgP<double> &b, S64 st, const uint32_
 {
     Pay64 p{g, b, st};
     k_deposit<Pay64><<<(unsigned)g.ncol, 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
+}
+
+void launch_features64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+                       float *X, hipStream_t s)
+{
+    Pay64 p{g, b, st};
+    k_features<Pay64><<<(unsigned)g.ncol, 256, 0, s>>>(g, p, perm, colstart, X);
 }

@@ -59,8 +59,8 @@ __device__ inline float dgelu_t(float z)
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
 {
-    __shared__ bf16 sA[GBM][GBK + GPAD];
-    __shared__ bf16 sB[GBN][GBK + GPAD];
+    __shared__ __attribute__((aligned(16))) bf16 sA[GBM][GBK + GPAD];
+    __shared__ __attribute__((aligned(16))) bf16 sB[GBN][GBK + GPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int bm = blockIdx.x * GBM, bn = blockIdx.y * GBN;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -248,14 +248,38 @@ __global__ void k_gate(const float *Y, const float *X, const float *fmin, const 
         }
         s2 += nm > 1 ? v / (nm - 1) : 0.0;
     }
-    const float sp = (float)sqrt(s2 / nout);
+    const double sp = sqrt(s2 / nout);
     bool inside = true;
     for (int f = 0; f < nin; f++) {
         const float x = X[(int64_t)c * nin + f];
         inside = inside && x >= fmin[f] && x <= fmax[f];
     }
-    if (spread) spread[c] = sp;
-    mask[c] = (inside && sp <= tau) ? 1 : 0;
+    if (spread) spread[c] = (float)sp;
+    mask[c] = (inside && sp <= (double)tau) ? 1 : 0;
+}
+
+__global__ void k_standardize(const float *X, const float *mean, const float *std, const float *lg, int64_t n,
+                              int nin, bf16 *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int f = (int)(i % nin);
+    float x = X[i];
+    if (lg[f] > 0.0f) x = log10f(fmaxf(x + lg[f], 1e-30f));
+    out[i] = (bf16)((x - mean[f]) / std[f]);
+}
+
+// drag[o][c] <- ensemble mean of de-standardised outputs where mask[c]
+__global__ void k_apply_drag(const float *Y, const float *mean, const float *std, const uint8_t *mask, int nm, int nc,
+                             int nout, double *drag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nc * nout) return;
+    const int c = (int)(i % nc), o = (int)(i / nc);
+    if (!mask[c]) return;
+    double s = 0.0;
+    for (int m = 0; m < nm; m++) s += (double)Y[((int64_t)m * nc + c) * nout + o] * std[o] + mean[o];
+    drag[i] = s / nm;
 }
 
 // ---------------------------------------------------------------------------
@@ -603,6 +627,32 @@ extern "C" rt_status sg_gate(sg_net n, const float *Yens, const float *Xraw, con
     if (n_cols == 0) return RT_OK;
     k_gate<<<nblk(n_cols), 256, 0, n->stream>>>(Yens, Xraw, fmin, fmax, n->cfg.n_members, n_cols, n->cfg.n_out,
                                                 n->cfg.n_in, tau, spread, mask);
+    SG_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status sg_standardize(sg_net n, const float *Xraw, const float *mean, const float *std,
+                                    const float *logfloor, int32_t n_cols, uint16_t *X)
+{
+    if (!n || !Xraw || !mean || !std || !logfloor || !X || n_cols < 0)
+        return sg_fail(n, RT_E_ARG, "bad sg_standardize arguments");
+    const int64_t tot = (int64_t)n_cols * n->cfg.n_in;
+    if (tot == 0) return RT_OK;
+    k_standardize<<<nblk(tot), 256, 0, n->stream>>>(Xraw, mean, std, logfloor, tot, n->cfg.n_in, (bf16 *)X);
+    SG_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status sg_apply_drag(sg_net n, const float *Yens, const float *mean, const float *std,
+                                   const uint8_t *mask, int32_t n_cols, int32_t nz, double *drag)
+{
+    if (!n || !Yens || !mean || !std || !mask || !drag || n_cols < 0)
+        return sg_fail(n, RT_E_ARG, "bad sg_apply_drag arguments");
+    if (nz < 1 || 2 * nz != n->cfg.n_out) return sg_fail(n, RT_E_ARG, "n_out must equal 2*nz");
+    const int64_t tot = (int64_t)n_cols * n->cfg.n_out;
+    if (tot == 0) return RT_OK;
+    k_apply_drag<<<nblk(tot), 256, 0, n->stream>>>(Yens, mean, std, mask, n->cfg.n_members, n_cols, n->cfg.n_out,
+                                                    drag);
     SG_HIP(hipGetLastError());
     return RT_OK;
 }

@@ -105,6 +105,9 @@ struct rt_ctx_s {
     int64_t hist_len;
     // flux scratch
     double *flux, *drag;
+    // per-column flags: 1 = the surrogate owns the column this step
+    uint8_t *frozen;
+    bool have_frozen;
     // counters
     DevCounters *dc;
     double *red;      // reduction scratch
@@ -160,9 +163,15 @@ void launch_store32(const Grid &g, S32 src, const uint32_t *perm, const DevCount
                     int64_t bound, hipStream_t s);
 
 void launch_step64(const Grid &g, const BgP<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
-                   const DevCounters *dc, int64_t bound, double dt, hipStream_t s);
+                   const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
+                   hipStream_t s);
 void launch_step32(const Grid &g, const BgP<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
-                   const DevCounters *dc, int64_t bound, double dt, hipStream_t s);
+                   const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
+                   hipStream_t s);
+void launch_features64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+                       float *X, hipStream_t s);
+void launch_features32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+                       float *X, hipStream_t s);
 
 // stable LSD radix sort of keys[0..*n) with 32-bit payload (identity if vals == NULL)
 void radix_sort(const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out, uint32_t *vals_out,
