@@ -157,6 +157,82 @@ def drag_errors(orc_state, run):
     return {"aligned": aligned, "raw": raw, "column_flips": flips, "active_set_flips": nset}
 
 
+def surrogate_report(log_rays=50_000_000, steps=100):
+    """The learned column surrogate with the tracer as fallback, on the global
+    grid with 50 M ray volumes: trained on tracer runs over perturbed global
+    backgrounds, then run coupled for `steps` steps at several gate
+    thresholds; drag error of every variant against the FP64 tracer after
+    the run, and time per step against the plain FP32 tracer."""
+    import numpy as np
+    import torch
+
+    from paper_2309_11257_amd import _rt
+    from paper_2309_11257_amd import surrogate as S
+    from paper_2309_11257_amd import workloads as W
+    t0 = time.perf_counter()
+    feats, drags = S.training_runs(4, 5_000_000, nx=360, ny=180, steps=60, every=20, spin=0)
+    hf, hd = S.training_runs(1, 5_000_000, nx=360, ny=180, steps=60, every=20, spin=0, first=4)
+    sur = S.ColumnSurrogate(120, n_members=4, max_batch=360 * 180, seed=11)
+    X, T = S.dataset(sur, feats, drags, fit=True)
+    Xh, Th = S.dataset(sur, hf, hd, fit=False)
+    del feats, drags, hf, hd
+    t1 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    sur.train(X, T, epochs=2, batch=4096, lr=1e-3)
+    ev1.record()
+    torch.cuda.synchronize()
+    train_ms = ev0.elapsed_time(ev1)
+    n_train_steps = 4 * 2 * (X.shape[0] // 4096)
+    Y = sur.predict(Xh).mean(dim=0).cpu().numpy().astype(np.float64)
+    Tn = Th.cpu().numpy().astype(np.float64)
+    zero = -sur.norm.y_mean / sur.norm.y_std
+    training = {"samples": int(X.shape[0]), "members": 4, "adam_steps": n_train_steps,
+                "train_ms_per_adam_step": round(train_ms / n_train_steps, 4),
+                "heldout_mse_network": round(float(np.mean((Y - Tn) ** 2)), 4),
+                "heldout_mse_climatology": round(float(np.mean(Tn ** 2)), 4),
+                "heldout_mse_zero_drag": round(float(np.mean((zero[None, :] - Tn) ** 2)), 4),
+                "data_and_setup_s": round(t1 - t0, 1)}
+    del X, T, Xh, Th
+    log(f"surrogate training: {training}")
+
+    w = W.make_c5(n_rays=log_rays, steps=steps)
+    ms64, ref = S.plain_run(w, steps, _rt.RT_FP64)
+    ref = ref.cpu().numpy()
+    ms32, d32 = S.plain_run(w, steps, _rt.RT_FP32)
+    err32 = rel_l2(d32.cpu().numpy(), ref)
+    # gate thresholds from the spread distribution of the initial state
+    tr = _rt.Tracer.for_workload(w, _rt.RT_FP32)
+    tr.init_background_from(w)
+    tr.set_rays(w.rays)
+    tr.step(w.dt)
+    Xraw = tr.features()
+    sp, inside = sur.gate(sur.predict(sur.inputs(Xraw)), Xraw, 1e30)
+    tr.close()
+    spn = sp.cpu().numpy()[inside.cpu().numpy() > 0]
+    taus = [0.0] + ([float(np.quantile(spn, q)) for q in (0.25, 0.5, 0.9)] if spn.size else [])
+    rows = []
+    for tau in taus:
+        row = {"tau": tau}
+        for mode in ("surrogate", "persistence", "zero"):
+            if tau == 0.0 and mode != "surrogate":
+                continue
+            res, _ = S.coupled_run(w, sur, tau, steps, mode=mode)
+            e = rel_l2(res.drag.cpu().numpy(), ref)
+            if mode == "surrogate":
+                row.update(trusted_fraction=round(res.trusted_fraction, 4), ms_per_step=round(res.ms_per_step, 4),
+                           speedup_vs_plain_fp32=round(ms32 / res.ms_per_step, 3), drag_rel_l2=e)
+            else:
+                row[f"{mode}_drag_rel_l2"] = e
+        rows.append(row)
+        log(f"surrogate coupled: {row}")
+    sur.close()
+    return {"workload": f"global 360x180x120, {w.n_rays} ray volumes, {steps} steps of {w.dt:g} s",
+            "reference": "FP64 tracer on the GPU (bitwise the CPU oracle on Cartesian grids, within 1e-13 on the sphere)",
+            "training": training, "plain_fp32": {"ms_per_step": round(ms32, 4), "drag_rel_l2": err32},
+            "plain_fp64_ms_per_step": round(ms64, 4), "coupled": rows}
+
+
 def load_traffic(kernel, rays):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source."""
@@ -180,6 +256,8 @@ def main():
     ap.add_argument("--rays", type=int, default=20_000_000, help="ray volumes (default: the full workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and the oracle drag error")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="also train the column surrogate and run it coupled with the tracer on 50 M volumes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -277,6 +355,11 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if args.surrogate:
+        try:
+            out["surrogate"] = surrogate_report()
+        except Exception as e:  # report, do not lose the line
+            out["surrogate"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 

@@ -157,14 +157,16 @@ rt_status rt_set_frozen_columns(rt_ctx ctx, const uint8_t *mask, int32_t where);
 
 /* Input features of the column surrogate from the current state (the
  * quantities the flux projection of Section 3b reads, summarised per column):
- *   X [ny*nx][3*nz + 32] float32, row j*nx + i:
+ *   X [ny*nx][3*nz + 48] float32, row j*nx + i:
  *     U, V, N2 at the column's cell centres (levels 0..nz-1);
  *     for each azimuth sector s = 0..7 of the horizontal wavevector (sector s
  *     centred on azimuth 45 s degrees, boundaries at 22.5 + 45 n degrees,
  *     decided by comparing |l| with tan(22.5 deg) |k| and |k| with
- *     tan(22.5 deg) |l|): sum of W, sum of |cg_z| k_h W (cg_z the intrinsic
- *     vertical group velocity at the carrier, Section 2a), W-weighted mean of
- *     log10 k_h and of log10 |m| (0 for an empty sector); W = N Px Py Pz.
+ *     tan(22.5 deg) |l|), six moments: sum of W, sum of |cg_z| k_h W (cg_z
+ *     the intrinsic vertical group velocity at the carrier, Section 2a), the
+ *     W-weighted means of log10 k_h, log10 |m| and the carrier height z, and
+ *     the W-weighted standard deviation of z (0 for an empty sector);
+ *     W = N Px Py Pz.
  * Sums are accumulated in double in a fixed order.  No synchronisation
  * unless where == RT_HOST. */
 rt_status rt_features(rt_ctx ctx, float *X, int32_t where);

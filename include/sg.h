@@ -99,6 +99,13 @@ rt_status sg_gate(sg_net net, const float *Yens, const float *Xraw, const float 
 rt_status sg_standardize(sg_net net, const float *Xraw, const float *mean, const float *std, const float *logfloor,
                          int32_t n_cols, uint16_t *X);
 
+/* Training targets from the tracer's drag: T[c][o] = (drag[o][c] - mean[o]) /
+ * std[o] for outputs o = comp*nz + k (n_out must equal 2*nz).
+ *   drag [2][nz][n_cols] float64 (rt_deposit_flux layout); mean, std [n_out]
+ *   float32; T [n_cols][n_out] float32 output.  All device pointers. */
+rt_status sg_targets(sg_net net, const double *drag, const float *mean, const float *std, int32_t n_cols, int32_t nz,
+                     float *T);
+
 /* Replace the tracer's drag in trusted columns by the surrogate's: for every
  * column c with mask[c] = 1 and output o = comp*nz + k (n_out must equal
  * 2*nz), drag[o][c] = mean over members of (Yens[m][c][o] * std[o] + mean[o]).

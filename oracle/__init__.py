@@ -254,7 +254,7 @@ def stats(rs: RaySet) -> dict:
 
 
 def features(bg: Background, rs: RaySet, cols: Optional[np.ndarray] = None) -> np.ndarray:
-    """Surrogate input features [nx*ny][3*nz + 32] of the current state
+    """Surrogate input features [nx*ny][3*nz + 48] of the current state
     (background profiles and per-sector ray-spectrum moments, see
     orc_features).  `cols` as in deposit()."""
     if cols is None:
@@ -263,7 +263,7 @@ def features(bg: Background, rs: RaySet, cols: Optional[np.ndarray] = None) -> n
         cols = np.asarray(cols, dtype=np.int32)
         assert cols.shape == (rs.n,)
         rs.a["col"][: rs.n] = cols
-    X = np.zeros((bg.nx * bg.ny, 3 * bg.nz + 32))
+    X = np.zeros((bg.nx * bg.ny, 3 * bg.nz + 48))
     lib().orc_features(bg.ref, rs.ref, rs.n, _ptr(X))
     return X
 

@@ -1009,13 +1009,14 @@ void orc_stats(const orc_rays *r, int64_t n, orc_tally *t)
 /* ------------------------------------------------------------------------
  * Column features of the surrogate (no counterpart in the paper; they
  * summarise the ray-volume state that the flux projection of Section 3b
- * reads).  Row c =
- * j*nx + i of X [ncol][3*nz + 32]:
+ * reads).  Row c = j*nx + i of X [ncol][3*nz + 48]:
  *   U, V, N2 at the column's cell centres, levels 0..nz-1;
  *   for each of 8 azimuth sectors s (centred on the directions s*45 degrees
- *   of the horizontal wavevector, boundaries at 22.5 + 45 n degrees):
- *   sum W, sum |cg_z| k_h W, W-weighted mean log10 k_h, W-weighted mean
- *   log10 |m|  (means 0 for an empty sector),
+ *   of the horizontal wavevector, boundaries at 22.5 + 45 n degrees), six
+ *   moments: sum W, sum |cg_z| k_h W, and the W-weighted means of log10 k_h,
+ *   log10 |m| and the carrier height z, and the W-weighted standard deviation
+ *   of z (sqrt of mean z^2 - mean^2, floored at 0); the means and the
+ *   deviation are 0 for an empty sector;
  * over the active rays whose carrier lies in the column (col[] must hold the
  * keys), summed in ascending index.  cg_z is the intrinsic vertical group
  * velocity at the carrier (Section 2a), W = N Px Py Pz the wave action of
@@ -1035,7 +1036,7 @@ static int azimuth_sector(double k, double l)
 
 void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X)
 {
-    int ncol = g->nx * g->ny, nf = 3 * g->nz + 32;
+    int ncol = g->nx * g->ny, nf = 3 * g->nz + 48;
     int c, k, s;
     int64_t i;
     memset(X, 0, sizeof(double) * (size_t)ncol * (size_t)nf);
@@ -1049,28 +1050,38 @@ void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X)
         }
     }
     for (i = 0; i < n; i++) {
-        double B[14], D[4], W, kh, *mom;
+        double B[14], D[4], W, kh, z, *mom;
         if (r->state[i] != ORC_ACTIVE) continue;
         orc_interp(g, r->x[i], r->y[i], r->z[i], B);
         orc_dispersion(B[2], B[12], r->k[i], r->l[i], r->m[i], D);
         W = ray_W(r, i);
         kh = sqrt(r->k[i] * r->k[i] + r->l[i] * r->l[i]);
+        z = r->z[i];
         s = azimuth_sector(r->k[i], r->l[i]);
-        mom = X + (size_t)r->col[i] * (size_t)nf + 3 * g->nz + 4 * s;
+        mom = X + (size_t)r->col[i] * (size_t)nf + 3 * g->nz + 6 * s;
         mom[0] += W;
         mom[1] += fabs(D[3]) * kh * W;
         mom[2] += W * log10(kh);
         mom[3] += W * log10(fabs(r->m[i]));
+        mom[4] += W * z;
+        mom[5] += W * z * z;
     }
     for (c = 0; c < ncol; c++)
         for (s = 0; s < 8; s++) {
-            double *mom = X + (size_t)c * (size_t)nf + 3 * g->nz + 4 * s;
+            double *mom = X + (size_t)c * (size_t)nf + 3 * g->nz + 6 * s;
             if (mom[0] > 0.0) {
+                double zm, var;
                 mom[2] = mom[2] / mom[0];
                 mom[3] = mom[3] / mom[0];
+                zm = mom[4] / mom[0];
+                var = mom[5] / mom[0] - zm * zm;
+                mom[4] = zm;
+                mom[5] = var > 0.0 ? sqrt(var) : 0.0;
             } else {
                 mom[2] = 0.0;
                 mom[3] = 0.0;
+                mom[4] = 0.0;
+                mom[5] = 0.0;
             }
         }
 }

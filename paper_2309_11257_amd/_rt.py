@@ -248,10 +248,10 @@ class Tracer:
             self._check(lib().rt_set_frozen_columns(self.h, m.ctypes.data, RT_HOST))
 
     def features(self, out=None, host: bool = False):
-        """Surrogate input features [ny*nx][3*nz + 32] float32 of the current
+        """Surrogate input features [ny*nx][3*nz + 48] float32 of the current
         state: a CUDA tensor, or a numpy array with host=True."""
         torch = self.torch
-        shape = (self.nx * self.ny, 3 * self.nz + 32)
+        shape = (self.nx * self.ny, 3 * self.nz + 48)
         if host:
             X = np.zeros(shape, np.float32) if out is None else out
             self._check(lib().rt_features(self.h, X.ctypes.data, RT_HOST))

@@ -37,10 +37,11 @@ def lib() -> C.CDLL:
         L.sg_gate.argtypes = [P, P, P, P, P, I32, F, P, P]
         L.sg_standardize.argtypes = [P, P, P, P, P, I32, P]
         L.sg_apply_drag.argtypes = [P, P, P, P, P, I32, I32, P]
+        L.sg_targets.argtypes = [P, P, P, P, I32, I32, P]
         L.sg_last_error.argtypes = [P]
         L.sg_last_error.restype = C.c_char_p
         for n in ("sg_create", "sg_destroy", "sg_get_params", "sg_set_params", "sg_forward", "sg_train_step",
-                  "sg_gradient", "sg_gate", "sg_standardize", "sg_apply_drag"):
+                  "sg_gradient", "sg_gate", "sg_standardize", "sg_apply_drag", "sg_targets"):
             getattr(L, n).restype = C.c_int32
         _bound = True
     return L
@@ -179,3 +180,14 @@ class Surrogate:
         assert drag.is_cuda and drag.dtype == torch.float64 and drag.is_contiguous()
         self._check(lib().sg_apply_drag(self.h, Yd.data_ptr(), mu.data_ptr(), sd.data_ptr(), mk.data_ptr(),
                                         mk.shape[0], nz, drag.data_ptr()))
+
+    def targets(self, drag, mean, std, nz: int, out=None):
+        """Standardised training targets [n_cols][2*nz] float32 from a device
+        drag field [2][nz][n_cols] float64."""
+        torch = self.torch
+        assert drag.is_cuda and drag.dtype == torch.float64 and drag.is_contiguous()
+        n = drag.numel() // (2 * nz)
+        mu, sd = self._dev(mean, torch.float32), self._dev(std, torch.float32)
+        T = torch.empty((n, 2 * nz), dtype=torch.float32, device=self.device) if out is None else out
+        self._check(lib().sg_targets(self.h, drag.data_ptr(), mu.data_ptr(), sd.data_ptr(), n, nz, T.data_ptr()))
+        return T

@@ -475,7 +475,7 @@ extern "C" rt_status rt_features(rt_ctx ctx, float *X, int32_t where)
     if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
     if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
     const Grid &g = ctx->g;
-    const size_t n = (size_t)g.ncol * (size_t)(3 * g.nz + 32);
+    const size_t n = (size_t)g.ncol * (size_t)(3 * g.nz + 48);
     float *dst = X;
     void *staged = nullptr;
     if (where == RT_HOST) {

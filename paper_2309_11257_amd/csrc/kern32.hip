@@ -607,7 +607,7 @@ struct Pay32 {
     }
     // spectral state, wave action and intrinsic vertical group velocity at
     // the carrier (surrogate features)
-    __device__ void spec(uint32_t s, double &kd, double &ld, double &md, double &W, double &cgz) const
+    __device__ void spec(uint32_t s, double &kd, double &ld, double &md, double &W, double &cgz, double &z) const
     {
         const uint32_t col = st.col[s];
         const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
@@ -625,6 +625,7 @@ struct Pay32 {
         md = m;
         W = st.W[s];
         cgz = (double)(-m * kh2 * sc);
+        z = ((double)st.lev[s] + (double)st.zeta[s]) * zdz;
     }
     __device__ void profile(int col, int k, double &u, double &v, double &n2) const
     {

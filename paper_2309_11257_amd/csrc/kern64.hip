@@ -390,7 +390,7 @@ struct Pay64 {
     }
     // spectral state, wave action and intrinsic vertical group velocity at
     // the carrier (surrogate features)
-    __device__ void spec(uint32_t s, double &k, double &l, double &m, double &W, double &cgz) const
+    __device__ void spec(uint32_t s, double &k, double &l, double &m, double &W, double &cgz, double &z) const
     {
         k = st.k[s];
         l = st.l[s];
@@ -405,6 +405,7 @@ struct Pay64 {
         const double K2 = kh2 + m2;
         const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
         cgz = -(((m * kh2) * (N2 - f2)) / (om * (K2 * K2)));
+        z = st.z[s];
     }
     __device__ void profile(int col, int k, double &u, double &v, double &n2) const
     {

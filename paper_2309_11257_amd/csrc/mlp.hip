@@ -269,6 +269,16 @@ __global__ void k_standardize(const float *X, const float *mean, const float *st
     out[i] = (bf16)((x - mean[f]) / std[f]);
 }
 
+// T[c][o] = (drag[o][c] - mean[o]) / std[o]: one thread per (c, o), o fastest
+// so the writes are contiguous
+__global__ void k_targets(const double *drag, const float *mean, const float *std, int nc, int nout, float *T)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nc * nout) return;
+    const int o = (int)(i % nout), c = (int)(i / nout);
+    T[i] = (float)((drag[(int64_t)o * nc + c] - (double)mean[o]) / (double)std[o]);
+}
+
 // drag[o][c] <- ensemble mean of de-standardised outputs where mask[c]
 __global__ void k_apply_drag(const float *Y, const float *mean, const float *std, const uint8_t *mask, int nm, int nc,
                              int nout, double *drag)
@@ -653,6 +663,18 @@ extern "C" rt_status sg_apply_drag(sg_net n, const float *Yens, const float *mea
     if (tot == 0) return RT_OK;
     k_apply_drag<<<nblk(tot), 256, 0, n->stream>>>(Yens, mean, std, mask, n->cfg.n_members, n_cols, n->cfg.n_out,
                                                     drag);
+    SG_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" rt_status sg_targets(sg_net n, const double *drag, const float *mean, const float *std, int32_t n_cols,
+                                int32_t nz, float *T)
+{
+    if (!n || !drag || !mean || !std || !T || n_cols < 0) return sg_fail(n, RT_E_ARG, "bad sg_targets arguments");
+    if (nz < 1 || 2 * nz != n->cfg.n_out) return sg_fail(n, RT_E_ARG, "n_out must equal 2*nz");
+    const int64_t tot = (int64_t)n_cols * n->cfg.n_out;
+    if (tot == 0) return RT_OK;
+    k_targets<<<nblk(tot), 256, 0, n->stream>>>(drag, mean, std, n_cols, n->cfg.n_out, T);
     SG_HIP(hipGetLastError());
     return RT_OK;
 }

@@ -257,14 +257,18 @@ def make_global(name: str, seed: int, n_rays: int, nx: int = 360, ny: int = 180,
     # convective share: 40 clusters of 9x9 columns at |phi| < 25 deg, 10x the mean
     mean_per_col = n_rays / float(nx * ny)
     per_conv = max(1, int(round(10.0 * mean_per_col)))
-    n_clusters, side = 40, 9
-    if nx < 3 * side or ny < 3 * side:
-        n_clusters, side = 4, 3
+    # 40 clusters of 9 x 9 columns on the 1-degree grid; on coarser grids the
+    # clusters shrink with the grid so that they still cover 5 % of the columns
+    n_clusters, side = 40, max(1, int(round(9 * nx / 360.0)))
     jrows = np.nonzero(np.abs(phid) < 25.0)[0]
     jlo, jhi = int(jrows.min()), int(jrows.max()) - side + 1
     taken = np.zeros((ny, nx), dtype=bool)
     clusters = []
+    attempts = 0
     while len(clusters) < n_clusters:
+        attempts += 1
+        if attempts > 100000:
+            raise ValueError("convective clusters do not fit the tropical band of this grid")
         ci = int(g.integers(0, nx))
         cj = int(g.integers(jlo, max(jlo + 1, jhi + 1)))
         ii = (ci + np.arange(side)) % nx
@@ -360,6 +364,17 @@ def make_c3(seed: int = 3, n_rays: int = 20_000_000, **kw) -> Workload:
 def make_c5(seed: int = 5, n_rays: int = 50_000_000, **kw) -> Workload:
     kw.setdefault("steps", 100)
     return make_global("c5", seed, n_rays, **kw)
+
+
+def make_c4(run: int, n_rays: int = 5_000_000, nx: int = 360, ny: int = 180, steps: int = 200) -> Workload:
+    """Surrogate training run `run`: the global recipe with seed 4000 + run,
+    jet winds scaled by a seeded factor in [0.7, 1.3] and N^2 by one in
+    [0.85, 1.15], so that the training backgrounds bracket the global one."""
+    w = make_global(f"c4_{run}", 4000 + run, n_rays, nx=nx, ny=ny, steps=steps)
+    g = _rng(9000 + run)
+    w.U = w.U * g.uniform(0.7, 1.3)
+    w.N2 = w.N2 * g.uniform(0.85, 1.15)
+    return w
 
 
 def make(name: str, **kw) -> Workload:

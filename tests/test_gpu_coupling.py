@@ -36,9 +36,13 @@ def test_features_fp64_match_oracle(rt, orc, name):
     assert got.shape == ref.shape
     # profiles: the float32 rounding of the inputs
     assert np.array_equal(got[:, :3 * nz], ref[:, :3 * nz].astype(np.float32))
-    # moments: double sums in another order, rounded to float32
-    assert np.allclose(got[:, 3 * nz:], ref[:, 3 * nz:].astype(np.float32), rtol=4e-7, atol=0)
-    assert (ref[:, 3 * nz::4] > 0).sum() > 20
+    # moments: double sums in another order, rounded to float32; the height
+    # spread (one-pass variance) within its cancellation floor
+    g6 = got[:, 3 * nz:].reshape(-1, 8, 6)
+    r6 = ref[:, 3 * nz:].reshape(-1, 8, 6)
+    assert np.allclose(g6[:, :, :5], r6[:, :, :5].astype(np.float32), rtol=4e-7, atol=0)
+    assert np.allclose(g6[:, :, 5], r6[:, :, 5], rtol=1e-6, atol=1e-6 * 100e3)
+    assert (r6[:, :, 0] > 0).sum() > 20
     # the device entry point gives the same matrix
     assert np.array_equal(tr.features().cpu().numpy(), got)
     tr.close()

@@ -151,21 +151,24 @@ def test_standardize():
 
 def test_features_brute_force(orc):
     """Features against a per-ray Python loop that recomputes the sector by
-    arctangent and the intrinsic group velocity from the closed form."""
+    arctangent and the intrinsic group velocity from the closed form, and
+    the height spread by a two-pass variance."""
     from paper_2309_11257_amd import workloads as W
     w = W.make_c1(n_rays=600)
     bg = orc.Background.from_workload(w)
     rs = orc.RaySet(w.rays)
-    orc.step(bg, rs, w.dt)
+    for _ in range(20):
+        orc.step(bg, rs, w.dt)
     X = orc.features(bg, rs)
     nz = w.nz
-    assert X.shape == (w.nx * w.ny, 3 * nz + 32)
+    assert X.shape == (w.nx * w.ny, 3 * nz + 48)
     # profiles
     c = 37
     i, j = c % w.nx, c // w.nx
     assert np.array_equal(X[c, :nz], w.U[:, j, i])
     assert np.array_equal(X[c, 2 * nz:3 * nz], w.N2[:, j, i])
-    ref = np.zeros((w.nx * w.ny, 8, 4))
+    sums = np.zeros((w.nx * w.ny, 8, 4))
+    members = {}
     snap = rs.snapshot()
     f2 = w.f[0] ** 2
     for q in range(len(snap["id"])):
@@ -180,10 +183,24 @@ def test_features_brute_force(orc):
         Wq = snap["n"][q] * snap["px"][q] * snap["py"][q] * snap["pz"][q]
         col = snap["col"][q]
         kh = math.sqrt(kh2)
-        ref[col, s] += [Wq, abs(cgz) * kh * Wq, Wq * math.log10(kh), Wq * math.log10(abs(m))]
-    ok = ref[:, :, 0] > 0
-    ref[:, :, 2] = np.where(ok, ref[:, :, 2] / np.where(ok, ref[:, :, 0], 1), 0)
-    ref[:, :, 3] = np.where(ok, ref[:, :, 3] / np.where(ok, ref[:, :, 0], 1), 0)
-    got = X[:, 3 * nz:].reshape(-1, 8, 4)
-    assert np.allclose(got, ref, rtol=1e-12, atol=0)
+        sums[col, s] += [Wq, abs(cgz) * kh * Wq, Wq * math.log10(kh), Wq * math.log10(abs(m))]
+        members.setdefault((col, s), []).append((Wq, snap["z"][q]))
+    got = X[:, 3 * nz:].reshape(-1, 8, 6)
+    ok = sums[:, :, 0] > 0
+    den = np.where(ok, sums[:, :, 0], 1)
+    assert np.allclose(got[:, :, 0], sums[:, :, 0], rtol=1e-12, atol=0)
+    assert np.allclose(got[:, :, 1], sums[:, :, 1], rtol=1e-12, atol=0)
+    assert np.allclose(got[:, :, 2], np.where(ok, sums[:, :, 2] / den, 0), rtol=1e-12, atol=0)
+    assert np.allclose(got[:, :, 3], np.where(ok, sums[:, :, 3] / den, 0), rtol=1e-12, atol=0)
+    nspread = 0
+    for (col, s), lst in members.items():
+        wv = np.array([a for a, _ in lst])
+        zv = np.array([b for _, b in lst])
+        zm = (wv * zv).sum() / wv.sum()
+        sd = math.sqrt((wv * (zv - zm) ** 2).sum() / wv.sum())
+        assert got[col, s, 4] == pytest.approx(zm, rel=1e-12)
+        assert abs(got[col, s, 5] - sd) <= 1e-6 * zm  # one-pass variance: cancellation floor
+        nspread += len(lst) > 1 and sd > 1.0
+    assert nspread > 5
+    assert np.all(got[~ok] == 0)
     assert got[:, :, 0].sum() == pytest.approx(orc.stats(rs)["sum_W"], rel=1e-12)
