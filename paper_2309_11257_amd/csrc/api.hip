@@ -219,7 +219,7 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
         ctx->bp64.G = pa + cells;
     } else {
         float4 *pa;
-        ALLOC(pa, float4, 4 * cells);
+        ALLOC(pa, float4, 3 * cells);
         ctx->bp32.A = pa;
         ctx->bp32.G = pa + cells;
     }
@@ -232,6 +232,8 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
         h.f2 = bgf + 12 * cells;
         h.f2y = bgf + 12 * cells + g.ny;
         h.rho = ctx->rho;
+        ctx->bp32.f2 = h.f2;
+        ctx->bp32.f2y = h.f2y;
     }
     // ray state, two buffers
     for (int buf = 0; buf < 2; buf++) {

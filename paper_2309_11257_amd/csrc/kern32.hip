@@ -45,52 +45,68 @@ __host__ __device__ inline G32 make_g32(const Grid &g)
     return h;
 }
 
+// one axis of a trilinear stencil: lower/upper node and the weight of the
+// upper one
+struct Axis {
+    int i0, i1;
+    float w;
+};
+
 // periodic axis: base cell ic, offset u in cell units
-__device__ inline void axis_per(int ic, float u, int n, int &i0, int &i1, float &w)
+__device__ inline Axis axis_per(int ic, float u, int n)
 {
+    Axis a;
     const float t = u - 0.5f;
     if (!(fabsf(t) < 1.0e6f)) {
-        i0 = 0;
-        i1 = 0;
-        w = t - t;
-        return;
+        a.i0 = 0;
+        a.i1 = 0;
+        a.w = t - t;
+        return a;
     }
     const float fl = floorf(t);
-    w = t - fl;
+    a.w = t - fl;
     int ii = ic + (int)fl;
     if (ii < 0 || ii >= n) {
         ii %= n;
         if (ii < 0) ii += n;
     }
-    i0 = ii;
-    i1 = (ii + 1 == n) ? 0 : ii + 1;
+    a.i0 = ii;
+    a.i1 = (ii + 1 == n) ? 0 : ii + 1;
+    return a;
 }
 
 // clamped axis (latitude rows, levels): value held beyond the end centres
-__device__ inline void axis_clamp(int ic, float u, int n, int &i0, int &i1, float &w)
+__device__ inline Axis axis_clamp(int ic, float u, int n)
 {
+    Axis a;
     const float t = u - 0.5f;
     if (!(fabsf(t) < 1.0e6f)) {
-        i0 = 0;
-        i1 = 0;
-        w = t - t;
-        return;
+        a.i0 = 0;
+        a.i1 = 0;
+        a.w = t - t;
+        return a;
     }
     const float fl = floorf(t);
     const int j0 = ic + (int)fl;
     if (j0 < 0) {
-        i0 = 0;
-        i1 = 0;
-        w = 0.0f;
+        a.i0 = 0;
+        a.i1 = 0;
+        a.w = 0.0f;
     } else if (j0 >= n - 1) {
-        i0 = n - 1;
-        i1 = n - 1;
-        w = 0.0f;
+        a.i0 = n - 1;
+        a.i1 = n - 1;
+        a.w = 0.0f;
     } else {
-        i0 = j0;
-        i1 = j0 + 1;
-        w = t - fl;
+        a.i0 = j0;
+        a.i1 = j0 + 1;
+        a.w = t - fl;
     }
+    return a;
+}
+
+__device__ inline Axis axis_y(const G32 &g, int jc, float eta)
+{
+    return g.geometry == RT_CARTESIAN ? axis_per(jc, eta, g.ny) : axis_clamp(jc, eta, g.ny);
 }
 
 struct Cell {
@@ -99,19 +115,24 @@ struct Cell {
     float wx, wy, wz;
 };
 
+__device__ inline Cell cell_of(const G32 &g, const Axis &x, const Axis &y, const Axis &z)
+{
+    Cell c;
+    c.c00 = (y.i0 * g.nx + x.i0) * g.nz;
+    c.c01 = (y.i0 * g.nx + x.i1) * g.nz;
+    c.c10 = (y.i1 * g.nx + x.i0) * g.nz;
+    c.c11 = (y.i1 * g.nx + x.i1) * g.nz;
+    c.k0 = z.i0;
+    c.k1 = z.i1;
+    c.wx = x.w;
+    c.wy = y.w;
+    c.wz = z.w;
+    return c;
+}
+
 __device__ inline void locate(const G32 &g, int ic, int jc, int kc, float xi, float eta, float zeta, Cell &c)
 {
-    int i0, i1, j0, j1;
-    axis_per(ic, xi, g.nx, i0, i1, c.wx);
-    if (g.geometry == RT_CARTESIAN)
-        axis_per(jc, eta, g.ny, j0, j1, c.wy);
-    else
-        axis_clamp(jc, eta, g.ny, j0, j1, c.wy);
-    axis_clamp(kc, zeta, g.nz, c.k0, c.k1, c.wz);
-    c.c00 = (j0 * g.nx + i0) * g.nz;
-    c.c01 = (j0 * g.nx + i1) * g.nz;
-    c.c10 = (j1 * g.nx + i0) * g.nz;
-    c.c11 = (j1 * g.nx + i1) * g.nz;
+    c = cell_of(g, axis_per(ic, xi, g.nx), axis_y(g, jc, eta), axis_clamp(kc, zeta, g.nz));
 }
 
 __device__ inline float lerp3(float a0, float a1, float b0, float b1, float d0, float d1, float e0, float e1,
@@ -126,94 +147,132 @@ __device__ inline float lerp3(float a0, float a1, float b0, float b1, float d0, 
     return c0 + c.wz * (c1 - c0);
 }
 
-// trilinear interpolation of a packed float4 record (R records per cell)
+// the eight corner records of a packed float4 field (R records per cell)
+template <int R>
+struct Corners {
+    float4 a0, a1, b0, b1, d0, d1, e0, e1;
+    __device__ inline Corners(const float4 *__restrict__ F, const Cell &c, int r)
+    {
+        a0 = F[(c.c00 + c.k0) * R + r];
+        a1 = F[(c.c01 + c.k0) * R + r];
+        b0 = F[(c.c10 + c.k0) * R + r];
+        b1 = F[(c.c11 + c.k0) * R + r];
+        d0 = F[(c.c00 + c.k1) * R + r];
+        d1 = F[(c.c01 + c.k1) * R + r];
+        e0 = F[(c.c10 + c.k1) * R + r];
+        e1 = F[(c.c11 + c.k1) * R + r];
+    }
+};
+#define TRI_COMP(K, comp, c) \
+    lerp3(K.a0.comp, K.a1.comp, K.b0.comp, K.b1.comp, K.d0.comp, K.d1.comp, K.e0.comp, K.e1.comp, c)
+
 template <int R>
 __device__ inline float4 tri4(const float4 *__restrict__ F, const Cell &c, int r)
 {
-    const float4 a0 = F[(c.c00 + c.k0) * R + r], a1 = F[(c.c01 + c.k0) * R + r];
-    const float4 b0 = F[(c.c10 + c.k0) * R + r], b1 = F[(c.c11 + c.k0) * R + r];
-    const float4 d0 = F[(c.c00 + c.k1) * R + r], d1 = F[(c.c01 + c.k1) * R + r];
-    const float4 e0 = F[(c.c10 + c.k1) * R + r], e1 = F[(c.c11 + c.k1) * R + r];
+    const Corners<R> K(F, c, r);
     float4 o;
-    o.x = lerp3(a0.x, a1.x, b0.x, b1.x, d0.x, d1.x, e0.x, e1.x, c);
-    o.y = lerp3(a0.y, a1.y, b0.y, b1.y, d0.y, d1.y, e0.y, e1.y, c);
-    o.z = lerp3(a0.z, a1.z, b0.z, b1.z, d0.z, d1.z, e0.z, e1.z, c);
-    o.w = lerp3(a0.w, a1.w, b0.w, b1.w, d0.w, d1.w, e0.w, e1.w, c);
+    o.x = TRI_COMP(K, x, c);
+    o.y = TRI_COMP(K, y, c);
+    o.z = TRI_COMP(K, z, c);
+    o.w = TRI_COMP(K, w, c);
     return o;
 }
 
-// group velocity component along one axis at a face: background wind (if
-// any) plus the intrinsic part from the dispersion relation
-__device__ inline float face_cg(const BgP<float> &b, const Cell &f, int axis, float k, float l, float m, float kh2,
-                                float m2, float invK2, float invK4)
+// f^2 and its latitude derivative depend on the row only: a linear
+// interpolation between rows (equal to the trilinear one of the replicated
+// field)
+__device__ inline float row_lerp(const float *__restrict__ f, const Axis &y)
 {
-    const float4 A = tri4<1>(b.A, f, 0);
-    const float om = sqrtf((A.z * kh2 + A.w * m2) * invK2);
-    const float s = (A.z - A.w) * invK4 / om;
-    if (axis == 0) return A.x + k * m2 * s;
-    if (axis == 1) return A.y + l * m2 * s;
-    return -m * kh2 * s;
+    const float a = f[y.i0], b = f[y.i1];
+    return a + y.w * (b - a);
+}
+
+// single-precision reciprocal and reciprocal square root (one rounding each,
+// within about one unit in the last place)
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// N2 and f2 at a carrier in the packed single-precision background
+__device__ inline void n2_f2(const G32 &g, const Bg32P &b, int ic, int jc, int kc, float xi, float eta, float zeta,
+                             float &N2, float &f2)
+{
+    const Axis ax = axis_per(ic, xi, g.nx), ay = axis_y(g, jc, eta), az = axis_clamp(kc, zeta, g.nz);
+    const Cell c = cell_of(g, ax, ay, az);
+    const Corners<1> K(b.A, c, 0);
+    N2 = TRI_COMP(K, z, c);
+    f2 = row_lerp(b.f2, ay);
 }
 
 // RK stage right-hand side in cell units: Y = (xi, eta, zeta, k, l, m, Dxi,
-// Deta, Dz), offsets relative to the base cell (ic, jc, kc), Dz in metres
+// Deta, Dz), offsets relative to the base cell (ic, jc, kc), Dz in metres.
+// Centre: 12 fields from three records per corner (U V N2 Ux | Uy Uz Vx Vy |
+// Vz N2x N2y N2z) plus f2 and (f2)_y by row.  Faces: (U or V) and N2 from the
+// first record; the face differs from the centre along one axis only, so the
+// other two axes are reused, and f2 is the centre's except on the y faces.
 template <bool SPH>
-__device__ inline void rhs(const G32 &g, const BgP<float> &b, int ic, int jc, int kc, float phi0, const float *Y,
-                           float *F)
+__device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc, float phi0, const float *Y, float *F)
 {
     const float xi = Y[0], eta = Y[1], zeta = Y[2], k = Y[3], l = Y[4], m = Y[5];
     const float kh2 = k * k + l * l;
     const float m2 = m * m;
     const float K2 = kh2 + m2;
-    const float invK2 = 1.0f / K2;
+    const float invK2 = rcp(K2);
     const float invK4 = invK2 * invK2;
-    Cell c;
-    locate(g, ic, jc, kc, xi, eta, zeta, c);
-    const float4 Ac = tri4<1>(b.A, c, 0);  // U V N2 f2
-    const float om = sqrtf((Ac.z * kh2 + Ac.w * m2) * invK2);
-    const float h = 0.5f * invK2 / om;
-    const float q = kh2 * h;
-    const float qf = m2 * h;
-    // gradient records one at a time: (Ux Uy Uz Vx) (Vy Vz N2x N2y) (N2z f2y)
-    float gk = 0.0f, gl = 0.0f, gm = 0.0f;
+    const Axis ax = axis_per(ic, xi, g.nx), ay = axis_y(g, jc, eta), az = axis_clamp(kc, zeta, g.nz);
+    const Cell c = cell_of(g, ax, ay, az);
+    const float f2c = row_lerp(b.f2, ay);
+    float gk, gl, gm, N2c;
+    {
+        const float4 A0 = tri4<1>(b.A, c, 0);  // U V N2 Ux
+        N2c = A0.z;
+        const float rom = rsq((N2c * kh2 + f2c * m2) * invK2);  // 1 / omega_hat
+        const float h = 0.5f * invK2 * rom;
+        const float q = kh2 * h;
+        const float qf = m2 * h;
+        gk = k * A0.w;
+        gl = qf * row_lerp(b.f2y, ay);
+        gm = 0.0f;
+        // gradient records one at a time (bounded register use)
 #pragma unroll 1
-    for (int r = 0; r < 3; r++) {
-        const float4 Gr = tri4<3>(b.G, c, r);
-        // r=0: k*Ux -> gk, k*Uy -> gl, k*Uz -> gm, l*Vx -> gk
-        // r=1: l*Vy -> gl, l*Vz -> gm, q*N2x -> gk, q*N2y -> gl
-        // r=2: q*N2z -> gm, qf*f2y -> gl
-        if (r == 0) {
-            gk += k * Gr.x + l * Gr.w;
-            gl += k * Gr.y;
-            gm += k * Gr.z;
-        } else if (r == 1) {
-            gl += l * Gr.x + q * Gr.w;
-            gm += l * Gr.y;
-            gk += q * Gr.z;
-        } else {
-            gm += q * Gr.x;
-            gl += qf * Gr.y;
+        for (int r = 0; r < 2; r++) {
+            const float4 Gr = tri4<2>(b.G, c, r);
+            if (r == 0) {  // Uy Uz Vx Vy
+                gl += k * Gr.x + l * Gr.w;
+                gm += k * Gr.y;
+                gk += l * Gr.z;
+            } else {  // Vz N2x N2y N2z
+                gm += l * Gr.x + q * Gr.w;
+                gk += q * Gr.y;
+                gl += q * Gr.z;
+            }
         }
     }
     // faces +x, -x, +y, -y, +z, -z, one at a time (bounded register use)
+    const float sdz = Y[8] * g.inv_dz;
     float cxp = 0.0f, cxm = 0.0f, cyp = 0.0f, cym = 0.0f, czp = 0.0f, czm = 0.0f;
 #pragma unroll 1
     for (int fc = 0; fc < 6; fc++) {
-        const int ax = fc >> 1;
+        const int axn = fc >> 1;
         const float sg = (fc & 1) ? -0.5f : 0.5f;
-        float px = xi, py = eta, pz = zeta;
-        if (ax == 0)
-            px += sg * Y[6];
-        else if (ax == 1)
-            py += sg * Y[7];
+        Axis fx = ax, fy = ay, fz = az;
+        if (axn == 0)
+            fx = axis_per(ic, xi + sg * Y[6], g.nx);
+        else if (axn == 1)
+            fy = axis_y(g, jc, eta + sg * Y[7]);
         else
-            pz += sg * (Y[8] * g.inv_dz);
-        Cell f;
-        locate(g, ic, jc, kc, px, py, pz, f);
-        const float4 A = tri4<1>(b.A, f, 0);
-        const float omf = sqrtf((A.z * kh2 + A.w * m2) * invK2);
-        const float sc = (A.z - A.w) * invK4 / omf;
-        const float v = ax == 0 ? A.x + k * m2 * sc : (ax == 1 ? A.y + l * m2 * sc : -m * kh2 * sc);
+            fz = axis_clamp(kc, zeta + sg * sdz, g.nz);
+        const Cell f = cell_of(g, fx, fy, fz);
+        const Corners<1> K(b.A, f, 0);
+        // wind component along the face normal: U on x faces, V on y faces
+        const bool useU = axn == 0;
+        const float wnd = lerp3(useU ? K.a0.x : K.a0.y, useU ? K.a1.x : K.a1.y, useU ? K.b0.x : K.b0.y,
+                                useU ? K.b1.x : K.b1.y, useU ? K.d0.x : K.d0.y, useU ? K.d1.x : K.d1.y,
+                                useU ? K.e0.x : K.e0.y, useU ? K.e1.x : K.e1.y, f);
+        const float N2f = TRI_COMP(K, z, f);
+        const float f2f = axn == 1 ? row_lerp(b.f2, fy) : f2c;
+        const float romf = rsq((N2f * kh2 + f2f * m2) * invK2);
+        const float sc = (N2f - f2f) * invK4 * romf;
+        const float v = axn == 0 ? wnd + k * m2 * sc : (axn == 1 ? wnd + l * m2 * sc : -m * kh2 * sc);
         cxp = fc == 0 ? v : cxp;
         cxm = fc == 1 ? v : cxm;
         cyp = fc == 2 ? v : cyp;
@@ -233,11 +292,12 @@ __device__ inline void rhs(const G32 &g, const BgP<float> &b, int ic, int jc, in
         F[8] = czp - czm;
     } else {
         const float r = g.a + ((float)kc + zeta) * g.dz;
-        const float ir = 1.0f / r;
+        const float ir = rcp(r);
         float sphi, cphi;
         sincosf(phi0 + eta * g.dyr, &sphi, &cphi);
-        const float tphi = sphi / cphi;
-        const float irc = ir / cphi;
+        const float icphi = rcp(cphi);
+        const float tphi = sphi * icphi;
+        const float irc = ir * icphi;
         const float uc = 0.5f * (cxp + cxm);
         const float vc = 0.5f * (cyp + cym);
         const float wc = 0.5f * (czp + czm);
@@ -275,7 +335,7 @@ __device__ inline void renorm_periodic(int &ic, float &u, int n)
 using f32::G32;
 
 template <bool SPH>
-__global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
+__global__ __launch_bounds__(256, 2) void k_step32(G32 g, Bg32P b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
                                                    uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc,
                                                    float dt, const uint8_t *__restrict__ frozen,
                                                    const uint32_t *__restrict__ skeys)
@@ -376,7 +436,7 @@ __global__ __launch_bounds__(256, 2) void k_step32(G32 g, BgP<float> b, S32 src,
     key_out[i] = key;
 }
 
-void launch_step32(const Grid &g, const BgP<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
+void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
                    hipStream_t s)
 {
@@ -387,6 +447,28 @@ void launch_step32(const Grid &g, const BgP<float> &b, S32 src, S32 dst, const u
         k_step32<true><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
     else
         k_step32<false><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
+}
+
+// ---------------------------------------------------------------------------
+// packed single-precision background: A = (U, V, N2, Ux),
+// G = (Uy, Uz, Vx, Vy), (Vz, N2x, N2y, N2z) at index col*nz + k
+// ---------------------------------------------------------------------------
+__global__ void k_pack32(Grid g, Bg<double> b, float4 *A, float4 *G)
+{
+    const int64_t cells = (int64_t)g.ncol * g.nz;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cells) return;
+    const int64_t col = e / g.nz, k = e % g.nz;
+    const int64_t s = k * g.ncol + col;
+    A[e] = make_float4((float)b.U[s], (float)b.V[s], (float)b.N2[s], (float)b.Ux[s]);
+    G[2 * e] = make_float4((float)b.Uy[s], (float)b.Uz[s], (float)b.Vx[s], (float)b.Vy[s]);
+    G[2 * e + 1] = make_float4((float)b.Vz[s], (float)b.N2x[s], (float)b.N2y[s], (float)b.N2z[s]);
+}
+
+void launch_pack32(const Grid &g, const Bg<double> &b, float4 *A, float4 *G, hipStream_t s)
+{
+    const int64_t cells = (int64_t)g.ncol * g.nz;
+    k_pack32<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, b, A, G);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,7 +651,7 @@ void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double 
 // ---------------------------------------------------------------------------
 struct Pay32 {
     G32 g;
-    BgP<float> b;
+    Bg32P b;
     S32 st;
     double zdz;  // level spacing in double
     __device__ void load(uint32_t s, double &zb, double &zt, double *bv) const
@@ -580,11 +662,8 @@ struct Pay32 {
         const float zeta = st.zeta[s];
         const float k = st.k[s], l = st.l[s], m = st.m[s];
         const float Dz = st.dz[s];
-        f32::Cell c;
-        f32::locate(g, ic, jc, kc, st.xi[s], st.eta[s], zeta, c);
-        const float4 Ac = f32::tri4<1>(b.A, c, 0);
-        const float N2 = Ac.z;
-        const float f2 = Ac.w;
+        float N2, f2;
+        f32::n2_f2(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta, N2, f2);
         const float kh2 = k * k + l * l;
         const float m2 = m * m;
         const float K2 = kh2 + m2;
@@ -611,15 +690,14 @@ struct Pay32 {
     {
         const uint32_t col = st.col[s];
         const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
-        f32::Cell c;
-        f32::locate(g, ic, jc, st.lev[s], st.xi[s], st.eta[s], st.zeta[s], c);
-        const float4 Ac = f32::tri4<1>(b.A, c, 0);
+        float N2, f2;
+        f32::n2_f2(g, b, ic, jc, st.lev[s], st.xi[s], st.eta[s], st.zeta[s], N2, f2);
         const float k = st.k[s], l = st.l[s], m = st.m[s];
         const float kh2 = k * k + l * l;
         const float m2 = m * m;
         const float K2 = kh2 + m2;
-        const float om = sqrtf((Ac.z * kh2 + Ac.w * m2) / K2);
-        const float sc = (Ac.z - Ac.w) / (K2 * K2) / om;
+        const float om = sqrtf((N2 * kh2 + f2 * m2) / K2);
+        const float sc = (N2 - f2) / (K2 * K2) / om;
         kd = k;
         ld = l;
         md = m;
@@ -636,14 +714,14 @@ struct Pay32 {
     }
 };
 
-void launch_deposit32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s)
 {
     Pay32 p{f32::make_g32(g), b, st, g.dz};
     k_deposit<Pay32><<<(unsigned)g.ncol, 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
 }
 
-void launch_features32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s)
 {
     Pay32 p{f32::make_g32(g), b, st, g.dz};

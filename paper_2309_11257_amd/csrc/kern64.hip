@@ -122,11 +122,6 @@ void launch_pack64(const Grid &g, const Bg<double> &b, double4 *A, double4 *G, h
     k_pack<double, double4><<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, b, A, G);
 }
 
-void launch_pack32(const Grid &g, const Bg<double> &b, float4 *A, float4 *G, hipStream_t s)
-{
-    const int64_t cells = (int64_t)g.ncol * g.nz;
-    k_pack<float, float4><<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, b, A, G);
-}
 
 // ---------------------------------------------------------------------------
 // load / store

@@ -47,6 +47,16 @@ struct BgP {
     const typename V4T<T>::type *G;  // [ncol*nz*3]
 };
 
+// Packed single-precision background for cell (column c, level k) at index
+// c*nz + k:  A = (U, V, N2, Ux), G = (Uy, Uz, Vx, Vy), (Vz, N2x, N2y, N2z);
+// f^2 and (f^2)_y by latitude row [ny].  The step's face evaluations need
+// only A; the centre needs A and both G records.
+struct Bg32P {
+    const float4 *A;  // [ncol*nz]
+    const float4 *G;  // [ncol*nz*2]
+    const float *f2, *f2y;
+};
+
 // double-precision state: absolute coordinates, as the public interface
 struct S64 {
     double *x, *y, *z, *k, *l, *m, *dx, *dy, *dz, *px, *py, *pz, *n;
@@ -87,7 +97,7 @@ struct rt_ctx_s {
     Bg<double> bg64;
     Bg<float> bg32;
     BgP<double> bp64;
-    BgP<float> bp32;
+    Bg32P bp32;
     double *rho;
     // state: double buffers
     S64 s64[2];
@@ -165,12 +175,12 @@ void launch_store32(const Grid &g, S32 src, const uint32_t *perm, const DevCount
 void launch_step64(const Grid &g, const BgP<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
                    hipStream_t s);
-void launch_step32(const Grid &g, const BgP<float> &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
+void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
                    hipStream_t s);
 void launch_features64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s);
-void launch_features32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s);
 
 // stable LSD radix sort of keys[0..*n) with 32-bit payload (identity if vals == NULL)
@@ -192,7 +202,7 @@ void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double 
 
 void launch_deposit64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s);
-void launch_deposit32(const Grid &g, const BgP<float> &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s);
 void launch_drag(const Grid &g, const double *rho, const double *flux, double *drag, hipStream_t s);
 

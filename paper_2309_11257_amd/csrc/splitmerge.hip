@@ -155,6 +155,7 @@ struct IO64 {
 // --- single-precision storage (positions as cell + offset) -----------------
 struct IO32 {
     S32 s;
+    const float *f2r;  // f^2 by latitude row
     __device__ RayD get(const Grid &g, uint32_t i) const
     {
         RayD r;
@@ -239,7 +240,8 @@ struct IO32 {
     }
     __device__ uint32_t column(const Grid &g, uint32_t i) const { (void)g; return s.col[i]; }
     __device__ void rewrap(const Grid &g, uint32_t i) const { (void)g; (void)i; }
-    // wave energy from the single-precision background (N2, f2), in double
+    // wave energy from the single-precision background (N2 from the packed A
+    // record, f2 by row), in double
     __device__ double energy(const Grid &g, const float4 *bA, uint32_t i) const
     {
         const RayD r = get(g, i);
@@ -247,12 +249,8 @@ struct IO32 {
         d64::locate(g, r.x, r.y, r.z, c);
         const int o[8] = {c.c00 + c.k0, c.c01 + c.k0, c.c10 + c.k0, c.c11 + c.k0,
                           c.c00 + c.k1, c.c01 + c.k1, c.c10 + c.k1, c.c11 + c.k1};
-        double vz[8], vw[8];
-        for (int q = 0; q < 8; q++) {
-            const float4 t = bA[o[q]];
-            vz[q] = t.z;
-            vw[q] = t.w;
-        }
+        double vz[8];
+        for (int q = 0; q < 8; q++) vz[q] = bA[o[q]].z;
         auto tri = [&](const double *v) {
             const double c00 = v[0] + c.wx * (v[1] - v[0]), c10 = v[2] + c.wx * (v[3] - v[2]);
             const double c01 = v[4] + c.wx * (v[5] - v[4]), c11 = v[6] + c.wx * (v[7] - v[6]);
@@ -261,7 +259,8 @@ struct IO32 {
         };
         double4 A;
         A.z = tri(vz);
-        A.w = tri(vw);
+        const int j0 = (c.c00 / g.nz) / g.nx, j1 = (c.c10 / g.nz) / g.nx;
+        A.w = (double)f2r[j0] + c.wy * ((double)f2r[j1] - (double)f2r[j0]);
         const double kh2 = r.k * r.k + r.l * r.l;
         const double m2 = r.m * r.m;
         const double K2 = kh2 + m2;
@@ -734,7 +733,8 @@ rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, r
         r = split_merge_impl<IO64, double4>(ctx, IO64{ctx->s64[ctx->cur]}, IO64{ctx->s64[1 - ctx->cur]}, ctx->bp64.A,
                                             alpha, nmax, mode);
     else
-        r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur]}, IO32{ctx->s32[1 - ctx->cur]}, ctx->bp32.A,
+        r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2},
+                                           IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2}, ctx->bp32.A,
                                            alpha, nmax, mode);
     rt_status r2 = sort_current_ext(ctx);
     prof_end(ctx);
