@@ -110,20 +110,28 @@ __device__ inline Axis axis_y(const G32 &g, int jc, float eta)
 }
 
 struct Cell {
-    int c00, c01, c10, c11;  // columns (j0,i0) (j0,i1) (j1,i0) (j1,i1), times nz
-    int k0, k1;
+    uint32_t c00, c01, c10, c11;  // columns (j0,i0) (j0,i1) (j1,i0) (j1,i1), times nz
+    uint32_t k0, k1;
     float wx, wy, wz;
 };
+
+// cell indices use 24-bit multiplies (full rate): every factor is below 2^24
+// (columns < 2^24 is checked at context creation) and every product below
+// 2^31 (the single-precision path's index limit)
+__device__ inline uint32_t col_base(const G32 &g, int j, int i)
+{
+    return __umul24(__umul24((uint32_t)j, (uint32_t)g.nx) + (uint32_t)i, (uint32_t)g.nz);
+}
 
 __device__ inline Cell cell_of(const G32 &g, const Axis &x, const Axis &y, const Axis &z)
 {
     Cell c;
-    c.c00 = (y.i0 * g.nx + x.i0) * g.nz;
-    c.c01 = (y.i0 * g.nx + x.i1) * g.nz;
-    c.c10 = (y.i1 * g.nx + x.i0) * g.nz;
-    c.c11 = (y.i1 * g.nx + x.i1) * g.nz;
-    c.k0 = z.i0;
-    c.k1 = z.i1;
+    c.c00 = col_base(g, y.i0, x.i0);
+    c.c01 = col_base(g, y.i0, x.i1);
+    c.c10 = col_base(g, y.i1, x.i0);
+    c.c11 = col_base(g, y.i1, x.i1);
+    c.k0 = (uint32_t)z.i0;
+    c.k1 = (uint32_t)z.i1;
     c.wx = x.w;
     c.wy = y.w;
     c.wz = z.w;
@@ -147,20 +155,29 @@ __device__ inline float lerp3(float a0, float a1, float b0, float b1, float d0, 
     return c0 + c.wz * (c1 - c0);
 }
 
+// record at a 32-bit byte offset from a uniform base (the packed arrays are
+// below 4 GiB, checked at context creation), so the load takes a scalar base
+// and a 32-bit vector offset
+__device__ inline float4 rec(const float4 *__restrict__ F, uint32_t index)
+{
+    return *(const float4 *)((const char *)F + (index << 4));
+}
+
 // the eight corner records of a packed float4 field (R records per cell)
 template <int R>
 struct Corners {
     float4 a0, a1, b0, b1, d0, d1, e0, e1;
     __device__ inline Corners(const float4 *__restrict__ F, const Cell &c, int r)
     {
-        a0 = F[(c.c00 + c.k0) * R + r];
-        a1 = F[(c.c01 + c.k0) * R + r];
-        b0 = F[(c.c10 + c.k0) * R + r];
-        b1 = F[(c.c11 + c.k0) * R + r];
-        d0 = F[(c.c00 + c.k1) * R + r];
-        d1 = F[(c.c01 + c.k1) * R + r];
-        e0 = F[(c.c10 + c.k1) * R + r];
-        e1 = F[(c.c11 + c.k1) * R + r];
+        const uint32_t rr = (uint32_t)r;
+        a0 = rec(F, (c.c00 + c.k0) * R + rr);
+        a1 = rec(F, (c.c01 + c.k0) * R + rr);
+        b0 = rec(F, (c.c10 + c.k0) * R + rr);
+        b1 = rec(F, (c.c11 + c.k0) * R + rr);
+        d0 = rec(F, (c.c00 + c.k1) * R + rr);
+        d1 = rec(F, (c.c01 + c.k1) * R + rr);
+        e0 = rec(F, (c.c10 + c.k1) * R + rr);
+        e1 = rec(F, (c.c11 + c.k1) * R + rr);
     }
 };
 #define TRI_COMP(K, comp, c) \
@@ -335,7 +352,7 @@ __device__ inline void renorm_periodic(int &ic, float &u, int n)
 using f32::G32;
 
 template <bool SPH>
-__global__ __launch_bounds__(256, 2) void k_step32(G32 g, Bg32P b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
+__global__ __launch_bounds__(256, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
                                                    uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc,
                                                    float dt, const uint8_t *__restrict__ frozen,
                                                    const uint32_t *__restrict__ skeys)
@@ -718,7 +735,7 @@ void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *per
                       double *flux, hipStream_t s)
 {
     Pay32 p{f32::make_g32(g), b, st, g.dz};
-    k_deposit<Pay32><<<(unsigned)g.ncol, 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
+    k_deposit<Pay32><<<deposit_blocks(g), 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
 }
 
 void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,

@@ -415,7 +415,7 @@ void launch_deposit64(const Grid &g, const BgP<double> &b, S64 st, const uint32_
                       double *flux, hipStream_t s)
 {
     Pay64 p{g, b, st};
-    k_deposit<Pay64><<<(unsigned)g.ncol, 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
+    k_deposit<Pay64><<<deposit_blocks(g), 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
 }
 
 void launch_features64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,

@@ -56,7 +56,63 @@ __device__ inline float dgelu_t(float z)
     return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * z * z);
 }
 
-template <int EPI>
+// Staging of one 128 x 32 operand tile (rows = m or n, 32 consecutive k)
+// from global memory: each thread moves two vectors of 8 bfloat16.  With the
+// operand k-contiguous a vector is 8 consecutive k of one row; otherwise it is
+// 8 consecutive rows at one k, transposed on the way into LDS.  Vectors that
+// are not fully inside the matrix, or not 16-byte aligned, are assembled
+// element by element (zero outside).
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+template <bool KCONT>
+struct Stage {
+    u16x8 v[2];
+    __device__ inline void load(const bf16 *src, int64_t srow, int64_t sk, int row0, int nrows, int k0, int kend,
+                                int tid)
+    {
+        const unsigned short *p = (const unsigned short *)src;
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            const int vi = tid + 256 * t;
+            int r, kk;
+            if (KCONT) {
+                r = vi >> 2;
+                kk = (vi & 3) * 8;
+            } else {
+                kk = vi >> 4;
+                r = (vi & 15) * 8;
+            }
+            const int gr = row0 + r, gk = k0 + kk;
+            const int64_t off = (int64_t)gr * srow + (int64_t)gk * sk;
+            const bool full = KCONT ? (gr < nrows && gk + 8 <= kend) : (gr + 8 <= nrows && gk < kend);
+            if (full && ((((uintptr_t)(p + off)) & 15) == 0)) {
+                v[t] = *(const u16x8 *)(p + off);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const int er = KCONT ? gr : gr + e, ek = KCONT ? gk + e : gk;
+                    v[t][e] = (er < nrows && ek < kend) ? p[(int64_t)er * srow + (int64_t)ek * sk] : (unsigned short)0;
+                }
+            }
+        }
+    }
+    __device__ inline void store(bf16 (*tile)[GBK + GPAD], int tid) const
+    {
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            const int vi = tid + 256 * t;
+            if (KCONT) {
+                *(u16x8 *)&tile[vi >> 2][(vi & 3) * 8] = v[t];
+            } else {
+                const int kk = vi >> 4, r = (vi & 15) * 8;
+#pragma unroll
+                for (int e = 0; e < 8; e++) ((unsigned short *)&tile[r + e][0])[kk] = v[t][e];
+            }
+        }
+    }
+};
+
+template <int EPI, bool KA, bool KB>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
 {
     __shared__ __attribute__((aligned(16))) bf16 sA[GBM][GBK + GPAD];
@@ -76,15 +132,21 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
 #pragma unroll
             for (int q = 0; q < 16; q++) acc[i][j][q] = 0.0f;
 
+    Stage<KA> ga;
+    Stage<KB> gb;
+    if (kbeg < kend) {
+        ga.load(a.A, a.am, a.ak, bm, a.M, kbeg, kend, tid);
+        gb.load(a.B, a.bn, a.bk, bn, a.N, kbeg, kend, tid);
+    }
     for (int k0 = kbeg; k0 < kend; k0 += GBK) {
-        for (int e = tid; e < GBM * GBK; e += 256) {
-            const int r = e / GBK, c = e % GBK;
-            const int gm = bm + r, gk = k0 + c;
-            sA[r][c] = (gm < a.M && gk < kend) ? a.A[(int64_t)gm * a.am + (int64_t)gk * a.ak] : (bf16)0.0f;
-            const int gn = bn + r;
-            sB[r][c] = (gn < a.N && gk < kend) ? a.B[(int64_t)gk * a.bk + (int64_t)gn * a.bn] : (bf16)0.0f;
-        }
+        __syncthreads();  // the previous tile has been consumed
+        ga.store(sA, tid);
+        gb.store(sB, tid);
         __syncthreads();
+        if (k0 + GBK < kend) {  // next tile's loads in flight during the MFMAs
+            ga.load(a.A, a.am, a.ak, bm, a.M, k0 + GBK, kend, tid);
+            gb.load(a.B, a.bn, a.bk, bn, a.N, k0 + GBK, kend, tid);
+        }
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 16) {
             bf16x8 af[2], bfr[2];
@@ -99,7 +161,6 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
                 for (int j = 0; j < 2; j++)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
     }
     // output element (row, col) of the 32x32 tile held in lane/item
 #pragma unroll
@@ -137,15 +198,20 @@ __global__ void k_sum_partials(const float *P, int64_t n, int S, float *out)
     out[i] = s;
 }
 
-// column sums (bias gradient) of a [M][N] bfloat16 matrix: one thread per
-// column, rows in order
-__global__ void k_colsum_bf16(const bf16 *D, int M, int N, float *out)
+// column sums (bias gradient) of a [M][N] bfloat16 matrix, first pass: chunk
+// p of the rows (in order) per thread and column, partial sums to part[p][N];
+// the partials are then added in chunk order (k_sum_partials)
+#define COLSUM_CHUNKS 32
+__global__ void k_colsum_bf16(const bf16 *D, int M, int N, float *part)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.y;
     if (c >= N) return;
+    const int rows = (M + COLSUM_CHUNKS - 1) / COLSUM_CHUNKS;
+    const int r0 = p * rows, r1 = min(M, r0 + rows);
     float s = 0.0f;
-    for (int r = 0; r < M; r++) s += (float)D[(int64_t)r * N + c];
-    out[c] = s;
+    for (int r = r0; r < r1; r++) s += (float)D[(int64_t)r * N + c];
+    part[(int64_t)p * N + c] = s;
 }
 
 // loss gradient dY = 2 (Y - T) / (B n_out) in bfloat16, and per-block partial
@@ -405,7 +471,9 @@ extern "C" rt_status sg_create(const sg_config *cfg, sg_net *out)
     // split-K partials for the largest weight gradient, and loss partials
     int64_t maxw = 0;
     for (int i = 0; i < n->nl; i++) maxw = maxw > (int64_t)n->L[i].in * n->L[i].out ? maxw : (int64_t)n->L[i].in * n->L[i].out;
-    n->part_len = 16 * maxw + (B * cfg->n_out + 255) / 256 + 16;
+    const int64_t maxo = cfg->n_hidden > cfg->n_out ? cfg->n_hidden : cfg->n_out;
+    const int64_t front = 16 * maxw > COLSUM_CHUNKS * maxo ? 16 * maxw : COLSUM_CHUNKS * maxo;
+    n->part_len = front + (B * cfg->n_out + 255) / 256 + 16;
     n->part = (float *)net_alloc(n, sizeof(float) * n->part_len);
     for (int i = 0; i < n->nl - 1 && ok; i++) {
         n->Z[i] = (float *)net_alloc(n, sizeof(float) * B * Hd);
@@ -490,11 +558,21 @@ extern "C" rt_status sg_set_params(sg_net n, int32_t member, const float *params
     return RT_OK;
 }
 
+// operand layouts picked at run time: A k-contiguous (ak == 1) or
+// m-contiguous (am == 1), B k-contiguous (bk == 1) or n-contiguous (bn == 1)
 template <int EPI>
 static void gemm(const GemmArgs &a, hipStream_t s)
 {
     dim3 grid((a.M + GBM - 1) / GBM, (a.N + GBN - 1) / GBN, a.ksplit);
-    k_gemm<EPI><<<grid, 256, 0, s>>>(a);
+    const bool ka = a.ak == 1, kb = a.bk == 1;
+    if (ka && kb)
+        k_gemm<EPI, true, true><<<grid, 256, 0, s>>>(a);
+    else if (ka)
+        k_gemm<EPI, true, false><<<grid, 256, 0, s>>>(a);
+    else if (kb)
+        k_gemm<EPI, false, true><<<grid, 256, 0, s>>>(a);
+    else
+        k_gemm<EPI, false, false><<<grid, 256, 0, s>>>(a);
 }
 
 // forward of one member for a batch of B; output to Yout [B][n_out]
@@ -574,7 +652,8 @@ static void backward(sg_net n, int mem, const bf16 *X, const float *T, int B, fl
             gemm<EPI_F32>(a, n->stream);
             const int64_t nw = (int64_t)l.out * l.in;
             k_sum_partials<<<nblk(nw), 256, 0, n->stream>>>(n->part, nw, a.ksplit, n->grad + l.woff);
-            k_colsum_bf16<<<nblk(l.out), 256, 0, n->stream>>>(dcur, B, l.out, n->grad + l.boff);
+            k_colsum_bf16<<<dim3(nblk(l.out), COLSUM_CHUNKS), 256, 0, n->stream>>>(dcur, B, l.out, n->part);
+            k_sum_partials<<<nblk(l.out), 256, 0, n->stream>>>(n->part, l.out, COLSUM_CHUNKS, n->grad + l.boff);
         }
         if (li > 0) {
             // d(in)[b][in] = sum_out d[b][out] W[out][in], times GELU'(Z_{li-1})
