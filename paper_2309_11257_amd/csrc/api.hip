@@ -216,9 +216,11 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     b.rho = ctx->rho;
     if (ctx->precision == RT_FP64) {
         double4 *pa;
-        ALLOC(pa, double4, 4 * cells);
+        ALLOC(pa, double4, 3 * cells);
         ctx->bp64.A = pa;
         ctx->bp64.G = pa + cells;
+        ctx->bp64.f2 = b.f2;
+        ctx->bp64.f2y = b.f2y;
     } else {
         float4 *pa;
         ALLOC(pa, float4, 3 * cells);

@@ -11,48 +11,69 @@
 
 namespace d64 {
 
+// One axis of a trilinear stencil: lower/upper node and the weight of the
+// upper one.
+struct Axis {
+    int i0, i1;
+    double w;
+};
+
 // Fractional index of a position on a cell-centred axis: g = (p - o)/d - 1/2.
-__device__ inline void axis_periodic(double p, double origin, double d, int n, int &i0, int &i1, double &w)
+__device__ inline Axis axis_periodic(double p, double origin, double d, int n)
 {
-    double g = (p - origin) / d - 0.5;
+    Axis a;
+    const double g = (p - origin) / d - 0.5;
     if (!(fabs(g) < 1.0e15)) {
-        i0 = 0;
-        i1 = 0;
-        w = g - g;
-        return;
+        a.i0 = 0;
+        a.i1 = 0;
+        a.w = g - g;
+        return a;
     }
-    double fl = floor(g);
-    w = g - fl;
-    long long ii = (long long)fl % n;
-    if (ii < 0) ii += n;
-    i0 = (int)ii;
-    i1 = (int)((ii + 1) % n);
+    const double fl = floor(g);
+    a.w = g - fl;
+    long long ii = (long long)fl;
+    if (ii < 0 || ii >= n) {
+        ii %= n;
+        if (ii < 0) ii += n;
+    }
+    a.i0 = (int)ii;
+    a.i1 = (ii + 1 == n) ? 0 : (int)ii + 1;
+    return a;
 }
 
-__device__ inline void axis_clamped(double p, double origin, double d, int n, int &i0, int &i1, double &w)
+__device__ inline Axis axis_clamped(double p, double origin, double d, int n)
 {
-    double g = (p - origin) / d - 0.5;
+    Axis a;
+    const double g = (p - origin) / d - 0.5;
     if (g != g) {
-        i0 = 0;
-        i1 = 0;
-        w = g;
-        return;
+        a.i0 = 0;
+        a.i1 = 0;
+        a.w = g;
+        return a;
     }
     if (g <= 0.0) {
-        i0 = 0;
-        i1 = 0;
-        w = 0.0;
+        a.i0 = 0;
+        a.i1 = 0;
+        a.w = 0.0;
     } else if (g >= (double)(n - 1)) {
-        i0 = n - 1;
-        i1 = n - 1;
-        w = 0.0;
+        a.i0 = n - 1;
+        a.i1 = n - 1;
+        a.w = 0.0;
     } else {
-        double fl = floor(g);
-        i0 = (int)fl;
-        i1 = i0 + 1;
-        w = g - fl;
+        const double fl = floor(g);
+        a.i0 = (int)fl;
+        a.i1 = a.i0 + 1;
+        a.w = g - fl;
     }
+    return a;
 }
+
+__device__ inline Axis axis_x(const Grid &g, double x) { return axis_periodic(x, g.x0, g.dx, g.nx); }
+__device__ inline Axis axis_y(const Grid &g, double y)
+{
+    return g.geometry == RT_CARTESIAN ? axis_periodic(y, g.y0, g.dy, g.ny) : axis_clamped(y, g.y0, g.dy, g.ny);
+}
+__device__ inline Axis axis_z(const Grid &g, double z) { return axis_clamped(z, 0.0, g.dz, g.nz); }
 
 // The eight corners of the interpolation cell: column indices of the four
 // (j, i) corners and the two levels, plus the weights.
@@ -62,47 +83,76 @@ struct Cell {
     double wx, wy, wz;
 };
 
+__device__ inline Cell cell_of(const Grid &g, const Axis &x, const Axis &y, const Axis &z)
+{
+    Cell c;
+    c.c00 = (y.i0 * g.nx + x.i0) * g.nz;
+    c.c01 = (y.i0 * g.nx + x.i1) * g.nz;
+    c.c10 = (y.i1 * g.nx + x.i0) * g.nz;
+    c.c11 = (y.i1 * g.nx + x.i1) * g.nz;
+    c.k0 = z.i0;
+    c.k1 = z.i1;
+    c.wx = x.w;
+    c.wy = y.w;
+    c.wz = z.w;
+    return c;
+}
+
 __device__ inline void locate(const Grid &g, double x, double y, double z, Cell &c)
 {
-    int i0, i1, j0, j1;
-    axis_periodic(x, g.x0, g.dx, g.nx, i0, i1, c.wx);
-    if (g.geometry == RT_CARTESIAN)
-        axis_periodic(y, g.y0, g.dy, g.ny, j0, j1, c.wy);
-    else
-        axis_clamped(y, g.y0, g.dy, g.ny, j0, j1, c.wy);
-    axis_clamped(z, 0.0, g.dz, g.nz, c.k0, c.k1, c.wz);
-    c.c00 = (j0 * g.nx + i0) * g.nz;
-    c.c01 = (j0 * g.nx + i1) * g.nz;
-    c.c10 = (j1 * g.nx + i0) * g.nz;
-    c.c11 = (j1 * g.nx + i1) * g.nz;
+    c = cell_of(g, axis_x(g, x), axis_y(g, y), axis_z(g, z));
 }
+
+__device__ inline double lerp3(double a0, double a1, double b0, double b1, double d0, double d1, double e0, double e1,
+                               const Cell &c)
+{
+    const double c00 = a0 + c.wx * (a1 - a0);
+    const double c10 = b0 + c.wx * (b1 - b0);
+    const double c01 = d0 + c.wx * (d1 - d0);
+    const double c11 = e0 + c.wx * (e1 - e0);
+    const double c0 = c00 + c.wy * (c10 - c00);
+    const double c1 = c01 + c.wy * (c11 - c01);
+    return c0 + c.wz * (c1 - c0);
+}
+
+// the eight corner records of a packed double4 field (R records per cell)
+template <int R>
+struct Corners {
+    double4 a0, a1, b0, b1, d0, d1, e0, e1;
+    __device__ inline Corners(const double4 *__restrict__ F, const Cell &c, int r)
+    {
+        a0 = F[(c.c00 + c.k0) * R + r];
+        a1 = F[(c.c01 + c.k0) * R + r];
+        b0 = F[(c.c10 + c.k0) * R + r];
+        b1 = F[(c.c11 + c.k0) * R + r];
+        d0 = F[(c.c00 + c.k1) * R + r];
+        d1 = F[(c.c01 + c.k1) * R + r];
+        e0 = F[(c.c10 + c.k1) * R + r];
+        e1 = F[(c.c11 + c.k1) * R + r];
+    }
+};
+#define TRI64(K, q, c) lerp3(K.a0.q, K.a1.q, K.b0.q, K.b1.q, K.d0.q, K.d1.q, K.e0.q, K.e1.q, c)
 
 // Trilinear interpolation of a packed 4-vector record, component by
 // component: x on the four corner rows, then y, then z.  R = records per cell.
 template <int R>
 __device__ inline double4 tri4(const double4 *__restrict__ F, const Cell &c, int r)
 {
-    const double4 a0 = F[(c.c00 + c.k0) * R + r], a1 = F[(c.c01 + c.k0) * R + r];
-    const double4 b0 = F[(c.c10 + c.k0) * R + r], b1 = F[(c.c11 + c.k0) * R + r];
-    const double4 d0 = F[(c.c00 + c.k1) * R + r], d1 = F[(c.c01 + c.k1) * R + r];
-    const double4 e0 = F[(c.c10 + c.k1) * R + r], e1 = F[(c.c11 + c.k1) * R + r];
+    const Corners<R> K(F, c, r);
     double4 o;
-#define TRI_(q)                                               \
-    {                                                         \
-        const double c00 = a0.q + c.wx * (a1.q - a0.q);      \
-        const double c10 = b0.q + c.wx * (b1.q - b0.q);      \
-        const double c01 = d0.q + c.wx * (d1.q - d0.q);      \
-        const double c11 = e0.q + c.wx * (e1.q - e0.q);      \
-        const double c0 = c00 + c.wy * (c10 - c00);           \
-        const double c1 = c01 + c.wy * (c11 - c01);           \
-        o.q = c0 + c.wz * (c1 - c0);                          \
-    }
-    TRI_(x)
-    TRI_(y)
-    TRI_(z)
-    TRI_(w)
-#undef TRI_
+    o.x = TRI64(K, x, c);
+    o.y = TRI64(K, y, c);
+    o.z = TRI64(K, z, c);
+    o.w = TRI64(K, w, c);
     return o;
+}
+
+// f^2 (or its latitude derivative) between rows: equal, bit for bit, to the
+// trilinear interpolation of the field replicated along x and z
+__device__ inline double row_lerp(const double *__restrict__ f, const Axis &y)
+{
+    const double a = f[y.i0], b = f[y.i1];
+    return a + y.w * (b - a);
 }
 
 // omega_hat^2 = (N^2 kh^2 + f^2 m^2)/K^2 (eq. dispersion, Gamma = 0)
@@ -115,9 +165,10 @@ __device__ inline double omega_hat(double N2, double f2, double kh2, double m2, 
 // Carrier wavevector tendency from the centre fields and gradients
 // (eq. eikonal-sphere 1-3, Gamma = 0; flat limit on the box); carrier motion
 // and extent rates from the group velocities at the opposing face centres
-// (Section 3a, Appendix B).
+// (Section 3a, Appendix B).  A face differs from the centre along one axis,
+// so only that axis is located again.
 template <bool SPH>
-__device__ inline void rhs(const Grid &g, const BgP<double> &b, const double *Y, double *F)
+__device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, double *F)
 {
     const double x = Y[0], y = Y[1], z = Y[2], k = Y[3], l = Y[4], m = Y[5];
     const double Dx = Y[6], Dy = Y[7], Dz = Y[8];
@@ -125,28 +176,29 @@ __device__ inline void rhs(const Grid &g, const BgP<double> &b, const double *Y,
     const double m2 = m * m;
     const double K2 = kh2 + m2;
     const double K4 = K2 * K2;
-    Cell c;
-    locate(g, x, y, z, c);
-    const double4 Ac = tri4<1>(b.A, c, 0);   // U V N2 f2
-    const double om = omega_hat(Ac.z, Ac.w, kh2, m2, K2);
+    const Axis ax = axis_x(g, x), ay = axis_y(g, y), az = axis_z(g, z);
+    const Cell c = cell_of(g, ax, ay, az);
+    const double4 A0 = tri4<1>(b.A, c, 0);  // U V N2 Ux
+    const double f2c = row_lerp(b.f2, ay);
+    const double om = omega_hat(A0.z, f2c, kh2, m2, K2);
     const double q = kh2 / ((2.0 * om) * K2);
     const double qf = m2 / ((2.0 * om) * K2);
-    // gradient records one at a time: (Ux Uy Uz Vx) (Vy Vz N2x N2y) (N2z f2y)
-    double Ux = 0, Uy = 0, Uz = 0, Vx = 0, Vy = 0, Vz = 0, N2x = 0, N2y = 0, N2z = 0, f2y = 0;
+    // gradient records one at a time: (Uy Uz Vx Vy) (Vz N2x N2y N2z)
+    const double Ux = A0.w;
+    double Uy = 0, Uz = 0, Vx = 0, Vy = 0, Vz = 0, N2x = 0, N2y = 0, N2z = 0;
 #pragma unroll 1
-    for (int r = 0; r < 3; r++) {
-        const double4 Gr = tri4<3>(b.G, c, r);
-        Ux = r == 0 ? Gr.x : Ux;
-        Uy = r == 0 ? Gr.y : Uy;
-        Uz = r == 0 ? Gr.z : Uz;
-        Vx = r == 0 ? Gr.w : Vx;
-        Vy = r == 1 ? Gr.x : Vy;
-        Vz = r == 1 ? Gr.y : Vz;
-        N2x = r == 1 ? Gr.z : N2x;
-        N2y = r == 1 ? Gr.w : N2y;
-        N2z = r == 2 ? Gr.x : N2z;
-        f2y = r == 2 ? Gr.y : f2y;
+    for (int r = 0; r < 2; r++) {
+        const double4 Gr = tri4<2>(b.G, c, r);
+        Uy = r == 0 ? Gr.x : Uy;
+        Uz = r == 0 ? Gr.y : Uz;
+        Vx = r == 0 ? Gr.z : Vx;
+        Vy = r == 0 ? Gr.w : Vy;
+        Vz = r == 1 ? Gr.x : Vz;
+        N2x = r == 1 ? Gr.y : N2x;
+        N2y = r == 1 ? Gr.z : N2y;
+        N2z = r == 1 ? Gr.w : N2z;
     }
+    const double f2y = row_lerp(b.f2y, ay);
     const double gk = (k * Ux + l * Vx) + q * N2x;
     const double gl = ((k * Uy + l * Vy) + q * N2y) + qf * f2y;
     const double gm = (k * Uz + l * Vz) + q * N2z;
@@ -155,22 +207,27 @@ __device__ inline void rhs(const Grid &g, const BgP<double> &b, const double *Y,
     double cxp = 0.0, cxm = 0.0, cyp = 0.0, cym = 0.0, czp = 0.0, czm = 0.0;
 #pragma unroll 1
     for (int fc = 0; fc < 6; fc++) {
-        const int ax = fc >> 1;
+        const int axn = fc >> 1;
         const double sg = (fc & 1) ? -0.5 : 0.5;
-        double px = x, py = y, pz = z;
-        if (ax == 0)
-            px = x + sg * Dx;
-        else if (ax == 1)
-            py = y + sg * Dy;
+        Axis fx = ax, fy = ay, fz = az;
+        if (axn == 0)
+            fx = axis_x(g, x + sg * Dx);
+        else if (axn == 1)
+            fy = axis_y(g, y + sg * Dy);
         else
-            pz = z + sg * Dz;
-        Cell f;
-        locate(g, px, py, pz, f);
-        const double4 Af = tri4<1>(b.A, f, 0);
-        const double omf = omega_hat(Af.z, Af.w, kh2, m2, K2);
-        const double num = ax == 0 ? k * m2 : (ax == 1 ? l * m2 : m * kh2);
-        const double t = (num * (Af.z - Af.w)) / (omf * K4);
-        const double v = ax == 0 ? Af.x + t : (ax == 1 ? Af.y + t : -t);
+            fz = axis_z(g, z + sg * Dz);
+        const Cell f = cell_of(g, fx, fy, fz);
+        const Corners<1> K(b.A, f, 0);
+        const double N2f = TRI64(K, z, f);
+        const double f2f = axn == 1 ? row_lerp(b.f2, fy) : f2c;
+        const bool useU = axn == 0;
+        const double wnd = lerp3(useU ? K.a0.x : K.a0.y, useU ? K.a1.x : K.a1.y, useU ? K.b0.x : K.b0.y,
+                                 useU ? K.b1.x : K.b1.y, useU ? K.d0.x : K.d0.y, useU ? K.d1.x : K.d1.y,
+                                 useU ? K.e0.x : K.e0.y, useU ? K.e1.x : K.e1.y, f);
+        const double omf = omega_hat(N2f, f2f, kh2, m2, K2);
+        const double num = axn == 0 ? k * m2 : (axn == 1 ? l * m2 : m * kh2);
+        const double t = (num * (N2f - f2f)) / (omf * K4);
+        const double v = axn == 2 ? -t : wnd + t;
         cxp = fc == 0 ? v : cxp;
         cxm = fc == 1 ? v : cxm;
         cyp = fc == 2 ? v : cyp;

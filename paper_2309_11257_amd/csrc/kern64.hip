@@ -84,42 +84,22 @@ void launch_gradients64(const Grid &g, const double *U, const double *V, const d
 }
 
 // packed column-major records (see rt_internal.h) from the [nz][ny][nx] fields
-template <typename T, typename V>
-__global__ void k_pack(Grid g, Bg<double> b, V *A, V *G)
+__global__ void k_pack64(Grid g, Bg<double> b, double4 *A, double4 *G)
 {
     const int64_t cells = (int64_t)g.ncol * g.nz;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // packed index col*nz + k
     if (e >= cells) return;
     const int64_t col = e / g.nz, k = e % g.nz;
     const int64_t s = k * g.ncol + col;  // source index
-    const int j = (int)(col / g.nx);
-    V a, g0, g1, g2;
-    a.x = (T)b.U[s];
-    a.y = (T)b.V[s];
-    a.z = (T)b.N2[s];
-    a.w = (T)b.f2[j];
-    g0.x = (T)b.Ux[s];
-    g0.y = (T)b.Uy[s];
-    g0.z = (T)b.Uz[s];
-    g0.w = (T)b.Vx[s];
-    g1.x = (T)b.Vy[s];
-    g1.y = (T)b.Vz[s];
-    g1.z = (T)b.N2x[s];
-    g1.w = (T)b.N2y[s];
-    g2.x = (T)b.N2z[s];
-    g2.y = (T)b.f2y[j];
-    g2.z = (T)0;
-    g2.w = (T)0;
-    A[e] = a;
-    G[3 * e + 0] = g0;
-    G[3 * e + 1] = g1;
-    G[3 * e + 2] = g2;
+    A[e] = make_double4(b.U[s], b.V[s], b.N2[s], b.Ux[s]);
+    G[2 * e] = make_double4(b.Uy[s], b.Uz[s], b.Vx[s], b.Vy[s]);
+    G[2 * e + 1] = make_double4(b.Vz[s], b.N2x[s], b.N2y[s], b.N2z[s]);
 }
 
 void launch_pack64(const Grid &g, const Bg<double> &b, double4 *A, double4 *G, hipStream_t s)
 {
     const int64_t cells = (int64_t)g.ncol * g.nz;
-    k_pack<double, double4><<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, b, A, G);
+    k_pack64<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, b, A, G);
 }
 
 
@@ -200,7 +180,7 @@ void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCount
 // buffer contiguously, so the state stays grouped by column.
 // ---------------------------------------------------------------------------
 template <bool SPH>
-__global__ __launch_bounds__(256, 2) void k_step64(Grid g, BgP<double> b, S64 src, S64 dst, const uint32_t *__restrict__ perm,
+__global__ __launch_bounds__(256, 2) void k_step64(Grid g, Bg64P b, S64 src, S64 dst, const uint32_t *__restrict__ perm,
                                                 uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc, double dt,
                                                 const uint8_t *__restrict__ frozen, const uint32_t *__restrict__ skeys)
 {
@@ -241,7 +221,7 @@ __global__ __launch_bounds__(256, 2) void k_step64(Grid g, BgP<double> b, S64 sr
     key_out[i] = key;
 }
 
-void launch_step64(const Grid &g, const BgP<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
+void launch_step64(const Grid &g, const Bg64P &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
                    hipStream_t s)
 {
@@ -351,18 +331,18 @@ void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double 
 // ---------------------------------------------------------------------------
 struct Pay64 {
     Grid g;
-    BgP<double> b;
+    Bg64P b;
     S64 st;
     __device__ void load(uint32_t s, double &zb, double &zt, double *bv) const
     {
         const double x = st.x[s], y = st.y[s], z = st.z[s];
         const double k = st.k[s], l = st.l[s], m = st.m[s], Dz = st.dz[s];
         const double W = W64(st, s);
-        d64::Cell c;
-        d64::locate(g, x, y, z, c);
-        const double4 Ac = d64::tri4<1>(b.A, c, 0);
-        const double N2 = Ac.z;
-        const double f2 = Ac.w;
+        const d64::Axis ay = d64::axis_y(g, y);
+        const d64::Cell c = d64::cell_of(g, d64::axis_x(g, x), ay, d64::axis_z(g, z));
+        const d64::Corners<1> K(b.A, c, 0);
+        const double N2 = TRI64(K, z, c);
+        const double f2 = d64::row_lerp(b.f2, ay);
         const double kh2 = k * k + l * l;
         const double m2 = m * m;
         const double K2 = kh2 + m2;
@@ -391,10 +371,10 @@ struct Pay64 {
         l = st.l[s];
         m = st.m[s];
         W = W64(st, s);
-        d64::Cell c;
-        d64::locate(g, st.x[s], st.y[s], st.z[s], c);
-        const double4 Ac = d64::tri4<1>(b.A, c, 0);
-        const double N2 = Ac.z, f2 = Ac.w;
+        const d64::Axis ay = d64::axis_y(g, st.y[s]);
+        const d64::Cell c = d64::cell_of(g, d64::axis_x(g, st.x[s]), ay, d64::axis_z(g, st.z[s]));
+        const d64::Corners<1> K(b.A, c, 0);
+        const double N2 = TRI64(K, z, c), f2 = d64::row_lerp(b.f2, ay);
         const double kh2 = k * k + l * l;
         const double m2 = m * m;
         const double K2 = kh2 + m2;
@@ -411,14 +391,14 @@ struct Pay64 {
     }
 };
 
-void launch_deposit64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_deposit64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s)
 {
     Pay64 p{g, b, st};
     k_deposit<Pay64><<<deposit_blocks(g), 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
 }
 
-void launch_features64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_features64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s)
 {
     Pay64 p{g, b, st};

@@ -24,27 +24,16 @@ struct Bg {
     const double *rho;   // [nz]
 };
 
-// Packed, column-major background used by the step and deposition kernels:
-// for cell (column c, level k) at index c*nz + k
-//   A = (U, V, N2, f^2)
-//   G = (Ux, Uy, Uz, Vx), (Vy, Vz, N2x, N2y), (N2z, (f^2)_y, 0, 0)
-// so a column's levels are contiguous and one trilinear corner costs one
-// 16/32-byte load per record.
-template <typename T>
-struct V4T;
-template <>
-struct V4T<float> {
-    typedef float4 type;
-};
-template <>
-struct V4T<double> {
-    typedef double4 type;
-};
-
-template <typename T>
-struct BgP {
-    const typename V4T<T>::type *A;  // [ncol*nz]
-    const typename V4T<T>::type *G;  // [ncol*nz*3]
+// Packed double-precision background for cell (column c, level k) at index
+// c*nz + k:  A = (U, V, N2, Ux), G = (Uy, Uz, Vx, Vy), (Vz, N2x, N2y, N2z);
+// f^2 and (f^2)_y by latitude row [ny] (their trilinear interpolation of the
+// row-replicated field equals the linear one between rows, bit for bit).
+// A column's levels are contiguous; a trilinear corner costs one 32-byte load
+// per record.
+struct Bg64P {
+    const double4 *A;  // [ncol*nz]
+    const double4 *G;  // [ncol*nz*2]
+    const double *f2, *f2y;
 };
 
 // Packed single-precision background for cell (column c, level k) at index
@@ -96,7 +85,7 @@ struct rt_ctx_s {
     bool have_bg;
     Bg<double> bg64;
     Bg<float> bg32;
-    BgP<double> bp64;
+    Bg64P bp64;
     Bg32P bp32;
     double *rho;
     // state: double buffers
@@ -172,13 +161,13 @@ void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCount
 void launch_store32(const Grid &g, S32 src, const uint32_t *perm, const DevCounters *dc, rt_rays out,
                     int64_t bound, hipStream_t s);
 
-void launch_step64(const Grid &g, const BgP<double> &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
+void launch_step64(const Grid &g, const Bg64P &b, S64 src, S64 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
                    hipStream_t s);
 void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
                    const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
                    hipStream_t s);
-void launch_features64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_features64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s);
 void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s);
@@ -200,7 +189,7 @@ void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t 
 void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 
-void launch_deposit64(const Grid &g, const BgP<double> &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
+void launch_deposit64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s);
 void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s);

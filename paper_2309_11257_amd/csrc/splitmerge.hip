@@ -53,6 +53,7 @@ __device__ inline double metric_y(const Grid &g, double z, double D)
 // --- double-precision storage ----------------------------------------------
 struct IO64 {
     S64 s;
+    const double *f2r;  // f^2 by latitude row
     __device__ RayD get(const Grid &g, uint32_t i) const
     {
         RayD r;
@@ -140,14 +141,15 @@ struct IO64 {
     }
     __device__ double energy(const Grid &g, const double4 *bA, uint32_t i) const
     {
-        d64::Cell c;
-        d64::locate(g, s.x[i], s.y[i], s.z[i], c);
-        const double4 A = d64::tri4<1>(bA, c, 0);
+        const d64::Axis ay = d64::axis_y(g, s.y[i]);
+        const d64::Cell c = d64::cell_of(g, d64::axis_x(g, s.x[i]), ay, d64::axis_z(g, s.z[i]));
+        const d64::Corners<1> K(bA, c, 0);
+        const double N2 = TRI64(K, z, c), f2 = d64::row_lerp(f2r, ay);
         const double k = s.k[i], l = s.l[i], m = s.m[i];
         const double kh2 = k * k + l * l;
         const double m2 = m * m;
         const double K2 = kh2 + m2;
-        const double om = d64::omega_hat(A.z, A.w, kh2, m2, K2);
+        const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
         return om * (((s.n[i] * s.px[i]) * s.py[i]) * s.pz[i]);
     }
 };
@@ -730,7 +732,8 @@ rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, r
     prof_begin(ctx, PC_SPLIT);
     rt_status r;
     if (ctx->precision == RT_FP64)
-        r = split_merge_impl<IO64, double4>(ctx, IO64{ctx->s64[ctx->cur]}, IO64{ctx->s64[1 - ctx->cur]}, ctx->bp64.A,
+        r = split_merge_impl<IO64, double4>(ctx, IO64{ctx->s64[ctx->cur], ctx->bp64.f2},
+                                            IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2}, ctx->bp64.A,
                                             alpha, nmax, mode);
     else
         r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2},
