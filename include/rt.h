@@ -100,7 +100,7 @@ typedef struct {
 
 /* Create a context on the current HIP device.  The grid and precision are
    fixed for the context's lifetime.  Errors: RT_E_ARG for bad sizes;
-   RT_E_UNSUPPORTED for nz > 1024 and, in single precision, for grids of
+   RT_E_UNSUPPORTED for nz > 640 and, in single precision, for grids of
    2^24 columns or more or nx*ny*nz >= 2^27 cells (32-bit offsets into the
    packed background). */
 rt_status rt_create(const rt_config *cfg, rt_ctx *out);

@@ -157,7 +157,7 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return RT_E_ARG;
     if ((int64_t)cfg->nx * cfg->ny > (int64_t)0x7ffffff0) return RT_E_ARG;
     if ((int64_t)cfg->nx * cfg->ny * cfg->nz > (int64_t)0x7ffffff0) return RT_E_ARG;
-    if (cfg->nz > 1024) return RT_E_UNSUPPORTED;
+    if (cfg->nz > 640) return RT_E_UNSUPPORTED;  // per-column deposition profiles in 64 KiB of LDS
     if (!(cfg->dx > 0 && cfg->dy > 0 && cfg->dz > 0)) return RT_E_ARG;
     if (cfg->geometry == RT_SPHERICAL && !(cfg->a > 0)) return RT_E_ARG;
     if (cfg->capacity < 0 || cfg->capacity > (int64_t)0xffffff00) return RT_E_ARG;
@@ -271,12 +271,19 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     ALLOC(ctx->flux, double, (int64_t)6 * (g.nz + 1) * g.ncol);
     ALLOC(ctx->drag, double, 2 * cells);
     ALLOC(ctx->frozen, uint8_t, g.ncol);
+    ALLOC(ctx->coslat, double, g.ny);
     ALLOC(ctx->dc, DevCounters, 1);
     ALLOC(ctx->red, double, 8 + 4 * (cap / 256 + 2));
     ALLOC(ctx->ired, int64_t, 8 + 2 * cap);
     ALLOC(ctx->sm, uint32_t, 8 * cap + 16 + scan_tmp_len(cap));
     if (hipMemsetAsync(ctx->dc, 0, sizeof(DevCounters), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->colstart, 0, sizeof(uint32_t) * ((size_t)g.ncol + 1), ctx->stream) != hipSuccess) {
+        ctx_release(ctx);
+        delete ctx;
+        return RT_E_DEVICE;
+    }
+    launch_coslat(g, ctx->coslat, ctx->stream);
+    if (hipGetLastError() != hipSuccess) {
         ctx_release(ctx);
         delete ctx;
         return RT_E_DEVICE;
@@ -533,7 +540,7 @@ extern "C" rt_status rt_deposit_flux(rt_ctx ctx, double *flux, double *drag, int
         launch_deposit32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
     prof_end(ctx);
     prof_begin(ctx, PC_DRAG);
-    launch_drag(g, ctx->rho, fdst, ddst, ctx->stream);
+    launch_drag(g, ctx->rho, ctx->coslat, fdst, ddst, ctx->stream);
     prof_end(ctx);
     HIP_OK(hipGetLastError());
     if (where == RT_HOST) {

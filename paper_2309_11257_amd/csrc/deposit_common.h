@@ -1,25 +1,22 @@
 // Per-column flux deposition shared by both precisions.
 //
-// Ray volumes arrive grouped by column (radix sort on the column key).  One
-// 256-thread workgroup owns DEP_CPW consecutive columns and, column after
-// column, walks each column's volumes in chunks of 256 in sorted order; the
-// finished profiles are written together so that the DEP_CPW columns of one
-// (field, level) row form one 32-byte segment of the [6][nz+1][ncol] output.  Within a chunk every contribution is converted to an
-// integer in a fixed-point format chosen from the chunk's largest
-// contribution (2^51 units for that value) and added into an int64 profile in
-// LDS; integer addition is associative, so the chunk total does not depend on
-// the order in which lanes arrive.  Chunk totals are added to a double
-// profile in chunk order.  The result is therefore bitwise reproducible from
-// run to run, with no floating-point atomics, and each contribution is
-// rounded once at the level of the chunk maximum's last bit -- the accuracy of
-// an ordinary double sum.
+// Ray volumes arrive grouped by column (radix sort on the column key).  A
+// workgroup of CPW waves owns CPW consecutive columns, one per wave (CPW = 4,
+// or 1 when four columns' profiles would not fit 64 KiB of LDS);
+// each wave walks its column's volumes in chunks of 64 in sorted order.
+// Within a chunk every contribution is converted to an integer in a
+// fixed-point format chosen from the chunk's largest possible contribution
+// (below 2^51 units) and added into an int64 profile in the wave's LDS;
+// integer addition is associative, so the chunk total does not depend on the
+// order in which lanes arrive.  Chunk totals are added to a double profile in
+// chunk order.  The result is therefore bitwise reproducible from run to run,
+// with no floating-point atomics, and each contribution is rounded once at
+// the level of the chunk maximum's last bit -- the accuracy of an ordinary
+// double sum.  At the end the finished profiles are written together, so
+// that the columns of one (field, level) row form one contiguous segment of
+// the [6][nz+1][ncol] output.
 #pragma once
 #include "rt_internal.h"
-
-// P::load(slot, zb, zt, bv[6]) fills the vertical span of the volume and its
-// six flux densities per unit height: (cgx k, cgx l, cgy k, cgy l, cgz k,
-// cgz l) * W / Dz.
-#define DEP_CPW 4
 
 // round x * scale (scale a power of two, |x * scale| <= 2^51) to the nearest
 // integer, ties to even: adding 1.5 * 2^52 puts the integer part in the low
@@ -31,103 +28,131 @@ __device__ inline long long to_fixed(double x, double scale)
     return (long long)(__double_as_longlong(y) - __double_as_longlong(magic));
 }
 
-template <class P>
-__global__ __launch_bounds__(256) void k_deposit(Grid g, P pl, const uint32_t *__restrict__ perm,
-                                                 const uint32_t *__restrict__ colstart, double *__restrict__ flux)
+// biased binary exponent of |x| (0 for zero)
+__device__ inline int bexp(double x) { return (int)((__double_as_longlong(x) >> 52) & 0x7ff); }
+
+__device__ inline int wave_max_i(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ inline int wave_min_i(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// ordering of this wave's LDS accesses across its lanes
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// P::load(slot, zb, zt, bv[6]) fills the vertical span of the volume and its
+// six flux densities per unit height: (cgx k, cgx l, cgy k, cgy l, cgz k,
+// cgz l) * W / Dz.
+template <class P, int CPW>
+__global__ __launch_bounds__(64 * CPW) void k_deposit(Grid g, P pl, const uint32_t *__restrict__ perm,
+                                                      const uint32_t *__restrict__ colstart, double *__restrict__ flux)
 {
     extern __shared__ unsigned long long dep_smem[];
     const int nzp = g.nz + 1;
-    unsigned long long *acc = dep_smem;                   // [6][nzp]
-    double *profs = (double *)(dep_smem + 6 * nzp);       // [DEP_CPW][6][nzp]
-    __shared__ double wmax[4][6];
-    __shared__ int sexp[6];
-    const int c_first = blockIdx.x * DEP_CPW;
-    const int ncols = min(DEP_CPW, g.ncol - c_first);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < 6 * nzp; e += 256) acc[e] = 0ull;
-    for (int e = tid; e < DEP_CPW * 6 * nzp; e += 256) profs[e] = 0.0;
-    __syncthreads();
-    for (int cl = 0; cl < ncols; cl++) {
-        const int c = c_first + cl;
-        double *prof = profs + (size_t)cl * 6 * nzp;
+    unsigned long long *acc = dep_smem + (size_t)wave * 6 * nzp;            // this wave's [6][nzp]
+    double *profs = (double *)(dep_smem + (size_t)CPW * 6 * nzp);      // [CPW][6][nzp]
+    double *prof = profs + (size_t)wave * 6 * nzp;
+    const int c_first = blockIdx.x * CPW;
+    const int ncols = min(CPW, g.ncol - c_first);
+    for (int e = lane; e < 6 * nzp; e += 64) {
+        acc[e] = 0ull;
+        prof[e] = 0.0;
+    }
+    wave_sync();
+    if (wave < ncols) {
+        const int c = c_first + wave;
         const uint32_t s0 = colstart[c], s1 = colstart[c + 1];
-        for (uint32_t base = s0; base < s1; base += 256) {
-            const uint32_t r = base + (uint32_t)tid;
+        for (uint32_t base = s0; base < s1; base += 64) {
+            const uint32_t r = base + (uint32_t)lane;
             const bool valid = r < s1;
             double zb = 0.0, zt = 0.0, bv[6] = {0, 0, 0, 0, 0, 0};
             if (valid) pl.load(perm[r], zb, zt, bv);
             const double h = valid ? fmin(zt - zb, g.dz) : 0.0;
-            double mv[6];
-    #pragma unroll
-            for (int q = 0; q < 6; q++) mv[q] = fabs(bv[q]) * h;
-    #pragma unroll
-            for (int q = 0; q < 6; q++)
-                for (int off = 32; off > 0; off >>= 1) mv[q] = fmax(mv[q], __shfl_xor(mv[q], off, 64));
-            if (lane == 0)
-    #pragma unroll
-                for (int q = 0; q < 6; q++) wmax[wave][q] = mv[q];
-            __syncthreads();
-            if (tid < 6) {
-                double m = fmax(fmax(wmax[0][tid], wmax[1][tid]), fmax(wmax[2][tid], wmax[3][tid]));
-                int e = 0;
-                if (m > 0.0 && m < 1.0e300) {
-                    frexp(m, &e);
-                    sexp[tid] = 51 - e;
-                } else {
-                    sexp[tid] = 0;
-                }
+            // per field: the largest possible contribution of the chunk sets
+            // the fixed-point scale (a bound on each |bv * overlap|)
+            double sc[6];
+            int sx[6];
+#pragma unroll
+            for (int q = 0; q < 6; q++) {
+                const int em = wave_max_i(bexp(fabs(bv[q]) * h));
+                sx[q] = (em > 0 && em < 0x7fe) ? 51 - (em - 1022) : 0;
+                sc[q] = ldexp(1.0, sx[q]);
             }
-            __syncthreads();
+            int klo = 0x7fffffff, khi = -1;
             if (valid) {
-                double sc[6];
-    #pragma unroll
-                for (int q = 0; q < 6; q++) sc[q] = ldexp(1.0, sexp[q]);
-                int klo = (int)floor(zb / g.dz), khi = (int)floor(zt / g.dz);
-                if (klo < 0) klo = 0;
-                if (khi > g.nz - 1) khi = g.nz - 1;
-                for (int kk = klo; kk <= khi; kk++) {
-                    const double lo = (double)kk * g.dz, hi = (double)(kk + 1) * g.dz;
-                    const double o = fmin(zt, hi) - fmax(zb, lo);
+                int lo = (int)floor(zb / g.dz), hi = (int)floor(zt / g.dz);
+                if (lo < 0) lo = 0;
+                if (hi > g.nz - 1) hi = g.nz - 1;
+                for (int kk = lo; kk <= hi; kk++) {
+                    const double lv = (double)kk * g.dz, hv = (double)(kk + 1) * g.dz;
+                    const double o = fmin(zt, hv) - fmax(zb, lv);
                     if (!(o > 0.0)) continue;
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < 4; q++) {
                         const long long v = to_fixed(bv[q] * o, sc[q]);
                         if (v) atomicAdd(&acc[q * nzp + kk], (unsigned long long)v);
                     }
                 }
-                klo = (int)floor(zb / g.dz + 0.5);
-                khi = (int)floor(zt / g.dz + 0.5);
-                if (klo < 0) klo = 0;
-                if (khi > g.nz) khi = g.nz;
-                for (int kk = klo; kk <= khi; kk++) {
-                    double lo = ((double)kk - 0.5) * g.dz, hi = ((double)kk + 0.5) * g.dz;
-                    if (lo < 0.0) lo = 0.0;
-                    if (hi > g.Lz) hi = g.Lz;
-                    const double o = fmin(zt, hi) - fmax(zb, lo);
+                klo = lo;
+                int lo2 = (int)floor(zb / g.dz + 0.5), hi2 = (int)floor(zt / g.dz + 0.5);
+                if (lo2 < 0) lo2 = 0;
+                if (hi2 > g.nz) hi2 = g.nz;
+                for (int kk = lo2; kk <= hi2; kk++) {
+                    double lv = ((double)kk - 0.5) * g.dz, hv = ((double)kk + 0.5) * g.dz;
+                    if (lv < 0.0) lv = 0.0;
+                    if (hv > g.Lz) hv = g.Lz;
+                    const double o = fmin(zt, hv) - fmax(zb, lv);
                     if (!(o > 0.0)) continue;
-    #pragma unroll
+#pragma unroll
                     for (int q = 4; q < 6; q++) {
                         const long long v = to_fixed(bv[q] * o, sc[q]);
                         if (v) atomicAdd(&acc[q * nzp + kk], (unsigned long long)v);
                     }
                 }
+                klo = min(klo, lo2);
+                khi = max(hi, hi2);
             }
-            __syncthreads();
-            for (int e = tid; e < 6 * nzp; e += 256) {
-                const long long v = (long long)acc[e];
-                if (v) {
-                    prof[e] += ldexp((double)v, -sexp[e / nzp]);
-                    acc[e] = 0ull;
+            // move the chunk's integer sums into the double profile, levels
+            // the chunk touched only
+            const int k0 = wave_min_i(klo), k1 = wave_max_i(khi);
+            wave_sync();
+            if (k1 >= k0) {
+                const int span = k1 - k0 + 1;
+                for (int e = lane; e < 6 * span; e += 64) {
+                    const int q = e / span, kk = k0 + e % span;
+                    const int at = q * nzp + kk;
+                    const long long v = (long long)acc[at];
+                    if (v) {
+                        int sq = sx[0];
+#pragma unroll
+                        for (int t = 1; t < 6; t++) sq = q == t ? sx[t] : sq;
+                        prof[at] += ldexp((double)v, -sq);
+                        acc[at] = 0ull;
+                    }
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
-    }  // columns of this workgroup
+    }
+    __syncthreads();
     // divide by the cell volume (levels) or staggered-cell volume (interfaces);
     // consecutive threads take consecutive columns of one (field, level) row
-    for (int e = tid; e < DEP_CPW * 6 * nzp; e += 256) {
-        const int cl = e % DEP_CPW, qk = e / DEP_CPW;
+    for (int e = tid; e < CPW * 6 * nzp; e += 64 * CPW) {
+        const int cl = e % CPW, qk = e / CPW;
         const int q = qk / nzp, kk = qk % nzp;
         if (cl >= ncols) continue;
         const int c = c_first + cl;
@@ -162,5 +187,17 @@ __global__ __launch_bounds__(256) void k_deposit(Grid g, P pl, const uint32_t *_
     }
 }
 
-inline size_t deposit_smem(const Grid &g) { return (size_t)(6 + 6 * DEP_CPW) * (size_t)(g.nz + 1) * 8; }
-inline unsigned deposit_blocks(const Grid &g) { return (unsigned)((g.ncol + DEP_CPW - 1) / DEP_CPW); }
+template <int CPW>
+inline size_t deposit_smem(const Grid &g) { return (size_t)(12 * CPW) * (size_t)(g.nz + 1) * 8; }
+
+// launch with four columns per workgroup when their profiles fit 64 KiB of
+// LDS, else one
+template <class P>
+inline void launch_deposit_k(const Grid &g, const P &p, const uint32_t *perm, const uint32_t *colstart, double *flux,
+                             hipStream_t s)
+{
+    if (deposit_smem<4>(g) <= 65536)
+        k_deposit<P, 4><<<(unsigned)((g.ncol + 3) / 4), 256, deposit_smem<4>(g), s>>>(g, p, perm, colstart, flux);
+    else
+        k_deposit<P, 1><<<(unsigned)g.ncol, 64, deposit_smem<1>(g), s>>>(g, p, perm, colstart, flux);
+}

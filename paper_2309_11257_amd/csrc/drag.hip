@@ -4,11 +4,24 @@
 // (periodic; on the sphere (1/(r cos phi)) [d_lambda Fx + d_phi(cos phi Fy)]
 // with one-sided differences at the first and last rows), vertical
 // divergence as the difference of the interface fluxes across the level.
-// One thread per cell; HBM-bound stencil.  Built with -ffp-contract=off.
+// One thread per cell; HBM-bound stencil.  The cosines of the row-centre
+// latitudes come from a per-row table (the same cos() of the same argument,
+// computed once).  Built with -ffp-contract=off.
 #include "rt_internal.h"
 
-__global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__ rho, const double *__restrict__ flux,
-                                              double *__restrict__ drag)
+__global__ void k_coslat(Grid g, double *cosr)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < g.ny) cosr[j] = cos(g.y0 + ((double)j + 0.5) * g.dy);
+}
+
+void launch_coslat(const Grid &g, double *cosr, hipStream_t s)
+{
+    k_coslat<<<(unsigned)((g.ny + 255) / 256), 256, 0, s>>>(g, cosr);
+}
+
+__global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__ rho, const double *__restrict__ cosr,
+                                              const double *__restrict__ flux, double *__restrict__ drag)
 {
     const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -32,21 +45,21 @@ __global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__
             divy = (Fy[at + (jp - j) * row] - Fy[at + (jm - j) * row]) / (2.0 * g.dy);
         } else {
             const double r = g.a + ((double)k + 0.5) * g.dz;
-            const double cj = cos(g.y0 + ((double)j + 0.5) * g.dy);
+            const double cj = cosr[j];
             const double rc = r * cj;
             double dphi;
             divx = ((Fx[at - i + ip] - Fx[at - i + im]) / (2.0 * g.dx)) / rc;
             if (g.ny == 1) {
                 dphi = 0.0;
             } else if (j == 0) {
-                const double c1 = cos(g.y0 + 1.5 * g.dy);
+                const double c1 = cosr[1];
                 dphi = (c1 * Fy[at + row] - cj * Fy[at]) / g.dy;
             } else if (j == g.ny - 1) {
-                const double cm = cos(g.y0 + ((double)j - 0.5) * g.dy);
+                const double cm = cosr[j - 1];
                 dphi = (cj * Fy[at] - cm * Fy[at - row]) / g.dy;
             } else {
-                const double cp = cos(g.y0 + ((double)j + 1.5) * g.dy);
-                const double cm = cos(g.y0 + ((double)j - 0.5) * g.dy);
+                const double cp = cosr[j + 1];
+                const double cm = cosr[j - 1];
                 dphi = (cp * Fy[at + row] - cm * Fy[at - row]) / (2.0 * g.dy);
             }
             divy = dphi / rc;
@@ -55,8 +68,8 @@ __global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__
     }
 }
 
-void launch_drag(const Grid &g, const double *rho, const double *flux, double *drag, hipStream_t s)
+void launch_drag(const Grid &g, const double *rho, const double *cosr, const double *flux, double *drag, hipStream_t s)
 {
     const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
-    k_drag<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, rho, flux, drag);
+    k_drag<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, rho, cosr, flux, drag);
 }

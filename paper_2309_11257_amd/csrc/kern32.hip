@@ -735,7 +735,7 @@ void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *per
                       double *flux, hipStream_t s)
 {
     Pay32 p{f32::make_g32(g), b, st, g.dz};
-    k_deposit<Pay32><<<deposit_blocks(g), 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
+    launch_deposit_k(g, p, perm, colstart, flux, s);
 }
 
 void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,

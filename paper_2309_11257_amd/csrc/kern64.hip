@@ -395,7 +395,7 @@ void launch_deposit64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *per
                       double *flux, hipStream_t s)
 {
     Pay64 p{g, b, st};
-    k_deposit<Pay64><<<deposit_blocks(g), 256, deposit_smem(g), s>>>(g, p, perm, colstart, flux);
+    launch_deposit_k(g, p, perm, colstart, flux, s);
 }
 
 void launch_features64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,

@@ -88,6 +88,7 @@ struct rt_ctx_s {
     Bg64P bp64;
     Bg32P bp32;
     double *rho;
+    double *coslat;  // cos of the row-centre latitudes [ny] (spherical drag)
     // state: double buffers
     S64 s64[2];
     S32 s32[2];
@@ -193,7 +194,8 @@ void launch_deposit64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *per
                       double *flux, hipStream_t s);
 void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s);
-void launch_drag(const Grid &g, const double *rho, const double *flux, double *drag, hipStream_t s);
+void launch_drag(const Grid &g, const double *rho, const double *cosr, const double *flux, double *drag, hipStream_t s);
+void launch_coslat(const Grid &g, double *cosr, hipStream_t s);
 
 void launch_copy_n(const uint32_t *src, uint32_t *dst, const DevCounters *dc, int64_t bound, hipStream_t s);
 void launch_set_sorted(DevCounters *dc, int64_t n, hipStream_t s);
