@@ -112,7 +112,8 @@ rt_status sg_targets(sg_net net, const double *drag, const float *mean, const fl
  * Untrusted columns are left as they are.
  *   Yens [n_members][n_cols][n_out] float32; mean, std [n_out] float32;
  *   mask [n_cols] uint8; drag [2][nz][n_cols] float64 (the layout of
- *   rt_deposit_flux's drag, columns j*nx + i).  All device pointers. */
+ *   rt_deposit_flux's drag, columns j*nx + i).  All device pointers.
+ * RT_E_UNSUPPORTED for n_out > 256. */
 rt_status sg_apply_drag(sg_net net, const float *Yens, const float *mean, const float *std, const uint8_t *mask,
                         int32_t n_cols, int32_t nz, double *drag);
 

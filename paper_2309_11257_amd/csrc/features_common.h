@@ -1,13 +1,13 @@
 // Per-column surrogate features, shared by both precisions.
 //
-// One 256-thread workgroup per column, as in the deposition: the column's ray
-// volumes (sorted order) are dealt to the threads round-robin; each thread
-// keeps its 8 sectors x 4 moments in registers (selected without indexing,
-// so nothing spills), and the workgroup combines them in a fixed order
-// (wave butterflies, then the four waves in turn), so the result does not
-// depend on scheduling.  The profile part copies U, V, N2 of the column from
-// the packed background.  Per sector: sum W, sum |cg_z| k_h W, W-weighted
-// means of log10 k_h, log10 |m| and z, W-weighted standard deviation of z.
+// One wave per column (four columns per 256-thread workgroup), as in the
+// deposition: the column's ray volumes (sorted order) are dealt to the lanes
+// round-robin; each lane keeps its 8 sectors x 6 moments in registers
+// (selected without indexing, so nothing spills), and the wave combines them
+// by a fixed butterfly, so the result does not depend on scheduling.  The
+// profile part copies U, V, N2 of the column from the packed background.
+// Per sector: sum W, sum |cg_z| k_h W, W-weighted means of log10 k_h,
+// log10 |m| and z, W-weighted standard deviation of z.
 #pragma once
 #include "rt_internal.h"
 
@@ -28,11 +28,11 @@ template <class P>
 __global__ __launch_bounds__(256) void k_features(Grid g, P pl, const uint32_t *__restrict__ perm,
                                                   const uint32_t *__restrict__ colstart, float *__restrict__ X)
 {
-    __shared__ double part[4][48];
-    const int c = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= g.ncol) return;  // whole wave
     const int nf = 3 * g.nz + 48;
-    for (int k = tid; k < g.nz; k += 256) {
+    for (int k = lane; k < g.nz; k += 64) {
         double u, v, n2;
         pl.profile(c, k, u, v, n2);
         X[(int64_t)c * nf + k] = (float)u;
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_features(Grid g, P pl, const uint32_t *
 #pragma unroll
     for (int q = 0; q < 48; q++) acc[q] = 0.0;
     const uint32_t s0 = colstart[c], s1 = colstart[c + 1];
-    for (uint32_t r = s0 + (uint32_t)tid; r < s1; r += 256) {
+    for (uint32_t r = s0 + (uint32_t)lane; r < s1; r += 64) {
         double k, l, m, W, cgz, z;
         pl.spec(perm[r], k, l, m, W, cgz, z);
         const double kh = sqrt(k * k + l * l);
@@ -57,19 +57,17 @@ __global__ __launch_bounds__(256) void k_features(Grid g, P pl, const uint32_t *
         }
     }
 #pragma unroll
-    for (int q = 0; q < 48; q++) {
-        double v = acc[q];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) part[wave][q] = v;
-    }
-    __syncthreads();
-    if (tid < 48) {
-        const double tot = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
-        part[0][tid] = tot;  // each thread rewrites only its own entry after reading it
-    }
-    __syncthreads();
-    if (tid < 8) {
-        const double *p = &part[0][6 * tid];
+    for (int q = 0; q < 48; q++)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+    if (lane < 8) {  // lane s writes sector s
+        double p[6];
+#pragma unroll
+        for (int q = 0; q < 6; q++) {
+            p[q] = acc[q];
+#pragma unroll
+            for (int t = 1; t < 8; t++) p[q] = lane == t ? acc[6 * t + q] : p[q];
+        }
         float o[6] = {(float)p[0], (float)p[1], 0.0f, 0.0f, 0.0f, 0.0f};
         if (p[0] > 0.0) {
             const double zm = p[4] / p[0];
@@ -80,6 +78,6 @@ __global__ __launch_bounds__(256) void k_features(Grid g, P pl, const uint32_t *
             o[5] = (float)(var > 0.0 ? sqrt(var) : 0.0);
         }
 #pragma unroll
-        for (int q = 0; q < 6; q++) X[(int64_t)c * nf + 3 * g.nz + 6 * tid + q] = o[q];
+        for (int q = 0; q < 6; q++) X[(int64_t)c * nf + 3 * g.nz + 6 * lane + q] = o[q];
     }
 }

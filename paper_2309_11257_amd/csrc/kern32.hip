@@ -742,5 +742,5 @@ void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *pe
                        float *X, hipStream_t s)
 {
     Pay32 p{f32::make_g32(g), b, st, g.dz};
-    k_features<Pay32><<<(unsigned)g.ncol, 256, 0, s>>>(g, p, perm, colstart, X);
+    k_features<Pay32><<<(unsigned)((g.ncol + 3) / 4), 256, 0, s>>>(g, p, perm, colstart, X);
 }

@@ -402,5 +402,5 @@ void launch_features64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *pe
                        float *X, hipStream_t s)
 {
     Pay64 p{g, b, st};
-    k_features<Pay64><<<(unsigned)g.ncol, 256, 0, s>>>(g, p, perm, colstart, X);
+    k_features<Pay64><<<(unsigned)((g.ncol + 3) / 4), 256, 0, s>>>(g, p, perm, colstart, X);
 }

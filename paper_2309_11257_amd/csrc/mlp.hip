@@ -297,13 +297,17 @@ __global__ void k_init(float *w, int64_t n, int64_t wcount, float bound, uint64_
 
 // gate: spread = sqrt(mean over outputs of the ensemble variance); trusted
 // if spread <= tau and all features inside the training range
-__global__ void k_gate(const float *Y, const float *X, const float *fmin, const float *fmax, int nm, int nc, int nout,
-                       int nin, float tau, float *spread, uint8_t *mask)
+// gate: one wave per column; lanes take outputs and features round-robin,
+// partial sums are combined by a fixed butterfly (deterministic)
+__global__ __launch_bounds__(256) void k_gate(const float *Y, const float *X, const float *fmin, const float *fmax,
+                                              int nm, int nc, int nout, int nin, float tau, float *spread,
+                                              uint8_t *mask)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= nc) return;  // whole wave
     double s2 = 0.0;
-    for (int o = 0; o < nout; o++) {
+    for (int o = lane; o < nout; o += 64) {
         double mu = 0.0;
         for (int m = 0; m < nm; m++) mu += Y[((int64_t)m * nc + c) * nout + o];
         mu /= nm;
@@ -314,14 +318,21 @@ __global__ void k_gate(const float *Y, const float *X, const float *fmin, const 
         }
         s2 += nm > 1 ? v / (nm - 1) : 0.0;
     }
-    const double sp = sqrt(s2 / nout);
-    bool inside = true;
-    for (int f = 0; f < nin; f++) {
+    int inside = 1;
+    for (int f = lane; f < nin; f += 64) {
         const float x = X[(int64_t)c * nin + f];
-        inside = inside && x >= fmin[f] && x <= fmax[f];
+        inside &= (x >= fmin[f] && x <= fmax[f]) ? 1 : 0;
     }
-    if (spread) spread[c] = (float)sp;
-    mask[c] = (inside && sp <= (double)tau) ? 1 : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        s2 += __shfl_xor(s2, off, 64);
+        inside &= __shfl_xor(inside, off, 64);
+    }
+    if (lane == 0) {
+        const double sp = sqrt(s2 / nout);
+        if (spread) spread[c] = (float)sp;
+        mask[c] = (inside && sp <= (double)tau) ? 1 : 0;
+    }
 }
 
 __global__ void k_standardize(const float *X, const float *mean, const float *std, const float *lg, int64_t n,
@@ -345,17 +356,28 @@ __global__ void k_targets(const double *drag, const float *mean, const float *st
     T[i] = (float)((drag[(int64_t)o * nc + c] - (double)mean[o]) / (double)std[o]);
 }
 
-// drag[o][c] <- ensemble mean of de-standardised outputs where mask[c]
-__global__ void k_apply_drag(const float *Y, const float *mean, const float *std, const uint8_t *mask, int nm, int nc,
-                             int nout, double *drag)
+// drag[o][c] <- ensemble mean of de-standardised outputs where mask[c]:
+// a block takes 32 columns, reads their output rows contiguously and writes
+// the drag rows contiguously, transposing through LDS
+#define APPLY_COLS 32
+__global__ __launch_bounds__(256) void k_apply_drag(const float *Y, const float *mean, const float *std,
+                                                    const uint8_t *mask, int nm, int nc, int nout, double *drag)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)nc * nout) return;
-    const int c = (int)(i % nc), o = (int)(i / nc);
-    if (!mask[c]) return;
-    double s = 0.0;
-    for (int m = 0; m < nm; m++) s += (double)Y[((int64_t)m * nc + c) * nout + o] * std[o] + mean[o];
-    drag[i] = s / nm;
+    extern __shared__ double ap_tile[];  // [APPLY_COLS][nout]
+    const int c0 = blockIdx.x * APPLY_COLS;
+    const int ncols = min(APPLY_COLS, nc - c0);
+    for (int e = threadIdx.x; e < ncols * nout; e += 256) {
+        const int cl = e / nout, o = e % nout;
+        double s = 0.0;
+        if (mask[c0 + cl])
+            for (int m = 0; m < nm; m++) s += (double)Y[((int64_t)m * nc + c0 + cl) * nout + o] * std[o] + mean[o];
+        ap_tile[cl * nout + o] = s / nm;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ncols * nout; e += 256) {
+        const int o = e / ncols, cl = e % ncols;
+        if (mask[c0 + cl]) drag[(int64_t)o * nc + c0 + cl] = ap_tile[cl * nout + o];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -714,8 +736,8 @@ extern "C" rt_status sg_gate(sg_net n, const float *Yens, const float *Xraw, con
 {
     if (!n || !Yens || !Xraw || !fmin || !fmax || !mask || n_cols < 0) return sg_fail(n, RT_E_ARG, "bad sg_gate arguments");
     if (n_cols == 0) return RT_OK;
-    k_gate<<<nblk(n_cols), 256, 0, n->stream>>>(Yens, Xraw, fmin, fmax, n->cfg.n_members, n_cols, n->cfg.n_out,
-                                                n->cfg.n_in, tau, spread, mask);
+    k_gate<<<(unsigned)((n_cols + 3) / 4), 256, 0, n->stream>>>(Yens, Xraw, fmin, fmax, n->cfg.n_members, n_cols,
+                                                               n->cfg.n_out, n->cfg.n_in, tau, spread, mask);
     SG_HIP(hipGetLastError());
     return RT_OK;
 }
@@ -740,8 +762,11 @@ extern "C" rt_status sg_apply_drag(sg_net n, const float *Yens, const float *mea
     if (nz < 1 || 2 * nz != n->cfg.n_out) return sg_fail(n, RT_E_ARG, "n_out must equal 2*nz");
     const int64_t tot = (int64_t)n_cols * n->cfg.n_out;
     if (tot == 0) return RT_OK;
-    k_apply_drag<<<nblk(tot), 256, 0, n->stream>>>(Yens, mean, std, mask, n->cfg.n_members, n_cols, n->cfg.n_out,
-                                                    drag);
+    if ((size_t)APPLY_COLS * n->cfg.n_out * sizeof(double) > 65536) return sg_fail(n, RT_E_UNSUPPORTED, "n_out too large");
+    k_apply_drag<<<(unsigned)((n_cols + APPLY_COLS - 1) / APPLY_COLS), 256,
+                   (size_t)APPLY_COLS * n->cfg.n_out * sizeof(double), n->stream>>>(Yens, mean, std, mask,
+                                                                                   n->cfg.n_members, n_cols,
+                                                                                   n->cfg.n_out, drag);
     SG_HIP(hipGetLastError());
     return RT_OK;
 }
