@@ -41,8 +41,12 @@ STEP_FLOPS = {"cartesian": 2200, "spherical": 2300}
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
-KERNEL_SOURCES = {"step": ["paper_2309_11257_amd/csrc/kern32.hip"],
-                  "deposit": ["paper_2309_11257_amd/csrc/deposit_common.h", "paper_2309_11257_amd/csrc/kern32.hip"]}
+# sources the counted kernels are built from (their HBM traffic in
+# profiles/traffic.json is used only while these are unchanged)
+KERNEL_SOURCES = {"step": ["paper_2309_11257_amd/csrc/f32.h", "paper_2309_11257_amd/csrc/step32.hip",
+                           "paper_2309_11257_amd/csrc/rt_internal.h"],
+                  "deposit": ["paper_2309_11257_amd/csrc/deposit_common.h", "paper_2309_11257_amd/csrc/kern32.hip",
+                              "paper_2309_11257_amd/csrc/f32.h", "paper_2309_11257_amd/csrc/rt_internal.h"]}
 
 
 def log(*a):

@@ -1,6 +1,6 @@
 """Build the gfx950 HIP library librt.so in-tree with hipcc.
 
-Every translation unit except the single-precision step kernels is built
+Every translation unit except the single-precision kernels and the MLP is built
 with -ffp-contract=off, so that the double-precision path evaluates the
 paper's formulas operation by operation (no fused multiply-adds).  All HIP
 code is built without packed-FP32 instructions.
@@ -24,6 +24,7 @@ SOURCES = {
     "api.hip": ["-ffp-contract=off"],
     "kern64.hip": ["-ffp-contract=off"],
     "kern32.hip": ["-ffp-contract=fast"],
+    "step32.hip": ["-ffp-contract=fast"],
     "sort.hip": ["-ffp-contract=off"],
     "drag.hip": ["-ffp-contract=off"],
     "splitmerge.hip": ["-ffp-contract=off"],

@@ -1,0 +1,120 @@
+// Single-precision RK3 step of every active ray volume (Appendix B:
+// Williamson's low-storage third-order scheme; Section 3a), followed by the
+// post-step wrap, removal and column key.  One thread per volume, volumes
+// read through the previous sort's permutation and written in sorted order.
+#include "f32.h"
+
+template <bool SPH>
+__global__ __launch_bounds__(256, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
+                                                   uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc,
+                                                   float dt, const uint8_t *__restrict__ frozen,
+                                                   const uint32_t *__restrict__ skeys)
+{
+    const int64_t i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= dc->n_active) return;
+    const uint32_t s = perm[i];
+    const uint32_t col = src.col[s];
+    int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
+    const int kc0 = src.lev[s];
+    float Y[9] = {src.xi[s], src.eta[s], src.zeta[s], src.k[s], src.l[s], src.m[s], src.dxi[s], src.deta[s], src.dz[s]};
+    float Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float F[9];
+    const float A[3] = {0.0f, -5.0f / 9.0f, -153.0f / 128.0f};
+    const float B[3] = {1.0f / 3.0f, 15.0f / 16.0f, 8.0f / 15.0f};
+    const float phi0 = g.y0 + (float)jc * g.dyr;
+    // volumes in columns handed to the surrogate keep their state this step
+    const int nst = (frozen && frozen[skeys[i]]) ? 0 : 3;
+#pragma unroll 1
+    for (int st = 0; st < nst; st++) {
+        f32::rhs<SPH>(g, b, ic, jc, kc0, phi0, Y, F);
+#pragma unroll
+        for (int c = 0; c < 9; c++) {
+            Q[c] = A[st] * Q[c] + dt * F[c];
+            Y[c] = Y[c] + B[st] * Q[c];
+        }
+    }
+    // post-step: validity, wrap, removal, column key
+    uint32_t key;
+    int kc = kc0;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 9; c++) ok = ok && isfinite(Y[c]);
+    ok = ok && Y[6] > 0.0f && Y[7] > 0.0f && Y[8] > 0.0f && (Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) > 0.0f;
+    ok = ok && fabsf(Y[0]) < 1.0e6f && fabsf(Y[1]) < 1.0e6f && fabsf(Y[2]) < 1.0e6f;
+    if (!ok) {
+        key = (uint32_t)(g.ncol + RK_INVALID);
+    } else {
+        f32::renorm_periodic(ic, Y[0], g.nx);
+        key = 0;
+        if (SPH) {
+            const float phi = phi0 + Y[1] * g.dyr;
+            if (fabsf(phi) >= g.pole) key = (uint32_t)(g.ncol + RK_POLE);
+            const float fl = floorf(Y[1]);
+            int jj = jc + (int)fl;
+            Y[1] = Y[1] - fl;
+            if (Y[1] >= 1.0f) {
+                Y[1] = 0.0f;
+                jj += 1;
+            }
+            if (jj < 0) {
+                jj = 0;
+                Y[1] = 0.0f;
+            }
+            if (jj > g.ny - 1) {
+                jj = g.ny - 1;
+                Y[1] = 0.999999940395f;
+            }
+            jc = jj;
+        } else {
+            f32::renorm_periodic(jc, Y[1], g.ny);
+        }
+        {
+            // level index + offset in [0, 1)
+            const float fl = floorf(Y[2]);
+            kc = kc0 + (int)fl;
+            Y[2] = Y[2] - fl;
+            if (Y[2] >= 1.0f) {
+                Y[2] = 0.0f;
+                kc += 1;
+            }
+        }
+        if (key == 0) {
+            if (kc < 0)
+                key = (uint32_t)(g.ncol + RK_BOTTOM);
+            else if (kc > g.nz || (kc == g.nz && Y[2] > 0.0f))
+                key = (uint32_t)(g.ncol + RK_TOP);
+            else
+                key = (uint32_t)(jc * g.nx + ic);
+        }
+    }
+    dst.col[i] = (uint32_t)(jc * g.nx + ic);
+    dst.lev[i] = kc;
+    dst.xi[i] = Y[0];
+    dst.eta[i] = Y[1];
+    dst.zeta[i] = Y[2];
+    dst.k[i] = Y[3];
+    dst.l[i] = Y[4];
+    dst.m[i] = Y[5];
+    dst.dxi[i] = Y[6];
+    dst.deta[i] = Y[7];
+    dst.dz[i] = Y[8];
+    dst.px[i] = src.px[s];
+    dst.py[i] = src.py[s];
+    dst.pz[i] = src.pz[s];
+    dst.W[i] = src.W[s];
+    dst.id[i] = src.id[s];
+    key_out[i] = key;
+}
+
+void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
+                   const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
+                   hipStream_t s)
+{
+    if (bound <= 0) return;
+    const unsigned nb = (unsigned)((bound + 255) / 256);
+    const G32 h = f32::make_g32(g);
+    if (g.geometry == RT_SPHERICAL)
+        k_step32<true><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
+    else
+        k_step32<false><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
+}
