@@ -129,16 +129,28 @@ __global__ void k_load64(Grid g, rt_rays in, int64_t n, S64 d, uint32_t *key)
     key[i] = kk;
 }
 
-// next free id = 1 + largest id loaded (ids are non-negative)
+// next free id = 1 + largest id loaded (ids are non-negative): grid-stride
+// maxima, one atomic per wave
 __global__ void k_maxid(const int64_t *id, int64_t n, DevCounters *dc)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicMax((unsigned long long *)&dc->next_id, (unsigned long long)(id[i] + 1));
+    unsigned long long v = 0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long c = (unsigned long long)(id[i] + 1);
+        v = c > v ? c : v;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0 && v) atomicMax((unsigned long long *)&dc->next_id, v);
 }
 
 void launch_maxid(const int64_t *id, int64_t n, DevCounters *dc, hipStream_t s)
 {
-    if (n > 0) k_maxid<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(id, n, dc);
+    if (n <= 0) return;
+    const int64_t nb = (n + 255) / 256;
+    k_maxid<<<(unsigned)(nb < 2048 ? nb : 2048), 256, 0, s>>>(id, n, dc);
 }
 
 void launch_load64(const Grid &g, const rt_rays &in, int64_t n, S64 dst, uint32_t *key, hipStream_t s)
