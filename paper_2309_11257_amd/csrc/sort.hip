@@ -34,10 +34,22 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *__restri
     __syncthreads();
     const int64_t n = *n_dev;
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int lane = tid & 63;
+    // lanes holding the same digit are counted by their lowest lane (keys
+    // arrive nearly sorted, so a wave usually holds one or two digits)
 #pragma unroll 4
     for (int it = 0; it < RS_ITEMS; it++) {
         const int64_t i = base + (int64_t)it * RS_THREADS + tid;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        const bool valid = i < n;
+        const uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; bit++) {
+            const bool b = (d >> bit) & 1u;
+            const unsigned long long m = __ballot(b);
+            peers &= b ? m : ~m;
+        }
+        if (valid && lane == __ffsll((long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
     hist[(int64_t)tid * nblocks + blockIdx.x] = h[tid];
