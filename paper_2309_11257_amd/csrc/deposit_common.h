@@ -31,32 +31,6 @@ __device__ inline long long to_fixed(double x, double scale)
 // biased binary exponent of |x| (0 for zero)
 __device__ inline int bexp(double x) { return (int)((__double_as_longlong(x) >> 52) & 0x7ff); }
 
-// Wave-wide maximum / minimum by data-parallel-primitive lane moves (no LDS
-// round trips): within quads, within rows of 16 (half mirror, mirror), then
-// across rows (broadcast of lane 15 and lane 31); lane 63 ends with the
-// result, which is read back as a wave-uniform value.  All 64 lanes must be
-// active.
-#define DPP_QUAD_1032 0xB1
-#define DPP_QUAD_2301 0x4E
-#define DPP_ROW_HALF_MIRROR 0x141
-#define DPP_ROW_MIRROR 0x140
-#define DPP_ROW_BCAST15 0x142
-#define DPP_ROW_BCAST31 0x143
-template <bool MAX>
-__device__ inline int wave_reduce_i(int v)
-{
-    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_QUAD_1032, 0xF, 0xF, false));
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_QUAD_2301, 0xF, 0xF, false));
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_ROW_HALF_MIRROR, 0xF, 0xF, false));
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_ROW_MIRROR, 0xF, 0xF, false));
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_ROW_BCAST15, 0xA, 0xF, false));
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_ROW_BCAST31, 0xC, 0xF, false));
-    return __builtin_amdgcn_readlane(v, 63);
-}
-__device__ inline int wave_max_i(int v) { return wave_reduce_i<true>(v); }
-__device__ inline int wave_min_i(int v) { return wave_reduce_i<false>(v); }
-
 // ordering of this wave's LDS accesses across its lanes
 __device__ inline void wave_sync()
 {

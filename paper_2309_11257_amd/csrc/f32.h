@@ -164,7 +164,9 @@ __device__ inline float4 rec(const float4 *__restrict__ F, uint32_t index)
 template <int R>
 struct Corners {
     float4 a0, a1, b0, b1, d0, d1, e0, e1;
-    __device__ inline Corners(const float4 *__restrict__ F, const Cell &c, int r)
+    __device__ inline Corners() {}
+    __device__ inline Corners(const float4 *__restrict__ F, const Cell &c, int r) { fill(F, c, r); }
+    __device__ inline void fill(const float4 *__restrict__ F, const Cell &c, int r)
     {
         const uint32_t rr = (uint32_t)r;
         a0 = rec(F, (c.c00 + c.k0) * R + rr);
@@ -217,6 +219,88 @@ __device__ inline void n2_f2(const G32 &g, const Bg32P &b, int ic, int jc, int k
     f2 = row_lerp(b.f2, ay);
 }
 
+// Per-wave stencil box in LDS.  When every volume of a wave lies in one
+// column and the wave's levels span at most WB_LMAX - 6, the wave stages the
+// A records of the 5 x 5 columns around it and the gradient records of the
+// 3 x 3 columns, for the levels kbase .. kbase + L - 1, and interpolates from
+// LDS; a lookup that falls outside the box for any lane of the wave goes to
+// global memory for the whole wave.
+#define WB_LMAX 13
+#define WB_A (25 * WB_LMAX)
+#define WB_RECS (WB_A + 18 * WB_LMAX)
+extern __shared__ float4 wb_lds[];
+
+struct WBox {
+    int on;  // wave-uniform
+    int ic, jc, kbase, L, base;
+};
+
+struct BCell {
+    int r00, r01, r10, r11, k0, k1;
+};
+
+__device__ inline int wrapd(int d, int n)
+{
+    if (d > n / 2) d -= n;
+    else if (d < -(n / 2)) d += n;
+    return d;
+}
+
+template <int RAD>
+__device__ inline bool box_of(const G32 &g, const WBox &w, const Axis &x, const Axis &y, const Axis &z, BCell &b)
+{
+    const int dx0 = wrapd(x.i0 - w.ic, g.nx), dx1 = wrapd(x.i1 - w.ic, g.nx);
+    int dy0 = y.i0 - w.jc, dy1 = y.i1 - w.jc;
+    if (g.geometry == RT_CARTESIAN) {
+        dy0 = wrapd(dy0, g.ny);
+        dy1 = wrapd(dy1, g.ny);
+    }
+    b.k0 = z.i0 - w.kbase;
+    b.k1 = z.i1 - w.kbase;
+    const int side = 2 * RAD + 1;
+    b.r00 = ((dy0 + RAD) * side + (dx0 + RAD)) * w.L;
+    b.r01 = ((dy0 + RAD) * side + (dx1 + RAD)) * w.L;
+    b.r10 = ((dy1 + RAD) * side + (dx0 + RAD)) * w.L;
+    b.r11 = ((dy1 + RAD) * side + (dx1 + RAD)) * w.L;
+    return abs(dx0) <= RAD && abs(dx1) <= RAD && abs(dy0) <= RAD && abs(dy1) <= RAD && b.k0 >= 0 && b.k1 < w.L;
+}
+
+template <int R>
+__device__ inline void fill_box(Corners<R> &K, int off, const BCell &b)
+{
+    K.a0 = wb_lds[off + b.r00 + b.k0];
+    K.a1 = wb_lds[off + b.r01 + b.k0];
+    K.b0 = wb_lds[off + b.r10 + b.k0];
+    K.b1 = wb_lds[off + b.r11 + b.k0];
+    K.d0 = wb_lds[off + b.r00 + b.k1];
+    K.d1 = wb_lds[off + b.r01 + b.k1];
+    K.e0 = wb_lds[off + b.r10 + b.k1];
+    K.e1 = wb_lds[off + b.r11 + b.k1];
+}
+
+// A corners of a cell: from the box when every lane of the wave is inside
+__device__ inline void corners_A(const G32 &g, const WBox &w, const Bg32P &b, const Axis &x, const Axis &y,
+                                 const Axis &z, const Cell &c, Corners<1> &K)
+{
+    BCell bc;
+    const bool in = w.on && box_of<2>(g, w, x, y, z, bc);
+    if (__ballot(!in) == 0ull)
+        fill_box(K, w.base, bc);
+    else
+        K.fill(b.A, c, 0);
+}
+
+__device__ inline void corners_G(const G32 &g, const WBox &w, const Bg32P &b, const Axis &x, const Axis &y,
+                                 const Axis &z, const Cell &c, int r, Corners<2> &K)
+{
+    BCell bc;
+    const bool in = w.on && box_of<1>(g, w, x, y, z, bc);
+    if (__ballot(!in) == 0ull)
+        fill_box(K, w.base + WB_A + r * 9 * WB_LMAX, bc);
+    else
+        K.fill(b.G, c, r);
+}
+
 // RK stage right-hand side in cell units: Y = (xi, eta, zeta, k, l, m, Dxi,
 // Deta, Dz), offsets relative to the base cell (ic, jc, kc), Dz in metres.
 // Centre: 12 fields from three records per corner (U V N2 Ux | Uy Uz Vx Vy |
@@ -224,7 +308,8 @@ __device__ inline void n2_f2(const G32 &g, const Bg32P &b, int ic, int jc, int k
 // first record; the face differs from the centre along one axis only, so the
 // other two axes are reused, and f2 is the centre's except on the y faces.
 template <bool SPH>
-__device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc, float phi0, const float *Y, float *F)
+__device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc, float phi0, const float *Y,
+                           float *F, const WBox &w)
 {
     const float xi = Y[0], eta = Y[1], zeta = Y[2], k = Y[3], l = Y[4], m = Y[5];
     const float kh2 = k * k + l * l;
@@ -237,7 +322,13 @@ __device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc,
     const float f2c = row_lerp(b.f2, ay);
     float gk, gl, gm, N2c;
     {
-        const float4 A0 = tri4<1>(b.A, c, 0);  // U V N2 Ux
+        Corners<1> KA;
+        corners_A(g, w, b, ax, ay, az, c, KA);
+        float4 A0;  // U V N2 Ux
+        A0.x = TRI_COMP(KA, x, c);
+        A0.y = TRI_COMP(KA, y, c);
+        A0.z = TRI_COMP(KA, z, c);
+        A0.w = TRI_COMP(KA, w, c);
         N2c = A0.z;
         const float rom = rsq((N2c * kh2 + f2c * m2) * invK2);  // 1 / omega_hat
         const float h = 0.5f * invK2 * rom;
@@ -249,7 +340,13 @@ __device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc,
         // gradient records one at a time (bounded register use)
 #pragma unroll 1
         for (int r = 0; r < 2; r++) {
-            const float4 Gr = tri4<2>(b.G, c, r);
+            Corners<2> KG;
+            corners_G(g, w, b, ax, ay, az, c, r, KG);
+            float4 Gr;
+            Gr.x = TRI_COMP(KG, x, c);
+            Gr.y = TRI_COMP(KG, y, c);
+            Gr.z = TRI_COMP(KG, z, c);
+            Gr.w = TRI_COMP(KG, w, c);
             if (r == 0) {  // Uy Uz Vx Vy
                 gl += k * Gr.x + l * Gr.w;
                 gm += k * Gr.y;
@@ -276,7 +373,8 @@ __device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc,
         else
             fz = axis_clamp(kc, zeta + sg * sdz, g.nz);
         const Cell f = cell_of(g, fx, fy, fz);
-        const Corners<1> K(b.A, f, 0);
+        Corners<1> K;
+        corners_A(g, w, b, fx, fy, fz, f, K);
         // wind component along the face normal: U on x faces, V on y faces
         const bool useU = axn == 0;
         const float wnd = lerp3(useU ? K.a0.x : K.a0.y, useU ? K.a1.x : K.a1.y, useU ? K.b0.x : K.b0.y,

@@ -126,6 +126,32 @@ enum { PC_STEP = 0, PC_SORT = 1, PC_DEPOSIT = 2, PC_DRAG = 3, PC_SPLIT = 4, PC_S
 void prof_begin(rt_ctx ctx, int cls);
 void prof_end(rt_ctx ctx);
 
+// Wave-wide maximum / minimum by data-parallel-primitive lane moves (no LDS
+// round trips): within quads, within rows of 16 (half mirror, mirror), then
+// across rows (broadcast of lane 15 and lane 31); lane 63 ends with the
+// result, which is read back as a wave-uniform value.  All 64 lanes must be
+// active.
+#define DPP_QUAD_1032 0xB1
+#define DPP_QUAD_2301 0x4E
+#define DPP_ROW_HALF_MIRROR 0x141
+#define DPP_ROW_MIRROR 0x140
+#define DPP_ROW_BCAST15 0x142
+#define DPP_ROW_BCAST31 0x143
+template <bool MAX>
+__device__ inline int wave_reduce_i(int v)
+{
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_QUAD_1032, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_QUAD_2301, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_ROW_HALF_MIRROR, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_ROW_MIRROR, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_ROW_BCAST15, 0xA, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, DPP_ROW_BCAST31, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ inline int wave_max_i(int v) { return wave_reduce_i<true>(v); }
+__device__ inline int wave_min_i(int v) { return wave_reduce_i<false>(v); }
+
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2);
 // remap so that each XCD walks a contiguous range of blocks -- for kernels
 // over column-sorted rays this keeps the background columns an XCD touches

@@ -2,6 +2,8 @@
 // Williamson's low-storage third-order scheme; Section 3a), followed by the
 // post-step wrap, removal and column key.  One thread per volume, volumes
 // read through the previous sort's permutation and written in sorted order.
+// A wave whose volumes share one column first stages the background stencil
+// they all use into LDS (see f32.h); its interpolations then read LDS.
 #include "f32.h"
 
 template <bool SPH>
@@ -11,11 +13,50 @@ __global__ __launch_bounds__(256, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 
                                                    const uint32_t *__restrict__ skeys)
 {
     const int64_t i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= dc->n_active) return;
-    const uint32_t s = perm[i];
-    const uint32_t col = src.col[s];
+    // stage the stencil box shared by the wave's volumes (all lanes take part:
+    // the wave-wide reductions need every lane)
+    const bool valid = i < dc->n_active;
+    const uint32_t s = valid ? perm[i] : 0u;
+    const uint32_t col = valid ? src.col[s] : 0xffffffffu;
+    const int kc0 = valid ? src.lev[s] : 0;
+    f32::WBox w;
+    {
+        const int lane = threadIdx.x & 63;
+        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)col);
+        const bool uni = __ballot(valid && col != c0) == 0ull && c0 != 0xffffffffu;
+        const int kmn = wave_min_i(valid ? kc0 : 0x7fffffff), kmx = wave_max_i(valid ? kc0 : -1);
+        w.base = (threadIdx.x >> 6) * WB_RECS;
+        w.ic = (int)(c0 % (uint32_t)g.nx);
+        w.jc = (int)(c0 / (uint32_t)g.nx);
+        // levels: margins of two levels below and three above the wave's
+        // range hold the faces of most volumes (a lookup outside the box
+        // reads global memory)
+        w.kbase = max(0, kmn - 2);
+        w.L = min(g.nz - 1, kmx + 3) - w.kbase + 1;
+        w.on = uni && w.L <= WB_LMAX;
+        if (w.on) {
+            for (int e = lane; e < 25 * w.L; e += 64) {
+                const int bxy = e / w.L, kk = e - bxy * w.L;
+                const int ii = (w.ic + (bxy % 5) - 2 + 2 * g.nx) % g.nx;
+                int jj = w.jc + bxy / 5 - 2;
+                jj = g.geometry == RT_CARTESIAN ? (jj + 2 * g.ny) % g.ny : min(max(jj, 0), g.ny - 1);
+                f32::wb_lds[w.base + e] = f32::rec(b.A, f32::col_base(g, jj, ii) + (uint32_t)(w.kbase + kk));
+            }
+            for (int e = lane; e < 18 * w.L; e += 64) {
+                const int r = e >= 9 * w.L ? 1 : 0, t = e - r * 9 * w.L;
+                const int bxy = t / w.L, kk = t - bxy * w.L;
+                const int ii = (w.ic + (bxy % 3) - 1 + 2 * g.nx) % g.nx;
+                int jj = w.jc + bxy / 3 - 1;
+                jj = g.geometry == RT_CARTESIAN ? (jj + 2 * g.ny) % g.ny : min(max(jj, 0), g.ny - 1);
+                f32::wb_lds[w.base + WB_A + r * 9 * WB_LMAX + t] =
+                    f32::rec(b.G, (f32::col_base(g, jj, ii) + (uint32_t)(w.kbase + kk)) * 2u + (uint32_t)r);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (!valid) return;
     int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
-    const int kc0 = src.lev[s];
     float Y[9] = {src.xi[s], src.eta[s], src.zeta[s], src.k[s], src.l[s], src.m[s], src.dxi[s], src.deta[s], src.dz[s]};
     float Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float F[9];
@@ -26,7 +67,7 @@ __global__ __launch_bounds__(256, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 
     const int nst = (frozen && frozen[skeys[i]]) ? 0 : 3;
 #pragma unroll 1
     for (int st = 0; st < nst; st++) {
-        f32::rhs<SPH>(g, b, ic, jc, kc0, phi0, Y, F);
+        f32::rhs<SPH>(g, b, ic, jc, kc0, phi0, Y, F, w);
 #pragma unroll
         for (int c = 0; c < 9; c++) {
             Q[c] = A[st] * Q[c] + dt * F[c];
@@ -113,8 +154,9 @@ void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32
     if (bound <= 0) return;
     const unsigned nb = (unsigned)((bound + 255) / 256);
     const G32 h = f32::make_g32(g);
+    const size_t lds = (size_t)4 * WB_RECS * sizeof(float4);  // one stencil box per wave
     if (g.geometry == RT_SPHERICAL)
-        k_step32<true><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
+        k_step32<true><<<nb, 256, lds, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
     else
-        k_step32<false><<<nb, 256, 0, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
+        k_step32<false><<<nb, 256, lds, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
 }
