@@ -6,11 +6,17 @@
 // they all use into LDS (see f32.h); its interpolations then read LDS.
 #include "f32.h"
 
+// one wave per workgroup: a workgroup's slot and stencil box are released as
+// soon as its wave ends, whatever the other waves' loads
+#define STEP_BLOCK 64
+
 template <bool SPH>
-__global__ __launch_bounds__(256, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 dst, const uint32_t *__restrict__ perm,
-                                                   uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc,
-                                                   float dt, const uint8_t *__restrict__ frozen,
-                                                   const uint32_t *__restrict__ skeys)
+__global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 dst,
+                                                          const uint32_t *__restrict__ perm,
+                                                          uint32_t *__restrict__ key_out,
+                                                          const DevCounters *__restrict__ dc, float dt,
+                                                          const uint8_t *__restrict__ frozen,
+                                                          const uint32_t *__restrict__ skeys)
 {
     const int64_t i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
     // stage the stencil box shared by the wave's volumes (all lanes take part:
@@ -25,7 +31,7 @@ __global__ __launch_bounds__(256, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 
         const uint32_t c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)col);
         const bool uni = __ballot(valid && col != c0) == 0ull && c0 != 0xffffffffu;
         const int kmn = wave_min_i(valid ? kc0 : 0x7fffffff), kmx = wave_max_i(valid ? kc0 : -1);
-        w.base = (threadIdx.x >> 6) * WB_RECS;
+        w.base = 0;
         w.ic = (int)(c0 % (uint32_t)g.nx);
         w.jc = (int)(c0 / (uint32_t)g.nx);
         // levels: margins of two levels below and three above the wave's
@@ -33,23 +39,62 @@ __global__ __launch_bounds__(256, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 
         // reads global memory)
         w.kbase = max(0, kmn - 2);
         w.L = min(g.nz - 1, kmx + 3) - w.kbase + 1;
-        w.on = uni && w.L <= WB_LMAX;
+        // one wrap corrects a column or row index when the grid has at least two
+        w.on = uni && w.L <= WB_LMAX && g.nx >= 2 && (g.geometry != RT_CARTESIAN || g.ny >= 2);
         if (w.on) {
-            for (int e = lane; e < 25 * w.L; e += 64) {
-                const int bxy = e / w.L, kk = e - bxy * w.L;
-                const int ii = (w.ic + (bxy % 5) - 2 + 2 * g.nx) % g.nx;
-                int jj = w.jc + bxy / 5 - 2;
-                jj = g.geometry == RT_CARTESIAN ? (jj + 2 * g.ny) % g.ny : min(max(jj, 0), g.ny - 1);
-                f32::wb_lds[w.base + e] = f32::rec(b.A, f32::col_base(g, jj, ii) + (uint32_t)(w.kbase + kk));
+            // a lane issues all of its loads before its LDS writes; t / L as
+            // (t * ceil(2^16 / L)) >> 16, exact for t < 512 and L <= 26
+            constexpr int NA = (25 * WB_LMAX + 63) / 64, NG = (18 * WB_LMAX + 63) / 64;
+            const int nA = 25 * w.L, nG = 18 * w.L, L9 = 9 * w.L;
+            const uint32_t mL = (65536u + (uint32_t)w.L - 1u) / (uint32_t)w.L;
+            float4 va[NA], vg[NG];
+#pragma unroll
+            for (int it = 0; it < NA; it++) {
+                const int e = lane + 64 * it;
+                if (e < nA) {
+                    const int bxy = (int)(((uint32_t)e * mL) >> 16), kk = e - bxy * w.L;
+                    int ii = w.ic + bxy % 5 - 2, jj = w.jc + bxy / 5 - 2;
+                    ii += ii < 0 ? g.nx : 0;
+                    ii -= ii >= g.nx ? g.nx : 0;
+                    if (g.geometry == RT_CARTESIAN) {
+                        jj += jj < 0 ? g.ny : 0;
+                        jj -= jj >= g.ny ? g.ny : 0;
+                    } else {
+                        jj = min(max(jj, 0), g.ny - 1);
+                    }
+                    va[it] = f32::rec(b.A, f32::col_base(g, jj, ii) + (uint32_t)(w.kbase + kk));
+                }
             }
-            for (int e = lane; e < 18 * w.L; e += 64) {
-                const int r = e >= 9 * w.L ? 1 : 0, t = e - r * 9 * w.L;
-                const int bxy = t / w.L, kk = t - bxy * w.L;
-                const int ii = (w.ic + (bxy % 3) - 1 + 2 * g.nx) % g.nx;
-                int jj = w.jc + bxy / 3 - 1;
-                jj = g.geometry == RT_CARTESIAN ? (jj + 2 * g.ny) % g.ny : min(max(jj, 0), g.ny - 1);
-                f32::wb_lds[w.base + WB_A + r * 9 * WB_LMAX + t] =
-                    f32::rec(b.G, (f32::col_base(g, jj, ii) + (uint32_t)(w.kbase + kk)) * 2u + (uint32_t)r);
+#pragma unroll
+            for (int it = 0; it < NG; it++) {
+                const int e = lane + 64 * it;
+                if (e < nG) {
+                    const int r = e >= L9 ? 1 : 0, t = e - r * L9;
+                    const int bxy = (int)(((uint32_t)t * mL) >> 16), kk = t - bxy * w.L;
+                    int ii = w.ic + bxy % 3 - 1, jj = w.jc + bxy / 3 - 1;
+                    ii += ii < 0 ? g.nx : 0;
+                    ii -= ii >= g.nx ? g.nx : 0;
+                    if (g.geometry == RT_CARTESIAN) {
+                        jj += jj < 0 ? g.ny : 0;
+                        jj -= jj >= g.ny ? g.ny : 0;
+                    } else {
+                        jj = min(max(jj, 0), g.ny - 1);
+                    }
+                    vg[it] = f32::rec(b.G, (f32::col_base(g, jj, ii) + (uint32_t)(w.kbase + kk)) * 2u + (uint32_t)r);
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < NA; it++) {
+                const int e = lane + 64 * it;
+                if (e < nA) f32::wb_lds[w.base + e] = va[it];
+            }
+#pragma unroll
+            for (int it = 0; it < NG; it++) {
+                const int e = lane + 64 * it;
+                if (e < nG) {
+                    const int r = e >= L9 ? 1 : 0;
+                    f32::wb_lds[w.base + WB_A + r * 9 * WB_LMAX + (e - r * L9)] = vg[it];
+                }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -152,11 +197,11 @@ void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32
                    hipStream_t s)
 {
     if (bound <= 0) return;
-    const unsigned nb = (unsigned)((bound + 255) / 256);
+    const unsigned nb = (unsigned)((bound + STEP_BLOCK - 1) / STEP_BLOCK);
     const G32 h = f32::make_g32(g);
-    const size_t lds = (size_t)4 * WB_RECS * sizeof(float4);  // one stencil box per wave
+    const size_t lds = (size_t)WB_RECS * sizeof(float4);  // the wave's stencil box
     if (g.geometry == RT_SPHERICAL)
-        k_step32<true><<<nb, 256, lds, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
+        k_step32<true><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
     else
-        k_step32<false><<<nb, 256, lds, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
+        k_step32<false><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
 }
