@@ -41,22 +41,31 @@ __device__ inline void wave_sync()
 // P::load(slot, zb, zt, bv[6]) fills the vertical span of the volume and its
 // six flux densities per unit height: (cgx k, cgx l, cgy k, cgy l, cgz k,
 // cgz l) * W / Dz.
-template <class P, int CPW>
-__global__ __launch_bounds__(64 * CPW) void k_deposit(Grid g, P pl, const uint32_t *__restrict__ perm,
+//
+// RP: with at most 128 levels and interfaces the double profile of a wave's
+// column lives in registers (lane j holds levels j and j + 64 of the six
+// fields), which halves the LDS of a workgroup; at the end it is stored over
+// the wave's integer profile (all zero by then) for the common write-out.
+template <class P, int CPW, bool RP>
+__global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, const uint32_t *__restrict__ perm,
                                                       const uint32_t *__restrict__ colstart, double *__restrict__ flux)
 {
     extern __shared__ unsigned long long dep_smem[];
     const int nzp = g.nz + 1;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    unsigned long long *acc = dep_smem + (size_t)wave * 6 * nzp;            // this wave's [6][nzp]
-    double *profs = (double *)(dep_smem + (size_t)CPW * 6 * nzp);      // [CPW][6][nzp]
+    unsigned long long *acc = dep_smem + (size_t)wave * 6 * nzp;  // this wave's [6][nzp]
+    // [CPW][6][nzp] finished profiles: after the integer ones, or over them
+    double *profs = (double *)(dep_smem + (RP ? 0 : (size_t)CPW * 6 * nzp));
     double *prof = profs + (size_t)wave * 6 * nzp;
+    double preg[6][2];
+#pragma unroll
+    for (int q = 0; q < 6; q++) preg[q][0] = preg[q][1] = 0.0;
     const int c_first = blockIdx.x * CPW;
     const int ncols = min(CPW, g.ncol - c_first);
     for (int e = lane; e < 6 * nzp; e += 64) {
         acc[e] = 0ull;
-        prof[e] = 0.0;
+        if (!RP) prof[e] = 0.0;
     }
     wave_sync();
     if (wave < ncols) {
@@ -116,7 +125,23 @@ __global__ __launch_bounds__(64 * CPW) void k_deposit(Grid g, P pl, const uint32
             // the chunk touched only
             const int k0 = wave_min_i(klo), k1 = wave_max_i(khi);
             wave_sync();
-            if (k1 >= k0) {
+            if (RP) {
+#pragma unroll
+                for (int sl = 0; sl < 2; sl++) {
+                    const int kk = lane + 64 * sl;
+                    if (kk >= k0 && kk <= k1) {
+#pragma unroll
+                        for (int q = 0; q < 6; q++) {
+                            const int at = q * nzp + kk;
+                            const long long v = (long long)acc[at];
+                            if (v) {
+                                preg[q][sl] += ldexp((double)v, -sx[q]);
+                                acc[at] = 0ull;
+                            }
+                        }
+                    }
+                }
+            } else if (k1 >= k0) {
                 const int span = k1 - k0 + 1;
                 for (int e = lane; e < 6 * span; e += 64) {
                     const int q = e / span, kk = k0 + e % span;
@@ -132,6 +157,17 @@ __global__ __launch_bounds__(64 * CPW) void k_deposit(Grid g, P pl, const uint32
                 }
             }
             wave_sync();
+        }
+    }
+    if (RP) {
+        wave_sync();
+#pragma unroll
+        for (int sl = 0; sl < 2; sl++) {
+            const int kk = lane + 64 * sl;
+            if (kk < nzp) {
+#pragma unroll
+                for (int q = 0; q < 6; q++) prof[q * nzp + kk] = preg[q][sl];
+            }
         }
     }
     __syncthreads();
@@ -173,17 +209,28 @@ __global__ __launch_bounds__(64 * CPW) void k_deposit(Grid g, P pl, const uint32
     }
 }
 
-template <int CPW>
-inline size_t deposit_smem(const Grid &g) { return (size_t)(12 * CPW) * (size_t)(g.nz + 1) * 8; }
+template <int CPW, bool RP>
+inline size_t deposit_smem(const Grid &g) { return (size_t)((RP ? 6 : 12) * CPW) * (size_t)(g.nz + 1) * 8; }
 
 // launch with four columns per workgroup when their profiles fit 64 KiB of
-// LDS, else one
+// LDS, else one; register profiles up to 128 levels and interfaces
+template <class P, bool RP>
+inline void launch_deposit_rp(const Grid &g, const P &p, const uint32_t *perm, const uint32_t *colstart,
+                              double *flux, hipStream_t s)
+{
+    if (deposit_smem<4, RP>(g) <= 65536)
+        k_deposit<P, 4, RP><<<(unsigned)((g.ncol + 3) / 4), 256, deposit_smem<4, RP>(g), s>>>(g, p, perm, colstart,
+                                                                                              flux);
+    else
+        k_deposit<P, 1, RP><<<(unsigned)g.ncol, 64, deposit_smem<1, RP>(g), s>>>(g, p, perm, colstart, flux);
+}
+
 template <class P>
 inline void launch_deposit_k(const Grid &g, const P &p, const uint32_t *perm, const uint32_t *colstart, double *flux,
                              hipStream_t s)
 {
-    if (deposit_smem<4>(g) <= 65536)
-        k_deposit<P, 4><<<(unsigned)((g.ncol + 3) / 4), 256, deposit_smem<4>(g), s>>>(g, p, perm, colstart, flux);
+    if (g.nz + 1 <= 128)
+        launch_deposit_rp<P, true>(g, p, perm, colstart, flux, s);
     else
-        k_deposit<P, 1><<<(unsigned)g.ncol, 64, deposit_smem<1>(g), s>>>(g, p, perm, colstart, flux);
+        launch_deposit_rp<P, false>(g, p, perm, colstart, flux, s);
 }
