@@ -127,8 +127,13 @@ rt_status rt_init_background(rt_ctx ctx, const double *U, const double *V, const
  * are counted as removed at load.  RT_E_CAPACITY if n > capacity. */
 rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int32_t where);
 
-/* Copy out the active ray volumes in the library's internal order (grouped
- * by column).  *n_inout: in = length of the caller's arrays, out = number
+/* Copy out the active ray volumes in the library's internal order: grouped
+ * by column.  The regrouping after rt_set_rays and every eighth one after it
+ * order each column's volumes by level index floor(z / dz) (clamped to
+ * 0 .. nz; when (number of columns + 6) * (nz + 1) fits 32 bits); otherwise,
+ * and for volumes with equal keys, each column's previous relative order is
+ * kept.  *n_inout: in = length of the caller's
+ * arrays, out = number
  * written.  Synchronises.  RT_E_ARG if the arrays are too short (then
  * *n_inout is set to the number needed and nothing is written). */
 rt_status rt_get_rays(rt_ctx ctx, rt_rays *rays, int64_t *n_inout, int32_t where);

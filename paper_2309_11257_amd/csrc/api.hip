@@ -304,21 +304,41 @@ extern "C" rt_status rt_destroy(rt_ctx ctx)
 
 extern "C" const char *rt_last_error(rt_ctx ctx) { return ctx ? ctx->err : "null context"; }
 
-static int key_bits(int ncol)
+static int bits_of(uint64_t maxkey)
 {
-    const uint32_t maxkey = (uint32_t)ncol + RK_NREASON;
     int b = 0;
     while ((1ull << b) <= maxkey) b++;
     return b;
 }
 
-// sort the current buffer's keys -> skeys/perm, column offsets, removal tallies
+// every this many regrouping sorts (and the first after a load) the column
+// key is refined by the level
+#define LEVEL_REFINE_EVERY 8
+
+// sort the current buffer's keys -> skeys/perm, column offsets, removal
+// tallies.  A refining sort orders each column's volumes by level (sort key
+// column x (nz + 1) + level, where that fits 32 bits; the sorted keys are
+// turned back into column keys); the column sorts in between are stable, so
+// the level order persists except for volumes that moved.  The step's waves
+// then span few levels and share one stencil box.
 static rt_status sort_current(rt_ctx ctx)
 {
     const int64_t bound = ctx->n_bound;
+    const uint64_t nl = (uint64_t)ctx->g.nz + 1;
+    const uint64_t maxcol = (uint64_t)ctx->g.ncol + RK_NREASON;
+    const bool bylev = maxcol * nl <= 0xffffffffull &&
+                       ctx->n_sorts % LEVEL_REFINE_EVERY == 0;
+    ctx->n_sorts++;
     prof_begin(ctx, PC_SORT);
+    if (bylev) {
+        if (ctx->precision == RT_FP64)
+            launch_levkey64(ctx->g, ctx->s64[ctx->cur], ctx->key[ctx->cur], ctx->dc, bound, ctx->stream);
+        else
+            launch_levkey32(ctx->g, ctx->s32[ctx->cur], ctx->key[ctx->cur], ctx->dc, bound, ctx->stream);
+    }
     radix_sort(ctx->key[ctx->cur], nullptr, ctx->skeys, ctx->perm, ctx->tk, ctx->tv, ctx->hist, &ctx->dc->n_sorted,
-               bound, key_bits(ctx->g.ncol), ctx->stream);
+               bound, bits_of(bylev ? maxcol * nl - 1 : maxcol), ctx->stream);
+    if (bylev) launch_colkey(ctx->skeys, ctx->dc, (uint32_t)nl, bound, ctx->stream);
     launch_colstart(ctx->skeys, ctx->dc, ctx->colstart, ctx->g.ncol, ctx->stream);
     if (ctx->precision == RT_FP64)
         launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->red, ctx->stream);
@@ -444,6 +464,7 @@ extern "C" rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int
     launch_set_sorted(ctx->dc, n, ctx->stream);
     launch_maxid(src.id, n, ctx->dc, ctx->stream);
     ctx->n_bound = n;
+    ctx->n_sorts = 0;
     rt_status st = sort_current(ctx);
     if (st) return st;
     if (staged) {

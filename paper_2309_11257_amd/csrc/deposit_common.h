@@ -18,13 +18,13 @@
 #pragma once
 #include "rt_internal.h"
 
-// round x * scale (scale a power of two, |x * scale| <= 2^51) to the nearest
+// round x * 2^e (|x * 2^e| <= 2^51) to the nearest
 // integer, ties to even: adding 1.5 * 2^52 puts the integer part in the low
 // mantissa bits of a double whose unit in the last place is 1
-__device__ inline long long to_fixed(double x, double scale)
+__device__ inline long long to_fixed(double x, int e)
 {
     const double magic = 6755399441055744.0;  // 1.5 * 2^52
-    const double y = x * scale + magic;
+    const double y = ldexp(x, e) + magic;
     return (long long)(__double_as_longlong(y) - __double_as_longlong(magic));
 }
 
@@ -79,26 +79,32 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
             const double h = valid ? fmin(zt - zb, g.dz) : 0.0;
             // per field: the largest possible contribution of the chunk sets
             // the fixed-point scale (a bound on each |bv * overlap|)
-            double sc[6];
             int sx[6];
 #pragma unroll
             for (int q = 0; q < 6; q++) {
                 const int em = wave_max_i(bexp(fabs(bv[q]) * h));
                 sx[q] = (em > 0 && em < 0x7fe) ? 51 - (em - 1022) : 0;
-                sc[q] = ldexp(1.0, sx[q]);
             }
             int klo = 0x7fffffff, khi = -1;
             if (valid) {
+                // columns sorted by level put the lanes of a chunk on the same
+                // levels: each lane starts its level loop at an offset of its
+                // own, so that one LDS add instruction spreads over several
+                // words instead of serialising on one (integer adds commute,
+                // so the sums do not depend on the order)
+
                 int lo = (int)floor(zb / g.dz), hi = (int)floor(zt / g.dz);
                 if (lo < 0) lo = 0;
                 if (hi > g.nz - 1) hi = g.nz - 1;
-                for (int kk = lo; kk <= hi; kk++) {
+                const int nk = hi - lo + 1;
+                int kk = nk > 0 ? lo + lane % nk : lo;
+                for (int t = 0; t < nk; t++, kk = kk == hi ? lo : kk + 1) {
                     const double lv = (double)kk * g.dz, hv = (double)(kk + 1) * g.dz;
                     const double o = fmin(zt, hv) - fmax(zb, lv);
                     if (!(o > 0.0)) continue;
 #pragma unroll
                     for (int q = 0; q < 4; q++) {
-                        const long long v = to_fixed(bv[q] * o, sc[q]);
+                        const long long v = to_fixed(bv[q] * o, sx[q]);
                         if (v) atomicAdd(&acc[q * nzp + kk], (unsigned long long)v);
                     }
                 }
@@ -106,7 +112,9 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                 int lo2 = (int)floor(zb / g.dz + 0.5), hi2 = (int)floor(zt / g.dz + 0.5);
                 if (lo2 < 0) lo2 = 0;
                 if (hi2 > g.nz) hi2 = g.nz;
-                for (int kk = lo2; kk <= hi2; kk++) {
+                const int nk2 = hi2 - lo2 + 1;
+                kk = nk2 > 0 ? lo2 + lane % nk2 : lo2;
+                for (int t = 0; t < nk2; t++, kk = kk == hi2 ? lo2 : kk + 1) {
                     double lv = ((double)kk - 0.5) * g.dz, hv = ((double)kk + 0.5) * g.dz;
                     if (lv < 0.0) lv = 0.0;
                     if (hv > g.Lz) hv = g.Lz;
@@ -114,7 +122,7 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                     if (!(o > 0.0)) continue;
 #pragma unroll
                     for (int q = 4; q < 6; q++) {
-                        const long long v = to_fixed(bv[q] * o, sc[q]);
+                        const long long v = to_fixed(bv[q] * o, sx[q]);
                         if (v) atomicAdd(&acc[q * nzp + kk], (unsigned long long)v);
                     }
                 }

@@ -119,7 +119,9 @@ __device__ inline double lerp3(double a0, double a1, double b0, double b1, doubl
 template <int R>
 struct Corners {
     double4 a0, a1, b0, b1, d0, d1, e0, e1;
-    __device__ inline Corners(const double4 *__restrict__ F, const Cell &c, int r)
+    __device__ inline Corners() {}
+    __device__ inline Corners(const double4 *__restrict__ F, const Cell &c, int r) { fill(F, c, r); }
+    __device__ inline void fill(const double4 *__restrict__ F, const Cell &c, int r)
     {
         a0 = F[(c.c00 + c.k0) * R + r];
         a1 = F[(c.c01 + c.k0) * R + r];
@@ -147,6 +149,93 @@ __device__ inline double4 tri4(const double4 *__restrict__ F, const Cell &c, int
     return o;
 }
 
+// Per-wave stencil box in LDS.  When every volume of a wave lies in one
+// column and the wave's levels span at most WB64_LMAX - 6, the wave stages the
+// A records of the 5 x 5 columns around it and the gradient records of the
+// 3 x 3 columns, for the levels kbase .. kbase + L - 1, and a lookup whose
+// corners lie in the box for every lane of the wave reads them from LDS; any
+// other lookup reads global memory for the whole wave.  The values are the
+// same either way.
+#define WB64_LMAX 13
+#define WB64_A (25 * WB64_LMAX)
+#define WB64_RECS (WB64_A + 18 * WB64_LMAX)
+extern __shared__ double4 wb64_lds[];
+
+struct WBox {
+    int on;  // wave-uniform
+    int ic, jc, kbase, L;
+};
+
+struct BCell {
+    int r00, r01, r10, r11, k0, k1;
+};
+
+__device__ inline int wrapd(int d, int n)
+{
+    if (d > n / 2)
+        d -= n;
+    else if (d < -(n / 2))
+        d += n;
+    return d;
+}
+
+// box position of a stencil ([dy][dx][k] layout, RAD columns around the
+// wave's column); false if any node lies outside the box
+template <int RAD>
+__device__ inline bool box_of(const Grid &g, const WBox &w, const Axis &x, const Axis &y, const Axis &z, BCell &b)
+{
+    const int dx0 = wrapd(x.i0 - w.ic, g.nx), dx1 = wrapd(x.i1 - w.ic, g.nx);
+    int dy0 = y.i0 - w.jc, dy1 = y.i1 - w.jc;
+    if (g.geometry == RT_CARTESIAN) {
+        dy0 = wrapd(dy0, g.ny);
+        dy1 = wrapd(dy1, g.ny);
+    }
+    b.k0 = z.i0 - w.kbase;
+    b.k1 = z.i1 - w.kbase;
+    const int side = 2 * RAD + 1;
+    b.r00 = ((dy0 + RAD) * side + (dx0 + RAD)) * w.L;
+    b.r01 = ((dy0 + RAD) * side + (dx1 + RAD)) * w.L;
+    b.r10 = ((dy1 + RAD) * side + (dx0 + RAD)) * w.L;
+    b.r11 = ((dy1 + RAD) * side + (dx1 + RAD)) * w.L;
+    return abs(dx0) <= RAD && abs(dx1) <= RAD && abs(dy0) <= RAD && abs(dy1) <= RAD && b.k0 >= 0 && b.k1 < w.L;
+}
+
+template <int R>
+__device__ inline void fill_box(Corners<R> &K, int off, const BCell &b)
+{
+    K.a0 = wb64_lds[off + b.r00 + b.k0];
+    K.a1 = wb64_lds[off + b.r01 + b.k0];
+    K.b0 = wb64_lds[off + b.r10 + b.k0];
+    K.b1 = wb64_lds[off + b.r11 + b.k0];
+    K.d0 = wb64_lds[off + b.r00 + b.k1];
+    K.d1 = wb64_lds[off + b.r01 + b.k1];
+    K.e0 = wb64_lds[off + b.r10 + b.k1];
+    K.e1 = wb64_lds[off + b.r11 + b.k1];
+}
+
+// A corners of a cell: from the box when every lane of the wave is inside
+__device__ inline void corners_A(const Grid &g, const WBox &w, const Bg64P &b, const Axis &x, const Axis &y,
+                                 const Axis &z, const Cell &c, Corners<1> &K)
+{
+    BCell bc;
+    const bool in = w.on && box_of<2>(g, w, x, y, z, bc);
+    if (__ballot(!in) == 0ull)
+        fill_box(K, 0, bc);
+    else
+        K.fill(b.A, c, 0);
+}
+
+__device__ inline void corners_G(const Grid &g, const WBox &w, const Bg64P &b, const Axis &x, const Axis &y,
+                                 const Axis &z, const Cell &c, int r, Corners<2> &K)
+{
+    BCell bc;
+    const bool in = w.on && box_of<1>(g, w, x, y, z, bc);
+    if (__ballot(!in) == 0ull)
+        fill_box(K, WB64_A + r * 9 * WB64_LMAX, bc);
+    else
+        K.fill(b.G, c, r);
+}
+
 // f^2 (or its latitude derivative) between rows: equal, bit for bit, to the
 // trilinear interpolation of the field replicated along x and z
 __device__ inline double row_lerp(const double *__restrict__ f, const Axis &y)
@@ -168,7 +257,7 @@ __device__ inline double omega_hat(double N2, double f2, double kh2, double m2, 
 // (Section 3a, Appendix B).  A face differs from the centre along one axis,
 // so only that axis is located again.
 template <bool SPH>
-__device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, double *F)
+__device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, double *F, const WBox &w)
 {
     const double x = Y[0], y = Y[1], z = Y[2], k = Y[3], l = Y[4], m = Y[5];
     const double Dx = Y[6], Dy = Y[7], Dz = Y[8];
@@ -178,7 +267,15 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
     const double K4 = K2 * K2;
     const Axis ax = axis_x(g, x), ay = axis_y(g, y), az = axis_z(g, z);
     const Cell c = cell_of(g, ax, ay, az);
-    const double4 A0 = tri4<1>(b.A, c, 0);  // U V N2 Ux
+    double4 A0;  // U V N2 Ux
+    {
+        Corners<1> KA;
+        corners_A(g, w, b, ax, ay, az, c, KA);
+        A0.x = TRI64(KA, x, c);
+        A0.y = TRI64(KA, y, c);
+        A0.z = TRI64(KA, z, c);
+        A0.w = TRI64(KA, w, c);
+    }
     const double f2c = row_lerp(b.f2, ay);
     const double om = omega_hat(A0.z, f2c, kh2, m2, K2);
     const double q = kh2 / ((2.0 * om) * K2);
@@ -188,7 +285,13 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
     double Uy = 0, Uz = 0, Vx = 0, Vy = 0, Vz = 0, N2x = 0, N2y = 0, N2z = 0;
 #pragma unroll 1
     for (int r = 0; r < 2; r++) {
-        const double4 Gr = tri4<2>(b.G, c, r);
+        Corners<2> KG;
+        corners_G(g, w, b, ax, ay, az, c, r, KG);
+        double4 Gr;
+        Gr.x = TRI64(KG, x, c);
+        Gr.y = TRI64(KG, y, c);
+        Gr.z = TRI64(KG, z, c);
+        Gr.w = TRI64(KG, w, c);
         Uy = r == 0 ? Gr.x : Uy;
         Uz = r == 0 ? Gr.y : Uz;
         Vx = r == 0 ? Gr.z : Vx;
@@ -217,7 +320,8 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
         else
             fz = axis_z(g, z + sg * Dz);
         const Cell f = cell_of(g, fx, fy, fz);
-        const Corners<1> K(b.A, f, 0);
+        Corners<1> K;
+        corners_A(g, w, b, fx, fy, fz, f, K);
         const double N2f = TRI64(K, z, f);
         const double f2f = axn == 1 ? row_lerp(b.f2, fy) : f2c;
         const bool useU = axn == 0;

@@ -148,6 +148,25 @@ __global__ void k_tally32(Grid g, S32 st, const uint32_t *perm, const uint32_t *
     if (tid < RK_NREASON) dc->removed[tid] += cnt[tid];
 }
 
+// sort key refined by the level: column key * (nz + 1) + level index, so that
+// the sort orders each column's volumes by level and a wave of the step
+// covers few levels (removed volumes keep their reason, at level 0)
+__global__ void k_levkey32(Grid g, const int32_t *__restrict__ lev, uint32_t *__restrict__ key,
+                           const DevCounters *__restrict__ dc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dc->n_sorted) return;
+    const uint32_t k = key[i];
+    const int l = k < (uint32_t)g.ncol ? min(max(lev[i], 0), g.nz) : 0;
+    key[i] = k * (uint32_t)(g.nz + 1) + (uint32_t)l;
+}
+
+void launch_levkey32(const Grid &g, S32 st, uint32_t *key, const DevCounters *dc, int64_t bound, hipStream_t s)
+{
+    if (bound <= 0) return;
+    k_levkey32<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(g, st.lev, key, dc);
+}
+
 void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc, double *red,
                     hipStream_t s)
 {

@@ -191,15 +191,89 @@ void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCount
 // Reads the current set in sorted order through perm, writes the next
 // buffer contiguously, so the state stays grouped by column.
 // ---------------------------------------------------------------------------
+// One wave per workgroup (a workgroup's slot and stencil box are released as
+// soon as its wave ends).  A wave whose volumes share one column first stages
+// the background stencil they use into LDS (dev64.h).
+#define STEP64_BLOCK 64
+
 template <bool SPH>
-__global__ __launch_bounds__(256, 2) void k_step64(Grid g, Bg64P b, S64 src, S64 dst, const uint32_t *__restrict__ perm,
-                                                uint32_t *__restrict__ key_out, const DevCounters *__restrict__ dc, double dt,
-                                                const uint8_t *__restrict__ frozen, const uint32_t *__restrict__ skeys)
+__global__ __launch_bounds__(STEP64_BLOCK, 2) void k_step64(Grid g, Bg64P b, S64 src, S64 dst,
+                                                            const uint32_t *__restrict__ perm,
+                                                            uint32_t *__restrict__ key_out,
+                                                            const DevCounters *__restrict__ dc, double dt,
+                                                            const uint8_t *__restrict__ frozen,
+                                                            const uint32_t *__restrict__ skeys)
 {
     const int64_t i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= dc->n_active) return;
-    const uint32_t s = perm[i];
-    double Y[9] = {src.x[s], src.y[s], src.z[s], src.k[s], src.l[s], src.m[s], src.dx[s], src.dy[s], src.dz[s]};
+    // all lanes take part in the staging (the wave-wide reductions need them)
+    const bool valid = i < dc->n_active;
+    const uint32_t s = valid ? perm[i] : 0u;
+    double Y[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid) {
+        Y[0] = src.x[s];
+        Y[1] = src.y[s];
+        Y[2] = src.z[s];
+        Y[3] = src.k[s];
+        Y[4] = src.l[s];
+        Y[5] = src.m[s];
+        Y[6] = src.dx[s];
+        Y[7] = src.dy[s];
+        Y[8] = src.dz[s];
+    }
+    d64::WBox w;
+    {
+        // the sorted key of an active slot is its volume's column
+        const uint32_t col = valid ? skeys[i] : 0xffffffffu;
+        const double q = floor(Y[2] / g.dz);
+        const int kc = q >= 0.0 ? (q < (double)(g.nz - 1) ? (int)q : g.nz - 1) : 0;  // NaN gives 0
+        const int lane = threadIdx.x & 63;
+        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)col);
+        const bool uni = __ballot(valid && col != c0) == 0ull && c0 < (uint32_t)g.ncol;
+        const int kmn = wave_min_i(valid ? kc : 0x7fffffff), kmx = wave_max_i(valid ? kc : -1);
+        w.ic = (int)(c0 % (uint32_t)g.nx);
+        w.jc = (int)(c0 / (uint32_t)g.nx);
+        // two levels below and three above the wave's levels hold the faces
+        // of most volumes
+        w.kbase = max(0, kmn - 2);
+        w.L = min(g.nz - 1, kmx + 3) - w.kbase + 1;
+        // one wrap corrects a column or row index when the grid has at least two
+        w.on = uni && w.L <= WB64_LMAX && g.nx >= 2 && (g.geometry != RT_CARTESIAN || g.ny >= 2);
+        if (w.on) {
+            // t / L as (t * ceil(2^16 / L)) >> 16, exact for t < 512 and L <= 26
+            const int nA = 25 * w.L, nG = 18 * w.L, L9 = 9 * w.L;
+            const uint32_t mL = (65536u + (uint32_t)w.L - 1u) / (uint32_t)w.L;
+            for (int e = lane; e < nA; e += 64) {
+                const int bxy = (int)(((uint32_t)e * mL) >> 16), kk = e - bxy * w.L;
+                int ii = w.ic + bxy % 5 - 2, jj = w.jc + bxy / 5 - 2;
+                ii += ii < 0 ? g.nx : 0;
+                ii -= ii >= g.nx ? g.nx : 0;
+                if (g.geometry == RT_CARTESIAN) {
+                    jj += jj < 0 ? g.ny : 0;
+                    jj -= jj >= g.ny ? g.ny : 0;
+                } else {
+                    jj = min(max(jj, 0), g.ny - 1);
+                }
+                d64::wb64_lds[e] = b.A[(jj * g.nx + ii) * g.nz + w.kbase + kk];
+            }
+            for (int e = lane; e < nG; e += 64) {
+                const int r = e >= L9 ? 1 : 0, t = e - r * L9;
+                const int bxy = (int)(((uint32_t)t * mL) >> 16), kk = t - bxy * w.L;
+                int ii = w.ic + bxy % 3 - 1, jj = w.jc + bxy / 3 - 1;
+                ii += ii < 0 ? g.nx : 0;
+                ii -= ii >= g.nx ? g.nx : 0;
+                if (g.geometry == RT_CARTESIAN) {
+                    jj += jj < 0 ? g.ny : 0;
+                    jj -= jj >= g.ny ? g.ny : 0;
+                } else {
+                    jj = min(max(jj, 0), g.ny - 1);
+                }
+                d64::wb64_lds[WB64_A + r * 9 * WB64_LMAX + t] = b.G[((jj * g.nx + ii) * g.nz + w.kbase + kk) * 2 + r];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (!valid) return;
     double Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double F[9];
     const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
@@ -208,7 +282,7 @@ __global__ __launch_bounds__(256, 2) void k_step64(Grid g, Bg64P b, S64 src, S64
     const int nst = (frozen && frozen[skeys[i]]) ? 0 : 3;
 #pragma unroll 1
     for (int st = 0; st < nst; st++) {
-        d64::rhs<SPH>(g, b, Y, F);
+        d64::rhs<SPH>(g, b, Y, F, w);
 #pragma unroll
         for (int c = 0; c < 9; c++) {
             Q[c] = A[st] * Q[c] + dt * F[c];
@@ -238,11 +312,12 @@ void launch_step64(const Grid &g, const Bg64P &b, S64 src, S64 dst, const uint32
                    hipStream_t s)
 {
     if (bound <= 0) return;
-    const unsigned nb = (unsigned)((bound + 255) / 256);
+    const unsigned nb = (unsigned)((bound + STEP64_BLOCK - 1) / STEP64_BLOCK);
+    const size_t lds = (size_t)WB64_RECS * sizeof(double4);  // the wave's stencil box
     if (g.geometry == RT_SPHERICAL)
-        k_step64<true><<<nb, 256, 0, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
+        k_step64<true><<<nb, STEP64_BLOCK, lds, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
     else
-        k_step64<false><<<nb, 256, 0, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
+        k_step64<false><<<nb, STEP64_BLOCK, lds, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,6 +352,28 @@ __global__ void k_tally64(Grid g, S64 st, const uint32_t *perm, const uint32_t *
     }
     if (tid == 0) dc->removed_W += sw[0];
     if (tid < RK_NREASON) dc->removed[tid] += cnt[tid];
+}
+
+// sort key refined by the level (as in single precision): column key *
+// (nz + 1) + floor(z / dz), clamped to 0 .. nz
+__global__ void k_levkey64(Grid g, const double *__restrict__ z, uint32_t *__restrict__ key,
+                           const DevCounters *__restrict__ dc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dc->n_sorted) return;
+    const uint32_t k = key[i];
+    int l = 0;
+    if (k < (uint32_t)g.ncol) {
+        const double q = floor(z[i] / g.dz);
+        l = q > (double)g.nz ? g.nz : (q >= 0.0 ? (int)q : 0);  // NaN gives 0
+    }
+    key[i] = k * (uint32_t)(g.nz + 1) + (uint32_t)l;
+}
+
+void launch_levkey64(const Grid &g, S64 st, uint32_t *key, const DevCounters *dc, int64_t bound, hipStream_t s)
+{
+    if (bound <= 0) return;
+    k_levkey64<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(g, st.z, key, dc);
 }
 
 void launch_tally64(const Grid &g, S64 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc, double *red,

@@ -94,6 +94,7 @@ struct rt_ctx_s {
     S32 s32[2];
     uint32_t *key[2];
     int cur;
+    int64_t n_sorts;  // regrouping sorts since the last load (some refine by level)
     int64_t cap;
     int64_t n_bound;  // host-side upper bound of active count (the device holds the exact one)
     bool have_rays;
@@ -208,6 +209,9 @@ int64_t radix_hist_len(int64_t bound);
 void scan_u32(uint32_t *t, int64_t len, uint32_t *parts, hipStream_t s);
 int64_t scan_tmp_len(int64_t len);
 void launch_colstart(const uint32_t *skeys, DevCounters *dc, uint32_t *colstart, int ncol, hipStream_t s);
+void launch_levkey32(const Grid &g, S32 st, uint32_t *key, const DevCounters *dc, int64_t bound, hipStream_t s);
+void launch_levkey64(const Grid &g, S64 st, uint32_t *key, const DevCounters *dc, int64_t bound, hipStream_t s);
+void launch_colkey(uint32_t *skeys, const DevCounters *dc, uint32_t nl, int64_t bound, hipStream_t s);
 
 void launch_tally64(const Grid &g, S64 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc,
                     double *red, hipStream_t s);

@@ -211,6 +211,20 @@ void radix_sort(const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out, 
     }
 }
 
+// sorted keys refined by the level back to column keys
+__global__ void k_colkey(uint32_t *__restrict__ skeys, const DevCounters *__restrict__ dc, uint32_t nl)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= dc->n_sorted) return;
+    skeys[i] = skeys[i] / nl;
+}
+
+void launch_colkey(uint32_t *skeys, const DevCounters *dc, uint32_t nl, int64_t bound, hipStream_t s)
+{
+    if (bound <= 0) return;
+    k_colkey<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(skeys, dc, nl);
+}
+
 // column c occupies sorted positions [colstart[c], colstart[c+1]); removed
 // volumes (keys >= ncol) follow at [colstart[ncol], n_sorted)
 __global__ void k_colstart(const uint32_t *__restrict__ skeys, DevCounters *dc, uint32_t *__restrict__ colstart, int ncol)

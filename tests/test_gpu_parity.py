@@ -244,18 +244,24 @@ def test_removal_tallies_match_oracle(rt, orc):
         assert s[key] == pytest.approx(so[key], rel=1e-13)
 
 
-def test_load_order_is_stable_column_sort(rt, orc):
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_load_order(rt, orc, prec):
+    """Loaded volumes come out as a stable sort by column and then level index
+    floor(z / dz), in both precisions."""
     w = c2_small(64)
     rng = np.random.default_rng(3)
     perm = rng.permutation(w.n_rays)
     rays = {k: v[perm].copy() for k, v in w.rays.items()}
-    tr = gpu_tracer(w, rt.RT_FP64, rays=rays)
+    tr = gpu_tracer(w, rt.RT_FP64 if prec == "fp64" else rt.RT_FP32, rays=rays)
     g = tr.get_rays()
     bg = orc.Background.from_workload(w)
     rs = orc.RaySet(rays)
     orc.keys(bg, rs)
-    expect = np.argsort(rs["col"], kind="stable")
+    lev = np.clip(np.floor(rays["z"] / w.dz), 0, w.nz).astype(np.int64)
+    key = rs["col"].astype(np.int64) * (w.nz + 1) + lev
+    expect = np.argsort(key, kind="stable")
     assert np.array_equal(g["id"], rays["id"][expect])
+    assert np.array_equal(tr.get_columns(), np.sort(rs["col"]))
 
 
 def test_api_errors(rt):
