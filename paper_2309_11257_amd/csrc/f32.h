@@ -199,7 +199,9 @@ __device__ inline float4 tri4(const float4 *__restrict__ F, const Cell &c, int r
 // field)
 __device__ inline float row_lerp(const float *__restrict__ f, const Axis &y)
 {
-    const float a = f[y.i0], b = f[y.i1];
+    // 32-bit byte offsets from the uniform base (rows are non-negative)
+    const char *p = (const char *)f;
+    const float a = *(const float *)(p + ((uint32_t)y.i0 << 2)), b = *(const float *)(p + ((uint32_t)y.i1 << 2));
     return a + y.w * (b - a);
 }
 
@@ -257,11 +259,12 @@ __device__ inline bool box_of(const G32 &g, const WBox &w, const Axis &x, const 
     }
     b.k0 = z.i0 - w.kbase;
     b.k1 = z.i1 - w.kbase;
+    // 24-bit products (full rate): the factors are small box offsets
     const int side = 2 * RAD + 1;
-    b.r00 = ((dy0 + RAD) * side + (dx0 + RAD)) * w.L;
-    b.r01 = ((dy0 + RAD) * side + (dx1 + RAD)) * w.L;
-    b.r10 = ((dy1 + RAD) * side + (dx0 + RAD)) * w.L;
-    b.r11 = ((dy1 + RAD) * side + (dx1 + RAD)) * w.L;
+    b.r00 = __mul24((dy0 + RAD) * side + (dx0 + RAD), w.L);
+    b.r01 = __mul24((dy0 + RAD) * side + (dx1 + RAD), w.L);
+    b.r10 = __mul24((dy1 + RAD) * side + (dx0 + RAD), w.L);
+    b.r11 = __mul24((dy1 + RAD) * side + (dx1 + RAD), w.L);
     return abs(dx0) <= RAD && abs(dx1) <= RAD && abs(dy0) <= RAD && abs(dy1) <= RAD && b.k0 >= 0 && b.k1 < w.L;
 }
 
