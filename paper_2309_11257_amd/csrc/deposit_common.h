@@ -38,7 +38,8 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// P::load(slot, zb, zt, bv[6]) fills the vertical span of the volume and its
+// P::load(slot, column, zb, zt, bv[6]) fills the vertical span of the volume
+// (in the column the sort grouped it in) and its
 // six flux densities per unit height: (cgx k, cgx l, cgy k, cgy l, cgz k,
 // cgz l) * W / Dz.
 //
@@ -75,15 +76,19 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
             const uint32_t r = base + (uint32_t)lane;
             const bool valid = r < s1;
             double zb = 0.0, zt = 0.0, bv[6] = {0, 0, 0, 0, 0, 0};
-            if (valid) pl.load(perm[r], zb, zt, bv);
+            if (valid) pl.load(perm[r], c, zb, zt, bv);
             const double h = valid ? fmin(zt - zb, g.dz) : 0.0;
             // per field: the largest possible contribution of the chunk sets
             // the fixed-point scale (a bound on each |bv * overlap|)
             int sx[6];
 #pragma unroll
-            for (int q = 0; q < 6; q++) {
-                const int em = wave_max_i(bexp(fabs(bv[q]) * h));
-                sx[q] = (em > 0 && em < 0x7fe) ? 51 - (em - 1022) : 0;
+            for (int q = 0; q < 6; q += 2) {
+                // two 11-bit exponents per reduction
+                const uint32_t pm = wave_max_u16x2(((uint32_t)bexp(fabs(bv[q]) * h) << 16) |
+                                                   (uint32_t)bexp(fabs(bv[q + 1]) * h));
+                const int ea = (int)(pm >> 16), eb = (int)(pm & 0xffffu);
+                sx[q] = (ea > 0 && ea < 0x7fe) ? 51 - (ea - 1022) : 0;
+                sx[q + 1] = (eb > 0 && eb < 0x7fe) ? 51 - (eb - 1022) : 0;
             }
             int klo = 0x7fffffff, khi = -1;
             if (valid) {

@@ -237,10 +237,6 @@ struct WBox {
     int ic, jc, kbase, L, base;
 };
 
-struct BCell {
-    int r00, r01, r10, r11, k0, k1;
-};
-
 __device__ inline int wrapd(int d, int n)
 {
     if (d > n / 2) d -= n;
@@ -248,37 +244,43 @@ __device__ inline int wrapd(int d, int n)
     return d;
 }
 
+// box position of a stencil: the box holds column (ic + d) mod nx at x
+// offset d (and the row the global lookup reads at y offset d), so the upper
+// x node of a cell is always the next box column and the upper y and z nodes
+// the next row and level unless the axis clamps them; one base index and two
+// strides (0 or a row, 0 or a level) locate all eight corners.  Layout
+// [dy][dx][k] with a column stride of WB_LMAX records.
+struct BCell {
+    int base, sy, sz;
+};
+
 template <int RAD>
 __device__ inline bool box_of(const G32 &g, const WBox &w, const Axis &x, const Axis &y, const Axis &z, BCell &b)
 {
-    const int dx0 = wrapd(x.i0 - w.ic, g.nx), dx1 = wrapd(x.i1 - w.ic, g.nx);
-    int dy0 = y.i0 - w.jc, dy1 = y.i1 - w.jc;
-    if (g.geometry == RT_CARTESIAN) {
-        dy0 = wrapd(dy0, g.ny);
-        dy1 = wrapd(dy1, g.ny);
-    }
-    b.k0 = z.i0 - w.kbase;
-    b.k1 = z.i1 - w.kbase;
-    // 24-bit products (full rate): the factors are small box offsets
+    const int dx0 = wrapd(x.i0 - w.ic, g.nx);
+    int dy0 = y.i0 - w.jc;
+    if (g.geometry == RT_CARTESIAN) dy0 = wrapd(dy0, g.ny);
+    const int ey = y.i1 - y.i0, k0 = z.i0 - w.kbase;  // ey: 0 (clamped) or 1 (or 1 - ny, periodic wrap)
     const int side = 2 * RAD + 1;
-    b.r00 = __mul24((dy0 + RAD) * side + (dx0 + RAD), w.L);
-    b.r01 = __mul24((dy0 + RAD) * side + (dx1 + RAD), w.L);
-    b.r10 = __mul24((dy1 + RAD) * side + (dx0 + RAD), w.L);
-    b.r11 = __mul24((dy1 + RAD) * side + (dx1 + RAD), w.L);
-    return abs(dx0) <= RAD && abs(dx1) <= RAD && abs(dy0) <= RAD && abs(dy1) <= RAD && b.k0 >= 0 && b.k1 < w.L;
+    b.base = __mul24((dy0 + RAD) * side + (dx0 + RAD), WB_LMAX) + k0;
+    b.sy = ey != 0 ? side * WB_LMAX : 0;
+    b.sz = z.i1 - z.i0;
+    return dx0 >= -RAD && dx0 < RAD && dy0 >= -RAD && dy0 + (ey != 0 ? 1 : 0) <= RAD && k0 >= 0 &&
+           k0 + b.sz < w.L;
 }
 
 template <int R>
 __device__ inline void fill_box(Corners<R> &K, int off, const BCell &b)
 {
-    K.a0 = wb_lds[off + b.r00 + b.k0];
-    K.a1 = wb_lds[off + b.r01 + b.k0];
-    K.b0 = wb_lds[off + b.r10 + b.k0];
-    K.b1 = wb_lds[off + b.r11 + b.k0];
-    K.d0 = wb_lds[off + b.r00 + b.k1];
-    K.d1 = wb_lds[off + b.r01 + b.k1];
-    K.e0 = wb_lds[off + b.r10 + b.k1];
-    K.e1 = wb_lds[off + b.r11 + b.k1];
+    const int p = off + b.base;
+    K.a0 = wb_lds[p];
+    K.a1 = wb_lds[p + WB_LMAX];
+    K.b0 = wb_lds[p + b.sy];
+    K.b1 = wb_lds[p + b.sy + WB_LMAX];
+    K.d0 = wb_lds[p + b.sz];
+    K.d1 = wb_lds[p + b.sz + WB_LMAX];
+    K.e0 = wb_lds[p + b.sy + b.sz];
+    K.e1 = wb_lds[p + b.sy + b.sz + WB_LMAX];
 }
 
 // A corners of a cell: from the box when every lane of the wave is inside

@@ -232,21 +232,23 @@ struct Pay32 {
     Bg32P b;
     S32 st;
     double zdz;  // level spacing in double
-    __device__ void load(uint32_t s, double &zb, double &zt, double *bv) const
+    __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
-        const uint32_t col = st.col[s];
-        const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
+        // the wave's column (the slot's own column, by the grouping)
+        const int jc = (int)((uint32_t)col / (uint32_t)g.nx), ic = col - jc * g.nx;
         const int kc = st.lev[s];
         const float zeta = st.zeta[s];
         const float k = st.k[s], l = st.l[s], m = st.m[s];
         const float Dz = st.dz[s];
         float N2, f2;
         f32::n2_f2(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta, N2, f2);
+        // group velocity as in the step: one-rounding reciprocal and
+        // reciprocal square root
         const float kh2 = k * k + l * l;
         const float m2 = m * m;
-        const float K2 = kh2 + m2;
-        const float om = sqrtf((N2 * kh2 + f2 * m2) / K2);
-        const float sc = (N2 - f2) / (K2 * K2) / om;
+        const float invK2 = f32::rcp(kh2 + m2);
+        const float rom = f32::rsq((N2 * kh2 + f2 * m2) * invK2);  // 1 / omega_hat
+        const float sc = (N2 - f2) * (invK2 * invK2) * rom;
         const double cx = (double)(k * m2 * sc);
         const double cy = (double)(l * m2 * sc);
         const double cz = (double)(-m * kh2 * sc);

@@ -442,7 +442,7 @@ struct Pay64 {
     Grid g;
     Bg64P b;
     S64 st;
-    __device__ void load(uint32_t s, double &zb, double &zt, double *bv) const
+    __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
         const double x = st.x[s], y = st.y[s], z = st.z[s];
         const double k = st.k[s], l = st.l[s], m = st.m[s], Dz = st.dz[s];

@@ -151,6 +151,23 @@ __device__ inline int wave_reduce_i(int v)
     return __builtin_amdgcn_readlane(v, 63);
 }
 __device__ inline int wave_max_i(int v) { return wave_reduce_i<true>(v); }
+// wave-wide maximum of the two 16-bit halves of v, each on its own (packed
+// 16-bit integer maximum)
+__device__ inline uint32_t wave_max_u16x2(uint32_t v)
+{
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    auto op = [](uint32_t a, int b) {
+        const u16x2 x = __builtin_bit_cast(u16x2, a), y = __builtin_bit_cast(u16x2, (uint32_t)b);
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, y));
+    };
+    v = op(v, __builtin_amdgcn_update_dpp((int)v, (int)v, DPP_QUAD_1032, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp((int)v, (int)v, DPP_QUAD_2301, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_HALF_MIRROR, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_MIRROR, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_BCAST15, 0xA, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_BCAST31, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
 __device__ inline int wave_min_i(int v) { return wave_reduce_i<false>(v); }
 
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2);

@@ -86,14 +86,18 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
 #pragma unroll
             for (int it = 0; it < NA; it++) {
                 const int e = lane + 64 * it;
-                if (e < nA) f32::wb_lds[w.base + e] = va[it];
+                if (e < nA) {
+                    const int bxy = (int)(((uint32_t)e * mL) >> 16), kk = e - bxy * w.L;
+                    f32::wb_lds[w.base + bxy * WB_LMAX + kk] = va[it];
+                }
             }
 #pragma unroll
             for (int it = 0; it < NG; it++) {
                 const int e = lane + 64 * it;
                 if (e < nG) {
-                    const int r = e >= L9 ? 1 : 0;
-                    f32::wb_lds[w.base + WB_A + r * 9 * WB_LMAX + (e - r * L9)] = vg[it];
+                    const int r = e >= L9 ? 1 : 0, tt = e - r * L9;
+                    const int bxy = (int)(((uint32_t)tt * mL) >> 16), kk = tt - bxy * w.L;
+                    f32::wb_lds[w.base + WB_A + r * 9 * WB_LMAX + bxy * WB_LMAX + kk] = vg[it];
                 }
             }
         }
