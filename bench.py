@@ -237,6 +237,120 @@ def surrogate_report(log_rays=50_000_000, steps=100):
             "plain_fp64_ms_per_step": round(ms64, 4), "coupled": rows}
 
 
+def _ev_ms(fn, reps):
+    """Mean GPU time of fn() over reps calls (events on the current stream,
+    which is the library's stream), after one untimed call."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _row(row, workload, precision, ms, nbytes, oracle_s, cores, sample, note=""):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"row": row, "workload": workload, "dtype": precision, "gpu_ms": round(ms, 4),
+            "algorithmic_bytes": int(nbytes), "achieved_GBs": round(gbs, 1), "bound": "hbm",
+            "peak_GBs": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 4),
+            "oracle_s": round(oracle_s, 3), "oracle_cores": cores, "oracle_sample": sample,
+            "gpu_vs_oracle": round(oracle_s / (ms * 1e-3), 1), "note": note}
+
+
+def rows_report():
+    """The rows of the path that the step line does not time: background
+    preparation (a0) and surrogate features (a11) on the global 20 M-volume
+    workload, vertical splitting with per-cell merging (a9, a10) on the full
+    jet box; each with its algorithmic HBM bytes and the oracle timed on the
+    same operation.  One JSON line per row."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2309_11257_amd import _rt
+    from paper_2309_11257_amd import workloads as W
+    out = []
+    cores = oracle.num_threads()
+    w3 = W.make_c3()
+    cells = w3.nx * w3.ny * w3.nz
+    t = time.perf_counter()
+    bg3 = oracle.Background.from_workload(w3)
+    t_bg = time.perf_counter() - t
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    U, V, N2, f, rho = dev(w3.U), dev(w3.V), dev(w3.N2), dev(w3.f), dev(w3.rho)
+    # a0: fields read once (U, V, N2), packed records written once (three
+    # records of 4 values per cell)
+    for prec, name, rec in ((_rt.RT_FP32, "f32", 4), (_rt.RT_FP64, "f64", 8)):
+        tr = _rt.Tracer.for_workload(w3, prec, capacity=1)
+        ms = _ev_ms(lambda: tr.init_background(U, V, N2, f, rho), 5)
+        out.append(_row("a0", f"global {w3.nx}x{w3.ny}x{w3.nz} background", name, ms, cells * (3 * 8 + 12 * rec),
+                        t_bg, cores, f"oracle background preparation of the same grid ({t_bg:.2f} s)",
+                        "gradients by centred differences, (f^2)_y, packing into 3 records per cell"))
+        tr.close()
+    del U, V, N2, f, rho
+    # a11: features of the 20 M volumes after one step
+    tr = _rt.Tracer.for_workload(w3, _rt.RT_FP32)
+    tr.init_background_from(w3)
+    tr.set_rays(w3.rays)
+    tr.step(w3.dt)
+    X = torch.empty((w3.nx * w3.ny, 3 * w3.nz + 48), dtype=torch.float32, device="cuda")
+    ms = _ev_ms(lambda: tr.features(X), 5)
+    tr.close()
+    del X
+    rs3 = oracle.RaySet(w3.rays)
+    oracle.step(bg3, rs3, w3.dt)
+    t = time.perf_counter()
+    oracle.features(bg3, rs3)
+    t_f = time.perf_counter() - t
+    ncol = w3.nx * w3.ny
+    # per volume: k, l, m, zeta, xi, eta, lev, col (4 B each) + W (8 B) + the
+    # sort permutation (4 B); per column: the background profiles in and the
+    # feature row out
+    nbytes = w3.n_rays * 48 + ncol * w3.nz * 16 + ncol * (3 * w3.nz + 48) * 4
+    out.append(_row("a11", f"global {w3.nx}x{w3.ny}x{w3.nz}, {w3.n_rays} ray volumes", "f32", ms, nbytes, t_f,
+                    cores, f"oracle features of the same state ({t_f:.2f} s)", "8 azimuth sectors x 6 moments"))
+    del rs3, bg3
+    # a9 + a10: split (alpha = 2) and per-cell merge (64) on the jet box
+    w2 = W.make_c2()
+    cap = 2 * w2.n_rays
+    for prec, name, vb in ((_rt.RT_FP64, "f64", 112), (_rt.RT_FP32, "f32", 72)):
+        tr = _rt.Tracer.for_workload(w2, prec, capacity=cap)
+        tr.init_background_from(w2)
+        tr.set_rays(w2.rays)
+        ms_tot, n_tot, nvol = 0.0, 0, 0
+        for _ in range(6):
+            tr.step(w2.dt)
+            tr.profile(True)
+            tr.profile_read()
+            nvol += tr.stats()["n_active"]
+            tr.split_merge(w2.split_alpha, w2.merge_nmax, _rt.RT_MERGE)
+            # all timed groups of the call (its regrouping sort times as a sort)
+            ms_tot += sum(v[0] for v in tr.profile_read().values())
+            tr.profile(False)
+            n_tot += 1
+        tr.close()
+        ms, nv = ms_tot / n_tot, nvol / n_tot
+        bg2 = oracle.Background.from_workload(w2)
+        rs2 = oracle.RaySet(w2.rays, capacity=cap)
+        oracle.step(bg2, rs2, w2.dt)
+        t = time.perf_counter()
+        oracle.split(bg2, rs2, w2.split_alpha)
+        oracle.merge(bg2, rs2, w2.merge_nmax)
+        t_sm = time.perf_counter() - t
+        # the state is compacted (read and written once) and regrouped
+        out.append(_row("a9+a10", f"jet box {w2.nx}x{w2.ny}x{w2.nz}, {int(nv)} ray volumes", name, ms, 2 * vb * nv,
+                        t_sm, cores, f"oracle split + merge after one step ({t_sm:.2f} s)",
+                        "compaction, split count/scan/write, cell-key sort, per-cell merge, regrouping sort; "
+                        "mean over the first 6 steps"))
+    for r in out:
+        print(json.dumps(r), flush=True)
+    return out
+
+
 def load_traffic(kernel, rays):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source."""
@@ -262,6 +376,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--surrogate", action="store_true",
                     help="also train the column surrogate and run it coupled with the tracer on 50 M volumes")
+    ap.add_argument("--rows", action="store_true",
+                    help="only time the rows the step line does not cover (a0, a9+a10, a11), one JSON line each")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -281,6 +397,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": n * 4}))
+        return
+
+    if args.rows:
+        rows_report()
         return
 
     from paper_2309_11257_amd import _rt

@@ -60,6 +60,8 @@ static void prof_fold(rt_ctx c)
     p->used = 0;
 }
 
+// groups must not nest: each prof_begin is closed by a prof_end before the
+// next prof_begin
 void prof_begin(rt_ctx c, int cls)
 {
     if (!c->prof_on) return;
@@ -274,6 +276,7 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     ALLOC(ctx->coslat, double, g.ny);
     ALLOC(ctx->dc, DevCounters, 1);
     ALLOC(ctx->red, double, 8 + 4 * (cap / 256 + 2));
+    ALLOC(ctx->tred, double, 256);  // removal tally partials
     ALLOC(ctx->ired, int64_t, 8 + 2 * cap);
     ALLOC(ctx->sm, uint32_t, 8 * cap + 16 + scan_tmp_len(cap));
     if (hipMemsetAsync(ctx->dc, 0, sizeof(DevCounters), ctx->stream) != hipSuccess ||
@@ -341,9 +344,9 @@ static rt_status sort_current(rt_ctx ctx)
     if (bylev) launch_colkey(ctx->skeys, ctx->dc, (uint32_t)nl, bound, ctx->stream);
     launch_colstart(ctx->skeys, ctx->dc, ctx->colstart, ctx->g.ncol, ctx->stream);
     if (ctx->precision == RT_FP64)
-        launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->red, ctx->stream);
+        launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
     else
-        launch_tally32(ctx->g, ctx->s32[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->red, ctx->stream);
+        launch_tally32(ctx->g, ctx->s32[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
     prof_end(ctx);
     HIP_OK(hipGetLastError());
     return RT_OK;

@@ -4,6 +4,8 @@
 // wave action W = N Px Py Pz is formed once in double at load and kept in
 // double, and every flux sum is accumulated in double.
 #include "dev64.h"
+#include "tally_common.h"
+#include "pack_common.h"
 #include "f32.h"
 #include "deposit_common.h"
 #include "features_common.h"
@@ -12,22 +14,9 @@
 // packed single-precision background: A = (U, V, N2, Ux),
 // G = (Uy, Uz, Vx, Vy), (Vz, N2x, N2y, N2z) at index col*nz + k
 // ---------------------------------------------------------------------------
-__global__ void k_pack32(Grid g, Bg<double> b, float4 *A, float4 *G)
-{
-    const int64_t cells = (int64_t)g.ncol * g.nz;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= cells) return;
-    const int64_t col = e / g.nz, k = e % g.nz;
-    const int64_t s = k * g.ncol + col;
-    A[e] = make_float4((float)b.U[s], (float)b.V[s], (float)b.N2[s], (float)b.Ux[s]);
-    G[2 * e] = make_float4((float)b.Uy[s], (float)b.Uz[s], (float)b.Vx[s], (float)b.Vy[s]);
-    G[2 * e + 1] = make_float4((float)b.Vz[s], (float)b.N2x[s], (float)b.N2y[s], (float)b.N2z[s]);
-}
-
 void launch_pack32(const Grid &g, const Bg<double> &b, float4 *A, float4 *G, hipStream_t s)
 {
-    const int64_t cells = (int64_t)g.ncol * g.nz;
-    k_pack32<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, b, A, G);
+    launch_pack_k<float, float4>(g, b, A, G, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -122,32 +111,8 @@ void launch_store32(const Grid &g, S32 src, const uint32_t *perm, const DevCount
 }
 
 // ---------------------------------------------------------------------------
-// tallies and diagnostics (deterministic, see kern64.hip)
+// tallies and diagnostics (deterministic, see kern64.hip and tally_common.h)
 // ---------------------------------------------------------------------------
-__global__ void k_tally32(Grid g, S32 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc)
-{
-    __shared__ double sw[256];
-    __shared__ int cnt[RK_NREASON];
-    const int tid = threadIdx.x;
-    if (tid < RK_NREASON) cnt[tid] = 0;
-    __syncthreads();
-    const int64_t a = dc->n_active, e = dc->n_sorted;
-    double w = 0.0;
-    for (int64_t i = a + tid; i < e; i += 256) {
-        const int reason = (int)(skeys[i] - (uint32_t)g.ncol);
-        if (reason >= 0 && reason < RK_NREASON) atomicAdd(&cnt[reason], 1);
-        if (reason != RK_INVALID && reason != RK_MERGED) w += st.W[perm[i]];
-    }
-    sw[tid] = w;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) sw[tid] += sw[tid + off];
-        __syncthreads();
-    }
-    if (tid == 0) dc->removed_W += sw[0];
-    if (tid < RK_NREASON) dc->removed[tid] += cnt[tid];
-}
-
 // sort key refined by the level: column key * (nz + 1) + level index, so that
 // the sort orders each column's volumes by level and a wave of the step
 // covers few levels (removed volumes keep their reason, at level 0)
@@ -167,11 +132,15 @@ void launch_levkey32(const Grid &g, S32 st, uint32_t *key, const DevCounters *dc
     k_levkey32<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(g, st.lev, key, dc);
 }
 
+struct W32 {
+    const double *w;
+    __device__ double W(uint32_t slot) const { return w[slot]; }
+};
+
 void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc, double *red,
                     hipStream_t s)
 {
-    (void)red;
-    k_tally32<<<1, 256, 0, s>>>(g, st, perm, skeys, dc);
+    launch_tally_k(g, W32{st.W}, perm, skeys, dc, red, s);
 }
 
 __global__ void k_stats32_part(S32 st, const uint32_t *perm, const DevCounters *dc, double *part)

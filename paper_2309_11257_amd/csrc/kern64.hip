@@ -4,6 +4,8 @@
 #include "deposit_common.h"
 #include "features_common.h"
 #include "dev64.h"
+#include "tally_common.h"
+#include "pack_common.h"
 
 // ---------------------------------------------------------------------------
 // background: centred-difference gradients (periodic in x, and in y on the
@@ -84,22 +86,9 @@ void launch_gradients64(const Grid &g, const double *U, const double *V, const d
 }
 
 // packed column-major records (see rt_internal.h) from the [nz][ny][nx] fields
-__global__ void k_pack64(Grid g, Bg<double> b, double4 *A, double4 *G)
-{
-    const int64_t cells = (int64_t)g.ncol * g.nz;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // packed index col*nz + k
-    if (e >= cells) return;
-    const int64_t col = e / g.nz, k = e % g.nz;
-    const int64_t s = k * g.ncol + col;  // source index
-    A[e] = make_double4(b.U[s], b.V[s], b.N2[s], b.Ux[s]);
-    G[2 * e] = make_double4(b.Uy[s], b.Uz[s], b.Vx[s], b.Vy[s]);
-    G[2 * e + 1] = make_double4(b.Vz[s], b.N2x[s], b.N2y[s], b.N2z[s]);
-}
-
 void launch_pack64(const Grid &g, const Bg<double> &b, double4 *A, double4 *G, hipStream_t s)
 {
-    const int64_t cells = (int64_t)g.ncol * g.nz;
-    k_pack64<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, b, A, G);
+    launch_pack_k<double, double4>(g, b, A, G, s);
 }
 
 
@@ -330,29 +319,10 @@ __device__ inline double W64(const S64 &st, uint32_t s)
     return ((st.n[s] * st.px[s]) * st.py[s]) * st.pz[s];
 }
 
-__global__ void k_tally64(Grid g, S64 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc)
-{
-    __shared__ double sw[256];
-    __shared__ int cnt[RK_NREASON];
-    const int tid = threadIdx.x;
-    if (tid < RK_NREASON) cnt[tid] = 0;
-    __syncthreads();
-    const int64_t a = dc->n_active, e = dc->n_sorted;
-    double w = 0.0;
-    for (int64_t i = a + tid; i < e; i += 256) {
-        const int reason = (int)(skeys[i] - (uint32_t)g.ncol);
-        if (reason >= 0 && reason < RK_NREASON) atomicAdd(&cnt[reason], 1);
-        if (reason != RK_INVALID && reason != RK_MERGED) w += W64(st, perm[i]);
-    }
-    sw[tid] = w;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) sw[tid] += sw[tid + off];
-        __syncthreads();
-    }
-    if (tid == 0) dc->removed_W += sw[0];
-    if (tid < RK_NREASON) dc->removed[tid] += cnt[tid];
-}
+struct W64s {
+    S64 st;
+    __device__ double W(uint32_t slot) const { return W64(st, slot); }
+};
 
 // sort key refined by the level (as in single precision): column key *
 // (nz + 1) + floor(z / dz), clamped to 0 .. nz
@@ -379,8 +349,7 @@ void launch_levkey64(const Grid &g, S64 st, uint32_t *key, const DevCounters *dc
 void launch_tally64(const Grid &g, S64 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc, double *red,
                     hipStream_t s)
 {
-    (void)red;
-    k_tally64<<<1, 256, 0, s>>>(g, st, perm, skeys, dc);
+    launch_tally_k(g, W64s{st}, perm, skeys, dc, red, s);
 }
 
 // sums of W, kW, lW, mW over the active set: per-block partials, then one

@@ -112,6 +112,7 @@ struct rt_ctx_s {
     // counters
     DevCounters *dc;
     double *red;      // reduction scratch
+    double *tred;     // removal tally partials [256]
     int64_t *ired;    // integer scratch
     uint32_t *sm;     // split/merge scratch
     // allocation bookkeeping

@@ -739,8 +739,8 @@ rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, r
         r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2},
                                            IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2}, ctx->bp32.A,
                                            alpha, nmax, mode);
+    prof_end(ctx);  // profile groups do not nest: the regrouping times as a sort
     rt_status r2 = sort_current_ext(ctx);
-    prof_end(ctx);
     if (r == RT_OK) r = r2;
     if (out && r == RT_OK) r = rt_get_stats(ctx, out);
     return r;
