@@ -35,49 +35,59 @@ struct GemmArgs {
     float *C;        // EPI_F32 / EPI_BIAS output, [M][ldc]
     int64_t ldc;
     const float *bias;  // [N]
-    float *Z;           // EPI_BIAS_GELU: pre-activation [M][ldc]
+    float *Z;           // EPI_BIAS_GELU: pre-activation [M][ldc] (null: not kept)
     bf16 *H;            // EPI_BIAS_GELU: activation; EPI_DGELU: output dZ, [M][ldc]
     const float *Zp;    // EPI_DGELU: pre-activation of this layer's input [M][ldc]
     int ksplit;         // split-K chunks (grid.z); partials at C + z*M*ldc
 };
 
+// tanh(u) = 1 - 2 / (1 + exp(2u)): one exponential and one reciprocal
+// (single-precision hardware approximations, far below the bfloat16 step of
+// the activations); exp overflow gives 1, underflow -1
+__device__ inline float tanh_e(float u)
+{
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * u));
+}
+
 __device__ inline float gelu_t(float z)
 {
     const float c = 0.7978845608028654f;  // sqrt(2/pi)
     const float u = c * (z + 0.044715f * z * z * z);
-    return 0.5f * z * (1.0f + tanhf(u));
+    return 0.5f * z * (1.0f + tanh_e(u));
 }
 
 __device__ inline float dgelu_t(float z)
 {
     const float c = 0.7978845608028654f;
     const float u = c * (z + 0.044715f * z * z * z);
-    const float t = tanhf(u);
+    const float t = tanh_e(u);
     return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * z * z);
 }
 
-// Staging of one 128 x 32 operand tile (rows = m or n, 32 consecutive k)
-// from global memory: each thread moves two vectors of 8 bfloat16.  With the
+// Staging of one 128 x GBK operand tile (rows = m or n, GBK consecutive k)
+// from global memory: each thread moves GBK / 16 vectors of 8 bfloat16.  With the
 // operand k-contiguous a vector is 8 consecutive k of one row; otherwise it is
 // 8 consecutive rows at one k, transposed on the way into LDS.  Vectors that
 // are not fully inside the matrix, or not 16-byte aligned, are assembled
 // element by element (zero outside).
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
+#define GNV (GBM * GBK / 8 / 256)
+
 template <bool KCONT>
 struct Stage {
-    u16x8 v[2];
+    u16x8 v[GNV];
     __device__ inline void load(const bf16 *src, int64_t srow, int64_t sk, int row0, int nrows, int k0, int kend,
                                 int tid)
     {
         const unsigned short *p = (const unsigned short *)src;
 #pragma unroll
-        for (int t = 0; t < 2; t++) {
+        for (int t = 0; t < GNV; t++) {
             const int vi = tid + 256 * t;
             int r, kk;
             if (KCONT) {
-                r = vi >> 2;
-                kk = (vi & 3) * 8;
+                r = vi / (GBK / 8);
+                kk = (vi % (GBK / 8)) * 8;
             } else {
                 kk = vi >> 4;
                 r = (vi & 15) * 8;
@@ -99,10 +109,10 @@ struct Stage {
     __device__ inline void store(bf16 (*tile)[GBK + GPAD], int tid) const
     {
 #pragma unroll
-        for (int t = 0; t < 2; t++) {
+        for (int t = 0; t < GNV; t++) {
             const int vi = tid + 256 * t;
             if (KCONT) {
-                *(u16x8 *)&tile[vi >> 2][(vi & 3) * 8] = v[t];
+                *(u16x8 *)&tile[vi / (GBK / 8)][(vi % (GBK / 8)) * 8] = v[t];
             } else {
                 const int kk = vi >> 4, r = (vi & 15) * 8;
 #pragma unroll
@@ -113,7 +123,8 @@ struct Stage {
 };
 
 template <int EPI, bool KA, bool KB>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
+// three waves per SIMD: the accumulators live in the unified register file
+__global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a)
 {
     __shared__ __attribute__((aligned(16))) bf16 sA[GBM][GBK + GPAD];
     __shared__ __attribute__((aligned(16))) bf16 sB[GBN][GBK + GPAD];
@@ -162,30 +173,41 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
     }
-    // output element (row, col) of the 32x32 tile held in lane/item
+    // output element (row, col) of the 32x32 tile held in lane/item: column
+    // and bias once per column block, one row base per row block and the
+    // item's row step from a scalar product; bounds are tested only in the
+    // tiles that cross the matrix edge
+    const bool full = bm + GBM <= a.M && bn + GBN <= a.N;
+    float *const Cz = (EPI == EPI_F32) ? a.C + (int64_t)blockIdx.z * a.M * a.ldc : a.C;
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int j = 0; j < 2; j++) {
+        const int col = bn + wn + j * 32 + (lane & 31);
+        float bj = 0.0f;
+        if (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) bj = col < a.N ? a.bias[col] : 0.0f;
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int i = 0; i < 2; i++) {
+            const int r0 = bm + wm + i * 32 + 4 * (lane >> 5);
+            const int64_t o0 = (int64_t)r0 * a.ldc + col;
 #pragma unroll
             for (int q = 0; q < 16; q++) {
-                const int row = bm + wm + i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                const int col = bn + wn + j * 32 + (lane & 31);
-                if (row >= a.M || col >= a.N) continue;
+                const int dr = 8 * (q >> 2) + (q & 3);
+                if (!full && (r0 + dr >= a.M || col >= a.N)) continue;
+                const int64_t o = o0 + (int64_t)dr * a.ldc;
                 const float v = acc[i][j][q];
-                const int64_t o = (int64_t)row * a.ldc + col;
                 if (EPI == EPI_F32) {
-                    a.C[(int64_t)blockIdx.z * a.M * a.ldc + o] = v;
+                    Cz[o] = v;
                 } else if (EPI == EPI_BIAS) {
-                    a.C[o] = v + a.bias[col];
+                    a.C[o] = v + bj;
                 } else if (EPI == EPI_BIAS_GELU) {
-                    const float z = v + a.bias[col];
-                    a.Z[o] = z;
+                    const float z = v + bj;
+                    if (a.Z) a.Z[o] = z;  // kept for the backward pass only
                     a.H[o] = (bf16)gelu_t(z);
                 } else {  // EPI_DGELU
                     a.H[o] = (bf16)(v * dgelu_t(a.Zp[o]));
                 }
             }
+        }
+    }
 }
 
 // sum of the split-K partials in chunk order
@@ -597,8 +619,9 @@ static void gemm(const GemmArgs &a, hipStream_t s)
         k_gemm<EPI, false, false><<<grid, 256, 0, s>>>(a);
 }
 
-// forward of one member for a batch of B; output to Yout [B][n_out]
-static void forward(sg_net n, int mem, const bf16 *X, float *Yout, int B)
+// forward of one member for a batch of B; output to Yout [B][n_out]; the
+// pre-activations are kept (for a backward pass) when keep_z
+static void forward(sg_net n, int mem, const bf16 *X, float *Yout, int B, bool keep_z)
 {
     const bf16 *in = X;
     for (int li = 0; li < n->nl; li++) {
@@ -617,7 +640,7 @@ static void forward(sg_net n, int mem, const bf16 *X, float *Yout, int B)
         a.ldc = l.out;
         a.ksplit = 1;
         if (li < n->nl - 1) {
-            a.Z = n->Z[li];
+            a.Z = keep_z ? n->Z[li] : nullptr;
             a.H = n->H[li];
             gemm<EPI_BIAS_GELU>(a, n->stream);
             in = n->H[li];
@@ -633,10 +656,10 @@ extern "C" rt_status sg_forward(sg_net n, int32_t member, const uint16_t *X, flo
     if (!n || !X || !Y || B < 1 || B > n->cfg.max_batch || member < -1 || member >= n->cfg.n_members)
         return sg_fail(n, RT_E_ARG, "bad sg_forward arguments");
     if (member >= 0) {
-        forward(n, member, (const bf16 *)X, Y, B);
+        forward(n, member, (const bf16 *)X, Y, B, false);
     } else {
         for (int m = 0; m < n->cfg.n_members; m++)
-            forward(n, m, (const bf16 *)X, Y + (int64_t)m * B * n->cfg.n_out, B);
+            forward(n, m, (const bf16 *)X, Y + (int64_t)m * B * n->cfg.n_out, B, false);
     }
     SG_HIP(hipGetLastError());
     return RT_OK;
@@ -705,7 +728,7 @@ extern "C" rt_status sg_gradient(sg_net n, int32_t member, const uint16_t *X, co
 {
     if (!n || !X || !T || !grads || B < 1 || B > n->cfg.max_batch || member < 0 || member >= n->cfg.n_members)
         return sg_fail(n, RT_E_ARG, "bad sg_gradient arguments");
-    forward(n, member, (const bf16 *)X, n->Yb, B);
+    forward(n, member, (const bf16 *)X, n->Yb, B, true);
     backward(n, member, (const bf16 *)X, T, B, nullptr);
     SG_HIP(hipMemcpyAsync(grads, n->grad, sizeof(float) * n->P,
                           where == RT_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, n->stream));
@@ -719,7 +742,7 @@ extern "C" rt_status sg_train_step(sg_net n, int32_t member, const uint16_t *X, 
 {
     if (!n || !X || !T || B < 1 || B > n->cfg.max_batch || member < 0 || member >= n->cfg.n_members)
         return sg_fail(n, RT_E_ARG, "bad sg_train_step arguments");
-    forward(n, member, (const bf16 *)X, n->Yb, B);
+    forward(n, member, (const bf16 *)X, n->Yb, B, true);
     backward(n, member, (const bf16 *)X, T, B, loss);
     n->t[member] += 1;
     const double b1 = 0.9, b2 = 0.999;
