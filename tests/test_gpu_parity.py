@@ -280,3 +280,66 @@ def test_api_errors(rt):
     with pytest.raises(rt.RTError) as e:
         tr.set_rays(big.rays)
     assert e.value.code == rt.RT_E_CAPACITY
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_level_refinement_every_sixteenth_regrouping(rt, orc, prec):
+    """The regrouping after a load and every sixteenth one after it order
+    each column's volumes by level; the ones in between keep the previous
+    order within a column (stable column sort)."""
+    w = c2_small(300)
+    tr = gpu_tracer(w, rt.RT_FP64 if prec == "fp64" else rt.RT_FP32)
+
+    def levels_sorted_within_columns():
+        g = tr.get_rays()
+        cols = tr.get_columns().astype(np.int64)
+        lev = np.clip(np.floor(np.asarray(g["z"]) / w.dz), 0, w.nz).astype(np.int64)
+        key = cols * (w.nz + 1) + lev
+        return bool(np.all(np.diff(cols) >= 0)), bool(np.all(np.diff(key) >= 0))
+
+    assert levels_sorted_within_columns() == (True, True)
+    spread = False
+    for s in range(1, 17):
+        tr.step(w.dt)
+        by_col, by_lev = levels_sorted_within_columns()
+        assert by_col, s
+        if s < 16:
+            spread = spread or not by_lev
+        else:
+            assert by_lev, "the sixteenth regrouping refines by level"
+    assert spread, "volumes never changed level order between refinements (the test checks nothing)"
+    tr.close()
+
+
+def test_removal_tally_is_deterministic(rt):
+    """The removal tally spreads over many workgroups with fixed chunks:
+    repeated runs give the same bits."""
+    w = W.make_c1(n_rays=4096)
+    w.rays["z"][:] = np.linspace(1.0e3, 63.9e3, 4096)
+    outs = []
+    for _ in range(2):
+        tr = gpu_tracer(w, rt.RT_FP64)
+        for _ in range(20):
+            tr.step(w.dt)
+        outs.append(tr.stats())
+        tr.close()
+    assert outs[0]["n_top"] > 20  # one volume per chunk: many workgroups take part
+    assert outs[0]["removed_W"] == outs[1]["removed_W"]
+    assert outs[0]["n_top"] == outs[1]["n_top"]
+
+
+def test_profile_reports_every_class(rt):
+    """Timing groups for the step, sort, deposition, drag and split/merge
+    are all reported (groups do not nest)."""
+    w = W.make_c2(cols=np.arange(0, 16384, 997))
+    tr = gpu_tracer(w, rt.RT_FP64, capacity=2 * w.n_rays)
+    tr.profile(True)
+    tr.profile_read()
+    tr.step(w.dt)
+    tr.deposit(host=True)
+    tr.split_merge(w.split_alpha, w.merge_nmax, rt.RT_MERGE)
+    p = tr.profile_read()
+    tr.profile(False)
+    for c in ("step", "sort", "deposit", "drag", "split_merge"):
+        assert c in p and p[c][1] >= 1 and p[c][0] > 0.0, (c, p)
+    tr.close()
