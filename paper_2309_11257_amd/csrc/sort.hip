@@ -3,8 +3,9 @@
 //
 // Each pass: (1) per-tile digit histograms, (2) an exclusive scan over the
 // digit-major histogram table, (3) a stable scatter where a tile ranks its keys
-// with wave ballots (64-lane match on the 8 digit bits) and per-wave counts
-// in LDS.  Tiles are 4096 keys (256 threads x 16 rounds, round-major so that
+// among the wave's lanes with the same digit (runs of lanes when the digits
+// do not decrease, else a 64-lane match on the 8 digit bits) and per-wave
+// counts in LDS.  Tiles are 4096 keys (256 threads x 16 rounds, round-major so that
 // consecutive keys of a round sit in consecutive lanes).  The element count
 // is read from device memory, so no host synchronisation is needed; the
 // grid is sized for an upper bound.
@@ -25,6 +26,35 @@ int64_t radix_hist_len(int64_t bound)
     return table + parts + 1;
 }
 
+// Lanes of the wave holding the same 8-bit digit as this lane (valid lanes
+// are a prefix of the wave).  The keys arrive nearly sorted, so a wave's
+// digits usually do not decrease from lane to lane; then equal digits are
+// runs of neighbouring lanes and one shuffle and one ballot find them.
+// Otherwise the digit is matched bit by bit with eight ballots.
+__device__ inline unsigned long long digit_peers(uint32_t d, bool valid, int lane)
+{
+    const uint32_t prev = (uint32_t)__shfl_up((int)d, 1, 64);  // lane 0: its own
+    if (__ballot(valid && lane > 0 && d < prev) == 0ull) {
+        const unsigned long long vm = __ballot(valid);
+        const unsigned long long heads = __ballot(valid && (lane == 0 || d != prev));
+        const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0 .. lane (all 64 for lane 63)
+        const int h = 63 - __clzll(heads & upto);             // this lane's run head (-1: invalid lane)
+        const unsigned long long above = heads & ~upto;
+        const int e = above ? __ffsll(above) - 1 : __popcll(vm);  // first lane after the run
+        const unsigned long long lo = h > 0 ? (1ull << h) - 1ull : 0ull;
+        const unsigned long long hi = e == 64 ? ~0ull : (1ull << e) - 1ull;
+        return valid ? (hi & ~lo) : 0ull;
+    }
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; bit++) {
+        const bool b = (d >> bit) & 1u;
+        const unsigned long long m = __ballot(b);
+        peers &= b ? m : ~m;
+    }
+    return valid ? peers : 0ull;
+}
+
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *__restrict__ keys, const int64_t *n_dev, int shift,
                                                         int64_t nblocks, uint32_t *__restrict__ hist)
 {
@@ -42,13 +72,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *__restri
         const int64_t i = base + (int64_t)it * RS_THREADS + tid;
         const bool valid = i < n;
         const uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
-        unsigned long long peers = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; bit++) {
-            const bool b = (d >> bit) & 1u;
-            const unsigned long long m = __ballot(b);
-            peers &= b ? m : ~m;
-        }
+        const unsigned long long peers = digit_peers(d, valid, lane);
         if (valid && lane == __ffsll((long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
@@ -147,13 +171,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t *__res
         const uint32_t key = valid ? kin[i] : 0u;
         const uint32_t val = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
         const uint32_t d = (key >> shift) & 255u;
-        unsigned long long peers = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; bit++) {
-            const bool b = (d >> bit) & 1u;
-            const unsigned long long m = __ballot(b);
-            peers &= b ? m : ~m;
-        }
+        const unsigned long long peers = digit_peers(d, valid, lane);
         const uint32_t rank = (uint32_t)__popcll(peers & below);
         const uint32_t cnt = (uint32_t)__popcll(peers);
         wcnt[0][tid] = 0;
