@@ -229,7 +229,8 @@ __device__ inline void n2_f2(const G32 &g, const Bg32P &b, int ic, int jc, int k
 // global memory for the whole wave.
 #define WB_LMAX 13
 #define WB_A (25 * WB_LMAX)
-#define WB_RECS (WB_A + 18 * WB_LMAX)
+#define WB_F2 (WB_A + 18 * WB_LMAX)  // five rows of (f2, (f2)_y, 0, 0) after the records
+#define WB_RECS (WB_F2 + 5)
 extern __shared__ float4 wb_lds[];
 
 struct WBox {
@@ -304,6 +305,215 @@ __device__ inline void corners_G(const G32 &g, const WBox &w, const Bg32P &b, co
         fill_box(K, w.base + WB_A + r * 9 * WB_LMAX, bc);
     else
         K.fill(b.G, c, r);
+}
+
+// Right-hand side from the centre's refraction sums (gk, gl, gm) and the face
+// velocities of each axis (sum s and half-difference h of the + and - faces).
+template <bool SPH>
+__device__ inline void assemble(const G32 &g, int kc, float phi0, const float *Y, float gk, float gl, float gm,
+                                float sx, float hx, float sy, float hy, float sz, float hz, float *F)
+{
+    const float k = Y[3], l = Y[4];
+    if (!SPH) {
+        F[0] = 0.5f * sx * g.inv_dx;
+        F[1] = 0.5f * sy * g.inv_dy;
+        F[2] = 0.5f * sz * g.inv_dz;
+        F[3] = -gk;
+        F[4] = -gl;
+        F[5] = -gm;
+        F[6] = 2.0f * hx * g.inv_dx;
+        F[7] = 2.0f * hy * g.inv_dy;
+        F[8] = 2.0f * hz;
+    } else {
+        const float r = g.a + ((float)kc + Y[2]) * g.dz;
+        const float ir = rcp(r);
+        float sphi, cphi;
+        sincosf(phi0 + Y[1] * g.dyr, &sphi, &cphi);
+        const float icphi = rcp(cphi);
+        const float tphi = sphi * icphi;
+        const float irc = ir * icphi;
+        const float uc = 0.5f * sx;
+        const float vc = 0.5f * sy;
+        const float wc = 0.5f * sz;
+        F[0] = uc * irc * g.inv_dx;
+        F[1] = vc * ir * g.inv_dy;
+        F[2] = wc * g.inv_dz;
+        F[3] = -gk * irc - k * wc * ir + k * tphi * vc * ir;
+        F[4] = -gl * ir - l * wc * ir - k * tphi * uc * ir;
+        F[5] = -gm + k * uc * ir + l * vc * ir;
+        F[6] = 2.0f * hx * irc * g.inv_dx;
+        F[7] = 2.0f * hy * ir * g.inv_dy;
+        F[8] = 2.0f * hz;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Box-only stage.  When every lookup of every lane of a wave lies in the
+// wave's stencil box, the stage works in box coordinates: a horizontal node
+// is an offset from the wave's column, so no periodic wrap or row clamp is
+// formed (the box holds the wrapped columns and the clamped rows; where a
+// row is clamped both nodes hold the same record, and interpolating between
+// equal values returns that value), and a lookup is one LDS base index.
+
+// lower node of one axis relative to the base cell and the upper node's
+// weight; the offset is clamped to +-1e6 cells (a non-finite offset belongs
+// to a state that is removed after the step)
+__device__ inline int bnode(float t, float &wgt)
+{
+    const float tc = fminf(fmaxf(t, -1.0e6f), 1.0e6f);
+    const float fl = floorf(tc);
+    wgt = tc - fl;
+    return (int)fl;
+}
+
+// level axis, clamped at the grid's ends: box level of the lower node, step to
+// the upper node (0 where clamped) and its weight
+__device__ inline int blev(const G32 &g, const WBox &w, int kc, float t, int &sz, float &wgt)
+{
+    float f;
+    const int j0 = kc + bnode(t, f);
+    const bool out = j0 < 0 || j0 >= g.nz - 1;
+    sz = out ? 0 : 1;
+    wgt = out ? 0.0f : f;
+    return (j0 < 0 ? 0 : (j0 >= g.nz - 1 ? g.nz - 1 : j0)) - w.kbase;
+}
+
+// face positions, written once so that the box test and the stage form the
+// same values
+__device__ inline float face_t(float c, float sg, float ext) { return fmaf(sg, ext, c) - 0.5f; }
+
+// every lookup of the stage in the box: centre nodes at offsets -1 or 0 (the
+// 3 x 3 gradient box), face nodes at -2 .. 1 (the 5 x 5 box), levels inside
+__device__ inline bool box_stage_in(const G32 &g, const WBox &w, int kc, const float *Y)
+{
+    float t;
+    int s0, s1, s2;
+    const int dx = bnode(Y[0] - 0.5f, t), dy = bnode(Y[1] - 0.5f, t);
+    const int dxp = bnode(face_t(Y[0], 0.5f, Y[6]), t), dxm = bnode(face_t(Y[0], -0.5f, Y[6]), t);
+    const int dyp = bnode(face_t(Y[1], 0.5f, Y[7]), t), dym = bnode(face_t(Y[1], -0.5f, Y[7]), t);
+    const float sdz = Y[8] * g.inv_dz;
+    const int k0 = blev(g, w, kc, Y[2] - 0.5f, s0, t);
+    const int kp = blev(g, w, kc, face_t(Y[2], 0.5f, sdz), s1, t);
+    const int km = blev(g, w, kc, face_t(Y[2], -0.5f, sdz), s2, t);
+    const uint32_t cen = (uint32_t)(dx + 1) | (uint32_t)(dy + 1);
+    const uint32_t fac = (uint32_t)(dxp + 2) | (uint32_t)(dxm + 2) | (uint32_t)(dyp + 2) | (uint32_t)(dym + 2);
+    return cen < 2u && fac < 4u && (uint32_t)k0 < (uint32_t)(w.L - s0) && (uint32_t)kp < (uint32_t)(w.L - s1) &&
+           (uint32_t)km < (uint32_t)(w.L - s2);
+}
+
+// eight corners from LDS: p the lower corner's record, sx/sy/sz the steps to
+// the upper nodes (records)
+template <int R>
+__device__ inline void box_corners(Corners<R> &K, int p, int sxs, int sys, int szs)
+{
+    K.a0 = wb_lds[p];
+    K.a1 = wb_lds[p + sxs];
+    K.b0 = wb_lds[p + sys];
+    K.b1 = wb_lds[p + sys + sxs];
+    K.d0 = wb_lds[p + szs];
+    K.d1 = wb_lds[p + szs + sxs];
+    K.e0 = wb_lds[p + szs + sys];
+    K.e1 = wb_lds[p + szs + sys + sxs];
+}
+
+// f2 or (f2)_y (component c of the row records) between box rows r and r + 1
+__device__ inline float box_row(int r, float wgt, int c)
+{
+    const float *f = (const float *)&wb_lds[WB_F2];
+    const float a = f[4 * r + c], b = f[4 * r + 4 + c];
+    return a + wgt * (b - a);
+}
+
+template <bool SPH>
+__device__ inline void rhs_box(const G32 &g, int kc, float phi0, const float *Y, float *F, const WBox &w)
+{
+    constexpr int SA = 5 * WB_LMAX, SG = 3 * WB_LMAX;  // row steps of the A and gradient boxes
+    const float k = Y[3], l = Y[4], m = Y[5];
+    const float kh2 = k * k + l * l;
+    const float m2 = m * m;
+    const float K2 = kh2 + m2;
+    const float invK2 = rcp(K2);
+    const float invK4 = invK2 * invK2;
+    Cell c;
+    int sz;
+    const int dx = bnode(Y[0] - 0.5f, c.wx), dy = bnode(Y[1] - 0.5f, c.wy);
+    const int kb = blev(g, w, kc, Y[2] - 0.5f, sz, c.wz);
+    const int pyz = (dy + 2) * SA + kb;  // A box: row and level of the centre
+    const float f2c = box_row(dy + 2, c.wy, 0);
+    float gk, gl, gm;
+    {
+        Corners<1> KA;
+        box_corners(KA, pyz + (dx + 2) * WB_LMAX, WB_LMAX, SA, sz);
+        const float N2c = TRI_COMP(KA, z, c);
+        const float rom = rsq((N2c * kh2 + f2c * m2) * invK2);  // 1 / omega_hat
+        const float h = 0.5f * invK2 * rom;
+        const float q = kh2 * h;
+        const float qf = m2 * h;
+        gk = k * TRI_COMP(KA, w, c);
+        gl = qf * box_row(dy + 2, c.wy, 1);
+        gm = 0.0f;
+        const int pg = WB_A + (dy + 1) * SG + (dx + 1) * WB_LMAX + kb;
+        // gradient records one at a time (bounded register use)
+#pragma unroll 1
+        for (int r = 0; r < 2; r++) {
+            Corners<2> KG;
+            box_corners(KG, pg + r * 9 * WB_LMAX, WB_LMAX, SG, sz);
+            const float4 Gr = make_float4(TRI_COMP(KG, x, c), TRI_COMP(KG, y, c), TRI_COMP(KG, z, c), TRI_COMP(KG, w, c));
+            if (r == 0) {  // Uy Uz Vx Vy
+                gl += k * Gr.x + l * Gr.w;
+                gm += k * Gr.y;
+                gk += l * Gr.z;
+            } else {  // Vz N2x N2y N2z
+                gm += l * Gr.x + q * Gr.w;
+                gk += q * Gr.y;
+                gl += q * Gr.z;
+            }
+        }
+    }
+    const float sdz = Y[8] * g.inv_dz;
+    float sx = 0.0f, hx = 0.0f, sy = 0.0f, hy = 0.0f, szs = 0.0f, hz = 0.0f;
+#pragma unroll 1
+    for (int sd = 0; sd < 2; sd++) {
+        const float sg = sd ? -0.5f : 0.5f;
+        Cell f = c;
+        const int d = bnode(face_t(Y[0], sg, Y[6]), f.wx);
+        Corners<1> K;
+        box_corners(K, pyz + (d + 2) * WB_LMAX, WB_LMAX, SA, sz);
+        const float N2f = TRI_COMP(K, z, f);
+        const float romf = rsq((N2f * kh2 + f2c * m2) * invK2);
+        const float v = TRI_COMP(K, x, f) + k * m2 * ((N2f - f2c) * invK4 * romf);
+        sx += v;
+        hx += sg * v;
+    }
+#pragma unroll 1
+    for (int sd = 0; sd < 2; sd++) {
+        const float sg = sd ? -0.5f : 0.5f;
+        Cell f = c;
+        const int d = bnode(face_t(Y[1], sg, Y[7]), f.wy);
+        Corners<1> K;
+        box_corners(K, (d + 2) * SA + (dx + 2) * WB_LMAX + kb, WB_LMAX, SA, sz);
+        const float N2f = TRI_COMP(K, z, f);
+        const float f2f = box_row(d + 2, f.wy, 0);
+        const float romf = rsq((N2f * kh2 + f2f * m2) * invK2);
+        const float v = TRI_COMP(K, y, f) + l * m2 * ((N2f - f2f) * invK4 * romf);
+        sy += v;
+        hy += sg * v;
+    }
+#pragma unroll 1
+    for (int sd = 0; sd < 2; sd++) {
+        const float sg = sd ? -0.5f : 0.5f;
+        Cell f = c;
+        int szf;
+        const int kf = blev(g, w, kc, face_t(Y[2], sg, sdz), szf, f.wz);
+        Corners<1> K;
+        box_corners(K, (dy + 2) * SA + (dx + 2) * WB_LMAX + kf, WB_LMAX, SA, szf);
+        const float N2f = TRI_COMP(K, z, f);
+        const float romf = rsq((N2f * kh2 + f2c * m2) * invK2);
+        const float v = -m * kh2 * ((N2f - f2c) * invK4 * romf);
+        szs += v;
+        hz += sg * v;
+    }
+    assemble<SPH>(g, kc, phi0, Y, gk, gl, gm, sx, hx, sy, hy, szs, hz, F);
 }
 
 // RK stage right-hand side in cell units: Y = (xi, eta, zeta, k, l, m, Dxi,
@@ -397,37 +607,8 @@ __device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc,
         czp = fc == 4 ? v : czp;
         czm = fc == 5 ? v : czm;
     }
-    if (!SPH) {
-        F[0] = 0.5f * (cxp + cxm) * g.inv_dx;
-        F[1] = 0.5f * (cyp + cym) * g.inv_dy;
-        F[2] = 0.5f * (czp + czm) * g.inv_dz;
-        F[3] = -gk;
-        F[4] = -gl;
-        F[5] = -gm;
-        F[6] = (cxp - cxm) * g.inv_dx;
-        F[7] = (cyp - cym) * g.inv_dy;
-        F[8] = czp - czm;
-    } else {
-        const float r = g.a + ((float)kc + zeta) * g.dz;
-        const float ir = rcp(r);
-        float sphi, cphi;
-        sincosf(phi0 + eta * g.dyr, &sphi, &cphi);
-        const float icphi = rcp(cphi);
-        const float tphi = sphi * icphi;
-        const float irc = ir * icphi;
-        const float uc = 0.5f * (cxp + cxm);
-        const float vc = 0.5f * (cyp + cym);
-        const float wc = 0.5f * (czp + czm);
-        F[0] = uc * irc * g.inv_dx;
-        F[1] = vc * ir * g.inv_dy;
-        F[2] = wc * g.inv_dz;
-        F[3] = -gk * irc - k * wc * ir + k * tphi * vc * ir;
-        F[4] = -gl * ir - l * wc * ir - k * tphi * uc * ir;
-        F[5] = -gm + k * uc * ir + l * vc * ir;
-        F[6] = (cxp - cxm) * irc * g.inv_dx;
-        F[7] = (cyp - cym) * ir * g.inv_dy;
-        F[8] = czp - czm;
-    }
+    assemble<SPH>(g, kc, phi0, Y, gk, gl, gm, cxp + cxm, 0.5f * (cxp - cxm), cyp + cym, 0.5f * (cyp - cym), czp + czm,
+                  0.5f * (czp - czm), F);
 }
 
 // move a periodic (cell, offset) pair back to offset in [0, 1)

@@ -171,17 +171,21 @@ __device__ inline uint32_t wave_max_u16x2(uint32_t v)
 }
 __device__ inline int wave_min_i(int v) { return wave_reduce_i<false>(v); }
 
-// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2);
-// remap so that each XCD walks a contiguous range of blocks -- for kernels
-// over column-sorted rays this keeps the background columns an XCD touches
-// in its own L2.
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Remap so that runs of XCD_CHUNK consecutive blocks land on one XCD: the
+// waves of a run share background columns in that XCD's L2, while the runs
+// are dealt round-robin so that every XCD gets an even share of each part
+// of the column-sorted range (the cost of a volume depends on where it is:
+// one contiguous eighth per XCD left the slowest XCD half as busy again as
+// the mean).  The ragged tail beyond whole rounds keeps the plain order.
+#define XCD_CHUNK 16
 __device__ inline int64_t xcd_block(int64_t nb)
 {
     const int64_t b = blockIdx.x;
-    const int64_t per = (nb + 7) / 8;
-    const int64_t x = b & 7, q = b >> 3;
-    const int64_t full = nb - (per - 1) * 8;  // XCDs that get `per` blocks
-    return x < full ? x * per + q : full * per + (x - full) * (per - 1) + q;
+    const int64_t full = nb / (8 * XCD_CHUNK) * (8 * XCD_CHUNK);
+    if (b >= full) return b;
+    const int64_t x = b & 7, q = b >> 3;  // XCD, and the block's turn on it
+    return (q / XCD_CHUNK) * (8 * XCD_CHUNK) + x * XCD_CHUNK + q % XCD_CHUNK;
 }
 
 // error helpers

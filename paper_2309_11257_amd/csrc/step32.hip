@@ -100,6 +100,17 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
                     f32::wb_lds[w.base + WB_A + r * 9 * WB_LMAX + bxy * WB_LMAX + kk] = vg[it];
                 }
             }
+            // f2 and (f2)_y of the five box rows
+            if (lane < 5) {
+                int jj = w.jc + lane - 2;
+                if (g.geometry == RT_CARTESIAN) {
+                    jj += jj < 0 ? g.ny : 0;
+                    jj -= jj >= g.ny ? g.ny : 0;
+                } else {
+                    jj = min(max(jj, 0), g.ny - 1);
+                }
+                f32::wb_lds[WB_F2 + lane] = make_float4(b.f2[jj], b.f2y[jj], 0.0f, 0.0f);
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -116,7 +127,12 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
     const int nst = (frozen && frozen[skeys[i]]) ? 0 : 3;
 #pragma unroll 1
     for (int st = 0; st < nst; st++) {
-        f32::rhs<SPH>(g, b, ic, jc, kc0, phi0, Y, F, w);
+        // a stage whose lookups all lie in the box, for every lane, runs the
+        // box-only form; otherwise each lookup tests the box itself
+        if (w.on && __ballot(!f32::box_stage_in(g, w, kc0, Y)) == 0ull)
+            f32::rhs_box<SPH>(g, kc0, phi0, Y, F, w);
+        else
+            f32::rhs<SPH>(g, b, ic, jc, kc0, phi0, Y, F, w);
 #pragma unroll
         for (int c = 0; c < 9; c++) {
             Q[c] = A[st] * Q[c] + dt * F[c];
