@@ -98,7 +98,14 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                 // words instead of serialising on one (integer adds commute,
                 // so the sums do not depend on the order)
 
-                int lo = (int)floor(zb / g.dz), hi = (int)floor(zt / g.dz);
+                // level span in level units: the double-precision payload divides
+                // (so it visits the same levels as a plain division); the
+                // single-precision one multiplies by 1/dz, which can differ only
+                // where a bound lies within rounding of an interface, and then by
+                // an overlap a few units in the last place of z wide
+                const double zbl = P::EXACT_LEVELS ? zb / g.dz : zb * pl.inv_dz;
+                const double ztl = P::EXACT_LEVELS ? zt / g.dz : zt * pl.inv_dz;
+                int lo = (int)floor(zbl), hi = (int)floor(ztl);
                 if (lo < 0) lo = 0;
                 if (hi > g.nz - 1) hi = g.nz - 1;
                 const int nk = hi - lo + 1;
@@ -114,7 +121,7 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                     }
                 }
                 klo = lo;
-                int lo2 = (int)floor(zb / g.dz + 0.5), hi2 = (int)floor(zt / g.dz + 0.5);
+                int lo2 = (int)floor(zbl + 0.5), hi2 = (int)floor(ztl + 0.5);
                 if (lo2 < 0) lo2 = 0;
                 if (hi2 > g.nz) hi2 = g.nz;
                 const int nk2 = hi2 - lo2 + 1;
@@ -185,15 +192,16 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
     }
     __syncthreads();
     // divide by the cell volume (levels) or staggered-cell volume (interfaces);
-    // consecutive threads take consecutive columns of one (field, level) row
+    // consecutive threads take consecutive columns of one (field, level) row,
+    // so a thread keeps one column (64 CPW is a multiple of CPW)
+    const int cl = tid % CPW;
+    if (cl >= ncols) return;
+    const int c = c_first + cl;
+    const double area_h = g.dx * g.dy;
+    const double cphi = g.geometry == RT_SPHERICAL ? cos(g.y0 + ((double)(c / g.nx) + 0.5) * g.dy) : 1.0;
     for (int e = tid; e < CPW * 6 * nzp; e += 64 * CPW) {
-        const int cl = e % CPW, qk = e / CPW;
+        const int qk = e / CPW;
         const int q = qk / nzp, kk = qk % nzp;
-        if (cl >= ncols) continue;
-        const int c = c_first + cl;
-        const int cj = c / g.nx;
-        double area_h = g.dx * g.dy, cphi = 1.0;
-        if (g.geometry == RT_SPHERICAL) cphi = cos(g.y0 + ((double)cj + 0.5) * g.dy);
         const double acc_v = profs[(size_t)cl * 6 * nzp + qk];
         double val;
         if (q < 4) {

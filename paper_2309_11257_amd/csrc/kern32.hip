@@ -200,7 +200,9 @@ struct Pay32 {
     G32 g;
     Bg32P b;
     S32 st;
-    double zdz;  // level spacing in double
+    double zdz;     // level spacing in double
+    double inv_dz;  // its reciprocal (level spans of the deposition)
+    static constexpr bool EXACT_LEVELS = false;
     __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
         // the wave's column (the slot's own column, by the grouping)
@@ -221,7 +223,7 @@ struct Pay32 {
         const double cx = (double)(k * m2 * sc);
         const double cy = (double)(l * m2 * sc);
         const double cz = (double)(-m * kh2 * sc);
-        const double sW = st.W[s] / (double)Dz;
+        const double sW = st.W[s] * (double)f32::rcp(Dz);
         const double kd = k, ld = l;
         bv[0] = (cx * kd) * sW;
         bv[1] = (cx * ld) * sW;
@@ -266,13 +268,13 @@ struct Pay32 {
 void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s)
 {
-    Pay32 p{f32::make_g32(g), b, st, g.dz};
+    Pay32 p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
     launch_deposit_k(g, p, perm, colstart, flux, s);
 }
 
 void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s)
 {
-    Pay32 p{f32::make_g32(g), b, st, g.dz};
+    Pay32 p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
     k_features<Pay32><<<(unsigned)((g.ncol + 3) / 4), 256, 0, s>>>(g, p, perm, colstart, X);
 }

@@ -411,6 +411,8 @@ struct Pay64 {
     Grid g;
     Bg64P b;
     S64 st;
+    double inv_dz;  // unused: the double-precision deposition divides
+    static constexpr bool EXACT_LEVELS = true;
     __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
         const double x = st.x[s], y = st.y[s], z = st.z[s];
@@ -472,13 +474,13 @@ struct Pay64 {
 void launch_deposit64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s)
 {
-    Pay64 p{g, b, st};
+    Pay64 p{g, b, st, 0.0};
     launch_deposit_k(g, p, perm, colstart, flux, s);
 }
 
 void launch_features64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s)
 {
-    Pay64 p{g, b, st};
+    Pay64 p{g, b, st, 0.0};
     k_features<Pay64><<<(unsigned)((g.ncol + 3) / 4), 256, 0, s>>>(g, p, perm, colstart, X);
 }
