@@ -205,6 +205,21 @@ __device__ inline float row_lerp(const float *__restrict__ f, const Axis &y)
     return a + y.w * (b - a);
 }
 
+// element idx of an array of 4-byte values, at a 32-bit byte offset from the
+// array's uniform base (idx < 2^30)
+template <class T>
+__device__ inline T at(const T *__restrict__ p, uint32_t idx)
+{
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    return *(const T *)((const char *)p + (idx << 2));
+}
+template <class T>
+__device__ inline void put(T *__restrict__ p, uint32_t idx, T v)
+{
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    *(T *)((char *)p + (idx << 2)) = v;
+}
+
 // single-precision reciprocal and reciprocal square root (one rounding each,
 // within about one unit in the last place)
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }

@@ -18,13 +18,16 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
                                                           const uint8_t *__restrict__ frozen,
                                                           const uint32_t *__restrict__ skeys)
 {
-    const int64_t i = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+    // 32-bit volume indices (the single-precision path holds fewer than 2^30
+    // volumes): 4-byte fields are read and written at 32-bit byte offsets from
+    // their uniform bases, which keeps one register per index live
+    const uint32_t i = (uint32_t)xcd_block(gridDim.x) * STEP_BLOCK + threadIdx.x;
     // stage the stencil box shared by the wave's volumes (all lanes take part:
     // the wave-wide reductions need every lane)
-    const bool valid = i < dc->n_active;
-    const uint32_t s = valid ? perm[i] : 0u;
-    const uint32_t col = valid ? src.col[s] : 0xffffffffu;
-    const int kc0 = valid ? src.lev[s] : 0;
+    const bool valid = (int64_t)i < dc->n_active;
+    const uint32_t s = valid ? f32::at(perm, i) : 0u;
+    const uint32_t col = valid ? f32::at(src.col, s) : 0xffffffffu;
+    const int kc0 = valid ? f32::at(src.lev, s) : 0;
     f32::WBox w;
     {
         const int lane = threadIdx.x & 63;
@@ -42,64 +45,46 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
         // one wrap corrects a column or row index when the grid has at least two
         w.on = uni && w.L <= WB_LMAX && g.nx >= 2 && (g.geometry != RT_CARTESIAN || g.ny >= 2);
         if (w.on) {
-            // a lane issues all of its loads before its LDS writes; t / L as
-            // (t * ceil(2^16 / L)) >> 16, exact for t < 512 and L <= 26
-            constexpr int NA = (25 * WB_LMAX + 63) / 64, NG = (18 * WB_LMAX + 63) / 64;
-            const int nA = 25 * w.L, nG = 18 * w.L, L9 = 9 * w.L;
-            const uint32_t mL = (65536u + (uint32_t)w.L - 1u) / (uint32_t)w.L;
+            // a lane keeps one box column (and gradient record) and a phase
+            // of its levels: A records by 50 lanes (25 columns x 2 phases,
+            // levels ph, ph + 2, ...), gradient records by 54 lanes (9
+            // columns x 2 records x 3 phases, levels ph, ph + 3, ...); the
+            // column is located once, the levels are immediate offsets, and
+            // all loads are issued before the LDS writes
+            constexpr int NA = (WB_LMAX + 1) / 2, NG = (WB_LMAX + 2) / 3;
+            const int ca = lane % 25, pa = lane / 25;  // pa: 0, 1 (2 idle)
+            const int gg = lane % 18, pg = lane / 18;  // pg: 0 .. 2 (3 idle)
+            const int rg = gg / 9, cg = gg % 9;
+            int ia = w.ic + ca % 5 - 2, ja = w.jc + ca / 5 - 2;
+            int ig = w.ic + cg % 3 - 1, jg = w.jc + cg / 3 - 1;
+            ia += ia < 0 ? g.nx : 0;
+            ia -= ia >= g.nx ? g.nx : 0;
+            ig += ig < 0 ? g.nx : 0;
+            ig -= ig >= g.nx ? g.nx : 0;
+            if (g.geometry == RT_CARTESIAN) {
+                ja += ja < 0 ? g.ny : 0;
+                ja -= ja >= g.ny ? g.ny : 0;
+                jg += jg < 0 ? g.ny : 0;
+                jg -= jg >= g.ny ? g.ny : 0;
+            } else {
+                ja = min(max(ja, 0), g.ny - 1);
+                jg = min(max(jg, 0), g.ny - 1);
+            }
+            const uint32_t ka = f32::col_base(g, ja, ia) + (uint32_t)(w.kbase + pa);
+            const uint32_t kg = (f32::col_base(g, jg, ig) + (uint32_t)(w.kbase + pg)) * 2u + (uint32_t)rg;
             float4 va[NA], vg[NG];
 #pragma unroll
-            for (int it = 0; it < NA; it++) {
-                const int e = lane + 64 * it;
-                if (e < nA) {
-                    const int bxy = (int)(((uint32_t)e * mL) >> 16), kk = e - bxy * w.L;
-                    int ii = w.ic + bxy % 5 - 2, jj = w.jc + bxy / 5 - 2;
-                    ii += ii < 0 ? g.nx : 0;
-                    ii -= ii >= g.nx ? g.nx : 0;
-                    if (g.geometry == RT_CARTESIAN) {
-                        jj += jj < 0 ? g.ny : 0;
-                        jj -= jj >= g.ny ? g.ny : 0;
-                    } else {
-                        jj = min(max(jj, 0), g.ny - 1);
-                    }
-                    va[it] = f32::rec(b.A, f32::col_base(g, jj, ii) + (uint32_t)(w.kbase + kk));
-                }
-            }
+            for (int t = 0; t < NA; t++)
+                if (pa < 2 && pa + 2 * t < w.L) va[t] = f32::rec(b.A, ka + 2u * t);
 #pragma unroll
-            for (int it = 0; it < NG; it++) {
-                const int e = lane + 64 * it;
-                if (e < nG) {
-                    const int r = e >= L9 ? 1 : 0, t = e - r * L9;
-                    const int bxy = (int)(((uint32_t)t * mL) >> 16), kk = t - bxy * w.L;
-                    int ii = w.ic + bxy % 3 - 1, jj = w.jc + bxy / 3 - 1;
-                    ii += ii < 0 ? g.nx : 0;
-                    ii -= ii >= g.nx ? g.nx : 0;
-                    if (g.geometry == RT_CARTESIAN) {
-                        jj += jj < 0 ? g.ny : 0;
-                        jj -= jj >= g.ny ? g.ny : 0;
-                    } else {
-                        jj = min(max(jj, 0), g.ny - 1);
-                    }
-                    vg[it] = f32::rec(b.G, (f32::col_base(g, jj, ii) + (uint32_t)(w.kbase + kk)) * 2u + (uint32_t)r);
-                }
-            }
+            for (int t = 0; t < NG; t++)
+                if (pg < 3 && pg + 3 * t < w.L) vg[t] = f32::rec(b.G, kg + 6u * t);
 #pragma unroll
-            for (int it = 0; it < NA; it++) {
-                const int e = lane + 64 * it;
-                if (e < nA) {
-                    const int bxy = (int)(((uint32_t)e * mL) >> 16), kk = e - bxy * w.L;
-                    f32::wb_lds[w.base + bxy * WB_LMAX + kk] = va[it];
-                }
-            }
+            for (int t = 0; t < NA; t++)
+                if (pa < 2 && pa + 2 * t < w.L) f32::wb_lds[ca * WB_LMAX + pa + 2 * t] = va[t];
 #pragma unroll
-            for (int it = 0; it < NG; it++) {
-                const int e = lane + 64 * it;
-                if (e < nG) {
-                    const int r = e >= L9 ? 1 : 0, tt = e - r * L9;
-                    const int bxy = (int)(((uint32_t)tt * mL) >> 16), kk = tt - bxy * w.L;
-                    f32::wb_lds[w.base + WB_A + r * 9 * WB_LMAX + bxy * WB_LMAX + kk] = vg[it];
-                }
-            }
+            for (int t = 0; t < NG; t++)
+                if (pg < 3 && pg + 3 * t < w.L) f32::wb_lds[WB_A + rg * 9 * WB_LMAX + cg * WB_LMAX + pg + 3 * t] = vg[t];
             // f2 and (f2)_y of the five box rows
             if (lane < 5) {
                 int jj = w.jc + lane - 2;
@@ -117,14 +102,15 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
     }
     if (!valid) return;
     int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
-    float Y[9] = {src.xi[s], src.eta[s], src.zeta[s], src.k[s], src.l[s], src.m[s], src.dxi[s], src.deta[s], src.dz[s]};
+    float Y[9] = {f32::at(src.xi, s),  f32::at(src.eta, s), f32::at(src.zeta, s), f32::at(src.k, s),   f32::at(src.l, s),
+                  f32::at(src.m, s),   f32::at(src.dxi, s), f32::at(src.deta, s), f32::at(src.dz, s)};
     float Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float F[9];
     const float A[3] = {0.0f, -5.0f / 9.0f, -153.0f / 128.0f};
     const float B[3] = {1.0f / 3.0f, 15.0f / 16.0f, 8.0f / 15.0f};
     const float phi0 = g.y0 + (float)jc * g.dyr;
     // volumes in columns handed to the surrogate keep their state this step
-    const int nst = (frozen && frozen[skeys[i]]) ? 0 : 3;
+    const int nst = (frozen && frozen[f32::at(skeys, i)]) ? 0 : 3;
 #pragma unroll 1
     for (int st = 0; st < nst; st++) {
         // a stage whose lookups all lie in the box, for every lane, runs the
@@ -193,23 +179,23 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
                 key = (uint32_t)(jc * g.nx + ic);
         }
     }
-    dst.col[i] = (uint32_t)(jc * g.nx + ic);
-    dst.lev[i] = kc;
-    dst.xi[i] = Y[0];
-    dst.eta[i] = Y[1];
-    dst.zeta[i] = Y[2];
-    dst.k[i] = Y[3];
-    dst.l[i] = Y[4];
-    dst.m[i] = Y[5];
-    dst.dxi[i] = Y[6];
-    dst.deta[i] = Y[7];
-    dst.dz[i] = Y[8];
-    dst.px[i] = src.px[s];
-    dst.py[i] = src.py[s];
-    dst.pz[i] = src.pz[s];
+    f32::put(dst.col, i, (uint32_t)(jc * g.nx + ic));
+    f32::put(dst.lev, i, kc);
+    f32::put(dst.xi, i, Y[0]);
+    f32::put(dst.eta, i, Y[1]);
+    f32::put(dst.zeta, i, Y[2]);
+    f32::put(dst.k, i, Y[3]);
+    f32::put(dst.l, i, Y[4]);
+    f32::put(dst.m, i, Y[5]);
+    f32::put(dst.dxi, i, Y[6]);
+    f32::put(dst.deta, i, Y[7]);
+    f32::put(dst.dz, i, Y[8]);
+    f32::put(dst.px, i, f32::at(src.px, s));
+    f32::put(dst.py, i, f32::at(src.py, s));
+    f32::put(dst.pz, i, f32::at(src.pz, s));
     dst.W[i] = src.W[s];
     dst.id[i] = src.id[s];
-    key_out[i] = key;
+    f32::put(key_out, i, key);
 }
 
 void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,

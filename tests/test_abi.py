@@ -43,5 +43,9 @@ def test_create_rejects_bad_config_without_touching_the_gpu():
     assert L.rt_create(ctypes.byref(cfg), ctypes.byref(h)) == _rt.RT_E_ARG  # geometry
     cfg = _rt.Config(0, 0, 4, 4, 4, 0, -1.0, 1.0, 1.0, 1.0, 10, _rt.ALLOC_FN(), _rt.FREE_FN(), None, None)
     assert L.rt_create(ctypes.byref(cfg), ctypes.byref(h)) == _rt.RT_E_ARG  # dx
+    # single precision addresses ray fields with 32-bit byte offsets
+    cfg = _rt.Config(0, _rt.RT_FP32, 4, 4, 4, 0, 1.0, 1.0, 1.0, 1.0, 1 << 30, _rt.ALLOC_FN(), _rt.FREE_FN(), None,
+                     None)
+    assert L.rt_create(ctypes.byref(cfg), ctypes.byref(h)) == _rt.RT_E_UNSUPPORTED
     assert L.rt_step(None, 1.0, 0) == _rt.RT_E_ARG
     assert L.rt_deposit_flux(None, None, None, 0) == _rt.RT_E_ARG
