@@ -63,7 +63,8 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         list(ex.map(run, [j[0] for j in jobs]))
     tmp = OUT + ".tmp"
-    run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *[j[1] for j in jobs]])
+    # -z defs: an undefined symbol fails the link instead of the first load
+    run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,-z,defs", "-o", tmp, *[j[1] for j in jobs]])
     os.replace(tmp, OUT)
     return OUT
 

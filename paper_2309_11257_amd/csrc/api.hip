@@ -272,6 +272,7 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     ctx->hist_len = radix_hist_len(cap);
     ALLOC(ctx->hist, uint32_t, ctx->hist_len);
     ALLOC(ctx->colstart, uint32_t, (int64_t)g.ncol + 1);
+    if (cfg->precision == RT_FP32) ALLOC(ctx->wcol, uint32_t, wave_table_len(cap, g.ncol));
     ALLOC(ctx->flux, double, (int64_t)6 * (g.nz + 1) * g.ncol);
     ALLOC(ctx->drag, double, 2 * cells);
     ALLOC(ctx->frozen, uint8_t, g.ncol);
@@ -344,7 +345,7 @@ static rt_status sort_current(rt_ctx ctx)
     radix_sort(ctx->key[ctx->cur], nullptr, ctx->skeys, ctx->perm, ctx->tk, ctx->tv, ctx->hist, &ctx->dc->n_sorted,
                bound, bits_of(bylev ? maxcol * nl - 1 : maxcol), ctx->stream);
     if (bylev) launch_colkey(ctx->skeys, ctx->dc, (uint32_t)nl, bound, ctx->stream);
-    launch_colstart(ctx->skeys, ctx->dc, ctx->colstart, ctx->g.ncol, ctx->stream);
+    launch_colstart(ctx->skeys, ctx->dc, ctx->colstart, ctx->wcol, ctx->g.ncol, ctx->stream);
     if (ctx->precision == RT_FP64)
         launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
     else
@@ -496,8 +497,8 @@ extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
         launch_step64(ctx->g, ctx->bp64, ctx->s64[ctx->cur], ctx->s64[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
                       ctx->n_bound, dt, frozen, ctx->skeys, ctx->stream);
     else
-        launch_step32(ctx->g, ctx->bp32, ctx->s32[ctx->cur], ctx->s32[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
-                      ctx->n_bound, dt, frozen, ctx->skeys, ctx->stream);
+        launch_step32(ctx->g, ctx->bp32, ctx->s32[ctx->cur], ctx->s32[nxt], ctx->perm, ctx->key[nxt], ctx->colstart,
+                      ctx->wcol, ctx->n_bound, dt, frozen, ctx->skeys, ctx->stream);
     prof_end(ctx);
     launch_sorted_from_active(ctx->dc, ctx->stream);
     ctx->cur = nxt;

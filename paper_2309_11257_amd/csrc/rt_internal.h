@@ -101,6 +101,7 @@ struct rt_ctx_s {
     // sorted view of the current buffer
     uint32_t *perm, *skeys;
     uint32_t *colstart;  // [ncol + 1]
+    uint32_t *wcol;      // single-precision step: column of each wave (wave table)
     // sort scratch
     uint32_t *tk, *tv, *hist;
     int64_t hist_len;
@@ -215,8 +216,9 @@ void launch_step64(const Grid &g, const Bg64P &b, S64 src, S64 dst, const uint32
                    const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
                    hipStream_t s);
 void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
-                   const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
-                   hipStream_t s);
+                   const uint32_t *colstart, const uint32_t *wcol, int64_t bound, double dt,
+                   const uint8_t *frozen, const uint32_t *skeys, hipStream_t s);
+int64_t wave_table_len(int64_t cap, int ncol);
 void launch_features64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s);
 void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
@@ -230,7 +232,9 @@ int64_t radix_hist_len(int64_t bound);
 // in-place exclusive scan of t[0..len) (parts: scan_tmp_len(len) scratch)
 void scan_u32(uint32_t *t, int64_t len, uint32_t *parts, hipStream_t s);
 int64_t scan_tmp_len(int64_t len);
-void launch_colstart(const uint32_t *skeys, DevCounters *dc, uint32_t *colstart, int ncol, hipStream_t s);
+// column offsets of the sorted keys; with wcol also the step's wave table
+void launch_colstart(const uint32_t *skeys, DevCounters *dc, uint32_t *colstart, uint32_t *wcol, int ncol,
+                     hipStream_t s);
 void launch_levkey32(const Grid &g, S32 st, uint32_t *key, const DevCounters *dc, int64_t bound, hipStream_t s);
 void launch_levkey64(const Grid &g, S64 st, uint32_t *key, const DevCounters *dc, int64_t bound, hipStream_t s);
 void launch_colkey(uint32_t *skeys, const DevCounters *dc, uint32_t nl, int64_t bound, hipStream_t s);

@@ -243,27 +243,53 @@ void launch_colkey(uint32_t *skeys, const DevCounters *dc, uint32_t nl, int64_t 
     k_colkey<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(skeys, dc, nl);
 }
 
-// column c occupies sorted positions [colstart[c], colstart[c+1]); removed
-// volumes (keys >= ncol) follow at [colstart[ncol], n_sorted)
-__global__ void k_colstart(const uint32_t *__restrict__ skeys, DevCounters *dc, uint32_t *__restrict__ colstart, int ncol)
+static __device__ inline int64_t lower_key(const uint32_t *__restrict__ skeys, int64_t n, uint32_t c)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > ncol) return;
-    int64_t lo = 0, hi = dc->n_sorted;
+    int64_t lo = 0, hi = n;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if (skeys[mid] < (uint32_t)c)
+        if (skeys[mid] < c)
             lo = mid + 1;
         else
             hi = mid;
     }
-    colstart[c] = (uint32_t)lo;
-    if (c == ncol) dc->n_active = lo;
+    return lo;
 }
 
-void launch_colstart(const uint32_t *skeys, DevCounters *dc, uint32_t *colstart, int ncol, hipStream_t s)
+// column c occupies sorted positions [colstart[c], colstart[c+1]); removed
+// volumes (keys >= ncol) follow at [colstart[ncol], n_sorted).
+//
+// Wave table of the single-precision step (wcol non-null): column c with
+// volumes at [s, e) gets waves c + s / 64 + j, j < ceil((e - s) / 64), each of
+// up to 64 consecutive volumes of that column; the next column's first wave
+// is c + 1 + e / 64, which is never below this column's last wave plus one,
+// so the columns' waves do not overlap and the gaps between them are marked
+// empty.  Waves from ncol + colstart[ncol] / 64 on are beyond every column.
+__global__ void k_colstart(const uint32_t *__restrict__ skeys, DevCounters *dc, uint32_t *__restrict__ colstart,
+                           uint32_t *__restrict__ wcol, int ncol)
 {
-    k_colstart<<<(unsigned)((ncol + 1 + 255) / 256), 256, 0, s>>>(skeys, dc, colstart, ncol);
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > ncol) return;
+    const int64_t n = dc->n_sorted;
+    const int64_t s = lower_key(skeys, n, (uint32_t)c);
+    colstart[c] = (uint32_t)s;
+    if (c == ncol) dc->n_active = s;
+    if (wcol && c < ncol) {
+        const int64_t e = lower_key(skeys, n, (uint32_t)c + 1u);
+        const int64_t w0 = c + s / 64, w1 = w0 + (e - s + 63) / 64, wn = c + 1 + e / 64;
+        for (int64_t w = w0; w < w1; w++) wcol[w] = (uint32_t)c;
+        for (int64_t w = w1; w < wn; w++) wcol[w] = 0xffffffffu;
+    }
+}
+
+// upper bound of the waves of the single-precision step: sum over columns of
+// ceil(n_c / 64) <= n / 64 + ncol
+int64_t wave_table_len(int64_t cap, int ncol) { return cap / 64 + ncol + 1; }
+
+void launch_colstart(const uint32_t *skeys, DevCounters *dc, uint32_t *colstart, uint32_t *wcol, int ncol,
+                     hipStream_t s)
+{
+    k_colstart<<<(unsigned)((ncol + 1 + 255) / 256), 256, 0, s>>>(skeys, dc, colstart, wcol, ncol);
 }
 
 __global__ void k_set_sorted(DevCounters *dc, int64_t n) { dc->n_sorted = n; }

@@ -2,8 +2,10 @@
 // Williamson's low-storage third-order scheme; Section 3a), followed by the
 // post-step wrap, removal and column key.  One thread per volume, volumes
 // read through the previous sort's permutation and written in sorted order.
-// A wave whose volumes share one column first stages the background stencil
-// they all use into LDS (see f32.h); its interpolations then read LDS.
+// Each wave takes up to 64 consecutive volumes of one column (a column of n
+// volumes has ceil(n / 64) waves of its own, from the wave table built with
+// the column offsets), so every wave first stages the background stencil its volumes
+// share into LDS (see f32.h); its interpolations then read LDS.
 #include "f32.h"
 
 // one wave per workgroup: a workgroup's slot and stencil box are released as
@@ -14,17 +16,25 @@ template <bool SPH>
 __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 dst,
                                                           const uint32_t *__restrict__ perm,
                                                           uint32_t *__restrict__ key_out,
-                                                          const DevCounters *__restrict__ dc, float dt,
+                                                          const uint32_t *__restrict__ colstart,
+                                                          const uint32_t *__restrict__ wcol, float dt,
                                                           const uint8_t *__restrict__ frozen,
                                                           const uint32_t *__restrict__ skeys)
 {
-    // 32-bit volume indices (the single-precision path holds fewer than 2^30
-    // volumes): 4-byte fields are read and written at 32-bit byte offsets from
-    // their uniform bases, which keeps one register per index live
-    const uint32_t i = (uint32_t)xcd_block(gridDim.x) * STEP_BLOCK + threadIdx.x;
+    // this wave's column and its chunk of the column's sorted positions (the
+    // grid is an upper bound of the waves; waves past the last column's and
+    // the gaps between columns exit here).  32-bit volume indices (the
+    // single-precision path holds fewer than 2^30 volumes): 4-byte fields are
+    // read and written at 32-bit byte offsets from their uniform bases, which
+    // keeps one register per index live
+    const uint32_t wv = (uint32_t)xcd_block(gridDim.x);
+    if (wv >= (uint32_t)g.ncol + colstart[g.ncol] / 64u) return;
+    const uint32_t cw = wcol[wv];
+    if (cw == 0xffffffffu) return;
+    const uint32_t i = colstart[cw] + 64u * (wv - cw - colstart[cw] / 64u) + threadIdx.x;
     // stage the stencil box shared by the wave's volumes (all lanes take part:
     // the wave-wide reductions need every lane)
-    const bool valid = (int64_t)i < dc->n_active;
+    const bool valid = i < colstart[cw + 1];
     const uint32_t s = valid ? f32::at(perm, i) : 0u;
     const uint32_t col = valid ? f32::at(src.col, s) : 0xffffffffu;
     const int kc0 = valid ? f32::at(src.lev, s) : 0;
@@ -199,15 +209,17 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
 }
 
 void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32_t *perm, uint32_t *key_out,
-                   const DevCounters *dc, int64_t bound, double dt, const uint8_t *frozen, const uint32_t *skeys,
-                   hipStream_t s)
+                   const uint32_t *colstart, const uint32_t *wcol, int64_t bound, double dt,
+                   const uint8_t *frozen, const uint32_t *skeys, hipStream_t s)
 {
     if (bound <= 0) return;
-    const unsigned nb = (unsigned)((bound + STEP_BLOCK - 1) / STEP_BLOCK);
+    const unsigned nb = (unsigned)wave_table_len(bound, g.ncol);  // an upper bound of the waves
     const G32 h = f32::make_g32(g);
     const size_t lds = (size_t)WB_RECS * sizeof(float4);  // the wave's stencil box
     if (g.geometry == RT_SPHERICAL)
-        k_step32<true><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
+        k_step32<true><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, colstart, wcol, (float)dt,
+                                                   frozen, skeys);
     else
-        k_step32<false><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, dc, (float)dt, frozen, skeys);
+        k_step32<false><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, colstart, wcol, (float)dt,
+                                                    frozen, skeys);
 }
