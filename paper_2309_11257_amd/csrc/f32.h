@@ -239,9 +239,9 @@ __device__ inline void n2_f2(const G32 &g, const Bg32P &b, int ic, int jc, int k
 // Per-wave stencil box in LDS.  When every volume of a wave lies in one
 // column and the wave's levels span at most WB_LMAX - 6, the wave stages the
 // A records of the 5 x 5 columns around it and the gradient records of the
-// 3 x 3 columns, for the levels kbase .. kbase + L - 1, and interpolates from
-// LDS; a lookup that falls outside the box for any lane of the wave goes to
-// global memory for the whole wave.
+// 3 x 3 columns, for the levels kbase .. kbase + L - 1, plus f2 and (f2)_y of
+// the five rows, and interpolates from LDS; a lookup that falls outside the
+// box for any lane of the wave goes to global memory for the whole wave.
 #define WB_LMAX 13
 #define WB_A (25 * WB_LMAX)
 #define WB_F2 (WB_A + 18 * WB_LMAX)  // five rows of (f2, (f2)_y, 0, 0) after the records

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
             // of its levels: A records by 50 lanes (25 columns x 2 phases,
             // levels ph, ph + 2, ...), gradient records by 54 lanes (9
             // columns x 2 records x 3 phases, levels ph, ph + 3, ...); the
-            // column is located once, the levels are immediate offsets, and
+            // column is located once, the levels are constant offsets, and
             // all loads are issued before the LDS writes
             constexpr int NA = (WB_LMAX + 1) / 2, NG = (WB_LMAX + 2) / 3;
             const int ca = lane % 25, pa = lane / 25;  // pa: 0, 1 (2 idle)
