@@ -401,18 +401,20 @@ __device__ inline float face_t(float c, float sg, float ext) { return fmaf(sg, e
 // 3 x 3 gradient box), face nodes at -2 .. 1 (the 5 x 5 box), levels inside
 __device__ inline bool box_stage_in(const G32 &g, const WBox &w, int kc, const float *Y)
 {
+    // horizontal nodes: floor(t) in lo .. hi exactly when lo <= t < hi + 1
+    // (false for a NaN); the stage forms the same t
+    const float tx = Y[0] - 0.5f, ty = Y[1] - 0.5f;
+    const float txp = face_t(Y[0], 0.5f, Y[6]), txm = face_t(Y[0], -0.5f, Y[6]);
+    const float typ = face_t(Y[1], 0.5f, Y[7]), tym = face_t(Y[1], -0.5f, Y[7]);
+    const bool hor = tx >= -1.0f && tx < 1.0f && ty >= -1.0f && ty < 1.0f && txp >= -2.0f && txp < 2.0f &&
+                     txm >= -2.0f && txm < 2.0f && typ >= -2.0f && typ < 2.0f && tym >= -2.0f && tym < 2.0f;
     float t;
     int s0, s1, s2;
-    const int dx = bnode(Y[0] - 0.5f, t), dy = bnode(Y[1] - 0.5f, t);
-    const int dxp = bnode(face_t(Y[0], 0.5f, Y[6]), t), dxm = bnode(face_t(Y[0], -0.5f, Y[6]), t);
-    const int dyp = bnode(face_t(Y[1], 0.5f, Y[7]), t), dym = bnode(face_t(Y[1], -0.5f, Y[7]), t);
     const float sdz = Y[8] * g.inv_dz;
     const int k0 = blev(g, w, kc, Y[2] - 0.5f, s0, t);
     const int kp = blev(g, w, kc, face_t(Y[2], 0.5f, sdz), s1, t);
     const int km = blev(g, w, kc, face_t(Y[2], -0.5f, sdz), s2, t);
-    const uint32_t cen = (uint32_t)(dx + 1) | (uint32_t)(dy + 1);
-    const uint32_t fac = (uint32_t)(dxp + 2) | (uint32_t)(dxm + 2) | (uint32_t)(dyp + 2) | (uint32_t)(dym + 2);
-    return cen < 2u && fac < 4u && (uint32_t)k0 < (uint32_t)(w.L - s0) && (uint32_t)kp < (uint32_t)(w.L - s1) &&
+    return hor && (uint32_t)k0 < (uint32_t)(w.L - s0) && (uint32_t)kp < (uint32_t)(w.L - s1) &&
            (uint32_t)km < (uint32_t)(w.L - s2);
 }
 
