@@ -67,11 +67,17 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *__restri
     const int lane = tid & 63;
     // lanes holding the same digit are counted by their lowest lane (keys
     // arrive nearly sorted, so a wave usually holds one or two digits)
-#pragma unroll 4
+    uint32_t kt[RS_ITEMS];  // all of the tile's keys in flight at once
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; it++) {
+        const int64_t i = base + (int64_t)it * RS_THREADS + tid;
+        kt[it] = i < n ? keys[i] : 0u;
+    }
+#pragma unroll
     for (int it = 0; it < RS_ITEMS; it++) {
         const int64_t i = base + (int64_t)it * RS_THREADS + tid;
         const bool valid = i < n;
-        const uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
+        const uint32_t d = valid ? (kt[it] >> shift) & 255u : 0u;
         const unsigned long long peers = digit_peers(d, valid, lane);
         if (valid && lane == __ffsll((long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
@@ -165,11 +171,21 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t *__res
     const int64_t n = *n_dev;
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // the tile's keys and values are loaded before the rounds, so that the
+    // rounds (and their barriers) do not wait on global memory one by one
+    uint32_t kt[RS_ITEMS], vt[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; it++) {
+        const int64_t i = base + (int64_t)it * RS_THREADS + tid;
+        kt[it] = i < n ? kin[i] : 0u;
+        vt[it] = i < n ? (vin ? vin[i] : (uint32_t)i) : 0u;
+    }
+#pragma unroll
     for (int it = 0; it < RS_ITEMS; it++) {
         const int64_t i = base + (int64_t)it * RS_THREADS + tid;
         const bool valid = i < n;
-        const uint32_t key = valid ? kin[i] : 0u;
-        const uint32_t val = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+        const uint32_t key = kt[it];
+        const uint32_t val = vt[it];
         const uint32_t d = (key >> shift) & 255u;
         const unsigned long long peers = digit_peers(d, valid, lane);
         const uint32_t rank = (uint32_t)__popcll(peers & below);
