@@ -38,6 +38,19 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
     const uint32_t s = valid ? f32::at(perm, i) : 0u;
     const uint32_t col = valid ? f32::at(src.col, s) : 0xffffffffu;
     const int kc0 = valid ? f32::at(src.lev, s) : 0;
+    // the state's loads are in flight during the staging
+    float Y[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid) {
+        Y[0] = f32::at(src.xi, s);
+        Y[1] = f32::at(src.eta, s);
+        Y[2] = f32::at(src.zeta, s);
+        Y[3] = f32::at(src.k, s);
+        Y[4] = f32::at(src.l, s);
+        Y[5] = f32::at(src.m, s);
+        Y[6] = f32::at(src.dxi, s);
+        Y[7] = f32::at(src.deta, s);
+        Y[8] = f32::at(src.dz, s);
+    }
     f32::WBox w;
     {
         const int lane = threadIdx.x & 63;
@@ -112,8 +125,6 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
     }
     if (!valid) return;
     int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
-    float Y[9] = {f32::at(src.xi, s),  f32::at(src.eta, s), f32::at(src.zeta, s), f32::at(src.k, s),   f32::at(src.l, s),
-                  f32::at(src.m, s),   f32::at(src.dxi, s), f32::at(src.deta, s), f32::at(src.dz, s)};
     float Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float F[9];
     const float A[3] = {0.0f, -5.0f / 9.0f, -153.0f / 128.0f};
