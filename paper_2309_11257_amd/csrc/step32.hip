@@ -146,6 +146,10 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
             Y[c] = Y[c] + B[st] * Q[c];
         }
     }
+    // the fields carried unchanged are read while the post-step runs
+    const float cpx = f32::at(src.px, s), cpy = f32::at(src.py, s), cpz = f32::at(src.pz, s);
+    const double cW = src.W[s];
+    const int64_t cid = src.id[s];
     // post-step: validity, wrap, removal, column key
     uint32_t key;
     int kc = kc0;
@@ -211,11 +215,11 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
     f32::put(dst.dxi, i, Y[6]);
     f32::put(dst.deta, i, Y[7]);
     f32::put(dst.dz, i, Y[8]);
-    f32::put(dst.px, i, f32::at(src.px, s));
-    f32::put(dst.py, i, f32::at(src.py, s));
-    f32::put(dst.pz, i, f32::at(src.pz, s));
-    dst.W[i] = src.W[s];
-    dst.id[i] = src.id[s];
+    f32::put(dst.px, i, cpx);
+    f32::put(dst.py, i, cpy);
+    f32::put(dst.pz, i, cpz);
+    dst.W[i] = cW;
+    dst.id[i] = cid;
     f32::put(key_out, i, key);
 }
 
