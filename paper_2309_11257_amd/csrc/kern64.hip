@@ -278,6 +278,9 @@ __global__ __launch_bounds__(STEP64_BLOCK, 2) void k_step64(Grid g, Bg64P b, S64
             Y[c] = Y[c] + B[st] * Q[c];
         }
     }
+    // the fields carried unchanged are read while the post-step runs
+    const double cpx = src.px[s], cpy = src.py[s], cpz = src.pz[s], cn = src.n[s];
+    const int64_t cid = src.id[s];
     const uint32_t key = d64::post_step(g, Y);
     dst.x[i] = Y[0];
     dst.y[i] = Y[1];
@@ -288,11 +291,11 @@ __global__ __launch_bounds__(STEP64_BLOCK, 2) void k_step64(Grid g, Bg64P b, S64
     dst.dx[i] = Y[6];
     dst.dy[i] = Y[7];
     dst.dz[i] = Y[8];
-    dst.px[i] = src.px[s];
-    dst.py[i] = src.py[s];
-    dst.pz[i] = src.pz[s];
-    dst.n[i] = src.n[s];
-    dst.id[i] = src.id[s];
+    dst.px[i] = cpx;
+    dst.py[i] = cpy;
+    dst.pz[i] = cpz;
+    dst.n[i] = cn;
+    dst.id[i] = cid;
     key_out[i] = key;
 }
 
