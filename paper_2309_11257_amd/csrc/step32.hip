@@ -36,7 +36,8 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
     // the wave-wide reductions need every lane)
     const bool valid = i < colstart[cw + 1];
     const uint32_t s = valid ? f32::at(perm, i) : 0u;
-    const uint32_t col = valid ? f32::at(src.col, s) : 0xffffffffu;
+    // every volume of the wave lies in column cw (a volume's stored column is
+    // its sort key)
     const int kc0 = valid ? f32::at(src.lev, s) : 0;
     // the state's loads are in flight during the staging
     float Y[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -54,19 +55,17 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
     f32::WBox w;
     {
         const int lane = threadIdx.x & 63;
-        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)col);
-        const bool uni = __ballot(valid && col != c0) == 0ull && c0 != 0xffffffffu;
         const int kmn = wave_min_i(valid ? kc0 : 0x7fffffff), kmx = wave_max_i(valid ? kc0 : -1);
         w.base = 0;
-        w.ic = (int)(c0 % (uint32_t)g.nx);
-        w.jc = (int)(c0 / (uint32_t)g.nx);
+        w.ic = (int)(cw % (uint32_t)g.nx);
+        w.jc = (int)(cw / (uint32_t)g.nx);
         // levels: margins of two levels below and three above the wave's
         // range hold the faces of most volumes (a lookup outside the box
         // reads global memory)
         w.kbase = max(0, kmn - 2);
         w.L = min(g.nz - 1, kmx + 3) - w.kbase + 1;
         // one wrap corrects a column or row index when the grid has at least two
-        w.on = uni && w.L <= WB_LMAX && g.nx >= 2 && (g.geometry != RT_CARTESIAN || g.ny >= 2);
+        w.on = w.L <= WB_LMAX && g.nx >= 2 && (g.geometry != RT_CARTESIAN || g.ny >= 2);
         if (w.on) {
             // a lane keeps one box column (and gradient record) and a phase
             // of its levels: A records by 50 lanes (25 columns x 2 phases,
@@ -124,7 +123,7 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
         __builtin_amdgcn_wave_barrier();
     }
     if (!valid) return;
-    int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
+    int ic = w.ic, jc = w.jc;
     float Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float F[9];
     const float A[3] = {0.0f, -5.0f / 9.0f, -153.0f / 128.0f};
