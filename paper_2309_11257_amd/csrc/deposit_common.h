@@ -77,6 +77,75 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
             const bool valid = r < s1;
             double zb = 0.0, zt = 0.0, bv[6] = {0, 0, 0, 0, 0, 0};
             if (valid) pl.load(perm[r], c, zb, zt, bv);
+            // the levels (lo .. hi) and interfaces (lo2 .. hi2) the volume
+            // overlaps, in level units: the double-precision payload divides
+            // (so it visits the same levels as a plain division); the
+            // single-precision one multiplies by 1/dz, which can differ only
+            // where a bound lies within rounding of an interface, and then by
+            // an overlap a few units in the last place of z wide
+            int lo = 0x7fffffff, hi = -1, lo2 = 0x7fffffff, hi2 = -1;
+            if (valid) {
+                const double zbl = P::EXACT_LEVELS ? zb / g.dz : zb * pl.inv_dz;
+                const double ztl = P::EXACT_LEVELS ? zt / g.dz : zt * pl.inv_dz;
+                lo = max((int)floor(zbl), 0);
+                hi = min((int)floor(ztl), g.nz - 1);
+                lo2 = max((int)floor(zbl + 0.5), 0);
+                hi2 = min((int)floor(ztl + 0.5), g.nz);
+            }
+            const int k0 = wave_min_i(min(lo, lo2)), k1 = wave_max_i(max(hi, hi2));
+            if (RP && 6 * nzp >= 8 * 64 && k1 - k0 < 8) {
+                // Chunk within eight levels (a column sorted by level): lane
+                // 8 g + s takes level (and interface) k0 + s for the volumes g,
+                // g + 8, ..., g + 56 of the chunk, read from the wave's LDS
+                // (its integer profile, zero between chunks), and the eight
+                // groups are added by a fixed butterfly: double sums in a
+                // fixed order, with no fixed-point scale.
+                double *vd = (double *)acc;
+                vd[lane] = zb;
+                vd[64 + lane] = zt;
+#pragma unroll
+                for (int q = 0; q < 6; q++) vd[128 + 64 * q + lane] = bv[q];
+                wave_sync();
+                const int sl8 = lane & 7, gi = lane >> 3, k = k0 + sl8;
+                const double lv = (double)k * g.dz, hv = (double)(k + 1) * g.dz;
+                double lv2 = ((double)k - 0.5) * g.dz, hv2 = ((double)k + 0.5) * g.dz;
+                if (lv2 < 0.0) lv2 = 0.0;
+                if (hv2 > g.Lz) hv2 = g.Lz;
+                const bool lev_ok = k <= g.nz - 1, itf_ok = k <= g.nz;
+                double sm[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const int j = gi + 8 * i;
+                    const double zbj = vd[j], ztj = vd[64 + j];
+                    double o = fmin(ztj, hv) - fmax(zbj, lv);
+                    double o2 = fmin(ztj, hv2) - fmax(zbj, lv2);
+                    o = (lev_ok && o > 0.0) ? o : 0.0;
+                    o2 = (itf_ok && o2 > 0.0) ? o2 : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) sm[q] += vd[128 + 64 * q + j] * o;
+#pragma unroll
+                    for (int q = 4; q < 6; q++) sm[q] += vd[128 + 64 * q + j] * o2;
+                }
+#pragma unroll
+                for (int q = 0; q < 6; q++)
+#pragma unroll
+                    for (int off = 8; off < 64; off <<= 1) sm[q] += __shfl_xor(sm[q], off, 64);
+                // level k0 + s (held by lanes s < 8) to the lane that keeps it:
+                // lane (k0 + s) mod 64, register slot (k0 + s) / 64
+                const int src = (lane - k0) & 63;
+                const bool take = src < 8, hi_slot = k0 + src >= 64;
+#pragma unroll
+                for (int q = 0; q < 6; q++) {
+                    const double v = __shfl(sm[q], src, 64);
+                    preg[q][0] += (take && !hi_slot) ? v : 0.0;
+                    preg[q][1] += (take && hi_slot) ? v : 0.0;
+                }
+                wave_sync();
+#pragma unroll
+                for (int t = 0; t < 8; t++) acc[64 * t + lane] = 0ull;
+                wave_sync();
+                continue;
+            }
             const double h = valid ? fmin(zt - zb, g.dz) : 0.0;
             // per field: the largest possible contribution of the chunk sets
             // the fixed-point scale (a bound on each |bv * overlap|)
@@ -90,24 +159,12 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                 sx[q] = (ea > 0 && ea < 0x7fe) ? 51 - (ea - 1022) : 0;
                 sx[q + 1] = (eb > 0 && eb < 0x7fe) ? 51 - (eb - 1022) : 0;
             }
-            int klo = 0x7fffffff, khi = -1;
             if (valid) {
                 // columns sorted by level put the lanes of a chunk on the same
                 // levels: each lane starts its level loop at an offset of its
                 // own, so that one LDS add instruction spreads over several
                 // words instead of serialising on one (integer adds commute,
                 // so the sums do not depend on the order)
-
-                // level span in level units: the double-precision payload divides
-                // (so it visits the same levels as a plain division); the
-                // single-precision one multiplies by 1/dz, which can differ only
-                // where a bound lies within rounding of an interface, and then by
-                // an overlap a few units in the last place of z wide
-                const double zbl = P::EXACT_LEVELS ? zb / g.dz : zb * pl.inv_dz;
-                const double ztl = P::EXACT_LEVELS ? zt / g.dz : zt * pl.inv_dz;
-                int lo = (int)floor(zbl), hi = (int)floor(ztl);
-                if (lo < 0) lo = 0;
-                if (hi > g.nz - 1) hi = g.nz - 1;
                 const int nk = hi - lo + 1;
                 int kk = nk > 0 ? lo + lane % nk : lo;
                 for (int t = 0; t < nk; t++, kk = kk == hi ? lo : kk + 1) {
@@ -120,10 +177,6 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                         if (v) atomicAdd(&acc[q * nzp + kk], (unsigned long long)v);
                     }
                 }
-                klo = lo;
-                int lo2 = (int)floor(zbl + 0.5), hi2 = (int)floor(ztl + 0.5);
-                if (lo2 < 0) lo2 = 0;
-                if (hi2 > g.nz) hi2 = g.nz;
                 const int nk2 = hi2 - lo2 + 1;
                 kk = nk2 > 0 ? lo2 + lane % nk2 : lo2;
                 for (int t = 0; t < nk2; t++, kk = kk == hi2 ? lo2 : kk + 1) {
@@ -138,12 +191,9 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                         if (v) atomicAdd(&acc[q * nzp + kk], (unsigned long long)v);
                     }
                 }
-                klo = min(klo, lo2);
-                khi = max(hi, hi2);
             }
             // move the chunk's integer sums into the double profile, levels
             // the chunk touched only
-            const int k0 = wave_min_i(klo), k1 = wave_max_i(khi);
             wave_sync();
             if (RP) {
 #pragma unroll
