@@ -12,9 +12,12 @@
 // chunk order.  The result is therefore bitwise reproducible from run to run,
 // with no floating-point atomics, and each contribution is rounded once at
 // the level of the chunk maximum's last bit -- the accuracy of an ordinary
-// double sum.  At the end the finished profiles are written together, so
-// that the columns of one (field, level) row form one contiguous segment of
-// the [6][nz+1][ncol] output.
+// double sum.  A chunk whose levels and interfaces lie within eight slots
+// (the usual case in a column sorted by level) instead adds its
+// contributions in double, level by level, in a fixed order (see the chunk
+// loop).  At the end the finished profiles are written together, so that the
+// columns of one (field, level) row form one contiguous segment of the
+// [6][nz+1][ncol] output.
 #pragma once
 #include "rt_internal.h"
 
