@@ -232,16 +232,12 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
         ctx->bp32.G = pa + cells;
     }
     if (ctx->precision == RT_FP32) {
-        float *bgf;
-        ALLOC(bgf, float, 12 * cells + 2 * (int64_t)g.ny);
-        Bg<float> &h = ctx->bg32;
-        const float **dst[12] = {&h.U, &h.V, &h.N2, &h.Ux, &h.Uy, &h.Uz, &h.Vx, &h.Vy, &h.Vz, &h.N2x, &h.N2y, &h.N2z};
-        for (int q = 0; q < 12; q++) *dst[q] = bgf + q * cells;
-        h.f2 = bgf + 12 * cells;
-        h.f2y = bgf + 12 * cells + g.ny;
-        h.rho = ctx->rho;
-        ctx->bp32.f2 = h.f2;
-        ctx->bp32.f2y = h.f2y;
+        // single-precision f2 and (f2)_y rows (the fields are rounded into the
+        // packed records themselves)
+        float *rows;
+        ALLOC(rows, float, 2 * (int64_t)g.ny);
+        ctx->bp32.f2 = rows;
+        ctx->bp32.f2y = rows + g.ny;
     }
     // ray state, two buffers
     for (int buf = 0; buf < 2; buf++) {
@@ -388,8 +384,7 @@ extern "C" rt_status rt_init_background(rt_ctx ctx, const double *U, const doubl
     launch_gradients64(g, ctx->bg64.U, ctx->bg64.V, ctx->bg64.N2, fstage, bgd + 3 * cells, (double *)ctx->bg64.f2,
                        (double *)ctx->bg64.f2y, ctx->stream);
     if (ctx->precision == RT_FP32) {
-        float *bgf = (float *)ctx->bg32.U;
-        launch_round32(bgd, bgf, 12 * cells + 2 * (int64_t)g.ny, ctx->stream);
+        launch_round32(bgd + 12 * cells, (float *)ctx->bp32.f2, 2 * (int64_t)g.ny, ctx->stream);
         launch_pack32(g, ctx->bg64, (float4 *)ctx->bp32.A, (float4 *)ctx->bp32.G, ctx->stream);
     } else {
         launch_pack64(g, ctx->bg64, (double4 *)ctx->bp64.A, (double4 *)ctx->bp64.G, ctx->stream);

@@ -84,7 +84,6 @@ struct rt_ctx_s {
     // background
     bool have_bg;
     Bg<double> bg64;
-    Bg<float> bg32;
     Bg64P bp64;
     Bg32P bp32;
     double *rho;
