@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_merge_cells(IO io, const Grid g, const 
     uint64_t *k2 = k1 + N;
     uint32_t *pl = (uint32_t *)(k2 + N);
     uint32_t *alive = pl + N;  // by position in the cell's original order
-    __shared__ int s_count, s_merged, s_done;
+    __shared__ int s_count, s_merged, s_done, s_np;
     for (int q = threadIdx.x; q < (int)cnt; q += blockDim.x) alive[q] = 1u;
     if (threadIdx.x == 0) {
         s_count = (int)cnt;
@@ -536,42 +536,45 @@ __global__ __launch_bounds__(256) void k_merge_cells(IO io, const Grid g, const 
         }
         __syncthreads();
         block_bitonic(k1, k2, pl, N);
+        // the pairs, chosen in sorted order as a sequential pass would: a
+        // record and the next one of the same group, until the cell holds
+        // nmax volumes (if no two records share a group, neighbours in
+        // sorted order); the list goes over the sorted ids, no longer needed
         if (threadIdx.x == 0) {
-            int count = s_count, merged = 0;
             int m_ = 0;
             while (m_ < N && pl[m_] != 0xffffffffu) m_++;
-            for (int q = 0; q + 1 < m_ && count > nmax;) {
+            const int want = s_count - nmax;
+            int np = 0;
+            for (int q = 0; q + 1 < m_ && np < want;) {
                 if (k1[q] == k1[q + 1]) {
-                    const uint32_t sa = perm3[start + pl[q]], sb = perm3[start + pl[q + 1]];
-                    RayD a = io.get(g, sa);
-                    const RayD b = io.get(g, sb);
-                    merge_pair(g, a, b);
-                    io.put(g, sa, a, true);
-                    key[sb] = (uint32_t)(g.ncol + RK_MERGED);
-                    alive[pl[q + 1]] = 0u;
-                    count--;
-                    merged++;
+                    k2[np++] = (uint64_t)q;
                     q += 2;
                 } else {
                     q += 1;
                 }
             }
-            if (merged == 0) {
-                for (int q = 0; q + 1 < m_ && count > nmax; q += 2) {
-                    const uint32_t sa = perm3[start + pl[q]], sb = perm3[start + pl[q + 1]];
-                    RayD a = io.get(g, sa);
-                    const RayD b = io.get(g, sb);
-                    merge_pair(g, a, b);
-                    io.put(g, sa, a, true);
-                    key[sb] = (uint32_t)(g.ncol + RK_MERGED);
-                    alive[pl[q + 1]] = 0u;
-                    count--;
-                    merged++;
-                }
-                if (merged == 0) s_done = 1;
-            }
-            s_count = count;
-            s_merged += merged;
+            if (np == 0)
+                for (int q = 0; q + 1 < m_ && np < want; q += 2) k2[np++] = (uint64_t)q;
+            s_np = np;
+        }
+        __syncthreads();
+        // the pairs are disjoint: merged in parallel
+        const int np = s_np;
+        for (int t = threadIdx.x; t < np; t += blockDim.x) {
+            const int q = (int)k2[t];
+            const uint32_t sa = perm3[start + pl[q]], sb = perm3[start + pl[q + 1]];
+            RayD a = io.get(g, sa);
+            const RayD b = io.get(g, sb);
+            merge_pair(g, a, b);
+            io.put(g, sa, a, true);
+            key[sb] = (uint32_t)(g.ncol + RK_MERGED);
+            alive[pl[q + 1]] = 0u;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (np == 0) s_done = 1;
+            s_count -= np;
+            s_merged += np;
         }
         __threadfence();
         __syncthreads();
