@@ -151,3 +151,51 @@ def test_fp32_sphere_pole_rows(rt, orc):
     err = rel_l2(drag, orc.drag(bg, ref))
     assert err <= 1e-5, err
     tr.close()
+
+
+def banded_rays(w, per_col, seed):
+    """per_col volumes in every column (one wave per column), at levels drawn
+    from bands that depend on the column: one band of four levels (the wave's
+    levels fit one stencil box), or two or three bands spread over 14 or 20
+    levels (too many levels for one box)."""
+    g = np.random.default_rng(seed)
+    bands = [[(4, 8)], [(2, 5), (13, 16)], [(2, 4), (11, 13), (20, 22)]]
+    ncol = w.nx * w.ny
+    c = np.repeat(np.arange(ncol), per_col)
+    n = c.size
+    i, j = c % w.nx, c // w.nx
+    x = w.x0 + (i + g.uniform(0.01, 0.99, n)) * w.dx
+    y = w.y0 + (j + g.uniform(0.01, 0.99, n)) * w.dy
+    z = np.empty(n)
+    for q in range(n):
+        b = bands[c[q] % 3]
+        lo, hi = b[g.integers(len(b))]
+        z[q] = g.uniform(lo, hi) * w.dz
+    lam_h = g.uniform(40.0e3, 400.0e3, n)
+    th = g.uniform(0.0, 2.0 * np.pi, n)
+    kh = 2.0 * np.pi / lam_h
+    m = np.where(g.random(n) < 0.5, -1.0, 1.0) * 2.0 * np.pi / g.uniform(1.5e3, 8.0e3, n)
+    ex = g.uniform(0.1, 2.0, n) * w.dx
+    ey = g.uniform(0.1, 2.0, n) * w.dy
+    ez = g.uniform(0.1, 1.5, n) * w.dz
+    dk, dl, dm = 0.1 * kh, 0.1 * kh, 0.1 * np.abs(m)
+    n_act = 1.0e-3 * np.abs(g.standard_normal(n)) / (kh * dk * dl * dm)
+    return W.rays_from(x, y, z, kh * np.cos(th), kh * np.sin(th), m, ex, ey, ez,
+                       20.0e3 * dk, 20.0e3 * dl, ez * dm, n_act)
+
+
+def test_fp32_level_groups(rt, orc):
+    """Single-precision waves whose levels do not fit one stencil box take the
+    general lookups, next to waves that fit one box.  Drag within 1e-5 of the
+    oracle with the kernel's integer decisions."""
+    w = box_grid(8, 8, nz=24)
+    rays = fp32_representable(w, banded_rays(w, 40, seed=41))
+    bg, rs, tr = run_both(orc, rt, w, rays, 3, rt.RT_FP32)
+    g = tr.get_rays()
+    assert len(g["id"]) == int(rs.active().sum())
+    ref, flips, nset = oracle_deposit_with_kernel_decisions(orc, bg, rs, g, tr.get_columns())
+    assert flips <= 2 and nset <= 2, (flips, nset)
+    _, drag = tr.deposit(host=True)
+    err = rel_l2(drag, orc.drag(bg, ref))
+    assert err <= 1e-5, err
+    tr.close()
