@@ -129,7 +129,7 @@ rt_status rt_init_background(rt_ctx ctx, const double *U, const double *V, const
 rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int32_t where);
 
 /* Copy out the active ray volumes in the library's internal order: grouped
- * by column.  The regrouping after rt_set_rays and every sixteenth one after it
+ * by column.  The regrouping after rt_set_rays and every fourth one after it
  * order each column's volumes by level index floor(z / dz) (clamped to
  * 0 .. nz; when (number of columns + 6) * (nz + 1) fits 32 bits); otherwise,
  * and for volumes with equal keys, each column's previous relative order is

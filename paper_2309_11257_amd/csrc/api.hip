@@ -315,7 +315,7 @@ static int bits_of(uint64_t maxkey)
 
 // every this many regrouping sorts (and the first after a load) the column
 // key is refined by the level
-#define LEVEL_REFINE_EVERY 16
+#define LEVEL_REFINE_EVERY 4
 
 // sort the current buffer's keys -> skeys/perm, column offsets, removal
 // tallies.  A refining sort orders each column's volumes by level (sort key
