@@ -68,26 +68,66 @@ def lib() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = C.CDLL(_LIB_PATH)
-        P = C.c_void_p
-        L.orc_prepare.argtypes = [P]
-        L.orc_interp.argtypes = [P, C.c_double, C.c_double, C.c_double, P]
-        L.orc_dispersion.argtypes = [C.c_double] * 5 + [P]
-        L.orc_rhs.argtypes = [P, P, P]
-        L.orc_step.argtypes = [P, P, C.c_int64, C.c_double, P]
-        L.orc_keys.argtypes = [P, P, C.c_int64]
-        L.orc_deposit.argtypes = [P, P, C.c_int64, P]
-        L.orc_drag.argtypes = [P, P, P]
-        L.orc_split.argtypes = [P, P, C.c_int64, C.c_int64, C.c_double, P, P]
-        L.orc_split.restype = C.c_int64
-        L.orc_merge.argtypes = [P, P, C.c_int64, C.c_int32, P]
-        L.orc_cap.argtypes = [P, P, C.c_int64, C.c_int32, P]
-        L.orc_stats.argtypes = [P, C.c_int64, P]
-        L.orc_features.argtypes = [P, P, C.c_int64, P]
-        L.orc_num_threads.restype = C.c_int
-        L.orc_set_threads.argtypes = [C.c_int]
-        _lib = L
+        _lib = _load(_LIB_PATH)
     return _lib
+
+
+def build_variant(source_text: str, path: str) -> str:
+    """Compile a modified copy of the oracle's C source (same flags as
+    build()) into `path`.  Used only by the tests that plant a mistake in the
+    oracle to show that its pins catch it."""
+    src = os.path.splitext(path)[0] + ".c"
+    with open(src, "w") as f:
+        f.write(source_text)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+                    "-shared", "-w", "-I", _HERE, "-o", path, src, "-lm"], check=True)
+    return path
+
+
+def source_text() -> str:
+    with open(os.path.join(_HERE, "orc.c")) as f:
+        return f.read()
+
+
+class using_library:
+    """Context manager: route every oracle call through the library at
+    `path` (a variant built by build_variant) and restore the real one."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = _load(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _load(path: str) -> C.CDLL:
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.orc_prepare.argtypes = [P]
+    L.orc_interp.argtypes = [P, C.c_double, C.c_double, C.c_double, P]
+    L.orc_dispersion.argtypes = [C.c_double] * 5 + [P]
+    L.orc_rhs.argtypes = [P, P, P]
+    L.orc_step.argtypes = [P, P, C.c_int64, C.c_double, P]
+    L.orc_keys.argtypes = [P, P, C.c_int64]
+    L.orc_deposit.argtypes = [P, P, C.c_int64, P]
+    L.orc_drag.argtypes = [P, P, P]
+    L.orc_split.argtypes = [P, P, C.c_int64, C.c_int64, C.c_double, P, P]
+    L.orc_split.restype = C.c_int64
+    L.orc_merge.argtypes = [P, P, C.c_int64, C.c_int32, P]
+    L.orc_cap.argtypes = [P, P, C.c_int64, C.c_int32, P]
+    L.orc_stats.argtypes = [P, C.c_int64, P]
+    L.orc_features.argtypes = [P, P, C.c_int64, P]
+    L.orc_num_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
+    return L
 
 
 def _ptr(a: np.ndarray) -> int:

@@ -250,10 +250,11 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
             ALLOC(s.id, int64_t, cap);
         } else {
             float *m;
-            ALLOC(m, float, 12 * cap);
+            ALLOC(m, float, 11 * cap);
             S32 &s = ctx->s32[buf];
-            float **f[12] = {&s.xi, &s.eta, &s.zeta, &s.k, &s.l, &s.m, &s.dxi, &s.deta, &s.dz, &s.px, &s.py, &s.pz};
-            for (int q = 0; q < 12; q++) *f[q] = m + q * cap;
+            float **f[11] = {&s.xi, &s.eta, &s.zeta, &s.k, &s.l, &s.dxi, &s.deta, &s.dz, &s.px, &s.py, &s.pz};
+            for (int q = 0; q < 11; q++) *f[q] = m + q * cap;
+            ALLOC(s.m, double, cap);
             ALLOC(s.col, uint32_t, cap);
             ALLOC(s.lev, int32_t, cap);
             ALLOC(s.W, double, cap);

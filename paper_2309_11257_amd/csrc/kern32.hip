@@ -63,7 +63,7 @@ __global__ void k_load32(Grid g, rt_rays in, int64_t n, S32 d, uint32_t *key)
     d.zeta[i] = zeta;
     d.k[i] = (float)Y[3];
     d.l[i] = (float)Y[4];
-    d.m[i] = (float)Y[5];
+    d.m[i] = Y[5];
     d.dxi[i] = (float)(Y[6] / g.dx);
     d.deta[i] = (float)(Y[7] / g.dy);
     d.dz[i] = (float)Y[8];
@@ -209,7 +209,7 @@ struct Pay32 {
         const int jc = (int)((uint32_t)col / (uint32_t)g.nx), ic = col - jc * g.nx;
         const int kc = st.lev[s];
         const float zeta = st.zeta[s];
-        const float k = st.k[s], l = st.l[s], m = st.m[s];
+        const float k = st.k[s], l = st.l[s], m = (float)st.m[s];
         const float Dz = st.dz[s];
         float N2, f2;
         f32::n2_f2(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta, N2, f2);
@@ -243,7 +243,7 @@ struct Pay32 {
         const int ic = (int)(col % (uint32_t)g.nx), jc = (int)(col / (uint32_t)g.nx);
         float N2, f2;
         f32::n2_f2(g, b, ic, jc, st.lev[s], st.xi[s], st.eta[s], st.zeta[s], N2, f2);
-        const float k = st.k[s], l = st.l[s], m = st.m[s];
+        const float k = st.k[s], l = st.l[s], m = (float)st.m[s];
         const float kh2 = k * k + l * l;
         const float m2 = m * m;
         const float K2 = kh2 + m2;
@@ -251,7 +251,7 @@ struct Pay32 {
         const float sc = (N2 - f2) / (K2 * K2) / om;
         kd = k;
         ld = l;
-        md = m;
+        md = st.m[s];
         W = st.W[s];
         cgz = (double)(-m * kh2 * sc);
         z = ((double)st.lev[s] + (double)st.zeta[s]) * zdz;

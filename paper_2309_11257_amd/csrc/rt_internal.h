@@ -54,11 +54,16 @@ struct S64 {
 
 // single-precision state: horizontal position as column index + offset in
 // cell units, height as level index + offset in level units; extents Dx, Dy
-// in cell units, Dz in metres; wave action W in double
+// in cell units, Dz in metres.  The vertical wavenumber m and the wave
+// action W are held in double: m grows without bound towards a critical
+// level, and the single-precision rounding of its running sum (at every RK
+// stage, and once more when stored) is what single-precision state loses
+// most drag accuracy to; every operation on m is still single precision
 struct S32 {
     uint32_t *col;
     int32_t *lev;
-    float *xi, *eta, *zeta, *k, *l, *m, *dxi, *deta, *dz, *px, *py, *pz;
+    float *xi, *eta, *zeta, *k, *l, *dxi, *deta, *dz, *px, *py, *pz;
+    double *m;
     double *W;
     int64_t *id;
 };

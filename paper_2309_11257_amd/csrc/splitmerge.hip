@@ -195,7 +195,7 @@ struct IO32 {
         s.zeta[i] = (float)(r.z / g.dz - fk);
         s.k[i] = (float)r.k;
         s.l[i] = (float)r.l;
-        s.m[i] = (float)r.m;
+        s.m[i] = r.m;
         s.dxi[i] = (float)(r.dx / g.dx);
         s.deta[i] = (float)(r.dy / g.dy);
         s.dz[i] = (float)r.dz;

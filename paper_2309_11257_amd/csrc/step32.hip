@@ -39,15 +39,18 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
     // every volume of the wave lies in column cw (a volume's stored column is
     // its sort key)
     const int kc0 = valid ? f32::at(src.lev, s) : 0;
-    // the state's loads are in flight during the staging
+    // the state's loads are in flight during the staging; m is carried in
+    // double (md) and rounded to single precision for each stage's arithmetic
     float Y[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double md = 0.0;
     if (valid) {
         Y[0] = f32::at(src.xi, s);
         Y[1] = f32::at(src.eta, s);
         Y[2] = f32::at(src.zeta, s);
         Y[3] = f32::at(src.k, s);
         Y[4] = f32::at(src.l, s);
-        Y[5] = f32::at(src.m, s);
+        md = src.m[s];
+        Y[5] = (float)md;
         Y[6] = f32::at(src.dxi, s);
         Y[7] = f32::at(src.deta, s);
         Y[8] = f32::at(src.dz, s);
@@ -142,7 +145,15 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
 #pragma unroll
         for (int c = 0; c < 9; c++) {
             Q[c] = A[st] * Q[c] + dt * F[c];
-            Y[c] = Y[c] + B[st] * Q[c];
+            if (c == 5) {
+                // the running sum of m in double: its single-precision
+                // rounding at every stage would cost the drag more accuracy
+                // than everything else in the step together
+                md = md + (double)(B[st] * Q[5]);
+                Y[5] = (float)md;
+            } else {
+                Y[c] = Y[c] + B[st] * Q[c];
+            }
         }
     }
     // the fields carried unchanged are read while the post-step runs
@@ -210,7 +221,7 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
     f32::put(dst.zeta, i, Y[2]);
     f32::put(dst.k, i, Y[3]);
     f32::put(dst.l, i, Y[4]);
-    f32::put(dst.m, i, Y[5]);
+    dst.m[i] = md;
     f32::put(dst.dxi, i, Y[6]);
     f32::put(dst.deta, i, Y[7]);
     f32::put(dst.dz, i, Y[8]);

@@ -28,6 +28,25 @@ def gpu_tracer(w, precision, rays=None, capacity=None):
     return tr
 
 
+def record_metric(name, **values):
+    """Append one measured parity figure (an error and what it is compared
+    with) as a JSON line to $RT_PARITY_LOG, or to gpurun_out/parity_metrics.jsonl
+    under the repository root when that folder exists, so that every run's
+    margin is kept beside its log."""
+    import json
+    import os
+    path = os.environ.get("RT_PARITY_LOG")
+    if not path:
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        out = os.path.join(root, "gpurun_out")
+        if not os.path.isdir(out):
+            return
+        path = os.path.join(out, "parity_metrics.jsonl")
+    with open(path, "a") as f:
+        f.write(json.dumps({"test": name, **{k: (float(v) if isinstance(v, (np.floating, float)) else v)
+                                             for k, v in values.items()}}) + "\n")
+
+
 def rel_l2(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -41,10 +60,63 @@ def assert_flux_close(got, ref, rtol, what=""):
     assert err <= rtol * max(scale, 1e-300), f"{what}: max abs err {err:.3e} vs scale {scale:.3e}"
 
 
-def oracle_deposit_with_kernel_decisions(orc, bg, rs, gpu_rays, gpu_cols):
+def _face_distance(g, a, b, n, periodic):
+    """Distance, in cell units, from the fractional index g to the face(s)
+    shared by the adjacent cells a and b of one axis (periodic axes wrap, so
+    cells 0 and n - 1 share the face at 0 = n, and on a two-cell axis the
+    two cells share both faces)."""
+    faces = []
+    if abs(a - b) == 1:
+        faces.append(float(max(a, b)))
+    if periodic and {a, b} == {0, n - 1}:
+        faces += [0.0, float(n)]
+    return min(abs(g - f) for f in faces)
+
+
+def check_flips_at_faces(bg, rs, gpu_rays, cols, face_tol):
+    """Every ray whose parent column the kernel decided differently from the
+    oracle must sit at the face between the two columns: the columns are
+    neighbours (sharing a face or a corner) and both the oracle's position
+    and the kernel's position of that ray lie within face_tol cells of the
+    shared face(s).  A real indexing error (a ray put in a column it is not
+    next to, or a shifted key) fails here.  Returns the largest face
+    distance seen (0 if there are no flips)."""
+    idx = np.nonzero((cols != rs["col"]) & (cols >= 0))[0]
+    if idx.size == 0:
+        return 0.0
+    gid = np.asarray(gpu_rays["id"])
+    o = np.argsort(gid, kind="stable")
+    nx, ny = bg.nx, bg.ny
+    cart = bg.geometry == 0
+    worst = 0.0
+    for i in idx:
+        co, ck = int(rs["col"][i]), int(cols[i])
+        p = o[np.searchsorted(gid[o], rs["id"][i])]
+        pos = {"oracle": (rs["x"][i], rs["y"][i]), "kernel": (gpu_rays["x"][p], gpu_rays["y"][p])}
+        io, jo, ik, jk = co % nx, co // nx, ck % nx, ck // nx
+        for axis, a, b, n, org, d, periodic in (("x", io, ik, nx, bg.x0, bg.dx, True),
+                                                ("y", jo, jk, ny, bg.y0, bg.dy, cart)):
+            if a == b:
+                continue
+            step = abs(a - b)
+            assert step == 1 or (periodic and step == n - 1), \
+                f"ray id {rs['id'][i]}: kernel column {ck} is not next to the oracle's {co} ({axis})"
+            for who, (x, y) in pos.items():
+                g = ((x if axis == "x" else y) - org) / d
+                dist = _face_distance(g, a, b, n, periodic)
+                worst = max(worst, dist)
+                assert dist <= face_tol, (f"ray id {rs['id'][i]}: {who} position is {dist:.3e} cells from the "
+                                          f"{axis} face between columns {co} and {ck} (allowed {face_tol:.1e})")
+    return worst
+
+
+def oracle_deposit_with_kernel_decisions(orc, bg, rs, gpu_rays, gpu_cols, face_tol=2e-6):
     """Oracle fluxes of the oracle's own ray states, with the integer
     decisions (which rays are active, which column each belongs to) taken
-    from the kernel's output.  Returns (flux, n_column_flips, n_set_flips)."""
+    from the kernel's output where they differ.  A differing column decision
+    is accepted only for a ray that both sides place within face_tol cells
+    of the face between the two columns (check_flips_at_faces).  Returns
+    (flux, n_column_flips, n_set_flips)."""
     ids = rs["id"]
     active = rs.active()
     gid = np.asarray(gpu_rays["id"])
@@ -59,22 +131,26 @@ def oracle_deposit_with_kernel_decisions(orc, bg, rs, gpu_rays, gpu_cols):
     cols = np.where(found & active, gc[p] if gs.size else -1, -1)
     n_set = int((found != active).sum())
     flips = int(((cols != rs["col"]) & (cols >= 0)).sum())
+    check_flips_at_faces(bg, rs, gpu_rays, cols, face_tol)
     save = rs.a["state"][: rs.n].copy()
+    save_col = rs.a["col"][: rs.n].copy()
     rs.a["state"][: rs.n][active & ~found] = orc.INVALID
     flux = orc.deposit(bg, rs, cols=cols)
     rs.a["state"][: rs.n] = save
+    rs.a["col"][: rs.n] = save_col
     return flux, flips, n_set
 
 
 def fp32_representable(w, rays):
     """The ray set rounded to what the single-precision state can hold
-    exactly: wavenumbers, extents and phase-space areas to float32, horizontal
-    positions to (cell + float32 offset) and heights to (level + float32
-    offset).  Feeding these to both the oracle and the FP32 path isolates the
+    exactly: horizontal wavenumbers, extents and phase-space areas to
+    float32, horizontal positions to (cell + float32 offset) and heights to
+    (level + float32 offset); the vertical wavenumber is held in double
+    there.  Feeding these to both the oracle and the FP32 path isolates the
     error made inside the steps from the rounding of the inputs."""
     f32 = lambda a: np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
     r = {k: np.array(v, copy=True) for k, v in rays.items()}
-    for f in ("k", "l", "m", "dz", "px", "py", "pz"):
+    for f in ("k", "l", "dz", "px", "py", "pz"):
         r[f] = f32(r[f])
     gx = (r["x"] - w.x0) / w.dx
     i = np.clip(np.floor(gx), 0, w.nx - 1)

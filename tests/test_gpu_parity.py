@@ -8,7 +8,7 @@ import pytest
 
 from paper_2309_11257_amd import workloads as W
 from helpers import (EVOLVING, FIELDS, assert_flux_close, by_id, fp32_representable, gpu_tracer,
-                     oracle_deposit_with_kernel_decisions, oracle_run, rel_l2)
+                     oracle_deposit_with_kernel_decisions, oracle_run, record_metric, rel_l2)
 
 pytestmark = pytest.mark.gpu
 
@@ -149,11 +149,12 @@ def test_fp32_drag_within_1e5(rt, orc, name):
 
 def test_fp32_drag_after_100_steps(rt, orc):
     """100 steps of the jet box in single precision from inputs both sides
-    hold exactly, both taking the kernel's column decisions.  Over 100 steps
-    the flow amplifies any per-step rounding, so the gate is the larger of
-    1e-5 and 2.5 times the floor that storing the state in single precision
-    imposes by itself: the oracle's own drag when its state is rounded to
-    the single-precision layout after every step."""
+    hold exactly, the oracle taking the kernel's column decisions where a
+    volume sits at a cell face (both positions within 1e-4 cells of it).
+    Gated at 1e-5 relative L2.  The storage floor -- the oracle's own drag
+    when its state is rounded to the single-precision layout after every
+    step -- is reported beside the error (measured on the CPU at 9.3e-7
+    with m held in double, 6.3e-6 with m in single precision)."""
     w = c2_small(400)
     rays = fp32_representable(w, w.rays)
     bg = orc.Background.from_workload(w)
@@ -168,15 +169,18 @@ def test_fp32_drag_after_100_steps(rt, orc):
             fl.a[f][: fl.n] = r[f]
         tr.step(w.dt)
     g = tr.get_rays()
-    ref, flips, nset = oracle_deposit_with_kernel_decisions(orc, bg, rs, g, tr.get_columns())
-    assert nset == 0 and flips <= 0.001 * len(g["id"]), (flips, nset)
+    ocols = rs["col"].copy()
+    ref, flips, nset = oracle_deposit_with_kernel_decisions(orc, bg, rs, g, tr.get_columns(), face_tol=1e-4)
     dref = orc.drag(bg, ref)
-    floor = rel_l2(orc.drag(bg, orc.deposit(bg, fl, cols=np.where(fl.active(), rs["col"], -1))), orc.drag(bg, orc.deposit(bg, rs)))
+    floor = rel_l2(orc.drag(bg, orc.deposit(bg, fl, cols=np.where(fl.active() & rs.active(), ocols, -1))),
+                   orc.drag(bg, orc.deposit(bg, rs, cols=np.where(rs.active(), ocols, -1))))
     _, drag = tr.deposit(host=True)
     err = rel_l2(drag, dref)
+    record_metric("fp32_drag_after_100_steps", err=err, floor=floor, gate=1e-5, column_flips=flips,
+                  active_set_flips=nset, rays=len(g["id"]))
     print(f"fp32 drag error after 100 steps {err:.3e}; single-precision storage floor {floor:.3e}")
-    assert floor > 0
-    assert err <= max(1e-5, 2.5 * floor), (err, floor)
+    assert nset == 0 and flips <= 0.001 * len(g["id"]), (flips, nset)
+    assert err <= 1e-5, f"fp32 drag error after 100 steps {err:.3e} (storage floor {floor:.3e}) exceeds 1e-5"
 
 
 def test_deposit_is_deterministic(rt):

@@ -1,0 +1,73 @@
+"""The oracle's pins must catch the plausible slips they were written for.
+
+Each case plants one mistake in a copy of the oracle's C source (a dropped
+metric weight, a dropped or sign-flipped term, a moved threshold), builds it
+on the CPU, runs the named pins against the planted build and requires at
+least one of them to fail.  The real oracle is untouched and restored after
+each case.  CPU only."""
+import pytest
+
+import test_oracle_pins as P
+import test_oracle_pins_sphere as S
+
+MUTATIONS = [
+    ("spherical drag without the cos(phi) weight of the meridional flux",
+     "dphi = (cp * Fy[IDX(g, i, j + 1, k)] - cm * Fy[IDX(g, i, j - 1, k)]) / (2.0 * g->dy);",
+     "dphi = (Fy[IDX(g, i, j + 1, k)] - Fy[IDX(g, i, j - 1, k)]) / (2.0 * g->dy);",
+     [S.test_spherical_drag_closed_form]),
+    ("spherical drag with r = a instead of a + z",
+     "double r = g->a + ((double)k + 0.5) * g->dz;\n                        double cj",
+     "double r = g->a;\n                        double cj",
+     [S.test_spherical_drag_closed_form]),
+    ("spherical drag with the zonal term not divided by r cos(phi)",
+     "divx = ((Fx[IDX(g, ip, j, k)] - Fx[IDX(g, im, j, k)]) / (2.0 * g->dx)) / rc;",
+     "divx = ((Fx[IDX(g, ip, j, k)] - Fx[IDX(g, im, j, k)]) / (2.0 * g->dx)) / r;",
+     [S.test_spherical_drag_closed_form]),
+    ("meridional refraction without the (f^2)_phi term",
+     "gl = ((k * B[4] + l * B[7]) + q * B[10]) + qf * B[13];",
+     "gl = (k * B[4] + l * B[7]) + q * B[10];",
+     [S.test_sphere_rotating_refraction_matches_latitude_gradient]),
+    ("meridional refraction with the (f^2)_phi term's sign flipped",
+     "gl = ((k * B[4] + l * B[7]) + q * B[10]) + qf * B[13];",
+     "gl = ((k * B[4] + l * B[7]) + q * B[10]) - qf * B[13];",
+     [S.test_sphere_rotating_refraction_matches_latitude_gradient]),
+    ("meridional metric term k tan(phi) u / r with the wrong sign",
+     "F[4] = ((-gl) / r - (l * wc) / r) - ((k * tphi) * uc) / r;",
+     "F[4] = ((-gl) / r - (l * wc) / r) + ((k * tphi) * uc) / r;",
+     [S.test_sphere_rotating_refraction_matches_latitude_gradient]),
+    ("pole removal at 89.4 degrees",
+     "if (fabs(Y[1]) >= 89.5 * (3.14159265358979323846 / 180.0)) return ORC_GONE_POLE;",
+     "if (fabs(Y[1]) >= 89.4 * (3.14159265358979323846 / 180.0)) return ORC_GONE_POLE;",
+     [lambda orc: S.test_pole_removal_step_and_tally(orc, 1.0)]),
+    ("pole removal at 89.6 degrees",
+     "if (fabs(Y[1]) >= 89.5 * (3.14159265358979323846 / 180.0)) return ORC_GONE_POLE;",
+     "if (fabs(Y[1]) >= 89.6 * (3.14159265358979323846 / 180.0)) return ORC_GONE_POLE;",
+     [lambda orc: S.test_pole_removal_step_and_tally(orc, -1.0)]),
+    ("pole removal that does not tally the wave action",
+     "if (r->state[i] != ORC_INVALID) t->removed_W += ray_W(r, i);",
+     "if (r->state[i] != ORC_INVALID && r->state[i] != ORC_GONE_POLE) t->removed_W += ray_W(r, i);",
+     [lambda orc: S.test_pole_removal_step_and_tally(orc, 1.0)]),
+    ("spherical cell area without cos(phi)",
+     "return (((r * r) * cos(phi)) * g->dx) * g->dy;",
+     "return ((r * r) * g->dx) * g->dy;",
+     [lambda orc: P.test_deposit_matches_brute_force(orc, "sphere")]),
+]
+
+
+@pytest.mark.parametrize("case", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_slip(orc, tmp_path, case):
+    name, old, new, pins = case
+    src = orc.source_text()
+    assert src.count(old) == 1, f"the oracle source no longer holds the line this case edits: {old!r}"
+    path = orc.build_variant(src.replace(old, new), str(tmp_path / "liborc_variant.so"))
+    caught = []
+    with orc.using_library(path):
+        for pin in pins:
+            try:
+                pin(orc)
+            except AssertionError:
+                caught.append(pin)
+    assert caught, f"no pin caught the planted slip: {name}"
+    # the real oracle still passes the same pins
+    for pin in pins:
+        pin(orc)
