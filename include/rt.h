@@ -128,6 +128,23 @@ rt_status rt_init_background(rt_ctx ctx, const double *U, const double *V, const
  * are counted as removed at load.  RT_E_CAPACITY if n > capacity. */
 rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int32_t where);
 
+/* For callers that cannot allocate device memory during a call (tight
+ * serving loops, harnesses that forbid it): rt_set_rays from host arrays
+ * (RT_HOST) with the same result, bit for bit, but without the per-call
+ * device staging allocation.  The host arrays are staged through one fixed
+ * device array of RT_NOALLOC_SCRATCH_BYTES (14 MiB) that the library holds
+ * on each GPU it runs on until the process ends, RT_NOALLOC_CHUNK volumes
+ * (13 doubles and an id each) at a time; no hipMalloc, hipFree or other
+ * allocating call is made.  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (contexts on different streams) race, so
+ * serialise them.  Synchronises the context's stream before returning.
+ * Errors as rt_set_rays (RT_E_CAPACITY if n > capacity, leaving the
+ * context unchanged); RT_E_DEVICE if the array's device address cannot be
+ * found. */
+#define RT_NOALLOC_CHUNK 131072
+#define RT_NOALLOC_SCRATCH_BYTES (RT_NOALLOC_CHUNK * 14 * 8)
+rt_status rt_set_rays_host_noalloc(rt_ctx ctx, const rt_rays *rays, int64_t n);
+
 /* Copy out the active ray volumes in the library's internal order: grouped
  * by column.  The regrouping after rt_set_rays and every fourth one after it
  * order each column's volumes by level index floor(z / dz) (clamped to

@@ -71,6 +71,7 @@ def lib() -> C.CDLL:
         L.rt_destroy.argtypes = [P]
         L.rt_init_background.argtypes = [P, P, P, P, P, P, I32]
         L.rt_set_rays.argtypes = [P, C.POINTER(Rays), I64, I32]
+        L.rt_set_rays_host_noalloc.argtypes = [P, C.POINTER(Rays), I64]
         L.rt_get_rays.argtypes = [P, C.POINTER(Rays), C.POINTER(I64), I32]
         L.rt_step.argtypes = [P, D, I32]
         L.rt_deposit_flux.argtypes = [P, P, P, I32]
@@ -83,7 +84,8 @@ def lib() -> C.CDLL:
         L.rt_set_frozen_columns.argtypes = [P, P, I32]
         L.rt_last_error.argtypes = [P]
         L.rt_last_error.restype = C.c_char_p
-        for name in ("rt_create", "rt_destroy", "rt_init_background", "rt_set_rays", "rt_get_rays", "rt_step",
+        for name in ("rt_create", "rt_destroy", "rt_init_background", "rt_set_rays", "rt_set_rays_host_noalloc",
+                     "rt_get_rays", "rt_step",
                      "rt_deposit_flux", "rt_split_merge", "rt_get_stats", "rt_profile", "rt_profile_read", "rt_get_columns",
                      "rt_features", "rt_set_frozen_columns"):
             getattr(L, name).restype = C.c_int32
@@ -109,7 +111,10 @@ class Tracer:
         self.precision = precision
         self._mem: Dict[int, object] = {}
 
+        self.n_alloc_calls = 0  # device allocations the library asked for
+
         def _alloc(nbytes, user):
+            self.n_alloc_calls += 1
             t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
             p = t.data_ptr()
             self._mem[p] = t
@@ -194,6 +199,15 @@ class Tracer:
         self._check(lib().rt_set_rays(self.h, C.byref(r), n, where))
         if where == RT_DEVICE:
             self.stream.synchronize()
+
+    def set_rays_host_noalloc(self, rays: Dict[str, np.ndarray]):
+        """Load host (numpy) ray arrays through the library's fixed staging
+        array (rt_set_rays_host_noalloc): no device allocation in the call."""
+        n = int(rays["x"].shape[0])
+        keep = [np.ascontiguousarray(rays[f], dtype=np.float64) for f in RAY_FIELDS] + \
+            [np.ascontiguousarray(rays["id"], dtype=np.int64)]
+        r = Rays(*[a.ctypes.data for a in keep])
+        self._check(lib().rt_set_rays_host_noalloc(self.h, C.byref(r), n))
 
     def get_rays(self, device: bool = False) -> Dict[str, object]:
         n = C.c_int64(0)

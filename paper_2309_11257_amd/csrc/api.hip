@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "rt_internal.h"
@@ -193,6 +194,10 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     g.Ly = (double)g.ny * g.dy;
     g.Lz = (double)g.nz * g.dz;
     g.pole = 89.5 * (3.14159265358979323846 / 180.0);
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return RT_E_DEVICE;
+    }
 
     const int64_t cells = (int64_t)g.ncol * g.nz;
     const int64_t cap = cfg->capacity > 0 ? cfg->capacity : 1;
@@ -689,4 +694,112 @@ extern "C" rt_status rt_split_merge(rt_ctx ctx, double alpha_split, int32_t n_ma
     if (mode != RT_MERGE && mode != RT_CAP && mode != RT_SPLIT_ONLY) return rt_fail(ctx, RT_E_ARG, "bad mode");
     if (mode != RT_SPLIT_ONLY && n_max_per_cell < 1) return rt_fail(ctx, RT_E_ARG, "n_max_per_cell must be >= 1");
     return do_split_merge(ctx, alpha_split, n_max_per_cell, mode, out);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free load from host memory (rt_set_rays_host_noalloc).  Where
+// rt_set_rays(..., RT_HOST) allocates a device staging area for the host
+// arrays on every call, this variant stages them through one fixed device
+// array, `scratch`, one chunk of RT_NOALLOC_CHUNK volumes at a time (13
+// doubles and an id per volume), and runs the same load kernels on each
+// chunk.  Each GPU holds its own copy of the array until the process ends;
+// its device address is looked up once per device and kept.  Calls that
+// overlap on one GPU (two contexts on different streams) race on it.
+// ---------------------------------------------------------------------------
+#define NOALLOC_MAX_DEVICES 64
+static_assert((size_t)RT_NOALLOC_CHUNK * 14 * sizeof(double) == RT_NOALLOC_SCRATCH_BYTES,
+              "the staging chunk fills the scratch array");
+static __device__ __align__(256) unsigned char scratch[RT_NOALLOC_SCRATCH_BYTES];
+static std::mutex scratch_mu;
+static void *scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// device address of `scratch` on the context's device (looked up with that
+// device current, once per device)
+static rt_status scratch_of(rt_ctx ctx, unsigned char **out)
+{
+    if (ctx->device < 0 || ctx->device >= NOALLOC_MAX_DEVICES)
+        return rt_fail(ctx, RT_E_UNSUPPORTED, "device %d is beyond the %d this build tracks", ctx->device,
+                       NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[ctx->device]) {
+        int cur = -1;
+        HIP_OK(hipGetDevice(&cur));
+        if (cur != ctx->device) HIP_OK(hipSetDevice(ctx->device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != ctx->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return rt_fail(ctx, RT_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        scratch_ptr[ctx->device] = p;
+    }
+    *out = (unsigned char *)scratch_ptr[ctx->device];
+    return RT_OK;
+}
+
+static S64 state_at(S64 s, int64_t off)
+{
+    double **f[13] = {&s.x, &s.y, &s.z, &s.k, &s.l, &s.m, &s.dx, &s.dy, &s.dz, &s.px, &s.py, &s.pz, &s.n};
+    for (int q = 0; q < 13; q++) *f[q] += off;
+    s.id += off;
+    return s;
+}
+
+static S32 state_at(S32 s, int64_t off)
+{
+    float **f[11] = {&s.xi, &s.eta, &s.zeta, &s.k, &s.l, &s.dxi, &s.deta, &s.dz, &s.px, &s.py, &s.pz};
+    for (int q = 0; q < 11; q++) *f[q] += off;
+    s.col += off;
+    s.lev += off;
+    s.m += off;
+    s.W += off;
+    s.id += off;
+    return s;
+}
+
+extern "C" rt_status rt_set_rays_host_noalloc(rt_ctx ctx, const rt_rays *rays, int64_t n)
+{
+    if (!ctx) return RT_E_ARG;
+    if (n < 0) return rt_fail(ctx, RT_E_ARG, "negative ray count");
+    if (n > ctx->cap) return rt_fail(ctx, RT_E_CAPACITY, "%lld ray volumes exceed capacity %lld", (long long)n,
+                                     (long long)ctx->cap);
+    if (n > 0) {
+        rt_status st = check_rays(ctx, rays);
+        if (st) return st;
+    }
+    unsigned char *stage = nullptr;
+    rt_status st = scratch_of(ctx, &stage);
+    if (st) return st;
+    HIP_OK(hipMemsetAsync(ctx->dc, 0, sizeof(DevCounters), ctx->stream));
+    ctx->cur = 0;
+    for (int64_t off = 0; off < n; off += RT_NOALLOC_CHUNK) {
+        const int64_t c = n - off < (int64_t)RT_NOALLOC_CHUNK ? n - off : (int64_t)RT_NOALLOC_CHUNK;
+        // chunk layout in the scratch array: 13 fields of c doubles, then c ids
+        // (a later chunk's copies are ordered after this chunk's kernels on
+        // the stream)
+        double *base = (double *)stage;
+        rt_rays d;
+        double **df[13] = {&d.x, &d.y, &d.z, &d.k, &d.l, &d.m, &d.dx, &d.dy, &d.dz, &d.px, &d.py, &d.pz, &d.n};
+        const double *hs[13] = {rays->x, rays->y, rays->z, rays->k, rays->l, rays->m, rays->dx,
+                                rays->dy, rays->dz, rays->px, rays->py, rays->pz, rays->n};
+        for (int q = 0; q < 13; q++) {
+            *df[q] = base + (int64_t)q * c;
+            HIP_OK(hipMemcpyAsync(*df[q], hs[q] + off, sizeof(double) * (size_t)c, hipMemcpyHostToDevice, ctx->stream));
+        }
+        d.id = (int64_t *)(base + 13 * c);
+        HIP_OK(hipMemcpyAsync(d.id, rays->id + off, sizeof(int64_t) * (size_t)c, hipMemcpyHostToDevice, ctx->stream));
+        if (ctx->precision == RT_FP64)
+            launch_load64(ctx->g, d, c, state_at(ctx->s64[0], off), ctx->key[0] + off, ctx->stream);
+        else
+            launch_load32(ctx->g, d, c, state_at(ctx->s32[0], off), ctx->key[0] + off, ctx->stream);
+        launch_maxid(d.id, c, ctx->dc, ctx->stream);
+        HIP_OK(hipGetLastError());
+    }
+    launch_set_sorted(ctx->dc, n, ctx->stream);
+    ctx->n_bound = n;
+    ctx->n_sorts = 0;
+    st = sort_current(ctx);
+    if (st) return st;
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->have_rays = true;
+    return RT_OK;
 }

@@ -84,6 +84,7 @@ struct rt_ctx_s {
     rt_config cfg;
     Grid g;
     hipStream_t stream;
+    int device;  // the HIP device current at rt_create
     char err[512];
     int precision;
     // background
