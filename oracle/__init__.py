@@ -125,6 +125,7 @@ def _load(path: str) -> C.CDLL:
     L.orc_cap.argtypes = [P, P, C.c_int64, C.c_int32, P]
     L.orc_stats.argtypes = [P, C.c_int64, P]
     L.orc_features.argtypes = [P, P, C.c_int64, P]
+    L.orc_saturation.argtypes = [P, P, C.c_int64, C.c_double, P, P, P]
     L.orc_num_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [C.c_int]
     return L
@@ -306,6 +307,16 @@ def features(bg: Background, rs: RaySet, cols: Optional[np.ndarray] = None) -> n
     X = np.zeros((bg.nx * bg.ny, 3 * bg.nz + 48))
     lib().orc_features(bg.ref, rs.ref, rs.n, _ptr(X))
     return X
+
+
+def saturation(bg: Background, rs: RaySet, dt: float):
+    """Spectral saturation of the current state (orc_saturation): returns
+    (P, Q, kappa) on [nz][ny][nx] and damps the densities of the active
+    volumes in place."""
+    shape = (bg.nz, bg.ny, bg.nx)
+    P, Q, K = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+    lib().orc_saturation(bg.ref, rs.ref, rs.n, float(dt), _ptr(P), _ptr(Q), _ptr(K))
+    return P, Q, K
 
 
 def set_threads(n: int) -> None:

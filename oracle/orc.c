@@ -1085,3 +1085,129 @@ void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X)
             }
         }
 }
+
+/* ------------------------------------------------------------------------
+ * Spectral saturation (Section 3c, eq. instability-threshold and
+ * eq. turbulent-diffusivity).  Static instability is judged per grid cell
+ * from the spectrally integrated quantity
+ *   P = sum_j P_j,  P_j = (m^2 kh^2 / (omega_hat K^2)) A_j alpha_j,
+ * with A_j = N_j dk dl dm the volume's wave action per unit physical volume
+ * and alpha_j the fraction of the cell's volume the ray volume fills.  With
+ * the projection of the fluxes (the whole volume in its carrier's column,
+ * spread uniformly over its height) A_j alpha_j for level k is
+ *   W_j (o_jk / Dz_j) / (A_c dz),  W_j = N_j Px Py Pz,
+ * o_jk the overlap of [z - Dz/2, z + Dz/2] with the level.  omega_hat and K
+ * are those of the carrier (Gamma = 0).  Where P exceeds rho_k / 2 the
+ * turbulent diffusivity
+ *   kappa = max(0, (P - rho/2) / (2 dt sum_j P_j K_j^2))
+ * damps every volume there: N_j <- N_j (1 - 2 kappa K_j^2 dt).  A volume
+ * that covers several levels takes the overlap-weighted mean of kappa over
+ * them (levels outside the domain contribute nothing); the factor is held at
+ * 0 or above, so that N never turns negative (the paper's argument that it
+ * stays positive assumes the excess built up over one step).
+ * Outputs P, Q = sum_j P_j K_j^2 and kappa on [nz][ny][nx]; the densities of
+ * the active volumes are updated in place.  Order of summation as in
+ * orc_deposit: column ascending, ray index ascending, level ascending.
+ * ------------------------------------------------------------------------ */
+static double saturation_weight(const orc_bg *g, const orc_rays *r, int64_t i, double *K2out)
+{
+    double B[14], D[4];
+    double k = r->k[i], l = r->l[i], m = r->m[i];
+    double kh2 = k * k + l * l;
+    double m2 = m * m;
+    double K2 = kh2 + m2;
+    orc_interp(g, r->x[i], r->y[i], r->z[i], B);
+    orc_dispersion(B[2], B[12], k, l, m, D);
+    *K2out = K2;
+    return (m2 * kh2) / (D[0] * K2);
+}
+
+void orc_saturation(const orc_bg *g, orc_rays *r, int64_t n, double dt, double *P, double *Q, double *kappa)
+{
+    int ncol = g->nx * g->ny;
+    size_t cells = (size_t)g->nz * (size_t)ncol;
+    int64_t *start = (int64_t *)calloc((size_t)ncol + 1, sizeof(int64_t));
+    int64_t *fill = (int64_t *)calloc((size_t)ncol + 1, sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t i;
+    int c;
+    orc_keys(g, r, n);
+    memset(P, 0, cells * sizeof(double));
+    memset(Q, 0, cells * sizeof(double));
+    for (i = 0; i < n; i++)
+        if (r->state[i] == ORC_ACTIVE) start[r->col[i] + 1]++;
+    for (c = 0; c < ncol; c++) start[c + 1] += start[c];
+    for (i = 0; i < n; i++)
+        if (r->state[i] == ORC_ACTIVE) {
+            int cc = r->col[i];
+            order[start[cc] + fill[cc]] = i;
+            fill[cc]++;
+        }
+    /* per-cell sums */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (c = 0; c < ncol; c++) {
+        int ci = c % g->nx, cj = c / g->nx;
+        int64_t p;
+        for (p = start[c]; p < start[c + 1]; p++) {
+            int64_t j = order[p];
+            double K2;
+            double s = saturation_weight(g, r, j, &K2);
+            double W = ray_W(r, j);
+            double zb = r->z[j] - 0.5 * r->dz[j], zt = r->z[j] + 0.5 * r->dz[j];
+            int kk, klo = (int)floor(zb / g->dz), khi = (int)floor(zt / g->dz);
+            if (klo < 0) klo = 0;
+            if (khi > g->nz - 1) khi = g->nz - 1;
+            for (kk = klo; kk <= khi; kk++) {
+                double lo = (double)kk * g->dz, hi = (double)(kk + 1) * g->dz;
+                double o = (zt < hi ? zt : hi) - (zb > lo ? zb : lo);
+                double vol, aw;
+                size_t at;
+                if (!(o > 0.0)) continue;
+                vol = cell_area(g, cj, ((double)kk + 0.5) * g->dz) * g->dz;
+                aw = (W * (o / r->dz[j])) / vol;
+                at = IDX(g, ci, cj, kk);
+                P[at] += s * aw;
+                Q[at] += (s * K2) * aw;
+            }
+        }
+    }
+    /* turbulent diffusivity per cell */
+    {
+        size_t at;
+        for (at = 0; at < cells; at++) {
+            int kk = (int)(at / (size_t)ncol);
+            double ex = P[at] - 0.5 * g->rho[kk];
+            kappa[at] = (ex > 0.0 && Q[at] > 0.0) ? ex / ((2.0 * dt) * Q[at]) : 0.0;
+        }
+    }
+    /* damping of every active volume by its overlap-weighted kappa */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (i = 0; i < n; i++) {
+        int ci, cj, kk, klo, khi;
+        double zb, zt, kbar = 0.0, K2, fac;
+        if (r->state[i] != ORC_ACTIVE) continue;
+        ci = r->col[i] % g->nx;
+        cj = r->col[i] / g->nx;
+        zb = r->z[i] - 0.5 * r->dz[i];
+        zt = r->z[i] + 0.5 * r->dz[i];
+        klo = (int)floor(zb / g->dz);
+        khi = (int)floor(zt / g->dz);
+        if (klo < 0) klo = 0;
+        if (khi > g->nz - 1) khi = g->nz - 1;
+        for (kk = klo; kk <= khi; kk++) {
+            double lo = (double)kk * g->dz, hi = (double)(kk + 1) * g->dz;
+            double o = (zt < hi ? zt : hi) - (zb > lo ? zb : lo);
+            if (!(o > 0.0)) continue;
+            kbar += (o / r->dz[i]) * kappa[IDX(g, ci, cj, kk)];
+        }
+        if (kbar > 0.0) {
+            K2 = (r->k[i] * r->k[i] + r->l[i] * r->l[i]) + r->m[i] * r->m[i];
+            fac = 1.0 - ((2.0 * kbar) * K2) * dt;
+            if (fac < 0.0) fac = 0.0;
+            r->n[i] = r->n[i] * fac;
+        }
+    }
+    free(start);
+    free(fill);
+    free(order);
+}

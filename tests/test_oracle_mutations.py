@@ -9,8 +9,29 @@ import pytest
 
 import test_oracle_pins as P
 import test_oracle_pins_sphere as S
+import test_oracle_saturation as T
 
 MUTATIONS = [
+    ("saturation weight without kh^2",
+     "return (m2 * kh2) / (D[0] * K2);",
+     "return m2 / (D[0] * K2);",
+     [lambda orc: T.test_monochromatic_limit(orc, 1.5)]),
+    ("saturation threshold rho instead of rho/2",
+     "double ex = P[at] - 0.5 * g->rho[kk];",
+     "double ex = P[at] - g->rho[kk];",
+     [lambda orc: T.test_monochromatic_limit(orc, 1.5)]),
+    ("saturation factor 1 - kappa K^2 dt (factor 2 dropped)",
+     "fac = 1.0 - ((2.0 * kbar) * K2) * dt;",
+     "fac = 1.0 - (kbar * K2) * dt;",
+     [T.test_threshold_restored_in_each_cell]),
+    ("saturation factor not held at zero",
+     "if (fac < 0.0) fac = 0.0;",
+     ";",
+     [T.test_density_never_negative_and_dt_independent]),
+    ("saturation kappa not weighted by the overlap fraction",
+     "kbar += (o / r->dz[i]) * kappa[IDX(g, ci, cj, kk)];",
+     "kbar += kappa[IDX(g, ci, cj, kk)];",
+     [lambda orc: T.test_saturation_matches_brute_force(orc, "box")]),
     ("spherical drag without the cos(phi) weight of the meridional flux",
      "dphi = (cp * Fy[IDX(g, i, j + 1, k)] - cm * Fy[IDX(g, i, j - 1, k)]) / (2.0 * g->dy);",
      "dphi = (Fy[IDX(g, i, j + 1, k)] - Fy[IDX(g, i, j - 1, k)]) / (2.0 * g->dy);",
