@@ -53,7 +53,7 @@ enum {
 enum { RT_CARTESIAN = 0, RT_SPHERICAL = 1 };
 enum { RT_FP64 = 0, RT_FP32 = 1 };
 enum { RT_HOST = 0, RT_DEVICE = 1 };
-enum { RT_STEP_DEPOSIT = 1, RT_STEP_SURROGATE = 2 };
+enum { RT_STEP_DEPOSIT = 1, RT_STEP_SURROGATE = 2, RT_STEP_SATURATE = 4 };
 enum { RT_MERGE = 0, RT_CAP = 1, RT_SPLIT_ONLY = 2 };
 
 typedef struct {
@@ -173,8 +173,27 @@ rt_status rt_get_columns(rt_ctx ctx, uint32_t *cols, int64_t *n_inout, int32_t w
  * see there).  With RT_STEP_SURROGATE the volumes whose parent column is
  * flagged by rt_set_frozen_columns keep their state unchanged for this step
  * (the column surrogate supplies that column's drag; RT_E_STATE if no flags
- * were set).  No synchronisation. */
+ * were set).  With RT_STEP_SATURATE the regrouped set is saturated with the
+ * same dt (rt_saturate) before any deposition (RT_E_ARG unless dt > 0).
+ * No synchronisation. */
 rt_status rt_step(rt_ctx ctx, double dt, int32_t flags);
+
+/* Spectral saturation of the current set (Section 3c, eq.
+ * instability-threshold and eq. turbulent-diffusivity).  Per grid cell,
+ *   P = sum_j (m^2 kh^2 / (omega_hat K^2)) A_j alpha_j  and  Q = sum_j P_j K^2,
+ * where A_j alpha_j for a level is the volume's wave action W = N Px Py Pz
+ * times its overlap fraction with the level, divided by the cell volume
+ * (the volume counts in its carrier's column, as for the fluxes); omega_hat
+ * and K^2 = k^2 + l^2 + m^2 at the carrier (Gamma = 0).  Then
+ *   kappa = max(0, (P - rho/2) / (2 dt Q))
+ * per cell, and every active volume's density is multiplied by
+ * max(0, 1 - 2 kbar K^2 dt), kbar the overlap-weighted mean of kappa over
+ * the levels it covers (parts outside the domain count as kappa = 0).  The
+ * sums are deterministic (bitwise identical between runs).
+ *   kappa  [nz][ny][nx] double, the turbulent diffusivity (m^2/s); may be NULL
+ * RT_E_ARG unless dt > 0 and finite; RT_E_STATE before a background and a
+ * ray set.  No synchronisation unless kappa is given with RT_HOST. */
+rt_status rt_saturate(rt_ctx ctx, double dt, double *kappa, int32_t where);
 
 /* Column flags for RT_STEP_SURROGATE: mask [ny*nx] uint8 (column j*nx + i),
  * 1 = frozen.  NULL clears all flags.  Copied on the stream (synchronises

@@ -125,7 +125,7 @@ def _load(path: str) -> C.CDLL:
     L.orc_cap.argtypes = [P, P, C.c_int64, C.c_int32, P]
     L.orc_stats.argtypes = [P, C.c_int64, P]
     L.orc_features.argtypes = [P, P, C.c_int64, P]
-    L.orc_saturation.argtypes = [P, P, C.c_int64, C.c_double, P, P, P]
+    L.orc_saturation.argtypes = [P, P, C.c_int64, C.c_double, P, P, P, C.c_int]
     L.orc_num_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [C.c_int]
     return L
@@ -309,13 +309,17 @@ def features(bg: Background, rs: RaySet, cols: Optional[np.ndarray] = None) -> n
     return X
 
 
-def saturation(bg: Background, rs: RaySet, dt: float):
+def saturation(bg: Background, rs: RaySet, dt: float, cols: Optional[np.ndarray] = None):
     """Spectral saturation of the current state (orc_saturation): returns
     (P, Q, kappa) on [nz][ny][nx] and damps the densities of the active
-    volumes in place."""
+    volumes in place.  `cols` as in deposit()."""
     shape = (bg.nz, bg.ny, bg.nx)
     P, Q, K = np.zeros(shape), np.zeros(shape), np.zeros(shape)
-    lib().orc_saturation(bg.ref, rs.ref, rs.n, float(dt), _ptr(P), _ptr(Q), _ptr(K))
+    if cols is not None:
+        cols = np.asarray(cols, dtype=np.int32)
+        assert cols.shape == (rs.n,)
+        rs.a["col"][: rs.n] = cols
+    lib().orc_saturation(bg.ref, rs.ref, rs.n, float(dt), _ptr(P), _ptr(Q), _ptr(K), 0 if cols is None else 1)
     return P, Q, K
 
 

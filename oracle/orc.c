@@ -1106,7 +1106,9 @@ void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X)
  * 0 or above, so that N never turns negative (the paper's argument that it
  * stays positive assumes the excess built up over one step).
  * Outputs P, Q = sum_j P_j K_j^2 and kappa on [nz][ny][nx]; the densities of
- * the active volumes are updated in place.  Order of summation as in
+ * the active volumes are updated in place.  With given_cols the column keys
+ * already in r->col are used (the parity tests hand in a lower-precision
+ * path's decision for a volume at a cell face), else they are computed.  Order of summation as in
  * orc_deposit: column ascending, ray index ascending, level ascending.
  * ------------------------------------------------------------------------ */
 static double saturation_weight(const orc_bg *g, const orc_rays *r, int64_t i, double *K2out)
@@ -1122,7 +1124,8 @@ static double saturation_weight(const orc_bg *g, const orc_rays *r, int64_t i, d
     return (m2 * kh2) / (D[0] * K2);
 }
 
-void orc_saturation(const orc_bg *g, orc_rays *r, int64_t n, double dt, double *P, double *Q, double *kappa)
+void orc_saturation(const orc_bg *g, orc_rays *r, int64_t n, double dt, double *P, double *Q, double *kappa,
+                    int given_cols)
 {
     int ncol = g->nx * g->ny;
     size_t cells = (size_t)g->nz * (size_t)ncol;
@@ -1131,7 +1134,7 @@ void orc_saturation(const orc_bg *g, orc_rays *r, int64_t n, double dt, double *
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     int64_t i;
     int c;
-    orc_keys(g, r, n);
+    if (!given_cols) orc_keys(g, r, n);
     memset(P, 0, cells * sizeof(double));
     memset(Q, 0, cells * sizeof(double));
     for (i = 0; i < n; i++)

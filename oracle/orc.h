@@ -80,7 +80,8 @@ void orc_merge(const orc_bg *g, orc_rays *r, int64_t n, int32_t n_max, orc_tally
 void orc_cap(const orc_bg *g, orc_rays *r, int64_t n, int32_t n_max, orc_tally *t);
 void orc_stats(const orc_rays *r, int64_t n, orc_tally *t);
 void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X);
-void orc_saturation(const orc_bg *g, orc_rays *r, int64_t n, double dt, double *P, double *Q, double *kappa);
+void orc_saturation(const orc_bg *g, orc_rays *r, int64_t n, double dt, double *P, double *Q, double *kappa,
+                    int given_cols);
 int orc_num_threads(void);
 void orc_set_threads(int n);
 

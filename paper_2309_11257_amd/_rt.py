@@ -20,7 +20,7 @@ RT_OK, RT_E_ARG, RT_E_STATE, RT_E_NOMEM, RT_E_CAPACITY, RT_E_DEVICE, RT_E_NUMERI
 RT_CARTESIAN, RT_SPHERICAL = 0, 1
 RT_FP64, RT_FP32 = 0, 1
 RT_HOST, RT_DEVICE = 0, 1
-RT_STEP_DEPOSIT, RT_STEP_SURROGATE = 1, 2
+RT_STEP_DEPOSIT, RT_STEP_SURROGATE, RT_STEP_SATURATE = 1, 2, 4
 RT_MERGE, RT_CAP, RT_SPLIT_ONLY = 0, 1, 2
 
 RAY_FIELDS = ("x", "y", "z", "k", "l", "m", "dx", "dy", "dz", "px", "py", "pz", "n")
@@ -75,6 +75,7 @@ def lib() -> C.CDLL:
         L.rt_get_rays.argtypes = [P, C.POINTER(Rays), C.POINTER(I64), I32]
         L.rt_step.argtypes = [P, D, I32]
         L.rt_deposit_flux.argtypes = [P, P, P, I32]
+        L.rt_saturate.argtypes = [P, D, P, I32]
         L.rt_split_merge.argtypes = [P, D, I32, I32, C.POINTER(Stats)]
         L.rt_get_stats.argtypes = [P, C.POINTER(Stats)]
         L.rt_get_columns.argtypes = [P, P, C.POINTER(I64), I32]
@@ -87,7 +88,7 @@ def lib() -> C.CDLL:
         for name in ("rt_create", "rt_destroy", "rt_init_background", "rt_set_rays", "rt_set_rays_host_noalloc",
                      "rt_get_rays", "rt_step",
                      "rt_deposit_flux", "rt_split_merge", "rt_get_stats", "rt_profile", "rt_profile_read", "rt_get_columns",
-                     "rt_features", "rt_set_frozen_columns"):
+                     "rt_features", "rt_set_frozen_columns", "rt_saturate"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -241,9 +242,24 @@ class Tracer:
         self._check(lib().rt_get_columns(self.h, out.ctypes.data, C.byref(n2), RT_HOST))
         return out[: n2.value]
 
-    def step(self, dt: float, deposit: bool = False, surrogate: bool = False):
-        flags = (RT_STEP_DEPOSIT if deposit else 0) | (RT_STEP_SURROGATE if surrogate else 0)
+    def step(self, dt: float, deposit: bool = False, surrogate: bool = False, saturate: bool = False):
+        flags = ((RT_STEP_DEPOSIT if deposit else 0) | (RT_STEP_SURROGATE if surrogate else 0)
+                 | (RT_STEP_SATURATE if saturate else 0))
         self._check(lib().rt_step(self.h, float(dt), flags))
+
+    def saturate(self, dt: float, host: bool = False, kappa=None):
+        """Spectral saturation of the current set (rt_saturate); returns the
+        turbulent diffusivity [nz, ny, nx] float64 (a CUDA tensor, or numpy
+        with host=True)."""
+        shape = (self.nz, self.ny, self.nx)
+        if host:
+            K = np.zeros(shape) if kappa is None else kappa
+            self._check(lib().rt_saturate(self.h, float(dt), K.ctypes.data, RT_HOST))
+            return K
+        torch = self.torch
+        K = torch.empty(shape, dtype=torch.float64, device=self.device) if kappa is None else kappa
+        self._check(lib().rt_saturate(self.h, float(dt), K.data_ptr(), RT_DEVICE))
+        return K
 
     def set_frozen_columns(self, mask=None):
         """Column flags [ny*nx] (uint8, 1 = frozen) for step(surrogate=True):
@@ -296,7 +312,7 @@ class Tracer:
         self._check(lib().rt_split_merge(self.h, float(alpha), int(n_max), int(mode), C.byref(s)))
         return s.as_dict()
 
-    PROFILE_CLASSES = ("step", "sort", "deposit", "drag", "split_merge", "stats", "c6", "c7")
+    PROFILE_CLASSES = ("step", "sort", "deposit", "drag", "split_merge", "stats", "saturation", "c7")
 
     def profile(self, on: bool = True):
         self._check(lib().rt_profile(self.h, 1 if on else 0))

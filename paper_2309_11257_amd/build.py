@@ -27,6 +27,7 @@ SOURCES = {
     "step32.hip": ["-ffp-contract=fast"],
     "sort.hip": ["-ffp-contract=off"],
     "drag.hip": ["-ffp-contract=off"],
+    "saturation.hip": ["-ffp-contract=off"],
     "splitmerge.hip": ["-ffp-contract=off"],
     "mlp.hip": ["-ffp-contract=fast"],
 }

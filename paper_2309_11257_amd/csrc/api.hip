@@ -277,6 +277,8 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     if (cfg->precision == RT_FP32) ALLOC(ctx->wcol, uint32_t, wave_table_len(cap, g.ncol));
     ALLOC(ctx->flux, double, (int64_t)6 * (g.nz + 1) * g.ncol);
     ALLOC(ctx->drag, double, 2 * cells);
+    ALLOC(ctx->satpq, double, (int64_t)2 * (g.nz + 1) * g.ncol);
+    ALLOC(ctx->kappa, double, cells);
     ALLOC(ctx->frozen, uint8_t, g.ncol);
     ALLOC(ctx->coslat, double, g.ny);
     ALLOC(ctx->dc, DevCounters, 1);
@@ -488,7 +490,9 @@ extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
     if (!ctx->have_bg) return rt_fail(ctx, RT_E_STATE, "rt_init_background has not been called");
     if (!ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "rt_set_rays has not been called");
     if (!std::isfinite(dt)) return rt_fail(ctx, RT_E_ARG, "dt must be finite");
-    if (flags & ~(RT_STEP_DEPOSIT | RT_STEP_SURROGATE)) return rt_fail(ctx, RT_E_ARG, "unknown rt_step flags");
+    if (flags & ~(RT_STEP_DEPOSIT | RT_STEP_SURROGATE | RT_STEP_SATURATE))
+        return rt_fail(ctx, RT_E_ARG, "unknown rt_step flags");
+    if ((flags & RT_STEP_SATURATE) && !(dt > 0.0)) return rt_fail(ctx, RT_E_ARG, "saturation needs dt > 0");
     if ((flags & RT_STEP_SURROGATE) && !ctx->have_frozen)
         return rt_fail(ctx, RT_E_STATE, "RT_STEP_SURROGATE needs rt_set_frozen_columns first");
     const uint8_t *frozen = (flags & RT_STEP_SURROGATE) ? ctx->frozen : nullptr;
@@ -505,7 +509,36 @@ extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
     ctx->cur = nxt;
     rt_status st = sort_current(ctx);
     if (st) return st;
+    if (flags & RT_STEP_SATURATE) {
+        st = rt_saturate(ctx, dt, nullptr, RT_DEVICE);
+        if (st) return st;
+    }
     if (flags & RT_STEP_DEPOSIT) return rt_deposit_flux(ctx, nullptr, nullptr, RT_DEVICE);
+    return RT_OK;
+}
+
+extern "C" rt_status rt_saturate(rt_ctx ctx, double dt, double *kappa, int32_t where)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return rt_fail(ctx, RT_E_ARG, "dt must be positive and finite");
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    const Grid &g = ctx->g;
+    prof_begin(ctx, PC_SAT);
+    if (ctx->precision == RT_FP64)
+        launch_saturation64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->colstart, ctx->dc, ctx->rho,
+                            dt, ctx->satpq, ctx->kappa, ctx->n_bound, ctx->stream);
+    else
+        launch_saturation32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->skeys, ctx->colstart, ctx->dc, ctx->rho,
+                            dt, ctx->satpq, ctx->kappa, ctx->n_bound, ctx->stream);
+    prof_end(ctx);
+    HIP_OK(hipGetLastError());
+    if (kappa) {
+        const size_t n = (size_t)g.nz * g.ncol;
+        HIP_OK(hipMemcpyAsync(kappa, ctx->kappa, sizeof(double) * n,
+                              where == RT_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, ctx->stream));
+        if (where == RT_HOST) HIP_OK(hipStreamSynchronize(ctx->stream));
+    }
     return RT_OK;
 }
 

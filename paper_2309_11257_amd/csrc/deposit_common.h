@@ -17,7 +17,10 @@
 // contributions in double, level by level, in a fixed order (see the chunk
 // loop).  At the end the finished profiles are written together, so that the
 // columns of one (field, level) row form one contiguous segment of the
-// [6][nz+1][ncol] output.
+// [NF][nz+1][ncol] output.  The payload decides the fields: P::NL fields
+// spread over the levels the volume overlaps (cell means) and P::NI over the
+// staggered interface cells (the flux deposition: 4 horizontal and 2
+// vertical pseudo-momentum fluxes; the saturation sums: 2 level fields).
 #pragma once
 #include "rt_internal.h"
 
@@ -41,33 +44,47 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// P::load(slot, column, zb, zt, bv[6]) fills the vertical span of the volume
-// (in the column the sort grouped it in) and its
-// six flux densities per unit height: (cgx k, cgx l, cgy k, cgy l, cgz k,
-// cgz l) * W / Dz.
+// P::load(slot, column, zb, zt, bv[NF]) fills the vertical span of the volume
+// (in the column the sort grouped it in) and its NF densities per unit
+// height (for the fluxes: (cgx k, cgx l, cgy k, cgy l, cgz k, cgz l) * W / Dz).
+//
+// Each wave owns dep_wave_words() 64-bit words of LDS: its integer profile
+// [NF][nzp] and, in the register-profile mode, the staging of a chunk for the
+// level-parallel path ((2 + NF) x 64 words).
 //
 // RP: with at most 128 levels and interfaces the double profile of a wave's
-// column lives in registers (lane j holds levels j and j + 64 of the six
-// fields), which halves the LDS of a workgroup; at the end it is stored over
-// the wave's integer profile (all zero by then) for the common write-out.
+// column lives in registers (lane j holds levels j and j + 64 of every
+// field), which halves the LDS of a workgroup; at the end it is stored over
+// the wave's own integer profile (all zero by then) for the common write-out.
+template <class P, bool RP>
+__host__ __device__ inline int dep_wave_words(int nzp)
+{
+    constexpr int NF = P::NL + P::NI;
+    return RP ? max(NF * nzp, (2 + NF) * 64) : NF * nzp;
+}
+
 template <class P, int CPW, bool RP>
 __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, const uint32_t *__restrict__ perm,
                                                       const uint32_t *__restrict__ colstart, double *__restrict__ flux)
 {
+    constexpr int NL = P::NL, NF = P::NL + P::NI;
+    static_assert(NF % 2 == 0 && NF <= 16, "fields are reduced in pairs");
     extern __shared__ unsigned long long dep_smem[];
     const int nzp = g.nz + 1;
+    const int WR = dep_wave_words<P, RP>(nzp);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    unsigned long long *acc = dep_smem + (size_t)wave * 6 * nzp;  // this wave's [6][nzp]
-    // [CPW][6][nzp] finished profiles: after the integer ones, or over them
-    double *profs = (double *)(dep_smem + (RP ? 0 : (size_t)CPW * 6 * nzp));
-    double *prof = profs + (size_t)wave * 6 * nzp;
-    double preg[6][2];
+    unsigned long long *acc = dep_smem + (size_t)wave * WR;  // this wave's [NF][nzp]
+    // [CPW][NF][nzp] finished profiles (stride WR): after the integer ones, or
+    // over each wave's own
+    double *profs = (double *)(dep_smem + (RP ? 0 : (size_t)CPW * WR));
+    double *prof = profs + (size_t)wave * WR;
+    double preg[NF][2];
 #pragma unroll
-    for (int q = 0; q < 6; q++) preg[q][0] = preg[q][1] = 0.0;
+    for (int q = 0; q < NF; q++) preg[q][0] = preg[q][1] = 0.0;
     const int c_first = blockIdx.x * CPW;
     const int ncols = min(CPW, g.ncol - c_first);
-    for (int e = lane; e < 6 * nzp; e += 64) {
+    for (int e = lane; e < WR; e += 64) {
         acc[e] = 0ull;
         if (!RP) prof[e] = 0.0;
     }
@@ -78,7 +95,9 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
         for (uint32_t base = s0; base < s1; base += 64) {
             const uint32_t r = base + (uint32_t)lane;
             const bool valid = r < s1;
-            double zb = 0.0, zt = 0.0, bv[6] = {0, 0, 0, 0, 0, 0};
+            double zb = 0.0, zt = 0.0, bv[NF];
+#pragma unroll
+            for (int q = 0; q < NF; q++) bv[q] = 0.0;
             if (valid) pl.load(perm[r], c, zb, zt, bv);
             // the levels (lo .. hi) and interfaces (lo2 .. hi2) the volume
             // overlaps, in level units: the double-precision payload divides
@@ -92,11 +111,13 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                 const double ztl = P::EXACT_LEVELS ? zt / g.dz : zt * pl.inv_dz;
                 lo = max((int)floor(zbl), 0);
                 hi = min((int)floor(ztl), g.nz - 1);
-                lo2 = max((int)floor(zbl + 0.5), 0);
-                hi2 = min((int)floor(ztl + 0.5), g.nz);
+                if (P::NI > 0) {
+                    lo2 = max((int)floor(zbl + 0.5), 0);
+                    hi2 = min((int)floor(ztl + 0.5), g.nz);
+                }
             }
             const int k0 = wave_min_i(min(lo, lo2)), k1 = wave_max_i(max(hi, hi2));
-            if (RP && 6 * nzp >= 8 * 64 && k1 - k0 < 8) {
+            if (RP && k1 - k0 < 8) {
                 // Chunk within eight levels (a column sorted by level): lane
                 // 8 g + s takes level (and interface) k0 + s for the volumes g,
                 // g + 8, ..., g + 56 of the chunk, read from the wave's LDS
@@ -107,7 +128,7 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                 vd[lane] = zb;
                 vd[64 + lane] = zt;
 #pragma unroll
-                for (int q = 0; q < 6; q++) vd[128 + 64 * q + lane] = bv[q];
+                for (int q = 0; q < NF; q++) vd[128 + 64 * q + lane] = bv[q];
                 wave_sync();
                 const int sl8 = lane & 7, gi = lane >> 3, k = k0 + sl8;
                 const double lv = (double)k * g.dz, hv = (double)(k + 1) * g.dz;
@@ -115,7 +136,9 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                 if (lv2 < 0.0) lv2 = 0.0;
                 if (hv2 > g.Lz) hv2 = g.Lz;
                 const bool lev_ok = k <= g.nz - 1, itf_ok = k <= g.nz;
-                double sm[6] = {0, 0, 0, 0, 0, 0};
+                double sm[NF];
+#pragma unroll
+                for (int q = 0; q < NF; q++) sm[q] = 0.0;
 #pragma unroll
                 for (int i = 0; i < 8; i++) {
                     const int j = gi + 8 * i;
@@ -125,12 +148,12 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                     o = (lev_ok && o > 0.0) ? o : 0.0;
                     o2 = (itf_ok && o2 > 0.0) ? o2 : 0.0;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) sm[q] += vd[128 + 64 * q + j] * o;
+                    for (int q = 0; q < NL; q++) sm[q] += vd[128 + 64 * q + j] * o;
 #pragma unroll
-                    for (int q = 4; q < 6; q++) sm[q] += vd[128 + 64 * q + j] * o2;
+                    for (int q = NL; q < NF; q++) sm[q] += vd[128 + 64 * q + j] * o2;
                 }
 #pragma unroll
-                for (int q = 0; q < 6; q++)
+                for (int q = 0; q < NF; q++)
 #pragma unroll
                     for (int off = 8; off < 64; off <<= 1) sm[q] += __shfl_xor(sm[q], off, 64);
                 // level k0 + s (held by lanes s < 8) to the lane that keeps it:
@@ -138,23 +161,23 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                 const int src = (lane - k0) & 63;
                 const bool take = src < 8, hi_slot = k0 + src >= 64;
 #pragma unroll
-                for (int q = 0; q < 6; q++) {
+                for (int q = 0; q < NF; q++) {
                     const double v = __shfl(sm[q], src, 64);
                     preg[q][0] += (take && !hi_slot) ? v : 0.0;
                     preg[q][1] += (take && hi_slot) ? v : 0.0;
                 }
                 wave_sync();
 #pragma unroll
-                for (int t = 0; t < 8; t++) acc[64 * t + lane] = 0ull;
+                for (int t = 0; t < 2 + NF; t++) acc[64 * t + lane] = 0ull;
                 wave_sync();
                 continue;
             }
             const double h = valid ? fmin(zt - zb, g.dz) : 0.0;
             // per field: the largest possible contribution of the chunk sets
             // the fixed-point scale (a bound on each |bv * overlap|)
-            int sx[6];
+            int sx[NF];
 #pragma unroll
-            for (int q = 0; q < 6; q += 2) {
+            for (int q = 0; q < NF; q += 2) {
                 // two 11-bit exponents per reduction
                 const uint32_t pm = wave_max_u16x2(((uint32_t)bexp(fabs(bv[q]) * h) << 16) |
                                                    (uint32_t)bexp(fabs(bv[q + 1]) * h));
@@ -175,23 +198,25 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                     const double o = fmin(zt, hv) - fmax(zb, lv);
                     if (!(o > 0.0)) continue;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
+                    for (int q = 0; q < NL; q++) {
                         const long long v = to_fixed(bv[q] * o, sx[q]);
                         if (v) atomicAdd(&acc[q * nzp + kk], (unsigned long long)v);
                     }
                 }
-                const int nk2 = hi2 - lo2 + 1;
-                kk = nk2 > 0 ? lo2 + lane % nk2 : lo2;
-                for (int t = 0; t < nk2; t++, kk = kk == hi2 ? lo2 : kk + 1) {
-                    double lv = ((double)kk - 0.5) * g.dz, hv = ((double)kk + 0.5) * g.dz;
-                    if (lv < 0.0) lv = 0.0;
-                    if (hv > g.Lz) hv = g.Lz;
-                    const double o = fmin(zt, hv) - fmax(zb, lv);
-                    if (!(o > 0.0)) continue;
+                if (P::NI > 0) {
+                    const int nk2 = hi2 - lo2 + 1;
+                    kk = nk2 > 0 ? lo2 + lane % nk2 : lo2;
+                    for (int t = 0; t < nk2; t++, kk = kk == hi2 ? lo2 : kk + 1) {
+                        double lv = ((double)kk - 0.5) * g.dz, hv = ((double)kk + 0.5) * g.dz;
+                        if (lv < 0.0) lv = 0.0;
+                        if (hv > g.Lz) hv = g.Lz;
+                        const double o = fmin(zt, hv) - fmax(zb, lv);
+                        if (!(o > 0.0)) continue;
 #pragma unroll
-                    for (int q = 4; q < 6; q++) {
-                        const long long v = to_fixed(bv[q] * o, sx[q]);
-                        if (v) atomicAdd(&acc[q * nzp + kk], (unsigned long long)v);
+                        for (int q = NL; q < NF; q++) {
+                            const long long v = to_fixed(bv[q] * o, sx[q]);
+                            if (v) atomicAdd(&acc[q * nzp + kk], (unsigned long long)v);
+                        }
                     }
                 }
             }
@@ -204,7 +229,7 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                     const int kk = lane + 64 * sl;
                     if (kk >= k0 && kk <= k1) {
 #pragma unroll
-                        for (int q = 0; q < 6; q++) {
+                        for (int q = 0; q < NF; q++) {
                             const int at = q * nzp + kk;
                             const long long v = (long long)acc[at];
                             if (v) {
@@ -216,14 +241,14 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
                 }
             } else if (k1 >= k0) {
                 const int span = k1 - k0 + 1;
-                for (int e = lane; e < 6 * span; e += 64) {
+                for (int e = lane; e < NF * span; e += 64) {
                     const int q = e / span, kk = k0 + e % span;
                     const int at = q * nzp + kk;
                     const long long v = (long long)acc[at];
                     if (v) {
                         int sq = sx[0];
 #pragma unroll
-                        for (int t = 1; t < 6; t++) sq = q == t ? sx[t] : sq;
+                        for (int t = 1; t < NF; t++) sq = q == t ? sx[t] : sq;
                         prof[at] += ldexp((double)v, -sq);
                         acc[at] = 0ull;
                     }
@@ -239,7 +264,7 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
             const int kk = lane + 64 * sl;
             if (kk < nzp) {
 #pragma unroll
-                for (int q = 0; q < 6; q++) prof[q * nzp + kk] = preg[q][sl];
+                for (int q = 0; q < NF; q++) prof[q * nzp + kk] = preg[q][sl];
             }
         }
     }
@@ -252,12 +277,12 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
     const int c = c_first + cl;
     const double area_h = g.dx * g.dy;
     const double cphi = g.geometry == RT_SPHERICAL ? cos(g.y0 + ((double)(c / g.nx) + 0.5) * g.dy) : 1.0;
-    for (int e = tid; e < CPW * 6 * nzp; e += 64 * CPW) {
+    for (int e = tid; e < CPW * NF * nzp; e += 64 * CPW) {
         const int qk = e / CPW;
         const int q = qk / nzp, kk = qk % nzp;
-        const double acc_v = profs[(size_t)cl * 6 * nzp + qk];
+        const double acc_v = profs[(size_t)cl * WR + qk];
         double val;
-        if (q < 4) {
+        if (q < NL) {
             if (kk == g.nz) {
                 val = 0.0;
             } else {
@@ -283,8 +308,11 @@ __global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, 
     }
 }
 
-template <int CPW, bool RP>
-inline size_t deposit_smem(const Grid &g) { return (size_t)((RP ? 6 : 12) * CPW) * (size_t)(g.nz + 1) * 8; }
+template <class P, int CPW, bool RP>
+inline size_t deposit_smem(const Grid &g)
+{
+    return (size_t)((RP ? 1 : 2) * CPW) * (size_t)dep_wave_words<P, RP>(g.nz + 1) * 8;
+}
 
 // launch with four columns per workgroup when their profiles fit 64 KiB of
 // LDS, else one; register profiles up to 128 levels and interfaces
@@ -292,11 +320,11 @@ template <class P, bool RP>
 inline void launch_deposit_rp(const Grid &g, const P &p, const uint32_t *perm, const uint32_t *colstart,
                               double *flux, hipStream_t s)
 {
-    if (deposit_smem<4, RP>(g) <= 65536)
-        k_deposit<P, 4, RP><<<(unsigned)((g.ncol + 3) / 4), 256, deposit_smem<4, RP>(g), s>>>(g, p, perm, colstart,
-                                                                                              flux);
+    if (deposit_smem<P, 4, RP>(g) <= 65536)
+        k_deposit<P, 4, RP><<<(unsigned)((g.ncol + 3) / 4), 256, deposit_smem<P, 4, RP>(g), s>>>(g, p, perm, colstart,
+                                                                                                 flux);
     else
-        k_deposit<P, 1, RP><<<(unsigned)g.ncol, 64, deposit_smem<1, RP>(g), s>>>(g, p, perm, colstart, flux);
+        k_deposit<P, 1, RP><<<(unsigned)g.ncol, 64, deposit_smem<P, 1, RP>(g), s>>>(g, p, perm, colstart, flux);
 }
 
 template <class P>

@@ -112,6 +112,8 @@ struct rt_ctx_s {
     int64_t hist_len;
     // flux scratch
     double *flux, *drag;
+    // saturation: level sums P and sum P_j K_j^2 [2][nz+1][ncol], kappa [nz][ncol]
+    double *satpq, *kappa;
     // per-column flags: 1 = the surrogate owns the column this step
     uint8_t *frozen;
     bool have_frozen;
@@ -130,7 +132,7 @@ struct rt_ctx_s {
     void *prof;  // std::vector of records, owned by api.hip
 };
 
-enum { PC_STEP = 0, PC_SORT = 1, PC_DEPOSIT = 2, PC_DRAG = 3, PC_SPLIT = 4, PC_STATS = 5, PC_N = 8 };
+enum { PC_STEP = 0, PC_SORT = 1, PC_DEPOSIT = 2, PC_DRAG = 3, PC_SPLIT = 4, PC_STATS = 5, PC_SAT = 6, PC_N = 8 };
 void prof_begin(rt_ctx ctx, int cls);
 void prof_end(rt_ctx ctx);
 
@@ -257,6 +259,13 @@ void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *per
                       double *flux, hipStream_t s);
 void launch_drag(const Grid &g, const double *rho, const double *cosr, const double *flux, double *drag, hipStream_t s);
 void launch_coslat(const Grid &g, double *cosr, hipStream_t s);
+// spectral saturation of the current (sorted) set: level sums, kappa, damping
+void launch_saturation64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *skeys,
+                         const uint32_t *colstart, const DevCounters *dc, const double *rho, double dt, double *PQ,
+                         double *kappa, int64_t bound, hipStream_t s);
+void launch_saturation32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *skeys,
+                         const uint32_t *colstart, const DevCounters *dc, const double *rho, double dt, double *PQ,
+                         double *kappa, int64_t bound, hipStream_t s);
 
 void launch_copy_n(const uint32_t *src, uint32_t *dst, const DevCounters *dc, int64_t bound, hipStream_t s);
 void launch_set_sorted(DevCounters *dc, int64_t n, hipStream_t s);
