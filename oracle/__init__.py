@@ -44,7 +44,7 @@ class _Bg(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("x0", C.c_double), ("y0", C.c_double), ("a", C.c_double)] + \
                [(n, C.c_void_p) for n in ("U", "V", "N2", "f2", "rho", "Ux", "Uy", "Uz", "Vx", "Vy", "Vz",
-                                           "N2x", "N2y", "N2z", "f2y")]
+                                           "N2x", "N2y", "N2z", "f2y", "f")]
 
 
 class _Rays(C.Structure):
@@ -126,6 +126,12 @@ def _load(path: str) -> C.CDLL:
     L.orc_stats.argtypes = [P, C.c_int64, P]
     L.orc_features.argtypes = [P, P, C.c_int64, P]
     L.orc_saturation.argtypes = [P, P, C.c_int64, C.c_double, P, P, P, C.c_int]
+    L.orc_full_fluxes.argtypes = [P, P, C.c_int64, P]
+    L.orc_smooth.argtypes = [P, P, C.c_int, P]
+    L.orc_divergence.argtypes = [P, P, P, P, P]
+    L.orc_full_tendencies.argtypes = [P, P, P]
+    L.orc_budget.argtypes = [P, P, C.c_int64, P]
+    L.orc_budget_terms.argtypes = [P, P, P]
     L.orc_num_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [C.c_int]
     return L
@@ -143,6 +149,7 @@ class Background:
         c = lambda v: np.ascontiguousarray(v, dtype=np.float64)
         self.U, self.V, self.N2 = c(U), c(V), c(N2)
         f = c(f)
+        self.f = f
         self.f2 = c(f * f)
         self.rho = c(rho)
         shape = (nz, ny, nx)
@@ -158,6 +165,7 @@ class Background:
         for n, v in self.grads.items():
             setattr(b, n, _ptr(v))
         b.f2y = _ptr(self.f2y)
+        b.f = _ptr(self.f)
         self._b = b
         self.geometry, self.nx, self.ny, self.nz = geometry, nx, ny, nz
         self.dx, self.dy, self.dz, self.x0, self.y0, self.a = dx, dy, dz, x0, y0, a
@@ -321,6 +329,59 @@ def saturation(bg: Background, rs: RaySet, dt: float, cols: Optional[np.ndarray]
         rs.a["col"][: rs.n] = cols
     lib().orc_saturation(bg.ref, rs.ref, rs.n, float(dt), _ptr(P), _ptr(Q), _ptr(K), 0 if cols is None else 1)
     return P, Q, K
+
+
+def full_fluxes(bg: Background, rs: RaySet) -> np.ndarray:
+    """Full flux formulation (orc_full_fluxes): [8][nz+1][ny][nx] = Fxu, Fxv,
+    Fyu, Fyv, Bu, Bv (levels), Fzu, Fzv (interfaces)."""
+    out = np.zeros((8, bg.nz + 1, bg.ny, bg.nx))
+    lib().orc_full_fluxes(bg.ref, rs.ref, rs.n, _ptr(out))
+    return out
+
+
+def smooth(bg: Background, fields: np.ndarray) -> np.ndarray:
+    """3/2/1-weighted horizontal smoothing of every [ny][nx] slice."""
+    f = np.ascontiguousarray(fields, dtype=np.float64)
+    assert f.shape[-2:] == (bg.ny, bg.nx)
+    out = np.zeros_like(f)
+    lib().orc_smooth(bg.ref, _ptr(f), int(f.size // (bg.ny * bg.nx)), _ptr(out))
+    return out
+
+
+def divergence(bg: Background, Fx, Fy, Fz=None) -> np.ndarray:
+    """div(Fx, Fy, Fz) on [nz][ny][nx]; Fx, Fy [nz+1][ny][nx] (levels), Fz on
+    interfaces or None."""
+    c = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    Fx, Fy = c(Fx), c(Fy)
+    Fz = c(Fz) if Fz is not None else None
+    out = np.zeros((bg.nz, bg.ny, bg.nx))
+    lib().orc_divergence(bg.ref, _ptr(Fx), _ptr(Fy), _ptr(Fz) if Fz is not None else None, _ptr(out))
+    return out
+
+
+def full_tendencies(bg: Background, flux8: np.ndarray) -> np.ndarray:
+    """du, dv, db [3][nz][ny][nx] of the full formulation (orc_full_tendencies)."""
+    f = np.ascontiguousarray(flux8, dtype=np.float64)
+    assert f.shape == (8, bg.nz + 1, bg.ny, bg.nx)
+    out = np.zeros((3, bg.nz, bg.ny, bg.nx))
+    lib().orc_full_tendencies(bg.ref, _ptr(f), _ptr(out))
+    return out
+
+
+def budget(bg: Background, rs: RaySet) -> np.ndarray:
+    """Wave-action budget fields [4][nz+1][ny][nx]: A, cgx A, cgy A (levels),
+    cgz A (interfaces)."""
+    out = np.zeros((4, bg.nz + 1, bg.ny, bg.nx))
+    lib().orc_budget(bg.ref, rs.ref, rs.n, _ptr(out))
+    return out
+
+
+def budget_terms(bg: Background, fields4: np.ndarray) -> np.ndarray:
+    """Horizontal and vertical propagation terms [2][nz][ny][nx]."""
+    f = np.ascontiguousarray(fields4, dtype=np.float64)
+    out = np.zeros((2, bg.nz, bg.ny, bg.nx))
+    lib().orc_budget_terms(bg.ref, _ptr(f), _ptr(out))
+    return out
 
 
 def set_threads(n: int) -> None:

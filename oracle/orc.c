@@ -615,45 +615,16 @@ void orc_drag(const orc_bg *g, const double *flux, double *drag)
 {
     size_t plane = (size_t)(g->nz + 1) * (size_t)g->ny * (size_t)g->nx;
     size_t cells = (size_t)g->nz * (size_t)g->ny * (size_t)g->nx;
-    int i, j, k, comp;
+    size_t at;
+    int comp;
     for (comp = 0; comp < 2; comp++) {
-        const double *Fx = flux + (size_t)(0 + comp) * plane;
-        const double *Fy = flux + (size_t)(2 + comp) * plane;
-        const double *Fz = flux + (size_t)(4 + comp) * plane;
         double *out = drag + (size_t)comp * cells;
-        for (k = 0; k < g->nz; k++)
-            for (j = 0; j < g->ny; j++)
-                for (i = 0; i < g->nx; i++) {
-                    int ip = (i + 1) % g->nx, im = (i + g->nx - 1) % g->nx;
-                    double divx, divy, divz;
-                    divz = (Fz[IDX(g, i, j, k + 1)] - Fz[IDX(g, i, j, k)]) / g->dz;
-                    if (g->geometry == ORC_CARTESIAN) {
-                        int jp = (j + 1) % g->ny, jm = (j + g->ny - 1) % g->ny;
-                        divx = (Fx[IDX(g, ip, j, k)] - Fx[IDX(g, im, j, k)]) / (2.0 * g->dx);
-                        divy = (Fy[IDX(g, i, jp, k)] - Fy[IDX(g, i, jm, k)]) / (2.0 * g->dy);
-                    } else {
-                        double r = g->a + ((double)k + 0.5) * g->dz;
-                        double cj = cos(g->y0 + ((double)j + 0.5) * g->dy);
-                        double rc = r * cj;
-                        double dphi;
-                        divx = ((Fx[IDX(g, ip, j, k)] - Fx[IDX(g, im, j, k)]) / (2.0 * g->dx)) / rc;
-                        if (g->ny == 1) {
-                            dphi = 0.0;
-                        } else if (j == 0) {
-                            double c1 = cos(g->y0 + 1.5 * g->dy);
-                            dphi = (c1 * Fy[IDX(g, i, 1, k)] - cj * Fy[IDX(g, i, 0, k)]) / g->dy;
-                        } else if (j == g->ny - 1) {
-                            double cm = cos(g->y0 + ((double)j - 0.5) * g->dy);
-                            dphi = (cj * Fy[IDX(g, i, j, k)] - cm * Fy[IDX(g, i, j - 1, k)]) / g->dy;
-                        } else {
-                            double cp = cos(g->y0 + ((double)j + 1.5) * g->dy);
-                            double cm = cos(g->y0 + ((double)j - 0.5) * g->dy);
-                            dphi = (cp * Fy[IDX(g, i, j + 1, k)] - cm * Fy[IDX(g, i, j - 1, k)]) / (2.0 * g->dy);
-                        }
-                        divy = dphi / rc;
-                    }
-                    out[IDX(g, i, j, k)] = -((divx + divy) + divz) / g->rho[k];
-                }
+        orc_divergence(g, flux + (size_t)(0 + comp) * plane, flux + (size_t)(2 + comp) * plane,
+                       flux + (size_t)(4 + comp) * plane, out);
+        for (at = 0; at < cells; at++) {
+            int k = (int)(at / ((size_t)g->ny * (size_t)g->nx));
+            out[at] = -(out[at] / g->rho[k]);
+        }
     }
 }
 
@@ -1213,4 +1184,347 @@ void orc_saturation(const orc_bg *g, orc_rays *r, int64_t n, double dt, double *
     free(start);
     free(fill);
     free(order);
+}
+
+/* ------------------------------------------------------------------------
+ * Full flux formulation (Section 2b, eq. fluxes:momentum, eq.
+ * fluxes:temperature, eq. fluxes:buoyancy, eq. mean-flow-impact).
+ * The momentum flux tensor, flux direction i (x, y, z) times momentum
+ * component (u, v):
+ *   rho <v_i u_j> = int [omega^2 cg_i kh_j N + f^2 (e_r x cg)_i (e_r x kh)_j N]
+ *                   / (omega^2 - f^2) d^3k,
+ * with e_r x a = (-a_y, a_x, 0), cg the intrinsic group velocity, and
+ * omega^2 - f^2 = kh^2 (N^2 - f^2) / K^2 (no cancellation).  The potential-
+ * temperature flux is deposited in its buoyancy form
+ *   <u' b'> = (g / theta) <u' theta'> = int (1/rho) cg_z (f N^2 / (omega^2 - f^2))
+ *             (e_r x kh) N d^3k,
+ * which needs no reference potential temperature (a caller with theta
+ * multiplies by theta / g).  Projection as the pseudo-momentum fluxes
+ * (orc_deposit): the horizontal components are cell means over the carrier's
+ * column, the vertical ones live on the staggered interfaces; rho of the
+ * level, omega, cg, N^2, f and f^2 at the carrier.
+ * Layout flux8 [8][nz+1][ny][nx]: Fxu, Fxv, Fyu, Fyv, Bu, Bv on levels
+ * (slot nz = 0), Fzu, Fzv on interfaces.
+ * ------------------------------------------------------------------------ */
+static void full_flux_ray(const orc_bg *g, const orc_rays *r, int64_t i, int c, double *flux)
+{
+    size_t plane = (size_t)(g->nz + 1) * (size_t)g->ny * (size_t)g->nx;
+    size_t colstride = (size_t)g->ny * (size_t)g->nx;
+    int ci = c % g->nx, cj = c / g->nx;
+    double B[14], D[4];
+    double W = ray_W(r, i);
+    double z = r->z[i], Dz = r->dz[i];
+    double zb = z - 0.5 * Dz, zt = z + 0.5 * Dz;
+    double Lz = (double)g->nz * g->dz;
+    double k = r->k[i], l = r->l[i], m = r->m[i];
+    double kh2 = k * k + l * l;
+    double K2 = kh2 + m * m;
+    double N2, f2, fs, om2, den, a1, a2, v[8];
+    int kk, klo, khi;
+    corners cc;
+
+    orc_interp(g, r->x[i], r->y[i], z, B);
+    orc_dispersion(B[2], B[12], k, l, m, D);
+    N2 = B[2];
+    f2 = B[12];
+    locate(g, r->x[i], r->y[i], z, &cc);
+    fs = rowlin(g->f, &cc);
+    om2 = D[0] * D[0];
+    den = (kh2 * (N2 - f2)) / K2; /* omega^2 - f^2 */
+    a1 = om2 / den;
+    a2 = f2 / den;
+    v[0] = a1 * (D[1] * k) + a2 * (D[2] * l); /* Fxu */
+    v[1] = a1 * (D[1] * l) - a2 * (D[2] * k); /* Fxv */
+    v[2] = a1 * (D[2] * k) - a2 * (D[1] * l); /* Fyu */
+    v[3] = a1 * (D[2] * l) + a2 * (D[1] * k); /* Fyv */
+    v[4] = -(((D[3] * fs) * N2) / den) * l;   /* Bu (times 1/rho at the level) */
+    v[5] = (((D[3] * fs) * N2) / den) * k;    /* Bv */
+    v[6] = a1 * (D[3] * k);                   /* Fzu */
+    v[7] = a1 * (D[3] * l);                   /* Fzv */
+
+    klo = (int)floor(zb / g->dz);
+    khi = (int)floor(zt / g->dz);
+    if (klo < 0) klo = 0;
+    if (khi > g->nz - 1) khi = g->nz - 1;
+    for (kk = klo; kk <= khi; kk++) {
+        double lo = (double)kk * g->dz, hi = (double)(kk + 1) * g->dz;
+        double o = (zt < hi ? zt : hi) - (zb > lo ? zb : lo);
+        double frac, vol;
+        size_t at;
+        int q;
+        if (!(o > 0.0)) continue;
+        frac = o / Dz;
+        vol = cell_area(g, cj, ((double)kk + 0.5) * g->dz) * g->dz;
+        at = (size_t)kk * colstride + (size_t)cj * (size_t)g->nx + (size_t)ci;
+        for (q = 0; q < 4; q++) flux[(size_t)q * plane + at] += ((v[q] * W) * frac) / vol;
+        for (q = 4; q < 6; q++) flux[(size_t)q * plane + at] += (((v[q] * W) * frac) / vol) / g->rho[kk];
+    }
+    klo = (int)floor(zb / g->dz + 0.5);
+    khi = (int)floor(zt / g->dz + 0.5);
+    if (klo < 0) klo = 0;
+    if (khi > g->nz) khi = g->nz;
+    for (kk = klo; kk <= khi; kk++) {
+        double lo = ((double)kk - 0.5) * g->dz, hi = ((double)kk + 0.5) * g->dz;
+        double o, frac, vol;
+        size_t at;
+        int q;
+        if (lo < 0.0) lo = 0.0;
+        if (hi > Lz) hi = Lz;
+        o = (zt < hi ? zt : hi) - (zb > lo ? zb : lo);
+        if (!(o > 0.0)) continue;
+        frac = o / Dz;
+        vol = cell_area(g, cj, (double)kk * g->dz) * (hi - lo);
+        at = (size_t)kk * colstride + (size_t)cj * (size_t)g->nx + (size_t)ci;
+        for (q = 6; q < 8; q++) flux[(size_t)q * plane + at] += ((v[q] * W) * frac) / vol;
+    }
+}
+
+/* the active rays grouped by column in index order (a stable counting sort) */
+static int64_t *column_order(const orc_bg *g, orc_rays *r, int64_t n, int64_t **start_out)
+{
+    int ncol = g->nx * g->ny;
+    int64_t *start = (int64_t *)calloc((size_t)ncol + 1, sizeof(int64_t));
+    int64_t *fill = (int64_t *)calloc((size_t)ncol + 1, sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t i;
+    int c;
+    orc_keys(g, r, n);
+    for (i = 0; i < n; i++)
+        if (r->state[i] == ORC_ACTIVE) start[r->col[i] + 1]++;
+    for (c = 0; c < ncol; c++) start[c + 1] += start[c];
+    for (i = 0; i < n; i++)
+        if (r->state[i] == ORC_ACTIVE) {
+            int cc = r->col[i];
+            order[start[cc] + fill[cc]] = i;
+            fill[cc]++;
+        }
+    free(fill);
+    *start_out = start;
+    return order;
+}
+
+void orc_full_fluxes(const orc_bg *g, orc_rays *r, int64_t n, double *flux8)
+{
+    int ncol = g->nx * g->ny;
+    int64_t *start, *order = column_order(g, r, n, &start);
+    int c;
+    memset(flux8, 0, (size_t)8 * (size_t)(g->nz + 1) * (size_t)ncol * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (c = 0; c < ncol; c++) {
+        int64_t p;
+        for (p = start[c]; p < start[c + 1]; p++) full_flux_ray(g, r, order[p], c, flux8);
+    }
+    free(start);
+    free(order);
+}
+
+/* ------------------------------------------------------------------------
+ * Horizontal smoothing (Appendix B, horizontal flux smoothing): each cell
+ * becomes the weighted mean of itself (weight 3), the cells sharing an edge
+ * with it (weight 2) and the cells sharing only a corner (weight 1) -- the
+ * ICON triangle weights carried over to the quadrilateral grid.  Periodic
+ * in x (and y on the box); on the sphere the rows beyond the first and last
+ * are left out and the weights of the present cells renormalised.  Applied
+ * to nslices horizontal slices [nslices][ny][nx].
+ * ------------------------------------------------------------------------ */
+void orc_smooth(const orc_bg *g, const double *in, int nslices, double *out)
+{
+    size_t slice = (size_t)g->ny * (size_t)g->nx;
+    int s;
+#pragma omp parallel for schedule(static)
+    for (s = 0; s < nslices; s++) {
+        const double *F = in + (size_t)s * slice;
+        double *O = out + (size_t)s * slice;
+        int i, j, di, dj;
+        for (j = 0; j < g->ny; j++)
+            for (i = 0; i < g->nx; i++) {
+                double sum = 0.0, wsum = 0.0;
+                for (dj = -1; dj <= 1; dj++) {
+                    int jj = j + dj;
+                    if (g->geometry == ORC_CARTESIAN) {
+                        jj = (jj + g->ny) % g->ny;
+                    } else if (jj < 0 || jj > g->ny - 1) {
+                        continue;
+                    }
+                    for (di = -1; di <= 1; di++) {
+                        int ii = (i + di + g->nx) % g->nx;
+                        double w = (di == 0 && dj == 0) ? 3.0 : ((di == 0 || dj == 0) ? 2.0 : 1.0);
+                        sum += w * F[(size_t)jj * (size_t)g->nx + (size_t)ii];
+                        wsum += w;
+                    }
+                }
+                O[(size_t)j * (size_t)g->nx + (size_t)i] = sum / wsum;
+            }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Divergence of a flux (Fx, Fy on levels [nz+1][ny][nx] with slot nz unused,
+ * Fz on interfaces, Fz may be NULL) with the operator of orc_drag: centred
+ * differences of the cell means (periodic; on the sphere (1/(r cos phi))
+ * [d_lambda Fx + d_phi (cos phi Fy)], one-sided at the first and last rows)
+ * plus the difference of the interface values across the level.
+ * out [nz][ny][nx].
+ * ------------------------------------------------------------------------ */
+void orc_divergence(const orc_bg *g, const double *Fx, const double *Fy, const double *Fz, double *out)
+{
+    int i, j, k;
+    for (k = 0; k < g->nz; k++)
+        for (j = 0; j < g->ny; j++)
+            for (i = 0; i < g->nx; i++) {
+                int ip = (i + 1) % g->nx, im = (i + g->nx - 1) % g->nx;
+                double divx, divy, divz;
+                divz = Fz ? (Fz[IDX(g, i, j, k + 1)] - Fz[IDX(g, i, j, k)]) / g->dz : 0.0;
+                if (g->geometry == ORC_CARTESIAN) {
+                    int jp = (j + 1) % g->ny, jm = (j + g->ny - 1) % g->ny;
+                    divx = (Fx[IDX(g, ip, j, k)] - Fx[IDX(g, im, j, k)]) / (2.0 * g->dx);
+                    divy = (Fy[IDX(g, i, jp, k)] - Fy[IDX(g, i, jm, k)]) / (2.0 * g->dy);
+                } else {
+                    double r = g->a + ((double)k + 0.5) * g->dz;
+                    double cj = cos(g->y0 + ((double)j + 0.5) * g->dy);
+                    double rc = r * cj;
+                    double dphi;
+                    divx = ((Fx[IDX(g, ip, j, k)] - Fx[IDX(g, im, j, k)]) / (2.0 * g->dx)) / rc;
+                    if (g->ny == 1) {
+                        dphi = 0.0;
+                    } else if (j == 0) {
+                        double c1 = cos(g->y0 + 1.5 * g->dy);
+                        dphi = (c1 * Fy[IDX(g, i, 1, k)] - cj * Fy[IDX(g, i, 0, k)]) / g->dy;
+                    } else if (j == g->ny - 1) {
+                        double cm = cos(g->y0 + ((double)j - 0.5) * g->dy);
+                        dphi = (cj * Fy[IDX(g, i, j, k)] - cm * Fy[IDX(g, i, j - 1, k)]) / g->dy;
+                    } else {
+                        double cp = cos(g->y0 + ((double)j + 1.5) * g->dy);
+                        double cm = cos(g->y0 + ((double)j - 0.5) * g->dy);
+                        dphi = (cp * Fy[IDX(g, i, j + 1, k)] - cm * Fy[IDX(g, i, j - 1, k)]) / (2.0 * g->dy);
+                    }
+                    divy = dphi / rc;
+                }
+                out[IDX(g, i, j, k)] = (divx + divy) + divz;
+            }
+}
+
+/* ------------------------------------------------------------------------
+ * Mean-flow tendencies of the full formulation (eq. mean-flow-impact and
+ * eq. mean-flow-impact-t in buoyancy form):
+ *   du = -(1/rho) div(Fx u, Fy u, Fz u) - (f/g) Bv,
+ *   dv = -(1/rho) div(Fx v, Fy v, Fz v) + (f/g) Bu,   ((f/g) e_r x <u'b'>)
+ *   db = -div_h(Bu, Bv)   (the buoyancy tendency, (g/theta) dtheta/dt),
+ * with f of the cell's row and g = 9.80665 m s^-2.  flux8 as written by
+ * orc_full_fluxes (possibly smoothed); out3 [3][nz][ny][nx].
+ * ------------------------------------------------------------------------ */
+#define ORC_GRAVITY 9.80665
+void orc_full_tendencies(const orc_bg *g, const double *flux8, double *out3)
+{
+    size_t plane = (size_t)(g->nz + 1) * (size_t)g->ny * (size_t)g->nx;
+    size_t cells = (size_t)g->nz * (size_t)g->ny * (size_t)g->nx;
+    double *div = (double *)malloc(sizeof(double) * cells);
+    size_t at;
+    int comp;
+    for (comp = 0; comp < 2; comp++) {
+        orc_divergence(g, flux8 + (size_t)comp * plane, flux8 + (size_t)(2 + comp) * plane,
+                       flux8 + (size_t)(6 + comp) * plane, div);
+        for (at = 0; at < cells; at++) {
+            int k = (int)(at / ((size_t)g->ny * (size_t)g->nx));
+            int j = (int)((at / (size_t)g->nx) % (size_t)g->ny);
+            double fg = g->f[j] / ORC_GRAVITY;
+            double el = comp == 0 ? -(fg * flux8[5 * plane + at]) : fg * flux8[4 * plane + at];
+            out3[(size_t)comp * cells + at] = -(div[at] / g->rho[k]) + el;
+        }
+    }
+    orc_divergence(g, flux8 + 4 * plane, flux8 + 5 * plane, NULL, div);
+    for (at = 0; at < cells; at++) out3[2 * cells + at] = -div[at];
+    free(div);
+}
+
+/* ------------------------------------------------------------------------
+ * Wave-action budget fields (Section 4, eq. wave-action-budget): the wave
+ * action per unit volume A = int N d^3k and its fluxes (cg_h A, cg_r A) =
+ * int (cg_h, cg_r) N d^3k with the ground-based group velocity (U + cg_x,
+ * V + cg_y, cg_z) at the carrier, projected like the fluxes.
+ * fields4 [4][nz+1][ny][nx]: A, cgx A, cgy A on levels, cgz A on interfaces.
+ * orc_budget_terms gives the horizontal and vertical propagation terms
+ * div_h(cg_h A) and d_z(cg_z A), terms2 [2][nz][ny][nx].  The saturation term
+ * is the change of A across orc_saturation divided by its time step.
+ * ------------------------------------------------------------------------ */
+static void budget_ray(const orc_bg *g, const orc_rays *r, int64_t i, int c, double *fields)
+{
+    size_t plane = (size_t)(g->nz + 1) * (size_t)g->ny * (size_t)g->nx;
+    size_t colstride = (size_t)g->ny * (size_t)g->nx;
+    int ci = c % g->nx, cj = c / g->nx;
+    double B[14], D[4], v[4];
+    double W = ray_W(r, i);
+    double z = r->z[i], Dz = r->dz[i];
+    double zb = z - 0.5 * Dz, zt = z + 0.5 * Dz;
+    double Lz = (double)g->nz * g->dz;
+    int kk, klo, khi;
+    orc_interp(g, r->x[i], r->y[i], z, B);
+    orc_dispersion(B[2], B[12], r->k[i], r->l[i], r->m[i], D);
+    v[0] = 1.0;
+    v[1] = B[0] + D[1];
+    v[2] = B[1] + D[2];
+    v[3] = D[3];
+    klo = (int)floor(zb / g->dz);
+    khi = (int)floor(zt / g->dz);
+    if (klo < 0) klo = 0;
+    if (khi > g->nz - 1) khi = g->nz - 1;
+    for (kk = klo; kk <= khi; kk++) {
+        double lo = (double)kk * g->dz, hi = (double)(kk + 1) * g->dz;
+        double o = (zt < hi ? zt : hi) - (zb > lo ? zb : lo);
+        double frac, vol;
+        size_t at;
+        int q;
+        if (!(o > 0.0)) continue;
+        frac = o / Dz;
+        vol = cell_area(g, cj, ((double)kk + 0.5) * g->dz) * g->dz;
+        at = (size_t)kk * colstride + (size_t)cj * (size_t)g->nx + (size_t)ci;
+        for (q = 0; q < 3; q++) fields[(size_t)q * plane + at] += ((v[q] * W) * frac) / vol;
+    }
+    klo = (int)floor(zb / g->dz + 0.5);
+    khi = (int)floor(zt / g->dz + 0.5);
+    if (klo < 0) klo = 0;
+    if (khi > g->nz) khi = g->nz;
+    for (kk = klo; kk <= khi; kk++) {
+        double lo = ((double)kk - 0.5) * g->dz, hi = ((double)kk + 0.5) * g->dz;
+        double o, frac, vol;
+        size_t at;
+        if (lo < 0.0) lo = 0.0;
+        if (hi > Lz) hi = Lz;
+        o = (zt < hi ? zt : hi) - (zb > lo ? zb : lo);
+        if (!(o > 0.0)) continue;
+        frac = o / Dz;
+        vol = cell_area(g, cj, (double)kk * g->dz) * (hi - lo);
+        at = (size_t)kk * colstride + (size_t)cj * (size_t)g->nx + (size_t)ci;
+        fields[3 * plane + at] += ((v[3] * W) * frac) / vol;
+    }
+}
+
+void orc_budget(const orc_bg *g, orc_rays *r, int64_t n, double *fields4)
+{
+    int ncol = g->nx * g->ny;
+    int64_t *start, *order = column_order(g, r, n, &start);
+    int c;
+    memset(fields4, 0, (size_t)4 * (size_t)(g->nz + 1) * (size_t)ncol * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (c = 0; c < ncol; c++) {
+        int64_t p;
+        for (p = start[c]; p < start[c + 1]; p++) budget_ray(g, r, order[p], c, fields4);
+    }
+    free(start);
+    free(order);
+}
+
+void orc_budget_terms(const orc_bg *g, const double *fields4, double *terms2)
+{
+    size_t plane = (size_t)(g->nz + 1) * (size_t)g->ny * (size_t)g->nx;
+    size_t cells = (size_t)g->nz * (size_t)g->ny * (size_t)g->nx;
+    size_t at;
+    int k, j, i;
+    orc_divergence(g, fields4 + plane, fields4 + 2 * plane, NULL, terms2);
+    for (k = 0; k < g->nz; k++)
+        for (j = 0; j < g->ny; j++)
+            for (i = 0; i < g->nx; i++) {
+                at = IDX(g, i, j, k);
+                terms2[cells + at] = (fields4[3 * plane + IDX(g, i, j, k + 1)] - fields4[3 * plane + at]) / g->dz;
+            }
 }

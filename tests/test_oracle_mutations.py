@@ -7,11 +7,40 @@ least one of them to fail.  The real oracle is untouched and restored after
 each case.  CPU only."""
 import pytest
 
+import test_oracle_fullflux as X
 import test_oracle_pins as P
 import test_oracle_pins_sphere as S
 import test_oracle_saturation as T
 
 MUTATIONS = [
+    ("full flux: f^2 term of Fxu with the wrong sign",
+     "v[0] = a1 * (D[1] * k) + a2 * (D[2] * l); /* Fxu */",
+     "v[0] = a1 * (D[1] * k) - a2 * (D[2] * l); /* Fxu */",
+     [lambda orc: X.test_full_fluxes_equal_polarization_stresses(orc, 1.2e-4)]),
+    ("full flux: omega^2/(omega^2 - f^2) factor dropped from the vertical flux",
+     "v[6] = a1 * (D[3] * k);                   /* Fzu */",
+     "v[6] = D[3] * k;                          /* Fzu */",
+     [lambda orc: X.test_full_fluxes_equal_polarization_stresses(orc, -0.9e-4)]),
+    ("buoyancy flux without 1/rho",
+     "for (q = 4; q < 6; q++) flux[(size_t)q * plane + at] += (((v[q] * W) * frac) / vol) / g->rho[kk];",
+     "for (q = 4; q < 6; q++) flux[(size_t)q * plane + at] += ((v[q] * W) * frac) / vol;",
+     [lambda orc: X.test_full_fluxes_equal_polarization_stresses(orc, 1.2e-4)]),
+    ("buoyancy flux with |f| instead of the signed f",
+     "fs = rowlin(g->f, &cc);",
+     "fs = sqrt(f2);",
+     [lambda orc: X.test_full_fluxes_equal_polarization_stresses(orc, -0.9e-4)]),
+    ("elastic term with the wrong sign",
+     "double el = comp == 0 ? -(fg * flux8[5 * plane + at]) : fg * flux8[4 * plane + at];",
+     "double el = comp == 0 ? fg * flux8[5 * plane + at] : -(fg * flux8[4 * plane + at]);",
+     [X.test_tendencies_closed_forms]),
+    ("smoothing with equal weights",
+     "double w = (di == 0 && dj == 0) ? 3.0 : ((di == 0 || dj == 0) ? 2.0 : 1.0);",
+     "double w = 1.0;",
+     [X.test_smoothing_weights]),
+    ("budget flux without the mean wind",
+     "v[1] = B[0] + D[1];",
+     "v[1] = D[1];",
+     [X.test_budget_fields_brute_force_and_totals]),
     ("saturation weight without kh^2",
      "return (m2 * kh2) / (D[0] * K2);",
      "return m2 / (D[0] * K2);",
@@ -37,8 +66,8 @@ MUTATIONS = [
      "dphi = (Fy[IDX(g, i, j + 1, k)] - Fy[IDX(g, i, j - 1, k)]) / (2.0 * g->dy);",
      [S.test_spherical_drag_closed_form]),
     ("spherical drag with r = a instead of a + z",
-     "double r = g->a + ((double)k + 0.5) * g->dz;\n                        double cj",
-     "double r = g->a;\n                        double cj",
+     "double r = g->a + ((double)k + 0.5) * g->dz;\n                    double cj",
+     "double r = g->a;\n                    double cj",
      [S.test_spherical_drag_closed_form]),
     ("spherical drag with the zonal term not divided by r cos(phi)",
      "divx = ((Fx[IDX(g, ip, j, k)] - Fx[IDX(g, im, j, k)]) / (2.0 * g->dx)) / rc;",
