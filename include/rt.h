@@ -227,6 +227,41 @@ rt_status rt_features(rt_ctx ctx, float *X, int32_t where);
  * synchronisation unless where == RT_HOST. */
 rt_status rt_deposit_flux(rt_ctx ctx, double *flux, double *drag, int32_t where);
 
+/* Full flux formulation of the current set (Section 2b, eq.
+ * fluxes:momentum, eq. fluxes:temperature, eq. fluxes:buoyancy) and the
+ * resulting mean-flow tendencies (eq. mean-flow-impact, eq.
+ * mean-flow-impact-t).  Per volume, with cg the intrinsic group velocity,
+ * e_r x a = (-a_y, a_x, 0) and omega^2 - f^2 = kh^2 (N^2 - f^2) / K^2:
+ *   momentum flux  [omega^2 cg_i kh_j + f^2 (e_r x cg)_i (e_r x kh)_j] / (omega^2 - f^2) W,
+ *   buoyancy flux  cg_z f N^2 / (omega^2 - f^2) (e_r x kh) W / rho
+ * (the potential-temperature flux in buoyancy form, <u'b'> =
+ * (g/theta) <u'theta'>), projected like rt_deposit_flux.
+ *   flux   [8][nz+1][ny][nx] double: Fxu, Fxv, Fyu, Fyv, Bu, Bv on levels
+ *          (slot nz = 0), Fzu, Fzv on interfaces; may be NULL
+ *   tend   [3][nz][ny][nx] double: du, dv = -(1/rho) div F + (f/g) e_r x <u'b'>
+ *          (g = 9.80665 m/s^2), db = -div_h <u'b'> (the buoyancy
+ *          tendency, (g/theta) dtheta/dt); may be NULL
+ *   smooth nonzero: every flux field is first smoothed horizontally
+ *          (Appendix B, horizontal flux smoothing: weights 3 for the cell,
+ *          2 for the cells sharing an edge, 1 for those sharing a corner;
+ *          the sphere's missing rows are left out and the weights
+ *          renormalised) and the tendencies use the smoothed fields
+ * Scratch is allocated from the context's allocator on the first call.
+ * Deterministic.  No synchronisation unless where == RT_HOST. */
+rt_status rt_full_fluxes(rt_ctx ctx, double *flux, double *tend, int32_t smooth, int32_t where);
+
+/* Wave-action budget of the current set (Section 4, eq. wave-action-budget):
+ *   fields [4][nz+1][ny][nx] double: A (wave action per unit volume), (U + cg_x) A,
+ *          (V + cg_y) A on levels, cg_z A on interfaces (ground-based group
+ *          velocity at the carrier), projected like rt_deposit_flux
+ *   terms  [2][nz][ny][nx] double: the horizontal propagation term
+ *          div_h(cg_h A) and the vertical one d_z(cg_z A)
+ *   smooth as rt_full_fluxes
+ * The saturation term is the change of A across rt_saturate divided by its
+ * time step.  Either output may be NULL.  Scratch is allocated on the first
+ * call.  No synchronisation unless where == RT_HOST. */
+rt_status rt_budget(rt_ctx ctx, double *fields, double *terms, int32_t smooth, int32_t where);
+
 /* Vertical splitting (Appendix B, ray volume splitting): every volume taller
  * than alpha_split * dz is halved (repeatedly, up to 64 pieces) into
  * volumes with the same wavevector and density.  Then, with mode RT_MERGE,

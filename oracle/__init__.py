@@ -126,11 +126,11 @@ def _load(path: str) -> C.CDLL:
     L.orc_stats.argtypes = [P, C.c_int64, P]
     L.orc_features.argtypes = [P, P, C.c_int64, P]
     L.orc_saturation.argtypes = [P, P, C.c_int64, C.c_double, P, P, P, C.c_int]
-    L.orc_full_fluxes.argtypes = [P, P, C.c_int64, P]
+    L.orc_full_fluxes.argtypes = [P, P, C.c_int64, P, C.c_int]
     L.orc_smooth.argtypes = [P, P, C.c_int, P]
     L.orc_divergence.argtypes = [P, P, P, P, P]
     L.orc_full_tendencies.argtypes = [P, P, P]
-    L.orc_budget.argtypes = [P, P, C.c_int64, P]
+    L.orc_budget.argtypes = [P, P, C.c_int64, P, C.c_int]
     L.orc_budget_terms.argtypes = [P, P, P]
     L.orc_num_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [C.c_int]
@@ -331,11 +331,22 @@ def saturation(bg: Background, rs: RaySet, dt: float, cols: Optional[np.ndarray]
     return P, Q, K
 
 
-def full_fluxes(bg: Background, rs: RaySet) -> np.ndarray:
+def _given_cols(rs: RaySet, cols) -> int:
+    if cols is None:
+        return 0
+    cols = np.asarray(cols, dtype=np.int32)
+    assert cols.shape == (rs.n,)
+    rs.a["col"][: rs.n] = cols
+    return 1
+
+
+def full_fluxes(bg: Background, rs: RaySet, cols: Optional[np.ndarray] = None) -> np.ndarray:
     """Full flux formulation (orc_full_fluxes): [8][nz+1][ny][nx] = Fxu, Fxv,
-    Fyu, Fyv, Bu, Bv (levels), Fzu, Fzv (interfaces)."""
+    Fyu, Fyv, Bu, Bv (levels), Fzu, Fzv (interfaces).  `cols` as in
+    deposit()."""
     out = np.zeros((8, bg.nz + 1, bg.ny, bg.nx))
-    lib().orc_full_fluxes(bg.ref, rs.ref, rs.n, _ptr(out))
+    given = _given_cols(rs, cols)
+    lib().orc_full_fluxes(bg.ref, rs.ref, rs.n, _ptr(out), given)
     return out
 
 
@@ -368,11 +379,12 @@ def full_tendencies(bg: Background, flux8: np.ndarray) -> np.ndarray:
     return out
 
 
-def budget(bg: Background, rs: RaySet) -> np.ndarray:
+def budget(bg: Background, rs: RaySet, cols: Optional[np.ndarray] = None) -> np.ndarray:
     """Wave-action budget fields [4][nz+1][ny][nx]: A, cgx A, cgy A (levels),
-    cgz A (interfaces)."""
+    cgz A (interfaces).  `cols` as in deposit()."""
     out = np.zeros((4, bg.nz + 1, bg.ny, bg.nx))
-    lib().orc_budget(bg.ref, rs.ref, rs.n, _ptr(out))
+    given = _given_cols(rs, cols)
+    lib().orc_budget(bg.ref, rs.ref, rs.n, _ptr(out), given)
     return out
 
 

@@ -1279,8 +1279,9 @@ static void full_flux_ray(const orc_bg *g, const orc_rays *r, int64_t i, int c, 
     }
 }
 
-/* the active rays grouped by column in index order (a stable counting sort) */
-static int64_t *column_order(const orc_bg *g, orc_rays *r, int64_t n, int64_t **start_out)
+/* the active rays grouped by column in index order (a stable counting sort);
+   with given_cols the keys already in r->col are used (see orc_saturation) */
+static int64_t *column_order(const orc_bg *g, orc_rays *r, int64_t n, int given_cols, int64_t **start_out)
 {
     int ncol = g->nx * g->ny;
     int64_t *start = (int64_t *)calloc((size_t)ncol + 1, sizeof(int64_t));
@@ -1288,7 +1289,7 @@ static int64_t *column_order(const orc_bg *g, orc_rays *r, int64_t n, int64_t **
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     int64_t i;
     int c;
-    orc_keys(g, r, n);
+    if (!given_cols) orc_keys(g, r, n);
     for (i = 0; i < n; i++)
         if (r->state[i] == ORC_ACTIVE) start[r->col[i] + 1]++;
     for (c = 0; c < ncol; c++) start[c + 1] += start[c];
@@ -1303,10 +1304,10 @@ static int64_t *column_order(const orc_bg *g, orc_rays *r, int64_t n, int64_t **
     return order;
 }
 
-void orc_full_fluxes(const orc_bg *g, orc_rays *r, int64_t n, double *flux8)
+void orc_full_fluxes(const orc_bg *g, orc_rays *r, int64_t n, double *flux8, int given_cols)
 {
     int ncol = g->nx * g->ny;
-    int64_t *start, *order = column_order(g, r, n, &start);
+    int64_t *start, *order = column_order(g, r, n, given_cols, &start);
     int c;
     memset(flux8, 0, (size_t)8 * (size_t)(g->nz + 1) * (size_t)ncol * sizeof(double));
 #pragma omp parallel for schedule(dynamic, 16)
@@ -1499,10 +1500,10 @@ static void budget_ray(const orc_bg *g, const orc_rays *r, int64_t i, int c, dou
     }
 }
 
-void orc_budget(const orc_bg *g, orc_rays *r, int64_t n, double *fields4)
+void orc_budget(const orc_bg *g, orc_rays *r, int64_t n, double *fields4, int given_cols)
 {
     int ncol = g->nx * g->ny;
-    int64_t *start, *order = column_order(g, r, n, &start);
+    int64_t *start, *order = column_order(g, r, n, given_cols, &start);
     int c;
     memset(fields4, 0, (size_t)4 * (size_t)(g->nz + 1) * (size_t)ncol * sizeof(double));
 #pragma omp parallel for schedule(dynamic, 16)

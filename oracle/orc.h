@@ -83,11 +83,11 @@ void orc_stats(const orc_rays *r, int64_t n, orc_tally *t);
 void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X);
 void orc_saturation(const orc_bg *g, orc_rays *r, int64_t n, double dt, double *P, double *Q, double *kappa,
                     int given_cols);
-void orc_full_fluxes(const orc_bg *g, orc_rays *r, int64_t n, double *flux8);
+void orc_full_fluxes(const orc_bg *g, orc_rays *r, int64_t n, double *flux8, int given_cols);
 void orc_smooth(const orc_bg *g, const double *in, int nslices, double *out);
 void orc_divergence(const orc_bg *g, const double *Fx, const double *Fy, const double *Fz, double *out);
 void orc_full_tendencies(const orc_bg *g, const double *flux8, double *out3);
-void orc_budget(const orc_bg *g, orc_rays *r, int64_t n, double *fields4);
+void orc_budget(const orc_bg *g, orc_rays *r, int64_t n, double *fields4, int given_cols);
 void orc_budget_terms(const orc_bg *g, const double *fields4, double *terms2);
 int orc_num_threads(void);
 void orc_set_threads(int n);

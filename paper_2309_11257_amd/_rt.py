@@ -76,6 +76,8 @@ def lib() -> C.CDLL:
         L.rt_step.argtypes = [P, D, I32]
         L.rt_deposit_flux.argtypes = [P, P, P, I32]
         L.rt_saturate.argtypes = [P, D, P, I32]
+        L.rt_full_fluxes.argtypes = [P, P, P, I32, I32]
+        L.rt_budget.argtypes = [P, P, P, I32, I32]
         L.rt_split_merge.argtypes = [P, D, I32, I32, C.POINTER(Stats)]
         L.rt_get_stats.argtypes = [P, C.POINTER(Stats)]
         L.rt_get_columns.argtypes = [P, P, C.POINTER(I64), I32]
@@ -88,7 +90,7 @@ def lib() -> C.CDLL:
         for name in ("rt_create", "rt_destroy", "rt_init_background", "rt_set_rays", "rt_set_rays_host_noalloc",
                      "rt_get_rays", "rt_step",
                      "rt_deposit_flux", "rt_split_merge", "rt_get_stats", "rt_profile", "rt_profile_read", "rt_get_columns",
-                     "rt_features", "rt_set_frozen_columns", "rt_saturate"):
+                     "rt_features", "rt_set_frozen_columns", "rt_saturate", "rt_full_fluxes", "rt_budget"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -306,6 +308,28 @@ class Tracer:
             drag = torch.empty((2, nz, ny, nx), dtype=torch.float64, device=self.device)
         self._check(lib().rt_deposit_flux(self.h, flux.data_ptr(), drag.data_ptr(), RT_DEVICE))
         return flux, drag
+
+    def _two_outputs(self, fn, shapes, smooth, host):
+        torch = self.torch
+        if host:
+            outs = [np.zeros(s) for s in shapes]
+            self._check(fn(self.h, outs[0].ctypes.data, outs[1].ctypes.data, 1 if smooth else 0, RT_HOST))
+            return tuple(outs)
+        outs = [torch.empty(s, dtype=torch.float64, device=self.device) for s in shapes]
+        self._check(fn(self.h, outs[0].data_ptr(), outs[1].data_ptr(), 1 if smooth else 0, RT_DEVICE))
+        return tuple(outs)
+
+    def full_fluxes(self, smooth: bool = False, host: bool = False):
+        """(flux [8, nz+1, ny, nx], tendencies [3, nz, ny, nx]) of the full
+        flux formulation (rt_full_fluxes)."""
+        nz, ny, nx = self.nz, self.ny, self.nx
+        return self._two_outputs(lib().rt_full_fluxes, [(8, nz + 1, ny, nx), (3, nz, ny, nx)], smooth, host)
+
+    def budget(self, smooth: bool = False, host: bool = False):
+        """(fields [4, nz+1, ny, nx], terms [2, nz, ny, nx]) of the wave-action
+        budget (rt_budget)."""
+        nz, ny, nx = self.nz, self.ny, self.nx
+        return self._two_outputs(lib().rt_budget, [(4, nz + 1, ny, nx), (2, nz, ny, nx)], smooth, host)
 
     def split_merge(self, alpha: float, n_max: int = 0, mode: int = RT_SPLIT_ONLY) -> dict:
         s = Stats()

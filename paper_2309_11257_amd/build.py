@@ -28,6 +28,7 @@ SOURCES = {
     "sort.hip": ["-ffp-contract=off"],
     "drag.hip": ["-ffp-contract=off"],
     "saturation.hip": ["-ffp-contract=off"],
+    "fullflux.hip": ["-ffp-contract=off"],
     "splitmerge.hip": ["-ffp-contract=off"],
     "mlp.hip": ["-ffp-contract=fast"],
 }

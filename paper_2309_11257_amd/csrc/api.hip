@@ -243,7 +243,9 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
         ALLOC(rows, float, 2 * (int64_t)g.ny);
         ctx->bp32.f2 = rows;
         ctx->bp32.f2y = rows + g.ny;
+        ALLOC(ctx->frow32, float, g.ny);
     }
+    ALLOC(ctx->frow, double, g.ny);
     // ray state, two buffers
     for (int buf = 0; buf < 2; buf++) {
         if (ctx->precision == RT_FP64) {
@@ -383,16 +385,16 @@ extern "C" rt_status rt_init_background(rt_ctx ctx, const double *U, const doubl
     HIP_OK(hipMemcpyAsync(bgd + cells, V, sizeof(double) * cells, kind, ctx->stream));
     HIP_OK(hipMemcpyAsync(bgd + 2 * cells, N2, sizeof(double) * cells, kind, ctx->stream));
     HIP_OK(hipMemcpyAsync(ctx->rho, rho, sizeof(double) * g.nz, kind, ctx->stream));
-    // f is staged in the flux scratch (ncol*(nz+1)*6 >= ny doubles)
-    double *fstage = nullptr;
-    if (f) {
-        fstage = ctx->flux;
-        HIP_OK(hipMemcpyAsync(fstage, f, sizeof(double) * g.ny, kind, ctx->stream));
-    }
-    launch_gradients64(g, ctx->bg64.U, ctx->bg64.V, ctx->bg64.N2, fstage, bgd + 3 * cells, (double *)ctx->bg64.f2,
+    // the signed Coriolis parameter by row (zero without f); f^2 and (f^2)_y follow
+    if (f)
+        HIP_OK(hipMemcpyAsync(ctx->frow, f, sizeof(double) * g.ny, kind, ctx->stream));
+    else
+        HIP_OK(hipMemsetAsync(ctx->frow, 0, sizeof(double) * g.ny, ctx->stream));
+    launch_gradients64(g, ctx->bg64.U, ctx->bg64.V, ctx->bg64.N2, ctx->frow, bgd + 3 * cells, (double *)ctx->bg64.f2,
                        (double *)ctx->bg64.f2y, ctx->stream);
     if (ctx->precision == RT_FP32) {
         launch_round32(bgd + 12 * cells, (float *)ctx->bp32.f2, 2 * (int64_t)g.ny, ctx->stream);
+        launch_round32(ctx->frow, ctx->frow32, g.ny, ctx->stream);
         launch_pack32(g, ctx->bg64, (float4 *)ctx->bp32.A, (float4 *)ctx->bp32.G, ctx->stream);
     } else {
         launch_pack64(g, ctx->bg64, (double4 *)ctx->bp64.A, (double4 *)ctx->bp64.G, ctx->stream);
@@ -610,6 +612,94 @@ extern "C" rt_status rt_deposit_flux(rt_ctx ctx, double *flux, double *drag, int
         if (drag) HIP_OK(hipMemcpyAsync(drag, ddst, sizeof(double) * nd, hipMemcpyDeviceToHost, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
     }
+    return RT_OK;
+}
+
+// a context scratch array allocated on first use
+static rt_status ensure_scratch(rt_ctx ctx, double **p, size_t n)
+{
+    if (!*p) {
+        *p = (double *)ctx_alloc(ctx, sizeof(double) * n);
+        if (!*p) return rt_fail(ctx, RT_E_NOMEM, "no device memory for %zu doubles of scratch", n);
+    }
+    return RT_OK;
+}
+
+// copy a device result to the caller's pointer (host or device); no copy
+// when the pointer is NULL
+static rt_status hand_out(rt_ctx ctx, double *dst, const double *src, size_t n, int32_t where)
+{
+    if (!dst) return RT_OK;
+    HIP_OK(hipMemcpyAsync(dst, src, sizeof(double) * n,
+                          where == RT_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, ctx->stream));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_full_fluxes(rt_ctx ctx, double *flux, double *tend, int32_t smooth, int32_t where)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    const Grid &g = ctx->g;
+    const size_t plane = (size_t)(g.nz + 1) * g.ncol, cells = (size_t)g.nz * g.ncol;
+    rt_status st = ensure_scratch(ctx, &ctx->full, 8 * plane);
+    if (!st) st = ensure_scratch(ctx, &ctx->fullt, 3 * cells);
+    if (!st && smooth) st = ensure_scratch(ctx, &ctx->fulls, 8 * plane);
+    if (st) return st;
+    prof_begin(ctx, PC_DEPOSIT);
+    if (ctx->precision == RT_FP64)
+        launch_full_fluxes64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->frow, ctx->perm, ctx->colstart, ctx->rho,
+                             ctx->full, ctx->stream);
+    else
+        launch_full_fluxes32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->frow32, ctx->perm, ctx->colstart, ctx->rho,
+                             ctx->full, ctx->stream);
+    const double *F = ctx->full;
+    if (smooth) {
+        launch_smooth(g, ctx->full, ctx->fulls, (int64_t)8 * (g.nz + 1), ctx->stream);
+        F = ctx->fulls;
+    }
+    prof_end(ctx);
+    prof_begin(ctx, PC_DRAG);
+    launch_full_tend(g, ctx->coslat, ctx->rho, ctx->frow, F, ctx->fullt, ctx->stream);
+    prof_end(ctx);
+    HIP_OK(hipGetLastError());
+    st = hand_out(ctx, flux, F, 8 * plane, where);
+    if (!st) st = hand_out(ctx, tend, ctx->fullt, 3 * cells, where);
+    if (st) return st;
+    if (where == RT_HOST) HIP_OK(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_budget(rt_ctx ctx, double *fields, double *terms, int32_t smooth, int32_t where)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    const Grid &g = ctx->g;
+    const size_t plane = (size_t)(g.nz + 1) * g.ncol, cells = (size_t)g.nz * g.ncol;
+    rt_status st = ensure_scratch(ctx, &ctx->bud, 4 * plane);
+    if (!st) st = ensure_scratch(ctx, &ctx->budt, 2 * cells);
+    if (!st && smooth) st = ensure_scratch(ctx, &ctx->buds, 4 * plane);
+    if (st) return st;
+    prof_begin(ctx, PC_DEPOSIT);
+    if (ctx->precision == RT_FP64)
+        launch_budget64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, ctx->bud, ctx->stream);
+    else
+        launch_budget32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, ctx->bud, ctx->stream);
+    const double *F = ctx->bud;
+    if (smooth) {
+        launch_smooth(g, ctx->bud, ctx->buds, (int64_t)4 * (g.nz + 1), ctx->stream);
+        F = ctx->buds;
+    }
+    prof_end(ctx);
+    prof_begin(ctx, PC_DRAG);
+    launch_budget_terms(g, ctx->coslat, F, ctx->budt, ctx->stream);
+    prof_end(ctx);
+    HIP_OK(hipGetLastError());
+    st = hand_out(ctx, fields, F, 4 * plane, where);
+    if (!st) st = hand_out(ctx, terms, ctx->budt, 2 * cells, where);
+    if (st) return st;
+    if (where == RT_HOST) HIP_OK(hipStreamSynchronize(ctx->stream));
     return RT_OK;
 }
 

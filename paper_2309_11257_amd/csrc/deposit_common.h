@@ -52,6 +52,9 @@ __device__ inline void wave_sync()
 // [NF][nzp] and, in the register-profile mode, the staging of a chunk for the
 // level-parallel path ((2 + NF) x 64 words).
 //
+// P::WAVES: waves per SIMD the register-profile form is built for (fewer for
+// payloads with more fields or more live values, so that nothing spills).
+//
 // RP: with at most 128 levels and interfaces the double profile of a wave's
 // column lives in registers (lane j holds levels j and j + 64 of every
 // field), which halves the LDS of a workgroup; at the end it is stored over
@@ -64,7 +67,7 @@ __host__ __device__ inline int dep_wave_words(int nzp)
 }
 
 template <class P, int CPW, bool RP>
-__global__ __launch_bounds__(64 * CPW, RP ? 6 : 2) void k_deposit(Grid g, P pl, const uint32_t *__restrict__ perm,
+__global__ __launch_bounds__(64 * CPW, RP ? P::WAVES : 2) void k_deposit(Grid g, P pl, const uint32_t *__restrict__ perm,
                                                       const uint32_t *__restrict__ colstart, double *__restrict__ flux)
 {
     constexpr int NL = P::NL, NF = P::NL + P::NI;

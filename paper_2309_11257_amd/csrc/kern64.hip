@@ -417,6 +417,7 @@ struct Pay64 {
     double inv_dz;  // unused: the double-precision deposition divides
     static constexpr bool EXACT_LEVELS = true;
     static constexpr int NL = 4, NI = 2;  // horizontal fluxes on levels, vertical on interfaces
+    static constexpr int WAVES = 6;
     __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
         const double x = st.x[s], y = st.y[s], z = st.z[s];

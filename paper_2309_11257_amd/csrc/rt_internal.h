@@ -114,6 +114,13 @@ struct rt_ctx_s {
     double *flux, *drag;
     // saturation: level sums P and sum P_j K_j^2 [2][nz+1][ncol], kappa [nz][ncol]
     double *satpq, *kappa;
+    // signed Coriolis parameter by row (double, and float for an FP32 context)
+    double *frow;
+    float *frow32;
+    // full fluxes and budget (allocated on first use): fields [8 or 4][nz+1][ncol],
+    // their smoothed copy, tendencies [3][nz][ncol]
+    double *full, *fulls, *fullt;
+    double *bud, *buds, *budt;
     // per-column flags: 1 = the surrogate owns the column this step
     uint8_t *frozen;
     bool have_frozen;
@@ -259,6 +266,21 @@ void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *per
                       double *flux, hipStream_t s);
 void launch_drag(const Grid &g, const double *rho, const double *cosr, const double *flux, double *drag, hipStream_t s);
 void launch_coslat(const Grid &g, double *cosr, hipStream_t s);
+// full fluxes [8][nz+1][ncol], budget fields [4][nz+1][ncol], smoothing of
+// [nslices][ncol] slices, the full tendencies [3][nz][ncol] and the budget
+// propagation terms [2][nz][ncol]
+void launch_full_fluxes64(const Grid &g, const Bg64P &b, S64 st, const double *frow, const uint32_t *perm,
+                          const uint32_t *colstart, const double *rho, double *F, hipStream_t s);
+void launch_full_fluxes32(const Grid &g, const Bg32P &b, S32 st, const float *frow, const uint32_t *perm,
+                          const uint32_t *colstart, const double *rho, double *F, hipStream_t s);
+void launch_budget64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart, double *F,
+                     hipStream_t s);
+void launch_budget32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart, double *F,
+                     hipStream_t s);
+void launch_smooth(const Grid &g, const double *in, double *out, int64_t nslices, hipStream_t s);
+void launch_full_tend(const Grid &g, const double *cosr, const double *rho, const double *frow, const double *F,
+                      double *out, hipStream_t s);
+void launch_budget_terms(const Grid &g, const double *cosr, const double *F, double *out, hipStream_t s);
 // spectral saturation of the current (sorted) set: level sums, kappa, damping
 void launch_saturation64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *skeys,
                          const uint32_t *colstart, const DevCounters *dc, const double *rho, double dt, double *PQ,

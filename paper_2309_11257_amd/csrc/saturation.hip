@@ -26,6 +26,7 @@ struct PaySat64 {
     double inv_dz;  // unused: the double-precision levels divide
     static constexpr bool EXACT_LEVELS = true;
     static constexpr int NL = 2, NI = 0;
+    static constexpr int WAVES = 6;
     __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
         (void)col;
@@ -58,6 +59,7 @@ struct PaySat32 {
     double inv_dz;  // its reciprocal (level spans)
     static constexpr bool EXACT_LEVELS = false;
     static constexpr int NL = 2, NI = 0;
+    static constexpr int WAVES = 6;
     __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
         const int jc = (int)((uint32_t)col / (uint32_t)g.nx), ic = col - jc * g.nx;

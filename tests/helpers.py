@@ -110,6 +110,22 @@ def check_flips_at_faces(bg, rs, gpu_rays, cols, face_tol):
     return worst
 
 
+def kernel_columns(bg, rs, gpu_rays, gpu_cols, face_tol=2e-6):
+    """The kernel's column decision for every volume of the oracle's set, in
+    the oracle's order (-1 where inactive); the active sets must agree and
+    every differing decision must sit at a cell face (check_flips_at_faces).
+    Returns (cols, n_column_flips)."""
+    ids = rs["id"]
+    gid = np.asarray(gpu_rays["id"])
+    o = np.argsort(gid, kind="stable")
+    p = o[np.clip(np.searchsorted(gid[o], ids), 0, max(gid.size - 1, 0))] if gid.size else np.zeros(ids.size, int)
+    found = gid[p] == ids if gid.size else np.zeros(ids.size, bool)
+    assert np.array_equal(found, rs.active()), "active sets differ"
+    cols = np.where(found, np.asarray(gpu_cols).astype(np.int64)[p] if gid.size else -1, -1)
+    check_flips_at_faces(bg, rs, gpu_rays, cols, face_tol)
+    return cols, int(((cols != rs["col"]) & (cols >= 0)).sum())
+
+
 def oracle_deposit_with_kernel_decisions(orc, bg, rs, gpu_rays, gpu_cols, face_tol=2e-6):
     """Oracle fluxes of the oracle's own ray states, with the integer
     decisions (which rays are active, which column each belongs to) taken
