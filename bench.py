@@ -30,17 +30,25 @@ sys.path.insert(0, ROOT)
 METRIC = "ray-volume updates/s (RK3+deposit) FP32 vs FP64 at stated drag error"
 UNIT = "ray-volume updates/s"
 
-# algorithmic work per ray volume and step (measurement):
-# state read 13 words, written 9 words
-STEP_BYTES = {"fp32": 88, "fp64": 176}
-# flops of one RK3 step of one ray volume (three stages of: centre
+# algorithmic HBM bytes per ray volume and step of the step kernel: the
+# state read (x, y, z, k, l, m, Dx, Dy, Dz, Px, Py, Pz, N: 13 values) and the
+# 9 evolving values written, at the path's precision -- single precision
+# except the vertical wavenumber, which both precisions hold in double
+# (FP32: 12 x 4 + 8 read, 8 x 4 + 8 written)
+STEP_BYTES = {"fp32": 96, "fp64": 176}
+# estimated flops of one RK3 step of one ray volume (three stages of: centre
 # interpolation of 12 fields, 6 face interpolations, 7 dispersion
 # evaluations, refraction, update), Cartesian count; spherical adds the
-# metric terms
+# metric terms.  An estimate, reported beside the HBM figure only, against
+# the vector rate without packed FP32 (which the build does not use)
 STEP_FLOPS = {"cartesian": 2200, "spherical": 2300}
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_FP64_TFLOPS = 78.6
+# late window: after the timed steps, advance untimed to this step and time
+# LATE_STEPS more (the volumes of a column spread over more levels as a run
+# goes on; the headline window sees the early part)
+LATE_AT, LATE_STEPS = 100, 20
 # sources the counted kernels are built from (their HBM traffic in
 # profiles/traffic.json is used only while these are unchanged)
 KERNEL_SOURCES = {"step": ["paper_2309_11257_amd/csrc/f32.h", "paper_2309_11257_amd/csrc/step32.hip",
@@ -68,7 +76,7 @@ def rel_l2(a, b):
     return float(np.sqrt(((a - b) ** 2).sum() / max((b * b).sum(), 1e-300)))
 
 
-def time_path(w, precision, steps, warmup):
+def time_path(w, precision, steps, warmup, late=True):
     import torch
 
     from paper_2309_11257_amd import _rt
@@ -105,6 +113,30 @@ def time_path(w, precision, steps, warmup):
     prof = tr.profile_read()
     tr.profile(False)
     n1 = tr.stats()["n_active"]
+    # late window (outside the timed region above): steps LATE_AT + 1 ..
+    # LATE_AT + LATE_STEPS of the same run
+    do_late, late = late, None
+    if do_late and LATE_AT > warmup + steps:
+        for _ in range(LATE_AT - warmup - steps):
+            tr.step(w.dt)
+            tr.deposit(flux, drag)
+        torch.cuda.synchronize()
+        m0 = tr.stats()["n_active"]
+        tr.profile(True)
+        tr.profile_read()
+        e0.record()
+        for _ in range(LATE_STEPS):
+            tr.step(w.dt)
+            tr.deposit(flux, drag)
+        e1.record()
+        torch.cuda.synchronize()
+        lms = e0.elapsed_time(e1)
+        lprof = tr.profile_read()
+        tr.profile(False)
+        m1 = tr.stats()["n_active"]
+        late = dict(steps=f"{LATE_AT + 1}-{LATE_AT + LATE_STEPS}", ms_per_step=round(lms / LATE_STEPS, 4),
+                    value=round(0.5 * (m0 + m1) * LATE_STEPS / (lms * 1e-3), 1),
+                    kernels_ms_avg={k: round(v[0] / max(v[1], 1), 4) for k, v in lprof.items()})
     tr.close()
     del flux, drag
     torch.cuda.empty_cache()
@@ -112,7 +144,7 @@ def time_path(w, precision, steps, warmup):
     updates = 0.5 * (n0 + n1) * steps
     return dict(ms_per_step=ms_per_step, wall_s=wall, value=updates / (ms * 1e-3), n_active=(n0, n1),
                 kernels={k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / max(v[1], 1)} for k, v in prof.items()},
-                drag1=drag1, ids1=ids1, cols1=cols1)
+                drag1=drag1, ids1=ids1, cols1=cols1, late=late)
 
 
 CPU_STEPS = 6  # oracle steps in the CPU baseline's sample (about 10 s on 16 threads)
@@ -322,7 +354,53 @@ def rows_report():
     nbytes = w3.n_rays * 48 + ncol * w3.nz * 16 + ncol * (3 * w3.nz + 48) * 4
     out.append(_row("a11", f"global {w3.nx}x{w3.ny}x{w3.nz}, {w3.n_rays} ray volumes", "f32", ms, nbytes, t_f,
                     cores, f"oracle features of the same state ({t_f:.2f} s)", "8 azimuth sectors x 6 moments"))
-    del rs3, bg3
+    # f1, f3: saturation, full fluxes with smoothing and tendencies, budget,
+    # each on the state after one step (densities scaled by 1e3 so that part
+    # of the cells saturate, as in the parity tests)
+    loud = dict(w3.rays)
+    loud["n"] = w3.rays["n"] * 1e3
+    cells = ncol * w3.nz
+    for prec, name in ((_rt.RT_FP32, "f32"), (_rt.RT_FP64, "f64")):
+        tr = _rt.Tracer.for_workload(w3, prec)
+        tr.init_background_from(w3)
+        tr.set_rays(loud)
+        tr.step(w3.dt)
+        K = torch.empty((w3.nz, w3.ny, w3.nx), dtype=torch.float64, device="cuda")
+        ms_sat = _ev_ms(lambda: tr.saturate(w3.dt, kappa=K), 5)
+        ms_full = _ev_ms(lambda: tr.full_fluxes(smooth=True), 5)
+        ms_bud = _ev_ms(lambda: tr.budget(), 5)
+        tr.close()
+        del K
+        vb = 48 if name == "f32" else 120  # state read per volume and pass (with the permutation)
+        t_sat = t_full = t_bud = 0.0
+        if name == "f32":
+            rs3 = oracle.RaySet(loud)
+            oracle.step(bg3, rs3, w3.dt)
+            t = time.perf_counter()
+            oracle.saturation(bg3, rs3, w3.dt)
+            t_sat = time.perf_counter() - t
+            t = time.perf_counter()
+            oracle.full_tendencies(bg3, oracle.smooth(bg3, oracle.full_fluxes(bg3, rs3)))
+            t_full = time.perf_counter() - t
+            t = time.perf_counter()
+            oracle.budget_terms(bg3, oracle.budget(bg3, rs3))
+            t_bud = time.perf_counter() - t
+            del rs3
+        wl = f"global {w3.nx}x{w3.ny}x{w3.nz}, {w3.n_rays} ray volumes"
+        # saturation: two passes over the state (sums, damping with the
+        # wave-action write), P, Q and kappa written and read per cell
+        out.append(_row("f1", wl, name, ms_sat, w3.n_rays * (2 * vb + 8) + cells * 48, t_sat, cores,
+                        f"oracle saturation of the same state ({t_sat:.2f} s)" if t_sat else "",
+                        "per-cell P and sum P K^2, kappa, overlap-weighted damping"))
+        # full fluxes: one pass over the state; 8 fields written, smoothed
+        # (read and written), read by the tendencies, 3 tendencies written
+        out.append(_row("f3-fluxes", wl, name, ms_full, w3.n_rays * vb + (ncol * (w3.nz + 1)) * 8 * 8 * 4 + cells * 24,
+                        t_full, cores, f"oracle full fluxes, smoothing and tendencies ({t_full:.2f} s)" if t_full else "",
+                        "momentum flux tensor, buoyancy flux, 3/2/1 smoothing, elastic term"))
+        out.append(_row("f3-budget", wl, name, ms_bud, w3.n_rays * vb + (ncol * (w3.nz + 1)) * 4 * 8 * 2 + cells * 16,
+                        t_bud, cores, f"oracle budget fields and terms ({t_bud:.2f} s)" if t_bud else "",
+                        "A, cg_h A, cg_z A and the propagation terms"))
+    del bg3
     # a9 + a10: split (alpha = 2) and per-cell merge (64) on the jet box
     w2 = W.make_c2()
     cap = 2 * w2.n_rays
@@ -383,6 +461,7 @@ def main():
     ap.add_argument("--rays", type=int, default=20_000_000, help="ray volumes (default: the full workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline and the oracle drag error")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-late", action="store_true", help="skip the late window (steps 101-120)")
     ap.add_argument("--surrogate", action="store_true",
                     help="also train the column surrogate and run it coupled with the tracer on 50 M volumes")
     ap.add_argument("--rows", action="store_true",
@@ -419,11 +498,11 @@ def main():
     w = W.make_c3(n_rays=args.rays)
     log(f"workload: {w.n_rays} ray volumes on {w.nx}x{w.ny}x{w.nz} ({time.perf_counter() - t:.1f} s)")
 
-    r32 = time_path(w, _rt.RT_FP32, args.steps, args.warmup)
+    r32 = time_path(w, _rt.RT_FP32, args.steps, args.warmup, late=not args.no_late)
     log(f"fp32: {r32['ms_per_step']:.3f} ms/step, {r32['value'] / 1e9:.2f} G upd/s, kernels {r32['kernels']}")
     r64 = None
     if not args.no_fp64:
-        r64 = time_path(w, _rt.RT_FP64, args.steps, args.warmup)
+        r64 = time_path(w, _rt.RT_FP64, args.steps, args.warmup, late=not args.no_late)
         log(f"fp64: {r64['ms_per_step']:.3f} ms/step, {r64['value'] / 1e9:.2f} G upd/s, kernels {r64['kernels']}")
 
     cpu = None
@@ -442,26 +521,33 @@ def main():
     nray = 0.5 * (r32["n_active"][0] + r32["n_active"][1])
     avg_s = kd["ms_avg"] * 1e-3
     geom = "spherical" if w.geometry == W.SPHERICAL else "cartesian"
+    cells = w.nx * w.ny * w.nz
     if name == "step":
+        # HBM roofline on the algorithmic bytes of the step kernel; the flop
+        # estimate against the unpacked vector rate is reported beside it
         gbs = STEP_BYTES["fp32"] * nray / avg_s / 1e9
         tflops = STEP_FLOPS[geom] * nray / avg_s / 1e12
-        hbm_frac = gbs / PEAK_HBM_GBS
-        alu_frac = tflops / PEAK_FP32_TFLOPS
         traffic = load_traffic("step", w.n_rays)
-        if alu_frac >= hbm_frac:
-            roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(alu_frac, 4), "traffic": traffic, "kernel": "k_step32",
-                    "hbm_achieved_GBs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4)}
-        else:
-            roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(hbm_frac, 4), "traffic": traffic, "kernel": "k_step32",
-                    "alu_achieved_TFLOPs": round(tflops, 3), "alu_frac": round(alu_frac, 4)}
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": "k_step32",
+                "algorithmic_bytes_per_launch": int(STEP_BYTES["fp32"] * nray),
+                "traffic_over_algorithmic": None if traffic is None else round(traffic / (STEP_BYTES["fp32"] * nray), 3),
+                "alu_estimate": {"flops_per_volume": STEP_FLOPS[geom], "achieved_TFLOPs": round(tflops, 3),
+                                 "peak_unpacked_TFLOPs": PEAK_FP32_UNPACKED_TFLOPS,
+                                 "frac": round(tflops / PEAK_FP32_UNPACKED_TFLOPS, 4)}}
     else:
         # deposition / sort / drag are HBM work: algorithmic bytes per ray
-        per = {"deposit": 36 + 0, "sort": 40, "drag": 0}[name] if name in ("deposit", "sort", "drag") else 0
+        per = {"deposit": 40, "sort": 40, "drag": 0}[name] if name in ("deposit", "sort", "drag") else 0
         gbs = per * nray / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": load_traffic(name, w.n_rays), "kernel": name}
+    # the whole step (step, sort, deposition, drag) against the HBM roofline
+    # of its algorithmic bytes: the state per volume plus, per cell, the
+    # background read (3 fields), the six flux fields (double) and the drag
+    # (2 fields, double)
+    step_bytes = STEP_BYTES["fp32"] * nray + cells * (3 * 4 + 6 * 8 + 2 * 8)
+    roof["whole_step"] = {"algorithmic_bytes": int(step_bytes), "ms": round(r32["ms_per_step"], 4),
+                          "frac": round(step_bytes / (r32["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     roof["kernel_ms_avg"] = round(kd["ms_avg"], 4)
 
     out = {
@@ -485,6 +571,8 @@ def main():
                                           "dtype": "f64"},
         "kernels_ms_avg": {k: round(v["ms_avg"], 4) for k, v in r32["kernels"].items()},
         "kernels_ms_avg_fp64": None if r64 is None else {k: round(v["ms_avg"], 4) for k, v in r64["kernels"].items()},
+        "late": r32["late"],
+        "late_fp64": None if r64 is None else r64["late"],
         "roofline": roof,
         "cpu_baseline": cpu,
     }
