@@ -54,10 +54,17 @@ class _Rays(C.Structure):
 class Tally(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_active", "n_top", "n_bottom", "n_pole", "n_invalid",
                                          "n_merged", "n_capped", "n_split")] + \
-               [(n, C.c_double) for n in ("sum_W", "sum_kW", "sum_lW", "sum_mW", "removed_W")]
+               [(n, C.c_double) for n in ("sum_W", "sum_kW", "sum_lW", "sum_mW", "removed_W")] + \
+               [("n_launched", C.c_int64), ("launched_W", C.c_double)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class LaunchParams(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("z_launch", "dt", "t_solstice", "F_s", "F_w", "lambda_h", "c_min", "c_max",
+                                          "c_center", "c_width")] + \
+               [("n_speeds", C.c_int32), ("flux_col", C.c_void_p)]
 
 
 _lib: Optional[C.CDLL] = None
@@ -132,6 +139,10 @@ def _load(path: str) -> C.CDLL:
     L.orc_full_tendencies.argtypes = [P, P, P]
     L.orc_budget.argtypes = [P, P, C.c_int64, P, C.c_int]
     L.orc_budget_terms.argtypes = [P, P, P]
+    L.orc_launch_flux.argtypes = [P, C.c_int, P]
+    L.orc_launch_flux.restype = C.c_double
+    L.orc_launch.argtypes = [P, P, C.c_int64, C.c_int64, P, P, P]
+    L.orc_launch.restype = C.c_int64
     L.orc_num_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [C.c_int]
     return L
@@ -394,6 +405,35 @@ def budget_terms(bg: Background, fields4: np.ndarray) -> np.ndarray:
     out = np.zeros((2, bg.nz, bg.ny, bg.nx))
     lib().orc_budget_terms(bg.ref, _ptr(f), _ptr(out))
     return out
+
+
+def launch_params(z_launch, dt, t_solstice=0.0, F_s=2.4e-3, F_w=8.0e-3, lambda_h=300e3, c_min=2.0, c_max=62.0,
+                  c_center=25.0, c_width=15.0, n_speeds=8, flux_col=None):
+    """Parameters of orc_launch; flux_col (numpy [ny*nx], Pa) is kept alive
+    on the returned structure."""
+    p = LaunchParams(z_launch, dt, t_solstice, F_s, F_w, lambda_h, c_min, c_max, c_center, c_width, n_speeds, None)
+    if flux_col is not None:
+        p._flux = np.ascontiguousarray(flux_col, dtype=np.float64)
+        p.flux_col = _ptr(p._flux)
+    return p
+
+
+def launch_flux(bg: Background, j: int, p: LaunchParams) -> float:
+    return float(lib().orc_launch_flux(bg.ref, int(j), C.byref(p)))
+
+
+def launch(bg: Background, rs: RaySet, p: LaunchParams, next_id: Optional[int] = None) -> dict:
+    """Append the volumes launched this step (orc_launch); returns the tally
+    with the next free id."""
+    t = Tally()
+    nid = C.c_int64(int(rs.a["id"][: rs.n].max()) + 1 if next_id is None and rs.n else (next_id or 0))
+    out = lib().orc_launch(bg.ref, rs.ref, rs.n, rs.cap, C.byref(p), C.byref(nid), C.byref(t))
+    if out < 0:
+        raise RuntimeError("launch exceeds capacity")
+    rs.n = int(out)
+    d = t.as_dict()
+    d["next_id"] = nid.value
+    return d
 
 
 def set_threads(n: int) -> None:

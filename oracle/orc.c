@@ -1529,3 +1529,134 @@ void orc_budget_terms(const orc_bg *g, const double *fields4, double *terms2)
                 terms2[cells + at] = (fields4[3 * plane + IDX(g, i, j, k + 1)] - fields4[3 * plane + at]) / g->dz;
             }
 }
+
+/* ------------------------------------------------------------------------
+ * Continuous launch (Section 3c, sources): a ghost layer below the launch
+ * height holds, in every column, the launch spectrum; each step the part of
+ * it that has propagated up out of the layer during dt is separated and
+ * activated as a new ray volume.
+ *  - Column launch flux: flux_col[c] if given, else on the sphere the
+ *    background source F_am(phi, t) = 1/2 [F_sol(phi)(1 + cos tau) +
+ *    F_sol(-phi)(1 - cos tau)], tau = 2 pi t / year, F_sol(phi) = alpha(phi)
+ *    F_s + alpha(-phi) F_w, phi of the row centre in degrees.
+ *  - Spectrum: four horizontal directions (east, north, west, south) with a
+ *    quarter of the flux each; intrinsic phase speeds c_b at the centres of
+ *    n_speeds equal bins of [c_min, c_max], weighted by
+ *    exp(-((c_b - c_center)/c_width)^2) normalised over the bins; one
+ *    horizontal wavelength.
+ *  - At the column centre at the launch height: omega_hat = kh c_b; a bin
+ *    propagates vertically only for f^2 < omega_hat^2 < N^2 (the others are
+ *    reflected in the ghost layer and discarded, their flux with them);
+ *    m = -sqrt(kh^2 (N^2 - omega_hat^2) / (omega_hat^2 - f^2)) (upward).
+ *  - New volume: what crossed the launch height during dt, from z_launch to
+ *    z_launch + cg_z dt; horizontal extents one cell at the column centre;
+ *    dk = dl = kh/10, dm = |m|/10; wave action W = F_bin A dt / kh (A the
+ *    cell's area at the launch height), so that the volume carries the
+ *    bin's pseudo-momentum flux; N = W / (Px Py Pz).
+ * New volumes are appended in order of column, direction, phase speed, with
+ * consecutive ids from *next_id.  Returns the new count, or -1 (nothing
+ * changed) if the capacity is short.
+ * ------------------------------------------------------------------------ */
+#define ORC_PI 3.14159265358979323846
+#define ORC_YEAR (365.25 * 86400.0)
+
+static double source_alpha(double phi_deg)
+{
+    if (phi_deg >= 80.0) {
+        double a = 1.0 - (phi_deg - 80.0) / 5.0;
+        if (a < 0.0) a = 0.0;
+        if (a > 1.0) a = 1.0;
+        return a;
+    }
+    if (phi_deg >= 50.0) return 1.0;
+    if (phi_deg >= 20.0) return 0.5 * (1.0 - cos(ORC_PI * (phi_deg - 20.0) / 30.0));
+    return 0.0;
+}
+
+double orc_launch_flux(const orc_bg *g, int j, const orc_launch_params *p)
+{
+    double phi, tau, fsol_n, fsol_s;
+    if (p->flux_col) return 0.0; /* per column: see orc_launch */
+    if (g->geometry != ORC_SPHERICAL) return 0.0;
+    phi = (g->y0 + ((double)j + 0.5) * g->dy) * (180.0 / ORC_PI);
+    tau = (2.0 * ORC_PI) * (p->t_solstice / ORC_YEAR);
+    fsol_n = source_alpha(phi) * p->F_s + source_alpha(-phi) * p->F_w;
+    fsol_s = source_alpha(-phi) * p->F_s + source_alpha(phi) * p->F_w;
+    return 0.5 * (fsol_n * (1.0 + cos(tau)) + fsol_s * (1.0 - cos(tau)));
+}
+
+int64_t orc_launch(const orc_bg *g, orc_rays *r, int64_t n, int64_t capacity, const orc_launch_params *p,
+                   int64_t *next_id, orc_tally *t)
+{
+    static const double dir_k[4] = {1.0, 0.0, -1.0, 0.0};
+    static const double dir_l[4] = {0.0, 1.0, 0.0, -1.0};
+    int ncol = g->nx * g->ny;
+    int pass, c, d, b;
+    double sw = 0.0, kh = (2.0 * ORC_PI) / p->lambda_h;
+    int64_t out = n, count = 0;
+    for (b = 0; b < p->n_speeds; b++) {
+        double cb = p->c_min + (((double)b + 0.5) * (p->c_max - p->c_min)) / (double)p->n_speeds;
+        double s = (cb - p->c_center) / p->c_width;
+        sw += exp(-(s * s));
+    }
+    for (pass = 0; pass < 2; pass++) {
+        if (pass == 1 && n + count > capacity) return -1;
+        for (c = 0; c < ncol; c++) {
+            int i = c % g->nx, j = c / g->nx;
+            double x = g->x0 + ((double)i + 0.5) * g->dx, y = g->y0 + ((double)j + 0.5) * g->dy;
+            double Fc = p->flux_col ? p->flux_col[c] : orc_launch_flux(g, j, p);
+            double B[14];
+            if (!(Fc > 0.0)) continue;
+            orc_interp(g, x, y, p->z_launch, B);
+            for (d = 0; d < 4; d++)
+                for (b = 0; b < p->n_speeds; b++) {
+                    double cb = p->c_min + (((double)b + 0.5) * (p->c_max - p->c_min)) / (double)p->n_speeds;
+                    double s = (cb - p->c_center) / p->c_width;
+                    double Fb = (0.25 * Fc) * (exp(-(s * s)) / sw);
+                    double om = kh * cb, om2 = om * om, N2 = B[2], f2 = B[12];
+                    double m, k, l, D[4], Dz, z, A, W, dk, dm, px, py, pz;
+                    int64_t o;
+                    if (!(om2 > f2 && om2 < N2) || !(Fb > 0.0)) continue;
+                    if (pass == 0) {
+                        count++;
+                        continue;
+                    }
+                    m = -sqrt(((kh * kh) * (N2 - om2)) / (om2 - f2));
+                    k = kh * dir_k[d];
+                    l = kh * dir_l[d];
+                    orc_dispersion(N2, f2, k, l, m, D);
+                    Dz = D[3] * p->dt;
+                    z = p->z_launch + 0.5 * Dz;
+                    A = cell_area(g, j, p->z_launch);
+                    W = ((Fb * A) * p->dt) / kh;
+                    dk = 0.1 * kh;
+                    dm = 0.1 * fabs(m);
+                    px = metric_x(g, y, z, g->dx) * dk;
+                    py = metric_y(g, z, g->dy) * dk;
+                    pz = Dz * dm;
+                    o = out++;
+                    r->x[o] = x;
+                    r->y[o] = y;
+                    r->z[o] = z;
+                    r->k[o] = k;
+                    r->l[o] = l;
+                    r->m[o] = m;
+                    r->dx[o] = g->dx;
+                    r->dy[o] = g->dy;
+                    r->dz[o] = Dz;
+                    r->px[o] = px;
+                    r->py[o] = py;
+                    r->pz[o] = pz;
+                    r->n[o] = W / ((px * py) * pz);
+                    r->id[o] = (*next_id)++;
+                    r->state[o] = ORC_ACTIVE;
+                    r->col[o] = c;
+                    if (t) {
+                        t->n_launched++;
+                        t->launched_W += W;
+                    }
+                }
+        }
+    }
+    return out;
+}

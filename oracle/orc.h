@@ -65,7 +65,22 @@ typedef struct {
 typedef struct {
     int64_t n_active, n_top, n_bottom, n_pole, n_invalid, n_merged, n_capped, n_split;
     double sum_W, sum_kW, sum_lW, sum_mW, removed_W;
+    int64_t n_launched;
+    double launched_W;
 } orc_tally;
+
+/* continuous launch from a ghost layer (orc_launch) */
+typedef struct {
+    double z_launch;           /* top of the ghost layer: the launch height (m) */
+    double dt;                 /* the step whose crossing the new volumes represent (s) */
+    double t_solstice;         /* time since the northern summer solstice (s) */
+    double F_s, F_w;           /* summer and winter launch fluxes of the latitudinal profile (Pa) */
+    double lambda_h;           /* horizontal wavelength (m) */
+    double c_min, c_max;       /* range of intrinsic horizontal phase speeds (m/s) */
+    double c_center, c_width;  /* Gaussian spectral weight over the phase speeds */
+    int32_t n_speeds;          /* phase-speed bins */
+    const double *flux_col;    /* [ny*nx] launch flux per column (Pa), or NULL: the profile (sphere) */
+} orc_launch_params;
 
 void orc_prepare(orc_bg *g);
 void orc_interp(const orc_bg *g, double x, double y, double z, double out[14]);
@@ -89,6 +104,9 @@ void orc_divergence(const orc_bg *g, const double *Fx, const double *Fy, const d
 void orc_full_tendencies(const orc_bg *g, const double *flux8, double *out3);
 void orc_budget(const orc_bg *g, orc_rays *r, int64_t n, double *fields4, int given_cols);
 void orc_budget_terms(const orc_bg *g, const double *fields4, double *terms2);
+double orc_launch_flux(const orc_bg *g, int j, const orc_launch_params *p);
+int64_t orc_launch(const orc_bg *g, orc_rays *r, int64_t n, int64_t capacity, const orc_launch_params *p,
+                   int64_t *next_id, orc_tally *t);
 int orc_num_threads(void);
 void orc_set_threads(int n);
 

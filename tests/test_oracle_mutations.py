@@ -8,11 +8,32 @@ each case.  CPU only."""
 import pytest
 
 import test_oracle_fullflux as X
+import test_oracle_launch as L
 import test_oracle_pins as P
 import test_oracle_pins_sphere as S
 import test_oracle_saturation as T
 
 MUTATIONS = [
+    ("launch flux split in two directions instead of four",
+     "double Fb = (0.25 * Fc) * (exp(-(s * s)) / sw);",
+     "double Fb = (0.5 * Fc) * (exp(-(s * s)) / sw);",
+     [L.test_launch_carries_the_column_flux]),
+    ("launch keeps inertial bins",
+     "if (!(om2 > f2 && om2 < N2) || !(Fb > 0.0)) continue;",
+     "if (!(om2 < N2) || !(Fb > 0.0)) continue;",
+     [L.test_launch_discards_bins_that_cannot_propagate]),
+    ("launched volume covers half the crossing",
+     "Dz = D[3] * p->dt;",
+     "Dz = D[3] * (0.5 * p->dt);",
+     [L.test_launch_carries_the_column_flux]),
+    ("seasonal cycle with the hemispheres swapped",
+     "return 0.5 * (fsol_n * (1.0 + cos(tau)) + fsol_s * (1.0 - cos(tau)));",
+     "return 0.5 * (fsol_n * (1.0 - cos(tau)) + fsol_s * (1.0 + cos(tau)));",
+     [L.test_source_profile_and_season_golden]),
+    ("source ramp between 20 and 50 degrees inverted",
+     "if (phi_deg >= 20.0) return 0.5 * (1.0 - cos(ORC_PI * (phi_deg - 20.0) / 30.0));",
+     "if (phi_deg >= 20.0) return 0.5 * (1.0 + cos(ORC_PI * (phi_deg - 20.0) / 30.0));",
+     [L.test_source_profile_and_season_golden]),
     ("full flux: f^2 term of Fxu with the wrong sign",
      "v[0] = a1 * (D[1] * k) + a2 * (D[2] * l); /* Fxu */",
      "v[0] = a1 * (D[1] * k) - a2 * (D[2] * l); /* Fxu */",
