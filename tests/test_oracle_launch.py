@@ -112,24 +112,30 @@ def test_launch_discards_bins_that_cannot_propagate(orc):
     N2, f0 = 1e-4, 1e-4
     w = _box(N2, f0)
     bg = orc.Background.from_workload(w)
-    lam = 100e3
-    kh = 2 * math.pi / lam
-    # intrinsic frequencies kh c span below f and above N
-    cmin, cmax, nb = 0.5, 200.0, 16
-    cb = cmin + (np.arange(nb) + 0.5) * (cmax - cmin) / nb
-    om = kh * cb
-    prop = (om > f0) & (om < math.sqrt(N2))
-    assert 0 < prop.sum() < nb
-    wts = np.exp(-(((cb - 50.0) / 40.0) ** 2))
     flux = np.full(w.nx * w.ny, 2e-3)
-    p = orc.launch_params(8e3, 30.0, lambda_h=lam, c_min=cmin, c_max=cmax, c_center=50.0, c_width=40.0,
-                          n_speeds=nb, flux_col=flux)
-    rs = orc.RaySet({f: np.zeros(0) for f in orc.RAY_FIELDS} | {"id": np.zeros(0, np.int64)}, capacity=10000)
-    orc.launch(bg, rs, p, next_id=0)
-    assert rs.n == 4 * int(prop.sum()) * w.nx * w.ny
-    Wv = rs["n"] * rs["px"] * rs["py"] * rs["pz"]
-    tot = (kh * Wv).sum()
-    assert tot == pytest.approx(flux.sum() * w.dx * w.dy * 30.0 * wts[prop].sum() / wts.sum(), rel=1e-12)
+    kinds = set()
+    # a long wavelength puts the slow bins below f (inertial), a short one
+    # puts the fast bins above N
+    for lam, cmin, cmax in ((1000e3, 1.0, 100.0), (100e3, 0.5, 200.0)):
+        kh = 2 * math.pi / lam
+        nb = 16
+        cb = cmin + (np.arange(nb) + 0.5) * (cmax - cmin) / nb
+        om = kh * cb
+        prop = (om > f0) & (om < math.sqrt(N2))
+        assert 0 < prop.sum() < nb
+        kinds |= {"inertial"} if (om <= f0).any() else set()
+        kinds |= {"fast"} if (om >= math.sqrt(N2)).any() else set()
+        wts = np.exp(-(((cb - 50.0) / 40.0) ** 2))
+        p = orc.launch_params(8e3, 30.0, lambda_h=lam, c_min=cmin, c_max=cmax, c_center=50.0, c_width=40.0,
+                              n_speeds=nb, flux_col=flux)
+        rs = orc.RaySet({f: np.zeros(0) for f in orc.RAY_FIELDS} | {"id": np.zeros(0, np.int64)}, capacity=10000)
+        orc.launch(bg, rs, p, next_id=0)
+        assert rs.n == 4 * int(prop.sum()) * w.nx * w.ny
+        assert np.isfinite(rs["m"]).all()
+        Wv = rs["n"] * rs["px"] * rs["py"] * rs["pz"]
+        tot = (kh * Wv).sum()
+        assert tot == pytest.approx(flux.sum() * w.dx * w.dy * 30.0 * wts[prop].sum() / wts.sum(), rel=1e-12)
+    assert kinds == {"inertial", "fast"}
     small = orc.RaySet({f: np.zeros(0) for f in orc.RAY_FIELDS} | {"id": np.zeros(0, np.int64)}, capacity=rs.n - 1)
     with pytest.raises(RuntimeError):
         orc.launch(bg, small, p, next_id=0)
