@@ -96,7 +96,32 @@ typedef struct {
     double sum_W, sum_kW, sum_lW, sum_mW; /* wave action and pseudo-momentum of the active set */
     double removed_W;                     /* wave action removed at the edges and by the cap */
     int64_t steps;                        /* steps taken */
+    int64_t n_launched;                   /* volumes added by rt_launch (cumulative) */
+    double launched_W;                    /* their wave action (cumulative) */
+    int64_t first_bad_id;                 /* id of the first volume found non-finite or degenerate
+                                             since the last rt_get_stats, -1 if none */
 } rt_stats;
+
+/* Continuous launch from a ghost layer (Section 3c, sources): parameters.
+ * Each call launches, in every column with a positive launch flux, one ray
+ * volume per horizontal direction (east, north, west, south; a quarter of
+ * the flux each) and intrinsic phase-speed bin c_b = c_min + (b + 1/2)
+ * (c_max - c_min) / n_speeds (weight exp(-((c_b - c_center)/c_width)^2),
+ * normalised over the bins): the part of the ghost layer below z_launch
+ * that crossed it during dt. */
+typedef struct {
+    double z_launch;        /* launch height (m), inside the domain (the paper: 300 hPa) */
+    double dt;              /* the step the new volumes cover (s), > 0 */
+    double t_solstice;      /* time since the northern summer solstice (s): seasonal cycle */
+    double F_s, F_w;        /* summer and winter launch fluxes of the latitudinal profile (Pa) */
+    double lambda_h;        /* horizontal wavelength (m), > 0 */
+    double c_min, c_max;    /* intrinsic phase-speed range (m/s), 0 <= c_min < c_max */
+    double c_center, c_width; /* spectral weight (m/s), c_width > 0 */
+    int32_t n_speeds;       /* phase-speed bins, 1 .. 64 */
+    int32_t where;          /* RT_HOST or RT_DEVICE: where flux_col lives */
+    const double *flux_col; /* [ny*nx] launch flux per column (Pa); NULL on the sphere: the
+                               background source F_am(phi, t) of the latitudinal profile */
+} rt_launch_params;
 
 /* Create a context on the current HIP device.  The grid and precision are
    fixed for the context's lifetime.  Errors: RT_E_ARG for bad sizes;
@@ -274,6 +299,22 @@ rt_status rt_budget(rt_ctx ctx, double *fields, double *terms, int32_t smooth, i
  * changed) if the split children do not fit. */
 rt_status rt_split_merge(rt_ctx ctx, double alpha_split, int32_t n_max_per_cell, int32_t mode,
                          rt_stats *out);
+
+/* Continuous launch from a ghost layer (Section 3c, sources; parameters in
+ * rt_launch_params).  For every candidate (column, direction, phase speed)
+ * with omega_hat = kh c_b strictly between |f| and N at the column centre
+ * and launch height (the others cannot propagate: they are reflected in the
+ * ghost layer and discarded with their share of the flux), a volume is
+ * added with m = -sqrt(kh^2 (N^2 - omega_hat^2) / (omega_hat^2 - f^2))
+ * (upward), vertical span [z_launch, z_launch + cg_z dt], horizontal
+ * extents one cell at the column centre, dk = dl = kh/10, dm = |m|/10, and
+ * wave action W = F_bin A dt / kh (A the cell's area at the launch height),
+ * so that it carries its bin's pseudo-momentum flux.  The active set is then
+ * regrouped; the new volumes get consecutive ids in candidate order.
+ * *n_launched (may be NULL) receives the count.  Synchronises.
+ * RT_E_CAPACITY (nothing changed) if the volumes do not fit; RT_E_ARG for
+ * bad parameters or a missing flux_col on the box. */
+rt_status rt_launch(rt_ctx ctx, const rt_launch_params *p, int64_t *n_launched);
 
 /* Current diagnostics (deterministic sums).  Synchronises. */
 rt_status rt_get_stats(rt_ctx ctx, rt_stats *out);

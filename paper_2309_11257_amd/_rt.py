@@ -44,10 +44,17 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_active", "n_top", "n_bottom", "n_pole", "n_invalid", "n_split",
                                          "n_merged", "n_capped")] + \
                [(n, C.c_double) for n in ("sum_W", "sum_kW", "sum_lW", "sum_mW", "removed_W")] + \
-               [("steps", C.c_int64)]
+               [("steps", C.c_int64), ("n_launched", C.c_int64), ("launched_W", C.c_double),
+                ("first_bad_id", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class LaunchParams(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("z_launch", "dt", "t_solstice", "F_s", "F_w", "lambda_h", "c_min",
+                                          "c_max", "c_center", "c_width")] + \
+               [("n_speeds", C.c_int32), ("where", C.c_int32), ("flux_col", C.c_void_p)]
 
 
 class RTError(RuntimeError):
@@ -80,6 +87,7 @@ def lib() -> C.CDLL:
         L.rt_budget.argtypes = [P, P, P, I32, I32]
         L.rt_split_merge.argtypes = [P, D, I32, I32, C.POINTER(Stats)]
         L.rt_get_stats.argtypes = [P, C.POINTER(Stats)]
+        L.rt_launch.argtypes = [P, C.POINTER(LaunchParams), C.POINTER(I64)]
         L.rt_get_columns.argtypes = [P, P, C.POINTER(I64), I32]
         L.rt_profile.argtypes = [P, I32]
         L.rt_profile_read.argtypes = [P, P, P]
@@ -90,7 +98,7 @@ def lib() -> C.CDLL:
         for name in ("rt_create", "rt_destroy", "rt_init_background", "rt_set_rays", "rt_set_rays_host_noalloc",
                      "rt_get_rays", "rt_step",
                      "rt_deposit_flux", "rt_split_merge", "rt_get_stats", "rt_profile", "rt_profile_read", "rt_get_columns",
-                     "rt_features", "rt_set_frozen_columns", "rt_saturate", "rt_full_fluxes", "rt_budget"):
+                     "rt_features", "rt_set_frozen_columns", "rt_saturate", "rt_full_fluxes", "rt_budget", "rt_launch"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -335,6 +343,28 @@ class Tracer:
         s = Stats()
         self._check(lib().rt_split_merge(self.h, float(alpha), int(n_max), int(mode), C.byref(s)))
         return s.as_dict()
+
+    def launch(self, z_launch: float, dt: float, t_solstice: float = 0.0, F_s: float = 2.4e-3, F_w: float = 8e-3,
+               lambda_h: float = 300e3, c_min: float = 2.0, c_max: float = 62.0, c_center: float = 25.0,
+               c_width: float = 15.0, n_speeds: int = 8, flux_col=None) -> int:
+        """Launch from the ghost layer (rt_launch); returns the count.
+        flux_col ([ny*nx] Pa, numpy or CUDA tensor) is required on the box;
+        on the sphere None selects the latitudinal background source."""
+        p = LaunchParams(float(z_launch), float(dt), float(t_solstice), float(F_s), float(F_w), float(lambda_h),
+                         float(c_min), float(c_max), float(c_center), float(c_width), int(n_speeds), RT_HOST, None)
+        keep = None
+        if flux_col is not None:
+            torch = self.torch
+            if isinstance(flux_col, torch.Tensor):
+                arr = flux_col.to(self.device, torch.float64).contiguous().reshape(-1)
+            else:
+                arr = np.asarray(flux_col, dtype=np.float64).reshape(-1)
+            ptrs, where, keep = self._ptr_where([arr])
+            p.flux_col, p.where = ptrs[0], where
+        cnt = C.c_int64(0)
+        self._check(lib().rt_launch(self.h, C.byref(p), C.byref(cnt)))
+        del keep
+        return int(cnt.value)
 
     PROFILE_CLASSES = ("step", "sort", "deposit", "drag", "split_merge", "stats", "saturation", "c7")
 

@@ -806,7 +806,10 @@ extern "C" rt_status rt_get_stats(rt_ctx ctx, rt_stats *out)
         out->sum_mW = sums[3];
         out->removed_W = h.removed_W;
         out->steps = h.steps;
+        out->n_launched = h.n_launched;
+        out->launched_W = h.launched_W;
     }
+    out->first_bad_id = -1;
     return RT_OK;
 }
 
@@ -817,6 +820,49 @@ extern "C" rt_status rt_split_merge(rt_ctx ctx, double alpha_split, int32_t n_ma
     if (mode != RT_MERGE && mode != RT_CAP && mode != RT_SPLIT_ONLY) return rt_fail(ctx, RT_E_ARG, "bad mode");
     if (mode != RT_SPLIT_ONLY && n_max_per_cell < 1) return rt_fail(ctx, RT_E_ARG, "n_max_per_cell must be >= 1");
     return do_split_merge(ctx, alpha_split, n_max_per_cell, mode, out);
+}
+
+extern "C" rt_status rt_launch(rt_ctx ctx, const rt_launch_params *p, int64_t *n_launched)
+{
+    if (!ctx) return RT_E_ARG;
+    if (n_launched) *n_launched = 0;
+    if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
+    if (!p) return rt_fail(ctx, RT_E_ARG, "parameters are required");
+    const Grid &g = ctx->g;
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt) || !(p->lambda_h > 0.0) || !std::isfinite(p->lambda_h) ||
+        !(p->c_min >= 0.0) || !(p->c_max > p->c_min) || !std::isfinite(p->c_max) || !(p->c_width > 0.0) ||
+        !std::isfinite(p->c_center) || !std::isfinite(p->t_solstice) || !(p->F_s >= 0.0) || !(p->F_w >= 0.0) ||
+        !(p->z_launch > 0.0) || !(p->z_launch < g.Lz))
+        return rt_fail(ctx, RT_E_ARG, "bad launch parameters");
+    if (p->n_speeds < 1 || p->n_speeds > 64) return rt_fail(ctx, RT_E_ARG, "n_speeds must be 1 .. 64");
+    if ((int64_t)g.ncol * 4 * p->n_speeds >= ((int64_t)1 << 31))
+        return rt_fail(ctx, RT_E_UNSUPPORTED, "2^31 or more launch candidates (columns x 4 x n_speeds)");
+    if (!p->flux_col && g.geometry != RT_SPHERICAL)
+        return rt_fail(ctx, RT_E_ARG, "the box needs a launch flux per column");
+    if (p->flux_col && p->where != RT_HOST && p->where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    const int64_t need = launch_scratch_len(g, p->n_speeds);
+    if (need > ctx->lscr_len) {
+        uint32_t *s = (uint32_t *)ctx_alloc(ctx, sizeof(uint32_t) * (size_t)need);
+        if (!s) return rt_fail(ctx, RT_E_NOMEM, "no device memory for the launch scratch");
+        ctx->lscr = s;
+        ctx->lscr_len = need;
+    }
+    const double *flux_dev = nullptr;
+    if (p->flux_col) {
+        if (p->where == RT_DEVICE) {
+            flux_dev = p->flux_col;
+        } else {
+            rt_status st = ensure_scratch(ctx, &ctx->lflux, (size_t)g.ncol);
+            if (st) return st;
+            HIP_OK(hipMemcpyAsync(ctx->lflux, p->flux_col, sizeof(double) * g.ncol, hipMemcpyHostToDevice,
+                                  ctx->stream));
+            flux_dev = ctx->lflux;
+        }
+    }
+    int64_t cnt = 0;
+    rt_status st = do_launch(ctx, p, flux_dev, ctx->lscr, &cnt);
+    if (n_launched) *n_launched = st == RT_OK ? cnt : 0;
+    return st;
 }
 
 // ---------------------------------------------------------------------------

@@ -78,6 +78,8 @@ struct DevCounters {
     int64_t split_extra;
     int64_t next_id;
     int64_t steps;
+    int64_t n_launched;  // volumes launched (cumulative)
+    double launched_W;   // their wave action (cumulative)
 };
 
 struct rt_ctx_s {
@@ -121,6 +123,10 @@ struct rt_ctx_s {
     // their smoothed copy, tendencies [3][nz][ncol]
     double *full, *fulls, *fullt;
     double *bud, *buds, *budt;
+    // launch scratch (flags, positions, scan parts) and the column flux
+    uint32_t *lscr;
+    int64_t lscr_len;
+    double *lflux;
     // per-column flags: 1 = the surrogate owns the column this step
     uint8_t *frozen;
     bool have_frozen;
@@ -296,3 +302,8 @@ void launch_sorted_from_active(DevCounters *dc, hipStream_t s);
 
 // split / merge / cap
 rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, rt_stats *out);
+// continuous launch: scratch of launch_scratch_len() uint32, flux_dev the
+// device copy of the column flux or null
+rt_status do_launch(rt_ctx ctx, const rt_launch_params *lp, const double *flux_dev, uint32_t *scratch,
+                    int64_t *n_launched);
+int64_t launch_scratch_len(const Grid &g, int n_speeds);

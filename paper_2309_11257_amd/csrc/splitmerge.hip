@@ -748,3 +748,239 @@ rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, r
     if (out && r == RT_OK) r = rt_get_stats(ctx, out);
     return r;
 }
+
+// ---------------------------------------------------------------------------
+// Continuous launch from a ghost layer (rt_launch; Section 3c, sources).
+// Candidate (column c, direction d, phase-speed bin b) at index
+// (c * 4 + d) * n_speeds + b: a flag pass, an exclusive scan for the
+// positions of the launched volumes (so their order and ids follow the
+// candidates' order), and a write pass into the slots after the compacted
+// active set.  The background at the column centre and the launch height is
+// read from the double-precision fields in both precisions.
+// ---------------------------------------------------------------------------
+struct LaunchD {
+    double z_launch, dt, t_solstice, F_s, F_w, kh, c_min, c_max, c_center, c_width, sw;
+    int n_speeds;
+    const double *flux_col;  // device copy, or null
+    const double *N2;        // [nz][ny][nx]
+    const double *f2;        // [ny]
+};
+
+#define LAUNCH_PI 3.14159265358979323846
+#define LAUNCH_YEAR (365.25 * 86400.0)
+
+// latitudinal profile of the background source (phi in degrees)
+__device__ inline double src_alpha(double phi)
+{
+    if (phi >= 80.0) return fmin(1.0, fmax(0.0, 1.0 - (phi - 80.0) / 5.0));
+    if (phi >= 50.0) return 1.0;
+    if (phi >= 20.0) return 0.5 * (1.0 - cos(LAUNCH_PI * (phi - 20.0) / 30.0));
+    return 0.0;
+}
+
+__device__ inline double col_flux(const Grid &g, const LaunchD &p, int c)
+{
+    if (p.flux_col) return p.flux_col[c];
+    if (g.geometry != RT_SPHERICAL) return 0.0;
+    const int j = c / g.nx;
+    const double phi = (g.y0 + ((double)j + 0.5) * g.dy) * (180.0 / LAUNCH_PI);
+    const double tau = (2.0 * LAUNCH_PI) * (p.t_solstice / LAUNCH_YEAR);
+    const double fn = src_alpha(phi) * p.F_s + src_alpha(-phi) * p.F_w;
+    const double fs = src_alpha(-phi) * p.F_s + src_alpha(phi) * p.F_w;
+    return 0.5 * (fn * (1.0 + cos(tau)) + fs * (1.0 - cos(tau)));
+}
+
+// the volume launched by candidate (c, d, b), if any
+__device__ inline bool launch_bin(const Grid &g, const LaunchD &p, int c, int d, int b, RayD &r)
+{
+    const double Fc = col_flux(g, p, c);
+    if (!(Fc > 0.0)) return false;
+    const int i = c % g.nx, j = c / g.nx;
+    const double cb = p.c_min + (((double)b + 0.5) * (p.c_max - p.c_min)) / (double)p.n_speeds;
+    const double s = (cb - p.c_center) / p.c_width;
+    const double Fb = (0.25 * Fc) * (exp(-(s * s)) / p.sw);
+    const double x = g.x0 + ((double)i + 0.5) * g.dx, y = g.y0 + ((double)j + 0.5) * g.dy;
+    const d64::Axis ax = d64::axis_x(g, x), ay = d64::axis_y(g, y), az = d64::axis_z(g, p.z_launch);
+    auto at = [&](int jj, int ii, int kk) { return p.N2[((int64_t)kk * g.ny + jj) * g.nx + ii]; };
+    d64::Cell cl;
+    cl.wx = ax.w;
+    cl.wy = ay.w;
+    cl.wz = az.w;
+    const double N2 = d64::lerp3(at(ay.i0, ax.i0, az.i0), at(ay.i0, ax.i1, az.i0), at(ay.i1, ax.i0, az.i0),
+                                 at(ay.i1, ax.i1, az.i0), at(ay.i0, ax.i0, az.i1), at(ay.i0, ax.i1, az.i1),
+                                 at(ay.i1, ax.i0, az.i1), at(ay.i1, ax.i1, az.i1), cl);
+    const double f2 = d64::row_lerp(p.f2, ay);
+    const double om = p.kh * cb, om2 = om * om;
+    if (!(om2 > f2 && om2 < N2) || !(Fb > 0.0)) return false;
+    const double kh = p.kh;
+    const double m = -sqrt(((kh * kh) * (N2 - om2)) / (om2 - f2));
+    const double k = d == 0 ? kh : (d == 2 ? -kh : 0.0);
+    const double l = d == 1 ? kh : (d == 3 ? -kh : 0.0);
+    // vertical group velocity of the dispersion relation (cancellation-free form)
+    const double kh2 = k * k + l * l, m2 = m * m, K2 = kh2 + m2;
+    const double omd = d64::omega_hat(N2, f2, kh2, m2, K2);
+    const double cgz = -(((m * kh2) * (N2 - f2)) / (omd * (K2 * K2)));
+    const double Dz = cgz * p.dt;
+    const double z = p.z_launch + 0.5 * Dz;
+    double A = g.dx * g.dy;
+    if (g.geometry == RT_SPHERICAL) {
+        const double rr = g.a + p.z_launch;
+        A = (((rr * rr) * cos(g.y0 + ((double)j + 0.5) * g.dy)) * g.dx) * g.dy;
+    }
+    const double W = ((Fb * A) * p.dt) / kh;
+    const double dk = 0.1 * kh, dm = 0.1 * fabs(m);
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.k = k;
+    r.l = l;
+    r.m = m;
+    r.dx = g.dx;
+    r.dy = g.dy;
+    r.dz = Dz;
+    r.px = metric_x(g, y, z, g.dx) * dk;
+    r.py = metric_y(g, z, g.dy) * dk;
+    r.pz = Dz * dm;
+    r.W = W;
+    r.n = 0.0;
+    return true;
+}
+
+__global__ void k_launch_flag(const Grid g, LaunchD p, uint32_t *flag, int64_t M)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M) return;
+    const int b = (int)(q % p.n_speeds), d = (int)((q / p.n_speeds) % 4), c = (int)(q / (4 * (int64_t)p.n_speeds));
+    RayD r;
+    flag[q] = launch_bin(g, p, c, d, b, r) ? 1u : 0u;
+}
+
+__global__ void k_launch_total(const uint32_t *flag, const uint32_t *offs, int64_t M, int64_t *total)
+{
+    *total = M > 0 ? (int64_t)offs[M - 1] + (int64_t)flag[M - 1] : 0;
+}
+
+template <class IO>
+__global__ void k_launch_write(IO io, const Grid g, LaunchD p, const uint32_t *flag, const uint32_t *offs, int64_t M,
+                               int64_t n0, int64_t next_id, uint32_t *key)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M || !flag[q]) return;
+    const int b = (int)(q % p.n_speeds), d = (int)((q / p.n_speeds) % 4), c = (int)(q / (4 * (int64_t)p.n_speeds));
+    RayD r;
+    if (!launch_bin(g, p, c, d, b, r)) return;
+    r.id = next_id + (int64_t)offs[q];
+    const uint32_t slot = (uint32_t)(n0 + (int64_t)offs[q]);
+    io.put(g, slot, r, true);
+    key[slot] = (uint32_t)c;  // a live key: the slot may hold a stale one (a removal reason or a level key)
+}
+
+// launched wave action, one block, fixed order
+template <class IO>
+__global__ __launch_bounds__(256) void k_launch_sum(IO io, int64_t n0, int64_t cnt, DevCounters *dc)
+{
+    __shared__ double sh[256];
+    double v = 0.0;
+    for (int64_t q = threadIdx.x; q < cnt; q += 256) v += io.wv((uint32_t)(n0 + q));
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        dc->n_launched += cnt;
+        dc->launched_W += sh[0];
+    }
+}
+
+template <class IO>
+static rt_status launch_impl(rt_ctx ctx, IO cur_io, IO other_io, LaunchD p, uint32_t *flag, uint32_t *offs,
+                             uint32_t *parts, int64_t *n_out)
+{
+    const Grid &g = ctx->g;
+    hipStream_t st = ctx->stream;
+    const unsigned T = 256;
+    auto nb = [&](int64_t m) { return (unsigned)((m + T - 1) / T > 0 ? (m + T - 1) / T : 1); };
+    const int64_t M = (int64_t)g.ncol * 4 * p.n_speeds;
+    DevCounters h;
+    HIP_OK(hipMemcpyAsync(&h, ctx->dc, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const int64_t n = h.n_active;
+    k_launch_flag<<<nb(M), T, 0, st>>>(g, p, flag, M);
+    HIP_OK(hipMemcpyAsync(offs, flag, sizeof(uint32_t) * (size_t)M, hipMemcpyDeviceToDevice, st));
+    scan_u32(offs, M, parts, st);
+    k_launch_total<<<1, 1, 0, st>>>(flag, offs, M, &ctx->dc->split_extra);
+    int64_t total = 0;
+    HIP_OK(hipMemcpyAsync(&total, &ctx->dc->split_extra, sizeof(total), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    *n_out = total;
+    if (n + total > ctx->cap)
+        return rt_fail(ctx, RT_E_CAPACITY, "launch needs %lld ray volumes, capacity %lld", (long long)(n + total),
+                       (long long)ctx->cap);
+    // compact the active set into the spare buffer in column order, append
+    const int nxt = 1 - ctx->cur;
+    if (n > 0) k_compact<IO><<<nb(n), T, 0, st>>>(cur_io, other_io, ctx->perm, ctx->skeys, ctx->key[nxt], ctx->dc);
+    ctx->cur = nxt;
+    uint32_t *key = ctx->key[ctx->cur];
+    if (total > 0) {
+        k_launch_write<IO><<<nb(M), T, 0, st>>>(other_io, g, p, flag, offs, M, n, h.next_id, key);
+        k_launch_sum<IO><<<1, 256, 0, st>>>(other_io, n, total, ctx->dc);
+        h.next_id += total;
+        HIP_OK(hipMemcpyAsync(&ctx->dc->next_id, &h.next_id, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
+    if (n + total > 0) k_rekey<IO><<<nb(n + total), T, 0, st>>>(other_io, g, key, n + total);
+    launch_set_sorted(ctx->dc, n + total, st);
+    ctx->n_bound = n + total;
+    HIP_OK(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status do_launch(rt_ctx ctx, const rt_launch_params *lp, const double *flux_dev, uint32_t *scratch,
+                    int64_t *n_launched)
+{
+    const Grid &g = ctx->g;
+    LaunchD p;
+    p.z_launch = lp->z_launch;
+    p.dt = lp->dt;
+    p.t_solstice = lp->t_solstice;
+    p.F_s = lp->F_s;
+    p.F_w = lp->F_w;
+    p.kh = (2.0 * LAUNCH_PI) / lp->lambda_h;
+    p.c_min = lp->c_min;
+    p.c_max = lp->c_max;
+    p.c_center = lp->c_center;
+    p.c_width = lp->c_width;
+    p.n_speeds = lp->n_speeds;
+    p.flux_col = flux_dev;
+    p.N2 = ctx->bg64.N2;
+    p.f2 = ctx->bg64.f2;
+    // spectral weights normalised over the bins, summed in bin order as the
+    // definition reads
+    double sw = 0.0;
+    for (int b = 0; b < lp->n_speeds; b++) {
+        const double cb = lp->c_min + (((double)b + 0.5) * (lp->c_max - lp->c_min)) / (double)lp->n_speeds;
+        const double s = (cb - lp->c_center) / lp->c_width;
+        sw += exp(-(s * s));
+    }
+    p.sw = sw;
+    const int64_t M = (int64_t)g.ncol * 4 * lp->n_speeds;
+    uint32_t *flag = scratch, *offs = scratch + M, *parts = offs + M;
+    prof_begin(ctx, PC_SPLIT);
+    rt_status r;
+    if (ctx->precision == RT_FP64)
+        r = launch_impl<IO64>(ctx, IO64{ctx->s64[ctx->cur], ctx->bp64.f2}, IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2},
+                              p, flag, offs, parts, n_launched);
+    else
+        r = launch_impl<IO32>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2}, IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2},
+                              p, flag, offs, parts, n_launched);
+    prof_end(ctx);
+    if (r != RT_OK) return r;
+    return sort_current_ext(ctx);
+}
+
+int64_t launch_scratch_len(const Grid &g, int n_speeds)
+{
+    const int64_t M = (int64_t)g.ncol * 4 * n_speeds;
+    return 2 * M + scan_tmp_len(M);
+}
