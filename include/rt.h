@@ -47,7 +47,7 @@ enum {
     RT_E_NOMEM = 3,       /* device allocation failed */
     RT_E_CAPACITY = 4,    /* ray count would exceed the configured capacity */
     RT_E_DEVICE = 5,      /* a HIP runtime call failed */
-    RT_E_NUMERIC = 6,     /* reserved: numeric failure reported by the device */
+    RT_E_NUMERIC = 6,     /* the device deactivated a non-finite or degenerate volume (rt_get_stats) */
     RT_E_UNSUPPORTED = 7  /* valid request that this build does not handle */
 };
 enum { RT_CARTESIAN = 0, RT_SPHERICAL = 1 };
@@ -98,8 +98,9 @@ typedef struct {
     int64_t steps;                        /* steps taken */
     int64_t n_launched;                   /* volumes added by rt_launch (cumulative) */
     double launched_W;                    /* their wave action (cumulative) */
-    int64_t first_bad_id;                 /* id of the first volume found non-finite or degenerate
-                                             since the last rt_get_stats, -1 if none */
+    int64_t first_bad_id;                 /* smallest id among the volumes deactivated as non-finite
+                                             or degenerate (at load or after a step) since the last
+                                             report, -1 if none */
 } rt_stats;
 
 /* Continuous launch from a ghost layer (Section 3c, sources): parameters.
@@ -316,7 +317,14 @@ rt_status rt_split_merge(rt_ctx ctx, double alpha_split, int32_t n_max_per_cell,
  * bad parameters or a missing flux_col on the box. */
 rt_status rt_launch(rt_ctx ctx, const rt_launch_params *p, int64_t *n_launched);
 
-/* Current diagnostics (deterministic sums).  Synchronises. */
+/* Current diagnostics (deterministic sums).  Synchronises.  A volume with a
+ * non-finite state, a non-positive extent or a zero wavevector (K^2 = 0) at
+ * load or after a step cannot be carried on: it is deactivated, counted in
+ * n_invalid, and the rest of the set is unaffected.  The next rt_get_stats
+ * then fills *out completely, sets first_bad_id to the smallest such id and
+ * returns RT_E_NUMERIC (rt_last_error names the id); the report is then
+ * cleared, so a later call returns RT_OK until another volume fails.
+ * rt_split_merge's statistics show first_bad_id without clearing it. */
 rt_status rt_get_stats(rt_ctx ctx, rt_stats *out);
 
 /* Kernel timing for benchmarks.  While on, the library brackets each group of

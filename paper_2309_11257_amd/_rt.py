@@ -58,9 +58,10 @@ class LaunchParams(C.Structure):
 
 
 class RTError(RuntimeError):
-    def __init__(self, code: int, msg: str):
+    def __init__(self, code: int, msg: str, stats: Optional[dict] = None):
         super().__init__(f"rt error {code}: {msg}")
         self.code = code
+        self.stats = stats  # the full statistics, for RT_E_NUMERIC from rt_get_stats
 
 
 _lib: Optional[C.CDLL] = None
@@ -378,6 +379,12 @@ class Tracer:
         return {c: (float(ms[i]), int(n[i])) for i, c in enumerate(self.PROFILE_CLASSES) if n[i]}
 
     def stats(self) -> dict:
+        """rt_get_stats; RT_E_NUMERIC (a volume was deactivated as
+        non-finite or degenerate since the last call) raises RTError with the
+        statistics attached, first_bad_id among them."""
         s = Stats()
-        self._check(lib().rt_get_stats(self.h, C.byref(s)))
+        st = lib().rt_get_stats(self.h, C.byref(s))
+        if st == RT_E_NUMERIC:
+            raise RTError(st, lib().rt_last_error(self.h).decode(), s.as_dict())
+        self._check(st)
         return s.as_dict()

@@ -777,10 +777,11 @@ extern "C" rt_status rt_get_columns(rt_ctx ctx, uint32_t *cols, int64_t *n_inout
     return RT_OK;
 }
 
-extern "C" rt_status rt_get_stats(rt_ctx ctx, rt_stats *out)
+// the diagnostics without consuming the numeric-failure report
+rt_status fill_stats(rt_ctx ctx, rt_stats *out)
 {
-    if (!ctx || !out) return rt_fail(ctx, RT_E_ARG, "out is required");
     memset(out, 0, sizeof(*out));
+    out->first_bad_id = -1;
     if (ctx->have_rays) {
         if (ctx->precision == RT_FP64)
             launch_stats64(ctx->s64[ctx->cur], ctx->perm, ctx->dc, ctx->red, ctx->n_bound, ctx->stream);
@@ -808,8 +809,24 @@ extern "C" rt_status rt_get_stats(rt_ctx ctx, rt_stats *out)
         out->steps = h.steps;
         out->n_launched = h.n_launched;
         out->launched_W = h.launched_W;
+        if (h.bad_key) out->first_bad_id = (int64_t)~h.bad_key;
     }
-    out->first_bad_id = -1;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_get_stats(rt_ctx ctx, rt_stats *out)
+{
+    if (!ctx || !out) return rt_fail(ctx, RT_E_ARG, "out is required");
+    rt_status st = fill_stats(ctx, out);
+    if (st) return st;
+    if (out->first_bad_id >= 0) {
+        // reported once: the next report covers volumes deactivated after this call
+        const uint64_t none = 0;
+        HIP_OK(hipMemcpyAsync(&ctx->dc->bad_key, &none, sizeof(none), hipMemcpyHostToDevice, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        return rt_fail(ctx, RT_E_NUMERIC, "ray volume id %lld (the smallest of those found) was non-finite or "
+                       "degenerate and has been deactivated", (long long)out->first_bad_id);
+    }
     return RT_OK;
 }
 

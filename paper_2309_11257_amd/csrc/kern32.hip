@@ -134,13 +134,15 @@ void launch_levkey32(const Grid &g, S32 st, uint32_t *key, const DevCounters *dc
 
 struct W32 {
     const double *w;
+    const int64_t *ids;
     __device__ double W(uint32_t slot) const { return w[slot]; }
+    __device__ int64_t id(uint32_t slot) const { return ids[slot]; }
 };
 
 void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc, double *red,
                     hipStream_t s)
 {
-    launch_tally_k(g, W32{st.W}, perm, skeys, dc, red, s);
+    launch_tally_k(g, W32{st.W, st.id}, perm, skeys, dc, red, s);
 }
 
 __global__ void k_stats32_part(S32 st, const uint32_t *perm, const DevCounters *dc, double *part)

@@ -325,6 +325,7 @@ __device__ inline double W64(const S64 &st, uint32_t s)
 struct W64s {
     S64 st;
     __device__ double W(uint32_t slot) const { return W64(st, slot); }
+    __device__ int64_t id(uint32_t slot) const { return st.id[slot]; }
 };
 
 // sort key refined by the level (as in single precision): column key *

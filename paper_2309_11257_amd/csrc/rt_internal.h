@@ -80,6 +80,8 @@ struct DevCounters {
     int64_t steps;
     int64_t n_launched;  // volumes launched (cumulative)
     double launched_W;   // their wave action (cumulative)
+    uint64_t bad_key;    // ~id of the smallest id deactivated as non-finite or degenerate since the
+                         // last report (the largest complement), 0 if none
 };
 
 struct rt_ctx_s {
@@ -304,6 +306,7 @@ void launch_sorted_from_active(DevCounters *dc, hipStream_t s);
 rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, rt_stats *out);
 // continuous launch: scratch of launch_scratch_len() uint32, flux_dev the
 // device copy of the column flux or null
+rt_status fill_stats(rt_ctx ctx, rt_stats *out);
 rt_status do_launch(rt_ctx ctx, const rt_launch_params *lp, const double *flux_dev, uint32_t *scratch,
                     int64_t *n_launched);
 int64_t launch_scratch_len(const Grid &g, int n_speeds);

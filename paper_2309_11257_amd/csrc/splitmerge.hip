@@ -745,7 +745,7 @@ rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, r
     prof_end(ctx);  // profile groups do not nest: the regrouping times as a sort
     rt_status r2 = sort_current_ext(ctx);
     if (r == RT_OK) r = r2;
-    if (out && r == RT_OK) r = rt_get_stats(ctx, out);
+    if (out && r == RT_OK) r = fill_stats(ctx, out);
     return r;
 }
 
