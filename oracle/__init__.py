@@ -44,7 +44,7 @@ class _Bg(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("x0", C.c_double), ("y0", C.c_double), ("a", C.c_double)] + \
                [(n, C.c_void_p) for n in ("U", "V", "N2", "f2", "rho", "Ux", "Uy", "Uz", "Vx", "Vy", "Vz",
-                                           "N2x", "N2y", "N2z", "f2y", "f")]
+                                           "N2x", "N2y", "N2z", "f2y", "f", "G2", "G2x", "G2y", "G2z")]
 
 
 class _Rays(C.Structure):
@@ -121,6 +121,8 @@ def _load(path: str) -> C.CDLL:
     L.orc_prepare.argtypes = [P]
     L.orc_interp.argtypes = [P, C.c_double, C.c_double, C.c_double, P]
     L.orc_dispersion.argtypes = [C.c_double] * 5 + [P]
+    L.orc_dispersion_g.argtypes = [C.c_double] * 6 + [P]
+    L.orc_interp_gamma.argtypes = [P, C.c_double, C.c_double, C.c_double, P]
     L.orc_rhs.argtypes = [P, P, P]
     L.orc_step.argtypes = [P, P, C.c_int64, C.c_double, P]
     L.orc_keys.argtypes = [P, P, C.c_int64]
@@ -154,9 +156,11 @@ def _ptr(a: np.ndarray) -> int:
 
 class Background:
     """A grid plus resolved fields U, V, N2 [nz][ny][nx], Coriolis parameter
-    f [ny] and reference density rho [nz]; gradients are filled on creation."""
+    f [ny], reference density rho [nz] and optionally the scale-height
+    correction Gamma^2 [nz][ny][nx] (None: Gamma = 0); gradients are filled
+    on creation."""
 
-    def __init__(self, geometry, nx, ny, nz, dx, dy, dz, x0, y0, a, U, V, N2, f, rho):
+    def __init__(self, geometry, nx, ny, nz, dx, dy, dz, x0, y0, a, U, V, N2, f, rho, G2=None):
         c = lambda v: np.ascontiguousarray(v, dtype=np.float64)
         self.U, self.V, self.N2 = c(U), c(V), c(N2)
         f = c(f)
@@ -177,6 +181,14 @@ class Background:
             setattr(b, n, _ptr(v))
         b.f2y = _ptr(self.f2y)
         b.f = _ptr(self.f)
+        self.G2 = None
+        if G2 is not None:
+            self.G2 = c(G2)
+            assert self.G2.shape == shape
+            self.G2grads = {n: np.zeros(shape) for n in ("G2x", "G2y", "G2z")}
+            b.G2 = _ptr(self.G2)
+            for n, v in self.G2grads.items():
+                setattr(b, n, _ptr(v))
         self._b = b
         self.geometry, self.nx, self.ny, self.nz = geometry, nx, ny, nz
         self.dx, self.dy, self.dz, self.x0, self.y0, self.a = dx, dy, dz, x0, y0, a
@@ -184,7 +196,8 @@ class Background:
 
     @classmethod
     def from_workload(cls, w) -> "Background":
-        return cls(w.geometry, w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.x0, w.y0, w.a, w.U, w.V, w.N2, w.f, w.rho)
+        return cls(w.geometry, w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.x0, w.y0, w.a, w.U, w.V, w.N2, w.f, w.rho,
+                   getattr(w, "G2", None))
 
     @property
     def ref(self):
@@ -195,6 +208,12 @@ class Background:
         lib().orc_interp(self.ref, float(x), float(y), float(z), _ptr(out))
         return out
 
+    def interp_gamma(self, x, y, z) -> np.ndarray:
+        """Gamma^2 and its x, y, z gradients at a point (zeros without Gamma)."""
+        out = np.zeros(4)
+        lib().orc_interp_gamma(self.ref, float(x), float(y), float(z), _ptr(out))
+        return out
+
     def rhs(self, Y) -> np.ndarray:
         Y = np.ascontiguousarray(Y, dtype=np.float64)
         F = np.zeros(9)
@@ -202,10 +221,14 @@ class Background:
         return F
 
 
-def dispersion(N2, f2, k, l, m) -> np.ndarray:
-    """(omega_hat, cg_x, cg_y, cg_z) intrinsic."""
+def dispersion(N2, f2, k, l, m, G2=None) -> np.ndarray:
+    """(omega_hat, cg_x, cg_y, cg_z) intrinsic; G2 the scale-height
+    correction Gamma^2 (None: Gamma = 0)."""
     out = np.zeros(4)
-    lib().orc_dispersion(float(N2), float(f2), float(k), float(l), float(m), _ptr(out))
+    if G2 is None:
+        lib().orc_dispersion(float(N2), float(f2), float(k), float(l), float(m), _ptr(out))
+    else:
+        lib().orc_dispersion_g(float(N2), float(f2), float(G2), float(k), float(l), float(m), _ptr(out))
     return out
 
 

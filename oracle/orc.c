@@ -82,6 +82,11 @@ void orc_prepare(orc_bg *g)
                 g->N2x[c] = ddx(g, g->N2, i, j, k);
                 g->N2y[c] = ddy(g, g->N2, i, j, k);
                 g->N2z[c] = ddz(g, g->N2, i, j, k);
+                if (g->G2) {
+                    g->G2x[c] = ddx(g, g->G2, i, j, k);
+                    g->G2y[c] = ddy(g, g->G2, i, j, k);
+                    g->G2z[c] = ddz(g, g->G2, i, j, k);
+                }
             }
     for (j = 0; j < g->ny; j++) {
         if (g->geometry == ORC_CARTESIAN) {
@@ -209,8 +214,24 @@ void orc_interp(const orc_bg *g, double x, double y, double z, double out[14])
     out[13] = rowlin(g->f2y, &c);
 }
 
-/* U, V, N2, f2 at one point (face evaluations) */
-static void interp4(const orc_bg *g, double x, double y, double z, double *U, double *V, double *N2, double *f2)
+/* Gamma^2 and its gradients (x, y, z) at one point; all zero without Gamma */
+void orc_interp_gamma(const orc_bg *g, double x, double y, double z, double out[4])
+{
+    corners c;
+    if (!g->G2) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        return;
+    }
+    locate(g, x, y, z, &c);
+    out[0] = trilin(g, g->G2, &c);
+    out[1] = trilin(g, g->G2x, &c);
+    out[2] = trilin(g, g->G2y, &c);
+    out[3] = trilin(g, g->G2z, &c);
+}
+
+/* U, V, N2, f2, Gamma^2 at one point (face evaluations) */
+static void interp5(const orc_bg *g, double x, double y, double z, double *U, double *V, double *N2, double *f2,
+                    double *G2)
 {
     corners c;
     locate(g, x, y, z, &c);
@@ -218,42 +239,65 @@ static void interp4(const orc_bg *g, double x, double y, double z, double *U, do
     *V = trilin(g, g->V, &c);
     *N2 = trilin(g, g->N2, &c);
     *f2 = rowlin(g->f2, &c);
+    *G2 = g->G2 ? trilin(g, g->G2, &c) : 0.0;
 }
 
 /* ------------------------------------------------------------------------
- * Dispersion relation (Section 2a, eq. dispersion) with Gamma = 0 and the
- * positive intrinsic branch:  omega_hat^2 = (N^2 kh^2 + f^2 m^2) / K^2.
+ * Dispersion relation (Section 2a, eq. dispersion) with the scale-height
+ * correction and the positive intrinsic branch:
+ *   omega_hat^2 = (N^2 kh^2 + f^2 (m^2 + Gamma^2)) / K^2,
+ *   K^2 = kh^2 + m^2 + Gamma^2.
  * Intrinsic group velocity = gradient of omega_hat in wavenumber space
- * (eq. eikonal, right), written with N^2 - omega_hat^2 = m^2 (N^2-f^2)/K^2
- * and omega_hat^2 - f^2 = kh^2 (N^2-f^2)/K^2 so that no difference of nearly
- * equal numbers is formed:
- *   cg_x = k m^2 (N^2-f^2) / (omega_hat K^4),   cg_y likewise with l,
+ * (eq. eikonal, right), written with
+ *   N^2 - omega_hat^2 = (m^2 + Gamma^2)(N^2 - f^2)/K^2,
+ *   omega_hat^2 - f^2 = kh^2 (N^2 - f^2)/K^2
+ * so that no difference of nearly equal numbers is formed:
+ *   cg_x = k (m^2 + Gamma^2)(N^2-f^2) / (omega_hat K^4),  cg_y likewise with l,
  *   cg_z = -m kh^2 (N^2-f^2) / (omega_hat K^4).
  * out: omega_hat, cg_x, cg_y, cg_z (intrinsic, i.e. without U).
+ * orc_dispersion is the case Gamma = 0.
  * ------------------------------------------------------------------------ */
-void orc_dispersion(double N2, double f2, double k, double l, double m, double out[4])
+void orc_dispersion_g(double N2, double f2, double G2, double k, double l, double m, double out[4])
 {
     double kh2 = k * k + l * l;
-    double m2 = m * m;
-    double K2 = kh2 + m2;
+    double M2 = m * m + G2;
+    double K2 = kh2 + M2;
     double K4 = K2 * K2;
-    double om = sqrt((N2 * kh2 + f2 * m2) / K2);
+    double om = sqrt((N2 * kh2 + f2 * M2) / K2);
     double d = N2 - f2;
     double den = om * K4;
     out[0] = om;
-    out[1] = ((k * m2) * d) / den;
-    out[2] = ((l * m2) * d) / den;
+    out[1] = ((k * M2) * d) / den;
+    out[2] = ((l * M2) * d) / den;
     out[3] = -(((m * kh2) * d) / den);
+}
+
+void orc_dispersion(double N2, double f2, double k, double l, double m, double out[4])
+{
+    orc_dispersion_g(N2, f2, 0.0, k, l, m, out);
+}
+
+/* the fields at a carrier (B as orc_interp) and the dispersion there */
+static void disp_at(const orc_bg *g, double x, double y, double z, double k, double l, double m, double B[14],
+                    double D[4], double *G2out)
+{
+    double G[4];
+    orc_interp(g, x, y, z, B);
+    orc_interp_gamma(g, x, y, z, G);
+    orc_dispersion_g(B[2], B[12], G[0], k, l, m, D);
+    if (G2out) *G2out = G[0];
 }
 
 /* ------------------------------------------------------------------------
  * Right-hand side of the ray-volume equations for one RK stage.
  * Y = (x, y, z, k, l, m, Dx, Dy, Dz), extents in coordinate units.
  *
- * Carrier wavenumber tendency (eq. eikonal-sphere 1-3 with Gamma = 0; the
- * Cartesian box is its flat limit) from the fields and gradients at the
- * centre, with d omega_hat / d N^2 = kh^2/(2 omega_hat K^2) and
- * d omega_hat / d f^2 = m^2/(2 omega_hat K^2).
+ * Carrier wavenumber tendency (eq. eikonal-sphere 1-3; the Cartesian box is
+ * its flat limit) from the fields and gradients at the centre, with
+ *   d omega_hat / d N^2     = kh^2 / (2 omega_hat K^2),
+ *   d omega_hat / d f^2     = (m^2 + Gamma^2) / (2 omega_hat K^2),
+ *   d omega_hat / d Gamma^2 = -(kh^2 / (2 omega_hat K^2)) (N^2 - f^2) / K^2,
+ * the bracketed sensitivities of the three equations.
  *
  * Carrier motion and extent rates (Section 3a and Appendix B): group
  * velocities at the centres of opposing faces, which carry the carrier's
@@ -264,59 +308,54 @@ void orc_dispersion(double N2, double f2, double k, double l, double m, double o
  * 1/(r cos phi) and 1/r; the metric terms use the carrier's own face-averaged
  * velocities (u_c, v_c, w_c).
  * ------------------------------------------------------------------------ */
+/* ground-based group velocity along axis axn (0: x, 1: y, 2: z) of a volume
+   with wavevector (k, l, m) at a face centre, from the background there */
+static double face_velocity(const orc_bg *g, double x, double y, double z, double k, double l, double m, int axn)
+{
+    double Uf, Vf, N2f, f2f, G2f, D[4];
+    interp5(g, x, y, z, &Uf, &Vf, &N2f, &f2f, &G2f);
+    orc_dispersion_g(N2f, f2f, G2f, k, l, m, D);
+    if (axn == 0) return Uf + D[1];
+    if (axn == 1) return Vf + D[2];
+    return D[3]; /* no vertical mean wind */
+}
+
 void orc_rhs(const orc_bg *g, const double Y[9], double F[9])
 {
     double x = Y[0], y = Y[1], z = Y[2], k = Y[3], l = Y[4], m = Y[5];
     double Dx = Y[6], Dy = Y[7], Dz = Y[8];
     double kh2 = k * k + l * l;
-    double m2 = m * m;
-    double K2 = kh2 + m2;
-    double K4 = K2 * K2;
-    double B[14];
-    double om, q, qf;
-    double Uf, Vf, N2f, f2f, omf;
+    double B[14], G[4];
+    double M2, K2, om, q, qf, qg;
     double cxp, cxm, cyp, cym, czp, czm;
-    double xp, xm, yp, ym, zp, zm;
     double gk, gl, gm;
 
     orc_interp(g, x, y, z, B);
-    om = sqrt((B[2] * kh2 + B[12] * m2) / K2);
+    orc_interp_gamma(g, x, y, z, G);
+    M2 = m * m + G[0];
+    K2 = kh2 + M2;
+    om = sqrt((B[2] * kh2 + B[12] * M2) / K2);
     q = kh2 / ((2.0 * om) * K2);
-    qf = m2 / ((2.0 * om) * K2);
+    qf = M2 / ((2.0 * om) * K2);
+    qg = -((kh2 * (B[2] - B[12])) / (((2.0 * om) * K2) * K2));
 
-    xp = x + 0.5 * Dx;
-    xm = x - 0.5 * Dx;
-    yp = y + 0.5 * Dy;
-    ym = y - 0.5 * Dy;
-    zp = z + 0.5 * Dz;
-    zm = z - 0.5 * Dz;
+    cxp = face_velocity(g, x + 0.5 * Dx, y, z, k, l, m, 0);
+    cxm = face_velocity(g, x - 0.5 * Dx, y, z, k, l, m, 0);
+    cyp = face_velocity(g, x, y + 0.5 * Dy, z, k, l, m, 1);
+    cym = face_velocity(g, x, y - 0.5 * Dy, z, k, l, m, 1);
+    czp = face_velocity(g, x, y, z + 0.5 * Dz, k, l, m, 2);
+    czm = face_velocity(g, x, y, z - 0.5 * Dz, k, l, m, 2);
 
-    /* x faces: zonal group velocity U + cg_x */
-    interp4(g, xp, y, z, &Uf, &Vf, &N2f, &f2f);
-    omf = sqrt((N2f * kh2 + f2f * m2) / K2);
-    cxp = Uf + ((k * m2) * (N2f - f2f)) / (omf * K4);
-    interp4(g, xm, y, z, &Uf, &Vf, &N2f, &f2f);
-    omf = sqrt((N2f * kh2 + f2f * m2) / K2);
-    cxm = Uf + ((k * m2) * (N2f - f2f)) / (omf * K4);
-    /* y faces: meridional group velocity V + cg_y */
-    interp4(g, x, yp, z, &Uf, &Vf, &N2f, &f2f);
-    omf = sqrt((N2f * kh2 + f2f * m2) / K2);
-    cyp = Vf + ((l * m2) * (N2f - f2f)) / (omf * K4);
-    interp4(g, x, ym, z, &Uf, &Vf, &N2f, &f2f);
-    omf = sqrt((N2f * kh2 + f2f * m2) / K2);
-    cym = Vf + ((l * m2) * (N2f - f2f)) / (omf * K4);
-    /* z faces: vertical group velocity cg_z (no vertical mean wind) */
-    interp4(g, x, y, zp, &Uf, &Vf, &N2f, &f2f);
-    omf = sqrt((N2f * kh2 + f2f * m2) / K2);
-    czp = -(((m * kh2) * (N2f - f2f)) / (omf * K4));
-    interp4(g, x, y, zm, &Uf, &Vf, &N2f, &f2f);
-    omf = sqrt((N2f * kh2 + f2f * m2) / K2);
-    czm = -(((m * kh2) * (N2f - f2f)) / (omf * K4));
-
-    /* refraction terms at the centre: B = U V N2 Ux Uy Uz Vx Vy Vz N2x N2y N2z f2 f2y */
+    /* refraction terms at the centre: B = U V N2 Ux Uy Uz Vx Vy Vz N2x N2y N2z f2 f2y,
+       G = Gamma^2 and its x, y, z gradients */
     gk = (k * B[3] + l * B[6]) + q * B[9];
     gl = ((k * B[4] + l * B[7]) + q * B[10]) + qf * B[13];
     gm = (k * B[5] + l * B[8]) + q * B[11];
+    if (g->G2) {
+        gk = gk + qg * G[1];
+        gl = gl + qg * G[2];
+        gm = gm + qg * G[3];
+    }
 
     if (g->geometry == ORC_CARTESIAN) {
         F[0] = 0.5 * (cxp + cxm);
@@ -531,8 +570,7 @@ static void deposit_ray(const orc_bg *g, const orc_rays *r, int64_t i, int c, do
     double k = r->k[i], l = r->l[i];
     int kk, klo, khi;
 
-    orc_interp(g, r->x[i], r->y[i], z, B);
-    orc_dispersion(B[2], B[12], k, l, r->m[i], D);
+    disp_at(g, r->x[i], r->y[i], z, k, l, r->m[i], B, D, NULL);
 
     klo = (int)floor(zb / g->dz);
     khi = (int)floor(zt / g->dz);
@@ -931,8 +969,7 @@ void orc_cap(const orc_bg *g, orc_rays *r, int64_t n, int32_t n_max, orc_tally *
         for (p = 0; p < len; p++) {
             int64_t idx = order[start[c] + p];
             double B[14], D[4];
-            orc_interp(g, r->x[idx], r->y[idx], r->z[idx], B);
-            orc_dispersion(B[2], B[12], r->k[idx], r->l[idx], r->m[idx], D);
+            disp_at(g, r->x[idx], r->y[idx], r->z[idx], r->k[idx], r->l[idx], r->m[idx], B, D, NULL);
             rec[p].E = D[0] * ray_W(r, idx);
             rec[p].id = r->id[idx];
             rec[p].idx = idx;
@@ -1023,8 +1060,7 @@ void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X)
     for (i = 0; i < n; i++) {
         double B[14], D[4], W, kh, z, *mom;
         if (r->state[i] != ORC_ACTIVE) continue;
-        orc_interp(g, r->x[i], r->y[i], r->z[i], B);
-        orc_dispersion(B[2], B[12], r->k[i], r->l[i], r->m[i], D);
+        disp_at(g, r->x[i], r->y[i], r->z[i], r->k[i], r->l[i], r->m[i], B, D, NULL);
         W = ray_W(r, i);
         kh = sqrt(r->k[i] * r->k[i] + r->l[i] * r->l[i]);
         z = r->z[i];
@@ -1068,7 +1104,8 @@ void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X)
  * spread uniformly over its height) A_j alpha_j for level k is
  *   W_j (o_jk / Dz_j) / (A_c dz),  W_j = N_j Px Py Pz,
  * o_jk the overlap of [z - Dz/2, z + Dz/2] with the level.  omega_hat and K
- * are those of the carrier (Gamma = 0).  Where P exceeds rho_k / 2 the
+ * are those of the carrier, K^2 = kh^2 + m^2 + Gamma^2 as the dispersion
+ * relation defines it.  Where P exceeds rho_k / 2 the
  * turbulent diffusivity
  *   kappa = max(0, (P - rho/2) / (2 dt sum_j P_j K_j^2))
  * damps every volume there: N_j <- N_j (1 - 2 kappa K_j^2 dt).  A volume
@@ -1084,13 +1121,13 @@ void orc_features(const orc_bg *g, const orc_rays *r, int64_t n, double *X)
  * ------------------------------------------------------------------------ */
 static double saturation_weight(const orc_bg *g, const orc_rays *r, int64_t i, double *K2out)
 {
-    double B[14], D[4];
+    double B[14], D[4], G2;
     double k = r->k[i], l = r->l[i], m = r->m[i];
     double kh2 = k * k + l * l;
     double m2 = m * m;
-    double K2 = kh2 + m2;
-    orc_interp(g, r->x[i], r->y[i], r->z[i], B);
-    orc_dispersion(B[2], B[12], k, l, m, D);
+    double K2;
+    disp_at(g, r->x[i], r->y[i], r->z[i], k, l, m, B, D, &G2);
+    K2 = kh2 + (m2 + G2);
     *K2out = K2;
     return (m2 * kh2) / (D[0] * K2);
 }
@@ -1218,13 +1255,13 @@ static void full_flux_ray(const orc_bg *g, const orc_rays *r, int64_t i, int c, 
     double Lz = (double)g->nz * g->dz;
     double k = r->k[i], l = r->l[i], m = r->m[i];
     double kh2 = k * k + l * l;
-    double K2 = kh2 + m * m;
+    double K2, G2;
     double N2, f2, fs, om2, den, a1, a2, v[8];
     int kk, klo, khi;
     corners cc;
 
-    orc_interp(g, r->x[i], r->y[i], z, B);
-    orc_dispersion(B[2], B[12], k, l, m, D);
+    disp_at(g, r->x[i], r->y[i], z, k, l, m, B, D, &G2);
+    K2 = kh2 + (m * m + G2);
     N2 = B[2];
     f2 = B[12];
     locate(g, r->x[i], r->y[i], z, &cc);
@@ -1459,8 +1496,7 @@ static void budget_ray(const orc_bg *g, const orc_rays *r, int64_t i, int c, dou
     double zb = z - 0.5 * Dz, zt = z + 0.5 * Dz;
     double Lz = (double)g->nz * g->dz;
     int kk, klo, khi;
-    orc_interp(g, r->x[i], r->y[i], z, B);
-    orc_dispersion(B[2], B[12], r->k[i], r->l[i], r->m[i], D);
+    disp_at(g, r->x[i], r->y[i], z, r->k[i], r->l[i], r->m[i], B, D, NULL);
     v[0] = 1.0;
     v[1] = B[0] + D[1];
     v[2] = B[1] + D[2];
@@ -1547,7 +1583,10 @@ void orc_budget_terms(const orc_bg *g, const double *fields4, double *terms2)
  *  - At the column centre at the launch height: omega_hat = kh c_b; a bin
  *    propagates vertically only for f^2 < omega_hat^2 < N^2 (the others are
  *    reflected in the ghost layer and discarded, their flux with them);
- *    m = -sqrt(kh^2 (N^2 - omega_hat^2) / (omega_hat^2 - f^2)) (upward).
+ *    m = -sqrt(kh^2 (N^2 - omega_hat^2) / (omega_hat^2 - f^2) - Gamma^2)
+ *    (upward), from the dispersion relation with the scale-height
+ *    correction; a bin for which the root is not positive is evanescent and
+ *    discarded too.
  *  - New volume: what crossed the launch height during dt, from z_launch to
  *    z_launch + cg_z dt; horizontal extents one cell at the column centre;
  *    dk = dl = kh/10, dm = |m|/10; wave action W = F_bin A dt / kh (A the
@@ -1605,26 +1644,29 @@ int64_t orc_launch(const orc_bg *g, orc_rays *r, int64_t n, int64_t capacity, co
             int i = c % g->nx, j = c / g->nx;
             double x = g->x0 + ((double)i + 0.5) * g->dx, y = g->y0 + ((double)j + 0.5) * g->dy;
             double Fc = p->flux_col ? p->flux_col[c] : orc_launch_flux(g, j, p);
-            double B[14];
+            double B[14], G[4];
             if (!(Fc > 0.0)) continue;
             orc_interp(g, x, y, p->z_launch, B);
+            orc_interp_gamma(g, x, y, p->z_launch, G);
             for (d = 0; d < 4; d++)
                 for (b = 0; b < p->n_speeds; b++) {
                     double cb = p->c_min + (((double)b + 0.5) * (p->c_max - p->c_min)) / (double)p->n_speeds;
                     double s = (cb - p->c_center) / p->c_width;
                     double Fb = (0.25 * Fc) * (exp(-(s * s)) / sw);
                     double om = kh * cb, om2 = om * om, N2 = B[2], f2 = B[12];
-                    double m, k, l, D[4], Dz, z, A, W, dk, dm, px, py, pz;
+                    double m, m2, k, l, D[4], Dz, z, A, W, dk, dm, px, py, pz;
                     int64_t o;
                     if (!(om2 > f2 && om2 < N2) || !(Fb > 0.0)) continue;
+                    m2 = ((kh * kh) * (N2 - om2)) / (om2 - f2) - G[0];
+                    if (!(m2 > 0.0)) continue; /* evanescent: Gamma^2 exceeds m^2 + Gamma^2 */
                     if (pass == 0) {
                         count++;
                         continue;
                     }
-                    m = -sqrt(((kh * kh) * (N2 - om2)) / (om2 - f2));
+                    m = -sqrt(m2);
                     k = kh * dir_k[d];
                     l = kh * dir_l[d];
-                    orc_dispersion(N2, f2, k, l, m, D);
+                    orc_dispersion_g(N2, f2, G[0], k, l, m, D);
                     Dz = D[3] * p->dt;
                     z = p->z_launch + 0.5 * Dz;
                     A = cell_area(g, j, p->z_launch);

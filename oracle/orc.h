@@ -53,6 +53,11 @@ typedef struct {
     double *Ux, *Uy, *Uz, *Vx, *Vy, *Vz, *N2x, *N2y, *N2z;
     double *f2y;        /* [ny] */
     const double *f;    /* [ny]: Coriolis parameter per row, signed */
+    /* scale-height correction Gamma^2 at cell centres [nz][ny][nx]
+       (Section 2a, eq. dispersion); NULL means Gamma = 0.  Its gradients are
+       filled by orc_prepare when it is given. */
+    const double *G2;
+    double *G2x, *G2y, *G2z;
 } orc_bg;
 
 typedef struct {
@@ -85,6 +90,8 @@ typedef struct {
 void orc_prepare(orc_bg *g);
 void orc_interp(const orc_bg *g, double x, double y, double z, double out[14]);
 void orc_dispersion(double N2, double f2, double k, double l, double m, double out[4]);
+void orc_dispersion_g(double N2, double f2, double G2, double k, double l, double m, double out[4]);
+void orc_interp_gamma(const orc_bg *g, double x, double y, double z, double out[4]);
 void orc_rhs(const orc_bg *g, const double Y[9], double F[9]);
 void orc_step(const orc_bg *g, orc_rays *r, int64_t n, double dt, orc_tally *t);
 void orc_keys(const orc_bg *g, orc_rays *r, int64_t n);

@@ -79,8 +79,8 @@ def test_full_fluxes_equal_polarization_stresses(orc, f0):
             assert F[4, lev, j, i] == pytest.approx(s * s * _avg(u2, b2), rel=1e-9, abs=1e-12 * scale), lev
             assert F[5, lev, j, i] == pytest.approx(s * s * _avg(v2, b2), rel=1e-9, abs=1e-12 * scale), lev
         # vertical fluxes on the interface kc + 1 (its staggered cell lies inside the volume)
-        assert F[6, kc + 1, j, i] == pytest.approx(rho * _avg(wz, u), rel=1e-9)
-        assert F[7, kc + 1, j, i] == pytest.approx(rho * _avg(wz, v), rel=1e-9)
+        assert F[6, kc + 1, j, i] == pytest.approx(rho * _avg(wz, u), rel=1e-9, abs=0)
+        assert F[7, kc + 1, j, i] == pytest.approx(rho * _avg(wz, v), rel=1e-9, abs=0)
         if f0 == 0.0:
             assert not F[4:6].any()
 
@@ -118,16 +118,16 @@ def test_smoothing_weights(orc):
     exp[1:4, 2:5] = np.array([[1, 2, 1], [2, 3, 2], [1, 2, 1]]) / 15.0
     assert np.allclose(S[0], exp, rtol=1e-15, atol=1e-17)
     assert np.allclose(S[1], 7.25, rtol=1e-15)
-    assert S[2].sum() == pytest.approx(F[2].sum(), rel=1e-13)
+    assert S[2].sum() == pytest.approx(F[2].sum(), rel=1e-13, abs=0)
     sph = W.analytic_sphere(nx=8, ny=6, nz=2)
     bgs = orc.Background.from_workload(sph)
     G = np.zeros((1, 6, 8))
     G[0, 0, 0] = 1.0
     Sg = orc.smooth(bgs, G)
-    assert Sg[0, 0, 0] == pytest.approx(3.0 / 11.0, rel=1e-15)
-    assert Sg[0, 0, 1] == pytest.approx(2.0 / 11.0, rel=1e-15)
-    assert Sg[0, 1, 0] == pytest.approx(2.0 / 15.0, rel=1e-15)  # row 1 has all its neighbours
-    assert Sg[0, 1, 7] == pytest.approx(1.0 / 15.0, rel=1e-15)  # periodic corner
+    assert Sg[0, 0, 0] == pytest.approx(3.0 / 11.0, rel=1e-15, abs=0)
+    assert Sg[0, 0, 1] == pytest.approx(2.0 / 11.0, rel=1e-15, abs=0)
+    assert Sg[0, 1, 0] == pytest.approx(2.0 / 15.0, rel=1e-15, abs=0)  # row 1 has all its neighbours
+    assert Sg[0, 1, 7] == pytest.approx(1.0 / 15.0, rel=1e-15, abs=0)  # periodic corner
 
 
 def test_tendencies_closed_forms(orc):
@@ -208,7 +208,7 @@ def test_budget_fields_brute_force_and_totals(orc):
     for q in range(4):
         assert np.abs(Fb[q] - ref[q]).max() <= 1e-13 * np.abs(ref[q]).max(), q
     tot = (Fb[0, :w.nz] * w.dx * w.dy * w.dz).sum()
-    assert tot == pytest.approx((rays["n"] * rays["px"] * rays["py"] * rays["pz"]).sum(), rel=1e-13)
+    assert tot == pytest.approx((rays["n"] * rays["px"] * rays["py"] * rays["pz"]).sum(), rel=1e-13, abs=0)
     # identical columns: no horizontal propagation term
     wi = W.make_c1(n_rays=256)
     g = np.arange(256)

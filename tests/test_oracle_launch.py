@@ -81,10 +81,10 @@ def test_launch_carries_the_column_flux(orc):
     cols = (np.floor(rs["y"] / w.dy) * w.nx + np.floor(rs["x"] / w.dx)).astype(int)
     assert np.all(np.diff(cols) >= 0) and 3 not in cols
     Wv = rs["n"] * rs["px"] * rs["py"] * rs["pz"]
-    assert t["launched_W"] == pytest.approx(Wv.sum(), rel=1e-12)
+    assert t["launched_W"] == pytest.approx(Wv.sum(), rel=1e-12, abs=0)
     for c in np.unique(cols):
         sel = cols == c
-        assert (kh * Wv[sel]).sum() == pytest.approx(flux[c] * A * dt, rel=1e-12)
+        assert (kh * Wv[sel]).sum() == pytest.approx(flux[c] * A * dt, rel=1e-12, abs=0)
         assert abs((rs["k"][sel] * Wv[sel]).sum()) <= 1e-12 * kh * Wv[sel].sum()
         assert abs((rs["l"][sel] * Wv[sel]).sum()) <= 1e-12 * kh * Wv[sel].sum()
     cb = 4.0 + (np.arange(8) + 0.5) * 5.0
@@ -92,12 +92,12 @@ def test_launch_carries_the_column_flux(orc):
         k, l, m = rs["k"][q], rs["l"][q], rs["m"][q]
         b = q % 8
         assert m < 0
-        assert math.hypot(k, l) == pytest.approx(kh, rel=1e-15)
-        assert _omega(N2, f0 * f0, k, l, m) == pytest.approx(kh * cb[b], rel=1e-13)
+        assert math.hypot(k, l) == pytest.approx(kh, rel=1e-15, abs=0)
+        assert _omega(N2, f0 * f0, k, l, m) == pytest.approx(kh * cb[b], rel=1e-13, abs=0)
         h = 1e-6 * abs(m)
         cgz = (_omega(N2, f0 * f0, k, l, m + h) - _omega(N2, f0 * f0, k, l, m - h)) / (2 * h)
-        assert rs["dz"][q] / dt == pytest.approx(cgz, rel=1e-7)
-        assert rs["z"][q] - 0.5 * rs["dz"][q] == pytest.approx(zl, rel=1e-15)
+        assert rs["dz"][q] / dt == pytest.approx(cgz, rel=1e-7, abs=0)
+        assert rs["z"][q] - 0.5 * rs["dz"][q] == pytest.approx(zl, rel=1e-15, abs=0)
     # directions east, north, west, south in turn for each column
     first = np.arange(0, n, 8)
     d = np.arange(first.size) % 4
@@ -134,7 +134,7 @@ def test_launch_discards_bins_that_cannot_propagate(orc):
         assert np.isfinite(rs["m"]).all()
         Wv = rs["n"] * rs["px"] * rs["py"] * rs["pz"]
         tot = (kh * Wv).sum()
-        assert tot == pytest.approx(flux.sum() * w.dx * w.dy * 30.0 * wts[prop].sum() / wts.sum(), rel=1e-12)
+        assert tot == pytest.approx(flux.sum() * w.dx * w.dy * 30.0 * wts[prop].sum() / wts.sum(), rel=1e-12, abs=0)
     assert kinds == {"inertial", "fast"}
     small = orc.RaySet({f: np.zeros(0) for f in orc.RAY_FIELDS} | {"id": np.zeros(0, np.int64)}, capacity=rs.n - 1)
     with pytest.raises(RuntimeError):
@@ -167,8 +167,8 @@ def test_launch_on_the_sphere(orc):
         B = bg.interp(7.5 * w.dx, phij, 9e3)
         om2 = (kh * cb) ** 2
         prop = (om2 > B[12]) & (om2 < B[2])  # slower bins are inertial near the poles
-        assert (kh * Wv[sel]).sum() == pytest.approx(fsol * A * 20.0 * wts[prop].sum() / wts.sum(), rel=1e-12)
+        assert (kh * Wv[sel]).sum() == pytest.approx(fsol * A * 20.0 * wts[prop].sum() / wts.sum(), rel=1e-12, abs=0)
     q = 0
     r = w.a + rs["z"][q]
-    assert rs["px"][q] == pytest.approx(r * math.cos(rs["y"][q]) * w.dx * 0.1 * kh, rel=1e-14)
-    assert rs["py"][q] == pytest.approx(r * w.dy * 0.1 * kh, rel=1e-14)
+    assert rs["px"][q] == pytest.approx(r * math.cos(rs["y"][q]) * w.dx * 0.1 * kh, rel=1e-14, abs=0)
+    assert rs["py"][q] == pytest.approx(r * w.dy * 0.1 * kh, rel=1e-14, abs=0)

@@ -41,7 +41,7 @@ def test_gelu_closed_forms():
     assert mlp.gelu(0.0) == 0.0
     assert mlp.dgelu(0.0) == pytest.approx(0.5, abs=1e-15)
     # large |z|: identity / zero
-    assert mlp.gelu(10.0) == pytest.approx(10.0, rel=1e-15)
+    assert mlp.gelu(10.0) == pytest.approx(10.0, rel=1e-15, abs=0)
     assert abs(mlp.gelu(-10.0)) < 1e-15
     # the tanh form approximates z Phi(z) to within 5e-4 absolute
     for z in np.linspace(-5, 5, 101):
@@ -61,7 +61,7 @@ def test_gelu_closed_forms():
     for z in (-3.1, -0.7, 0.2, 1.3, 2.9):
         zd = Decimal(z)
         fd = float((g(zd + h) - g(zd - h)) / (2 * h))
-        assert mlp.dgelu(z) == pytest.approx(fd, rel=1e-12)
+        assert mlp.dgelu(z) == pytest.approx(fd, rel=1e-12, abs=0)
 
 
 def test_hand_network():
@@ -75,7 +75,7 @@ def test_hand_network():
     def g(z):
         return 0.5 * z * (1 + math.tanh(math.sqrt(2 / math.pi) * (z + 0.044715 * z ** 3)))
 
-    assert y[0, 0] == pytest.approx(g(1.5) - 2 * g(1.0) + 0.25, rel=1e-15)
+    assert y[0, 0] == pytest.approx(g(1.5) - 2 * g(1.0) + 0.25, rel=1e-15, abs=0)
 
 
 def test_gradient_finite_differences():
@@ -109,7 +109,7 @@ def test_loss_is_mean_square():
     X = np.ones((3, SMALL.n_in))
     Y, _ = mlp.forward(p, SMALL, X, emulate=False)
     L, _ = mlp.loss_and_grad(p, SMALL, X, Y + 2.0, emulate=False)
-    assert L == pytest.approx(4.0, rel=1e-14)
+    assert L == pytest.approx(4.0, rel=1e-14, abs=0)
 
 
 def test_adam_first_step_closed_form():
@@ -136,7 +136,7 @@ def test_gate_closed_forms():
     b = np.array([[2.0, 4.0], [0.0, 0.0], [3.0, 3.0]])
     X = np.array([[0.5], [0.5], [5.0]])
     sp, mask = mlp.gate(np.stack([a, b]), X, [0.0], [1.0], tau=10.0)
-    assert sp[0] == pytest.approx(math.sqrt((0.5 + 2.0) / 2), rel=1e-15)
+    assert sp[0] == pytest.approx(math.sqrt((0.5 + 2.0) / 2), rel=1e-15, abs=0)
     assert sp[1] == 0.0
     assert list(mask) == [1, 1, 0]
     _, mask0 = mlp.gate(np.stack([a, b]), X, [0.0], [1.0], tau=0.0)
@@ -198,9 +198,9 @@ def test_features_brute_force(orc):
         zv = np.array([b for _, b in lst])
         zm = (wv * zv).sum() / wv.sum()
         sd = math.sqrt((wv * (zv - zm) ** 2).sum() / wv.sum())
-        assert got[col, s, 4] == pytest.approx(zm, rel=1e-12)
+        assert got[col, s, 4] == pytest.approx(zm, rel=1e-12, abs=0)
         assert abs(got[col, s, 5] - sd) <= 1e-6 * zm  # one-pass variance: cancellation floor
         nspread += len(lst) > 1 and sd > 1.0
     assert nspread > 5
     assert np.all(got[~ok] == 0)
-    assert got[:, :, 0].sum() == pytest.approx(orc.stats(rs)["sum_W"], rel=1e-12)
+    assert got[:, :, 0].sum() == pytest.approx(orc.stats(rs)["sum_W"], rel=1e-12, abs=0)

@@ -8,6 +8,7 @@ each case.  CPU only."""
 import pytest
 
 import test_oracle_fullflux as X
+import test_oracle_gamma as G
 import test_oracle_launch as L
 import test_oracle_pins as P
 import test_oracle_pins_sphere as S
@@ -18,10 +19,42 @@ MUTATIONS = [
      "double Fb = (0.25 * Fc) * (exp(-(s * s)) / sw);",
      "double Fb = (0.5 * Fc) * (exp(-(s * s)) / sw);",
      [L.test_launch_carries_the_column_flux]),
-    ("launch keeps inertial bins",
-     "if (!(om2 > f2 && om2 < N2) || !(Fb > 0.0)) continue;",
-     "if (!(om2 < N2) || !(Fb > 0.0)) continue;",
-     [L.test_launch_discards_bins_that_cannot_propagate]),
+    ("launch keeps bins made evanescent by Gamma",
+     "if (!(m2 > 0.0)) continue; /* evanescent: Gamma^2 exceeds m^2 + Gamma^2 */",
+     ";",
+     [G.test_launch_with_gamma]),
+    ("launch ignores Gamma",
+     "m2 = ((kh * kh) * (N2 - om2)) / (om2 - f2) - G[0];",
+     "m2 = ((kh * kh) * (N2 - om2)) / (om2 - f2);",
+     [G.test_launch_with_gamma]),
+    ("Gamma dropped from the dispersion relation",
+     "double M2 = m * m + G2;",
+     "double M2 = m * m;",
+     [G.test_dispersion_is_the_gamma_free_relation_at_shifted_m]),
+    ("K^2 without Gamma^2 in the dispersion relation",
+     "double K2 = kh2 + M2;",
+     "double K2 = kh2 + m * m;",
+     [G.test_dispersion_is_the_gamma_free_relation_at_shifted_m]),
+    ("refraction by Gamma^2 gradients with the wrong sign",
+     "qg = -((kh2 * (B[2] - B[12])) / (((2.0 * om) * K2) * K2));",
+     "qg = (kh2 * (B[2] - B[12])) / (((2.0 * om) * K2) * K2);",
+     [lambda orc: G.test_refraction_by_gamma_gradients_conserves_frequency(orc, "gamma_xz")]),
+    ("(f^2)_phi refraction weight without Gamma^2",
+     "qf = M2 / ((2.0 * om) * K2);",
+     "qf = (m * m) / ((2.0 * om) * K2);",
+     [lambda orc: G.test_refraction_by_gamma_gradients_conserves_frequency(orc, "beta")]),
+    ("faces evaluated without Gamma",
+     "*G2 = g->G2 ? trilin(g, g->G2, &c) : 0.0;",
+     "*G2 = 0.0;",
+     [G.test_extent_rates_use_gamma_at_the_faces]),
+    ("Gamma^2 gradient taken from N^2",
+     "g->G2x[c] = ddx(g, g->G2, i, j, k);",
+     "g->G2x[c] = ddx(g, g->N2, i, j, k);",
+     [G.test_gamma_fields_interpolate_and_differentiate_exactly]),
+    ("saturation K^2 without Gamma^2",
+     "K2 = kh2 + (m2 + G2);",
+     "K2 = kh2 + m2;",
+     [G.test_saturation_and_deposit_are_gamma_free_at_shifted_m]),
     ("launched volume covers half the crossing",
      "Dz = D[3] * p->dt;",
      "Dz = D[3] * (0.5 * p->dt);",

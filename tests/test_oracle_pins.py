@@ -38,11 +38,11 @@ def omega_hat(N2, f2, k, l, m):
 def test_dispersion_limits(orc):
     N2, f2 = 4e-4, 1e-8
     # pure horizontal wavevector -> omega = N; pure vertical -> omega = |f|
-    assert orc.dispersion(N2, f2, 1e-4, 0.0, 0.0)[0] == pytest.approx(0.02, rel=1e-15)
-    assert orc.dispersion(N2, f2, 0.0, 0.0, -1e-3)[0] == pytest.approx(1e-4, rel=1e-15)
+    assert orc.dispersion(N2, f2, 1e-4, 0.0, 0.0)[0] == pytest.approx(0.02, rel=1e-15, abs=0)
+    assert orc.dispersion(N2, f2, 0.0, 0.0, -1e-3)[0] == pytest.approx(1e-4, rel=1e-15, abs=0)
     # hydrostatic non-rotating limit omega ~ N kh / |m|
     om = orc.dispersion(N2, 0.0, 1e-6, 0.0, -1e-2)[0]
-    assert om == pytest.approx(0.02 * 1e-6 / 1e-2, rel=1e-7)
+    assert om == pytest.approx(0.02 * 1e-6 / 1e-2, rel=1e-7, abs=0)
     # bounded by f and N
     rng = np.random.default_rng(0)
     for _ in range(200):
@@ -76,10 +76,10 @@ def test_group_velocity_is_wavenumber_gradient(orc):
             ap[idx] += h
             am[idx] -= h
             fd = float((om50(ap) - om50(am)) / (2 * h))
-            assert c == pytest.approx(fd, rel=1e-12)
+            assert c == pytest.approx(fd, rel=1e-12, abs=0)
         K2 = k * k + l * l + m * m
-        assert cx == pytest.approx(k * (N2 - om * om) / (om * K2), rel=1e-9)
-        assert cz == pytest.approx(m * (f2 - om * om) / (om * K2), rel=1e-9)
+        assert cx == pytest.approx(k * (N2 - om * om) / (om * K2), rel=1e-9, abs=0)
+        assert cz == pytest.approx(m * (f2 - om * om) / (om * K2), rel=1e-9, abs=0)
 
 
 # --------------------------------------------------------------------------
@@ -97,12 +97,12 @@ def test_interpolation_exact_for_linear_fields(orc):
         y = rng.uniform(0.5 * w.dy, (w.ny - 1.5) * w.dy)
         z = rng.uniform(0.5 * w.dz, (w.nz - 0.5) * w.dz)
         B = bg.interp(x, y, z)
-        assert B[0] == pytest.approx(a * x * 1e-5 + b * y * 1e-5 + c * z * 1e-3 + 7.0, rel=1e-13)
-        assert B[1] == pytest.approx(0.3, rel=1e-15)
-        assert B[2] == pytest.approx(1e-4 + 1e-9 * z, rel=1e-13)
+        assert B[0] == pytest.approx(a * x * 1e-5 + b * y * 1e-5 + c * z * 1e-3 + 7.0, rel=1e-13, abs=0)
+        assert B[1] == pytest.approx(0.3, rel=1e-15, abs=0)
+        assert B[2] == pytest.approx(1e-4 + 1e-9 * z, rel=1e-13, abs=0)
         # gradients: dU/dz exact in the interior, d/dz of N2
-        assert B[5] == pytest.approx(c * 1e-3, rel=1e-9)
-        assert B[11] == pytest.approx(1e-9, rel=1e-9)
+        assert B[5] == pytest.approx(c * 1e-3, rel=1e-9, abs=0)
+        assert B[11] == pytest.approx(1e-9, rel=1e-9, abs=0)
 
 
 def test_interpolation_reproduces_nodes_and_wraps(orc):
@@ -119,10 +119,10 @@ def test_interpolation_reproduces_nodes_and_wraps(orc):
     x, y, z = 0.1 * w.dx, 3.9 * w.dy, 2.2 * w.dz
     B1 = bg.interp(x, y, z)
     B2 = bg.interp(x + 5 * w.dx, y - 4 * w.dy, z)
-    assert B1[0] == pytest.approx(B2[0], rel=1e-12)
+    assert B1[0] == pytest.approx(B2[0], rel=1e-12, abs=0)
     # halfway between the last and first centre (across the seam) is the mean
     B3 = bg.interp(0.0, 0.5 * w.dy, 0.5 * w.dz)
-    assert B3[0] == pytest.approx(0.5 * (w.U[0, 0, 0] + w.U[0, 0, 4]), rel=1e-13)
+    assert B3[0] == pytest.approx(0.5 * (w.U[0, 0, 0] + w.U[0, 0, 4]), rel=1e-13, abs=0)
     # vertical clamp below the first and above the last level centre
     B4 = bg.interp(0.5 * w.dx, 0.5 * w.dy, 0.1 * w.dz)
     assert B4[0] == w.U[0, 0, 0]
@@ -167,14 +167,14 @@ def test_refraction_matches_gradient_of_frequency(orc):
         gx = (Om(x + h[0], y, z) - Om(x - h[0], y, z)) / (2 * h[0])
         gy = (Om(x, y + h[1], z) - Om(x, y - h[1], z)) / (2 * h[1])
         gz = (Om(x, y, z + h[2]) - Om(x, y, z - h[2])) / (2 * h[2])
-        assert F[3] == pytest.approx(-gx, rel=1e-6)
-        assert F[4] == pytest.approx(-gy, rel=1e-6)
-        assert F[5] == pytest.approx(-gz, rel=1e-6)
+        assert F[3] == pytest.approx(-gx, rel=1e-6, abs=0)
+        assert F[4] == pytest.approx(-gy, rel=1e-6, abs=0)
+        assert F[5] == pytest.approx(-gz, rel=1e-6, abs=0)
         # tiny volume: the carrier moves with the local group velocity U + cg
         om, cx, cy, cz = orc.dispersion(fN(x, y, z), 1e-8 + 2e-14 * y, k, l, m)
-        assert F[0] == pytest.approx(fU(x, y, z) + cx, rel=1e-9)
-        assert F[1] == pytest.approx(fV(x, y, z) + cy, rel=1e-9)
-        assert F[2] == pytest.approx(cz, rel=1e-6)
+        assert F[0] == pytest.approx(fU(x, y, z) + cx, rel=1e-9, abs=0)
+        assert F[1] == pytest.approx(fV(x, y, z) + cy, rel=1e-9, abs=0)
+        assert F[2] == pytest.approx(cz, rel=1e-6, abs=0)
 
 
 # --------------------------------------------------------------------------
@@ -256,13 +256,13 @@ def test_rk3_matches_published_butcher_weights(orc):
         return orc.dispersion(N2, f2, k, l, m)[3]
 
     pred = 20e3 + dt * sum(bi * g(ci * dt) for bi, ci in zip(G["b"], G["c"]))
-    assert rs["m"][0] == pytest.approx(m0 - k * Lam * dt, rel=1e-13)
+    assert rs["m"][0] == pytest.approx(m0 - k * Lam * dt, rel=1e-13, abs=0)
     assert rs["z"][0] == pytest.approx(pred, rel=1e-13, abs=1e-9)
     # sanity of the golden table itself: 2N-storage (A,B) reproduces (b,c)
     A, B = G["A"], G["B"]
     c2 = B[0]
     c3 = B[0] + B[1] * (A[1] + 1)
-    assert (c2, c3) == pytest.approx(G["c"][1:], rel=1e-15)
+    assert (c2, c3) == pytest.approx(G["c"][1:], rel=1e-15, abs=0)
 
 
 def test_constant_shear_closed_form_and_order(orc):
@@ -280,7 +280,7 @@ def test_constant_shear_closed_form_and_order(orc):
             orc.step(bg, rs, T / nsteps)
         mT = m0 - k * Lam * T
         zT = 20e3 - (omega_hat(N2, f2, k, 0, mT) - omega_hat(N2, f2, k, 0, m0)) / (k * Lam)
-        assert rs["m"][0] == pytest.approx(mT, rel=1e-12)
+        assert rs["m"][0] == pytest.approx(mT, rel=1e-12, abs=0)
         errs.append(abs(rs["z"][0] - zT))
     assert errs[0] > 0
     assert errs[0] / errs[1] > 7.0 and errs[1] / errs[2] > 7.0
@@ -372,7 +372,7 @@ def test_liouville_area_in_z_m(orc):
     for _ in range(60):
         orc.step(bg, rs, 60.0)
     a1 = area(rs["z"], rs["m"])
-    assert a1 == pytest.approx(a0, rel=2e-3)
+    assert a1 == pytest.approx(a0, rel=2e-3, abs=0)
     # the area actually deformed (the test is not vacuous)
     assert abs(np.ptp(rs["z"]) - 2 * hz) > 0.01 * hz
 
@@ -400,8 +400,8 @@ def test_volume_extent_tracks_face_rays(orc):
             B = bg.interp(*p)
             _, cx, cy, cz = orc.dispersion(B[2], B[12], k, l, m)
             vals.append((B[0] + cx, B[1] + cy, cz)[ax])
-        assert F[6 + ax] == pytest.approx(vals[0] - vals[1], rel=1e-12)
-        assert F[ax] == pytest.approx(0.5 * (vals[0] + vals[1]), rel=1e-12)
+        assert F[6 + ax] == pytest.approx(vals[0] - vals[1], rel=1e-12, abs=0)
+        assert F[ax] == pytest.approx(0.5 * (vals[0] + vals[1]), rel=1e-12, abs=0)
         assert abs(F[6 + ax]) > 1e-6 * abs(F[ax])
 
 
@@ -422,7 +422,7 @@ def test_wave_action_budget_with_exits(orc):
         ntop += t["n_top"]
     assert ntop > 0
     W1 = orc.stats(rs)["sum_W"]
-    assert W1 + removed == pytest.approx(W0, rel=1e-14)
+    assert W1 + removed == pytest.approx(W0, rel=1e-14, abs=0)
     # per-ray wave action never changes without sources (N and P constant)
     act = rs.active()
     assert np.array_equal(rs["n"][act] * rs["px"][act], w.rays["n"][act] * w.rays["px"][act])
@@ -631,7 +631,7 @@ def test_identical_column_rays_zero_horizontal_divergence(orc):
     _, _, _, cz = orc.dispersion(B[2], B[12], w.rays["k"][0], w.rays["l"][0], w.rays["m"][0])
     Wr = w.rays["n"][0] * w.rays["px"][0] * w.rays["py"][0] * w.rays["pz"][0]
     kk = 3  # ray spans [2.5, 3.5] km, interface 3 at 3 km covers [2.5, 3.5]
-    assert flux[4, kk, 0, 0] == pytest.approx(cz * w.rays["k"][0] * Wr / (w.rays["dz"][0] * w.dx * w.dy), rel=1e-14)
+    assert flux[4, kk, 0, 0] == pytest.approx(cz * w.rays["k"][0] * Wr / (w.rays["dz"][0] * w.dx * w.dy), rel=1e-14, abs=0)
 
 
 # --------------------------------------------------------------------------
@@ -652,7 +652,7 @@ def test_split_halves_and_preserves_deposit(orc):
     assert (rs["dz"] <= 2.0 * w.dz).all()
     s1 = orc.stats(rs)
     for key in ("sum_W", "sum_kW", "sum_lW", "sum_mW"):
-        assert s1[key] == pytest.approx(s0[key], rel=1e-14)
+        assert s1[key] == pytest.approx(s0[key], rel=1e-14, abs=0)
     f1 = orc.deposit(bg, rs)
     assert np.abs(f1 - f0).max() <= 1e-13 * np.abs(f0).max()
     # pieces tile the parent exactly: first child keeps id and slot
@@ -661,7 +661,7 @@ def test_split_halves_and_preserves_deposit(orc):
     zb = rs["z"][kids] - rs["dz"][kids] / 2
     zt = rs["z"][kids] + rs["dz"][kids] / 2
     order = np.argsort(zb)
-    assert zb[order][0] == pytest.approx(w.rays["z"][big] - w.rays["dz"][big] / 2, rel=1e-15)
+    assert zb[order][0] == pytest.approx(w.rays["z"][big] - w.rays["dz"][big] / 2, rel=1e-15, abs=0)
     assert np.allclose(zt[order][:-1], zb[order][1:], rtol=1e-15)
     assert rs["id"][big] == big
     # capacity shortfall leaves everything unchanged
@@ -682,10 +682,10 @@ def test_merge_conserves_and_caps_counts(orc):
     assert t["n_merged"] > 0
     a_ = rs.active()
     mom1 = [(rs[f][a_] * Wv(rs)[a_]).sum() for f in ("x", "y", "z")]
-    assert mom1 == pytest.approx(mom0, rel=1e-13)
+    assert mom1 == pytest.approx(mom0, rel=1e-13, abs=0)
     s1 = orc.stats(rs)
     for key in ("sum_W", "sum_kW", "sum_lW", "sum_mW"):
-        assert s1[key] == pytest.approx(s0[key], rel=1e-13)
+        assert s1[key] == pytest.approx(s0[key], rel=1e-13, abs=0)
     act = rs.active()
     cell = rs["col"][act].astype(np.int64) * w.nz + np.clip(np.floor(rs["z"][act] / w.dz), 0, w.nz - 1).astype(np.int64)
     assert np.bincount(cell).max() <= 16
@@ -714,7 +714,7 @@ def test_cap_removes_lowest_energy(orc):
         sel = col == c
         thr = np.sort(E[sel])[28]
         assert (E[sel & gone] <= thr).all() and (E[sel & ~gone] >= np.sort(E[sel])[27]).all()
-    assert t["removed_W"] == pytest.approx((before["n"] * before["px"] * before["py"] * before["pz"])[gone].sum(), rel=1e-13)
+    assert t["removed_W"] == pytest.approx((before["n"] * before["px"] * before["py"] * before["pz"])[gone].sum(), rel=1e-13, abs=0)
 
 
 # --------------------------------------------------------------------------

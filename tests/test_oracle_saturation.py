@@ -50,8 +50,8 @@ def test_monochromatic_limit(orc, ratio):
     n0 = rs["n"].copy()
     bg = orc.Background.from_workload(w)
     P, Q, kap = orc.saturation(bg, rs, 60.0)
-    assert P[kc, 2, 1] / (0.5 * rho) == pytest.approx(B2 * m * m / (N2 * N2), rel=1e-12)
-    assert Q[kc, 2, 1] == pytest.approx(P[kc, 2, 1] * K * K, rel=1e-12)
+    assert P[kc, 2, 1] / (0.5 * rho) == pytest.approx(B2 * m * m / (N2 * N2), rel=1e-12, abs=0)
+    assert Q[kc, 2, 1] == pytest.approx(P[kc, 2, 1] * K * K, rel=1e-12, abs=0)
     others = np.ones(P.shape, bool)
     others[kc, 2, 1] = False
     assert not P[others].any() and not kap[others].any()
@@ -60,9 +60,9 @@ def test_monochromatic_limit(orc, ratio):
         assert np.array_equal(rs["n"], n0)
     else:
         # factor 1 - (P - rho/2) K^2 / (P K^2) = (rho/2) / P
-        assert rs["n"][0] / n0[0] == pytest.approx(1.0 / ratio, rel=1e-13)
+        assert rs["n"][0] / n0[0] == pytest.approx(1.0 / ratio, rel=1e-13, abs=0)
         P2, _, _ = orc.saturation(bg, rs, 60.0)
-        assert P2[kc, 2, 1] == pytest.approx(0.5 * rho, rel=1e-13)
+        assert P2[kc, 2, 1] == pytest.approx(0.5 * rho, rel=1e-13, abs=0)
 
 
 def _spectrum_in_cells(w, rng, n_per, lz=(1e3, 8e3), dz_frac=0.4):
@@ -117,12 +117,12 @@ def test_threshold_restored_in_each_cell(orc):
     P2, _, _ = orc.saturation(bg, orc.RaySet({f: rs[f].copy() for f in rays}), 30.0)
     K2 = rays["k"] ** 2 + rays["l"] ** 2 + rays["m"] ** 2
     for (i, j, k), fac in zip(cells, (1.25, 1.1, 0.8, 0.5)):
-        assert P[k, j, i] / (0.5 * w.rho[k]) == pytest.approx(fac, rel=1e-12)
+        assert P[k, j, i] / (0.5 * w.rho[k]) == pytest.approx(fac, rel=1e-12, abs=0)
         sel = (ci == i) & (cj == j) & (ck == k)
         if fac > 1:
-            assert P2[k, j, i] == pytest.approx(0.5 * w.rho[k], rel=1e-12)
+            assert P2[k, j, i] == pytest.approx(0.5 * w.rho[k], rel=1e-12, abs=0)
             kk = kap[k, j, i]
-            assert kk == pytest.approx((P[k, j, i] - 0.5 * w.rho[k]) / (2 * 30.0 * Q[k, j, i]), rel=1e-14)
+            assert kk == pytest.approx((P[k, j, i] - 0.5 * w.rho[k]) / (2 * 30.0 * Q[k, j, i]), rel=1e-14, abs=0)
             expect = n0[sel] * (1 - 2 * kk * K2[sel] * 30.0)
             assert np.allclose(rs["n"][sel], expect, rtol=1e-13, atol=0)
         else:
