@@ -149,6 +149,23 @@ rt_status rt_destroy(rt_ctx ctx);
 rt_status rt_init_background(rt_ctx ctx, const double *U, const double *V, const double *N2,
                              const double *f, const double *rho, int32_t where);
 
+/* Scale-height correction Gamma (Section 2a, eq. dispersion, where K^2 =
+ * k.k + Gamma^2, and the d Gamma^2 terms of eq. eikonal-sphere 1-3).
+ *   G2  [nz][ny][nx] double: Gamma^2 at the cell centres (>= 0, finite); it
+ *       is interpolated like N^2 to the carrier and the faces, and its
+ *       gradients are formed on the device by the same centred differences.
+ *       NULL switches the correction off (Gamma = 0, the default).
+ * With the correction on, every evaluation of the dispersion relation uses
+ * omega_hat^2 = (N^2 kh^2 + f^2 (m^2 + Gamma^2)) / K^2 and the group
+ * velocity derived from it: the step (frequency, face velocities, refraction
+ * including d omega_hat / d Gamma^2 = -(kh^2/(2 omega_hat K^2))(N^2-f^2)/K^2),
+ * the deposition, saturation (K^2 with Gamma^2), full fluxes, budget, the
+ * cap's wave energy, the surrogate features, and the launch (a bin whose
+ * m^2 + Gamma^2 from the dispersion relation does not exceed Gamma^2 is
+ * evanescent and discarded).  Host input is copied before return; RT_E_ARG
+ * for a negative or non-finite value (host input only). */
+rt_status rt_set_scale_height(rt_ctx ctx, const double *G2, int32_t where);
+
 /* Load n ray volumes (replacing any current set).  n may be 0.  Volumes
  * outside the vertical domain, with non-finite state or non-positive extents
  * are counted as removed at load.  RT_E_CAPACITY if n > capacity. */

@@ -1212,7 +1212,9 @@ void orc_saturation(const orc_bg *g, orc_rays *r, int64_t n, double dt, double *
             kbar += (o / r->dz[i]) * kappa[IDX(g, ci, cj, kk)];
         }
         if (kbar > 0.0) {
-            K2 = (r->k[i] * r->k[i] + r->l[i] * r->l[i]) + r->m[i] * r->m[i];
+            double G[4];
+            orc_interp_gamma(g, r->x[i], r->y[i], r->z[i], G); /* K^2 includes Gamma^2 */
+            K2 = (r->k[i] * r->k[i] + r->l[i] * r->l[i]) + (r->m[i] * r->m[i] + G[0]);
             fac = 1.0 - ((2.0 * kbar) * K2) * dt;
             if (fac < 0.0) fac = 0.0;
             r->n[i] = r->n[i] * fac;

@@ -89,6 +89,7 @@ def lib() -> C.CDLL:
         L.rt_split_merge.argtypes = [P, D, I32, I32, C.POINTER(Stats)]
         L.rt_get_stats.argtypes = [P, C.POINTER(Stats)]
         L.rt_launch.argtypes = [P, C.POINTER(LaunchParams), C.POINTER(I64)]
+        L.rt_set_scale_height.argtypes = [P, P, I32]
         L.rt_get_columns.argtypes = [P, P, C.POINTER(I64), I32]
         L.rt_profile.argtypes = [P, I32]
         L.rt_profile_read.argtypes = [P, P, P]
@@ -99,7 +100,7 @@ def lib() -> C.CDLL:
         for name in ("rt_create", "rt_destroy", "rt_init_background", "rt_set_rays", "rt_set_rays_host_noalloc",
                      "rt_get_rays", "rt_step",
                      "rt_deposit_flux", "rt_split_merge", "rt_get_stats", "rt_profile", "rt_profile_read", "rt_get_columns",
-                     "rt_features", "rt_set_frozen_columns", "rt_saturate", "rt_full_fluxes", "rt_budget", "rt_launch"):
+                     "rt_features", "rt_set_frozen_columns", "rt_saturate", "rt_full_fluxes", "rt_budget", "rt_launch", "rt_set_scale_height"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -198,6 +199,21 @@ class Tracer:
 
     def init_background_from(self, w):
         self.init_background(w.U, w.V, w.N2, w.f, w.rho)
+        if getattr(w, "G2", None) is not None:
+            self.set_scale_height(w.G2)
+
+    def set_scale_height(self, G2):
+        """Gamma^2 [nz][ny][nx] (numpy or CUDA tensor), or None for Gamma = 0
+        (rt_set_scale_height)."""
+        if G2 is None:
+            self._check(lib().rt_set_scale_height(self.h, None, RT_HOST))
+            return
+        torch = self.torch
+        arr = G2.to(self.device, torch.float64) if isinstance(G2, torch.Tensor) else np.asarray(G2, np.float64)
+        ptrs, where, keep = self._ptr_where([arr])
+        self._check(lib().rt_set_scale_height(self.h, ptrs[0], where))
+        if where == RT_DEVICE:
+            self.stream.synchronize()
 
     def set_rays(self, rays: Dict[str, object]):
         torch = self.torch

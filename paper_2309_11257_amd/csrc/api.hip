@@ -438,6 +438,41 @@ static void unstage(rt_ctx ctx, void *p)
     }
 }
 
+extern "C" rt_status rt_set_scale_height(rt_ctx ctx, const double *G2, int32_t where)
+{
+    if (!ctx) return RT_E_ARG;
+    if (!G2) {
+        ctx->bp64.Gm = nullptr;
+        ctx->bp32.Gm = nullptr;
+        return RT_OK;
+    }
+    if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
+    const Grid &g = ctx->g;
+    const int64_t cells = (int64_t)g.ncol * g.nz;
+    if (where == RT_HOST)
+        for (int64_t i = 0; i < cells; i++)
+            if (!(G2[i] >= 0.0) || !std::isfinite(G2[i]))
+                return rt_fail(ctx, RT_E_ARG, "Gamma^2 at cell %lld must be finite and non-negative", (long long)i);
+    if (!ctx->g2raw) {
+        double *raw = (double *)ctx_alloc(ctx, sizeof(double) * (size_t)cells);
+        double4 *p64 = (double4 *)ctx_alloc(ctx, sizeof(double4) * (size_t)cells);
+        float4 *p32 = ctx->precision == RT_FP32 ? (float4 *)ctx_alloc(ctx, sizeof(float4) * (size_t)cells) : nullptr;
+        if (!raw || !p64 || (ctx->precision == RT_FP32 && !p32))
+            return rt_fail(ctx, RT_E_NOMEM, "no device memory for the scale-height correction");
+        ctx->g2raw = raw;
+        ctx->gm64 = p64;
+        ctx->gm32 = p32;
+    }
+    HIP_OK(hipMemcpyAsync(ctx->g2raw, G2, sizeof(double) * (size_t)cells,
+                          where == RT_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, ctx->stream));
+    launch_gamma_pack(g, ctx->g2raw, ctx->gm64, ctx->gm32, ctx->stream);
+    HIP_OK(hipGetLastError());
+    if (where == RT_HOST) HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->bp64.Gm = ctx->gm64;
+    ctx->bp32.Gm = ctx->gm32;
+    return RT_OK;
+}
+
 extern "C" rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int32_t where)
 {
     if (!ctx) return RT_E_ARG;

@@ -244,29 +244,63 @@ __device__ inline double row_lerp(const double *__restrict__ f, const Axis &y)
     return a + y.w * (b - a);
 }
 
-// omega_hat^2 = (N^2 kh^2 + f^2 m^2)/K^2 (eq. dispersion, Gamma = 0)
-__device__ inline double omega_hat(double N2, double f2, double kh2, double m2, double K2)
+// omega_hat^2 = (N^2 kh^2 + f^2 M2)/K^2 (eq. dispersion) with M2 = m^2 +
+// Gamma^2 and K^2 = kh^2 + M2 (m^2 and kh^2 + m^2 where Gamma = 0)
+__device__ inline double omega_hat(double N2, double f2, double kh2, double M2, double K2)
 {
-    return sqrt((N2 * kh2 + f2 * m2) / K2);
+    return sqrt((N2 * kh2 + f2 * M2) / K2);
+}
+
+// Gamma^2 at a cell's interpolation point, 0 where Gamma = 0 (the branch is
+// uniform: the field is there for every volume or for none)
+__device__ inline double gam2(const double4 *Gm, const Cell &c)
+{
+    if (!Gm) return 0.0;
+    // the first component of each corner record only
+    const double *G = (const double *)Gm;
+    return lerp3(G[4 * (c.c00 + c.k0)], G[4 * (c.c01 + c.k0)], G[4 * (c.c10 + c.k0)], G[4 * (c.c11 + c.k0)],
+                 G[4 * (c.c00 + c.k1)], G[4 * (c.c01 + c.k1)], G[4 * (c.c10 + c.k1)], G[4 * (c.c11 + c.k1)], c);
+}
+__device__ inline double gam2(const Bg64P &b, const Cell &c) { return gam2(b.Gm, c); }
+
+__device__ inline double gam2_at(const Grid &g, const Bg64P &b, double x, double y, double z)
+{
+    if (!b.Gm) return 0.0;
+    Cell c;
+    locate(g, x, y, z, c);
+    return gam2(b, c);
 }
 
 // Right-hand side of one RK stage.  Y = (x, y, z, k, l, m, Dx, Dy, Dz).
 // Carrier wavevector tendency from the centre fields and gradients
-// (eq. eikonal-sphere 1-3, Gamma = 0; flat limit on the box); carrier motion
-// and extent rates from the group velocities at the opposing face centres
-// (Section 3a, Appendix B).  A face differs from the centre along one axis,
-// so only that axis is located again.
-template <bool SPH>
+// (eq. eikonal-sphere 1-3; flat limit on the box); carrier motion and extent
+// rates from the group velocities at the opposing face centres (Section 3a,
+// Appendix B).  A face differs from the centre along one axis, so only that
+// axis is located again.  GAM: with the scale-height correction, Gamma^2 at
+// the centre and each face and its gradients at the centre (m^2 is replaced
+// by M2 = m^2 + Gamma^2 in the frequency and the horizontal group velocity,
+// and d omega_hat / d Gamma^2 = -(kh^2 / (2 omega_hat K^2)) (N^2 - f^2)/K^2
+// weighs the gradients).
+template <bool SPH, bool GAM>
 __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, double *F, const WBox &w)
 {
     const double x = Y[0], y = Y[1], z = Y[2], k = Y[3], l = Y[4], m = Y[5];
     const double Dx = Y[6], Dy = Y[7], Dz = Y[8];
     const double kh2 = k * k + l * l;
     const double m2 = m * m;
-    const double K2 = kh2 + m2;
-    const double K4 = K2 * K2;
     const Axis ax = axis_x(g, x), ay = axis_y(g, y), az = axis_z(g, z);
     const Cell c = cell_of(g, ax, ay, az);
+    double4 Gc = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (GAM) {
+        const Corners<1> KG(b.Gm, c, 0);
+        Gc.x = TRI64(KG, x, c);
+        Gc.y = TRI64(KG, y, c);
+        Gc.z = TRI64(KG, z, c);
+        Gc.w = TRI64(KG, w, c);
+    }
+    const double M2 = GAM ? m2 + Gc.x : m2;
+    const double K2 = kh2 + M2;
+    const double K4 = K2 * K2;
     double4 A0;  // U V N2 Ux
     {
         Corners<1> KA;
@@ -277,9 +311,9 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
         A0.w = TRI64(KA, w, c);
     }
     const double f2c = row_lerp(b.f2, ay);
-    const double om = omega_hat(A0.z, f2c, kh2, m2, K2);
+    const double om = omega_hat(A0.z, f2c, kh2, M2, K2);
     const double q = kh2 / ((2.0 * om) * K2);
-    const double qf = m2 / ((2.0 * om) * K2);
+    const double qf = M2 / ((2.0 * om) * K2);
     // gradient records one at a time: (Uy Uz Vx Vy) (Vz N2x N2y N2z)
     const double Ux = A0.w;
     double Uy = 0, Uz = 0, Vx = 0, Vy = 0, Vz = 0, N2x = 0, N2y = 0, N2z = 0;
@@ -302,9 +336,15 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
         N2z = r == 1 ? Gr.w : N2z;
     }
     const double f2y = row_lerp(b.f2y, ay);
-    const double gk = (k * Ux + l * Vx) + q * N2x;
-    const double gl = ((k * Uy + l * Vy) + q * N2y) + qf * f2y;
-    const double gm = (k * Uz + l * Vz) + q * N2z;
+    double gk = (k * Ux + l * Vx) + q * N2x;
+    double gl = ((k * Uy + l * Vy) + q * N2y) + qf * f2y;
+    double gm = (k * Uz + l * Vz) + q * N2z;
+    if (GAM) {
+        const double qg = -((kh2 * (A0.z - f2c)) / (((2.0 * om) * K2) * K2));
+        gk = gk + qg * Gc.y;
+        gl = gl + qg * Gc.z;
+        gm = gm + qg * Gc.w;
+    }
 
     // faces: +x, -x, +y, -y, +z, -z, one at a time (bounded register use)
     double cxp = 0.0, cxm = 0.0, cyp = 0.0, cym = 0.0, czp = 0.0, czm = 0.0;
@@ -328,9 +368,12 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
         const double wnd = lerp3(useU ? K.a0.x : K.a0.y, useU ? K.a1.x : K.a1.y, useU ? K.b0.x : K.b0.y,
                                  useU ? K.b1.x : K.b1.y, useU ? K.d0.x : K.d0.y, useU ? K.d1.x : K.d1.y,
                                  useU ? K.e0.x : K.e0.y, useU ? K.e1.x : K.e1.y, f);
-        const double omf = omega_hat(N2f, f2f, kh2, m2, K2);
-        const double num = axn == 0 ? k * m2 : (axn == 1 ? l * m2 : m * kh2);
-        const double t = (num * (N2f - f2f)) / (omf * K4);
+        const double M2f = GAM ? m2 + gam2(b, f) : m2;
+        const double K2f = GAM ? kh2 + M2f : K2;
+        const double K4f = GAM ? K2f * K2f : K4;
+        const double omf = omega_hat(N2f, f2f, kh2, M2f, K2f);
+        const double num = axn == 0 ? k * M2f : (axn == 1 ? l * M2f : m * kh2);
+        const double t = (num * (N2f - f2f)) / (omf * K4f);
         const double v = axn == 2 ? -t : wnd + t;
         cxp = fc == 0 ? v : cxp;
         cxm = fc == 1 ? v : cxm;

@@ -236,6 +236,27 @@ __device__ inline void n2_f2(const G32 &g, const Bg32P &b, int ic, int jc, int k
     f2 = row_lerp(b.f2, ay);
 }
 
+// Gamma^2 at a cell's interpolation point, 0 where Gamma = 0 (a uniform
+// branch: the field is there for every volume or for none)
+__device__ inline float gam2(const Bg32P &b, const Cell &c)
+{
+    if (!b.Gm) return 0.0f;
+    // the first component of each corner record only (32-bit byte offsets)
+    const char *G = (const char *)b.Gm;
+    auto at = [&](uint32_t idx) { return *(const float *)(G + (idx << 4)); };
+    return lerp3(at(c.c00 + c.k0), at(c.c01 + c.k0), at(c.c10 + c.k0), at(c.c11 + c.k0), at(c.c00 + c.k1),
+                 at(c.c01 + c.k1), at(c.c10 + c.k1), at(c.c11 + c.k1), c);
+}
+
+__device__ inline float gam2_at(const G32 &g, const Bg32P &b, int ic, int jc, int kc, float xi, float eta,
+                                float zeta)
+{
+    if (!b.Gm) return 0.0f;
+    Cell c;
+    locate(g, ic, jc, kc, xi, eta, zeta, c);
+    return gam2(b, c);
+}
+
 // Per-wave stencil box in LDS.  When every volume of a wave lies in one
 // column and the wave's levels span at most WB_LMAX - 6, the wave stages the
 // A records of the 5 x 5 columns around it and the gradient records of the
@@ -539,18 +560,26 @@ __device__ inline void rhs_box(const G32 &g, int kc, float phi0, const float *Y,
 // Vz N2x N2y N2z) plus f2 and (f2)_y by row.  Faces: (U or V) and N2 from the
 // first record; the face differs from the centre along one axis only, so the
 // other two axes are reused, and f2 is the centre's except on the y faces.
-template <bool SPH>
+// GAM: with the scale-height correction (global lookups of the Gamma^2
+// records): m^2 -> M2 = m^2 + Gamma^2 in the frequency and the horizontal
+// group velocity at the centre and each face, K^2 = kh^2 + M2, and the
+// Gamma^2 gradients weighed by d omega_hat / d Gamma^2 =
+// -(kh^2 / (2 omega_hat K^2)) (N^2 - f^2) / K^2.
+template <bool SPH, bool GAM>
 __device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc, float phi0, const float *Y,
                            float *F, const WBox &w)
 {
     const float xi = Y[0], eta = Y[1], zeta = Y[2], k = Y[3], l = Y[4], m = Y[5];
     const float kh2 = k * k + l * l;
     const float m2 = m * m;
-    const float K2 = kh2 + m2;
-    const float invK2 = rcp(K2);
-    const float invK4 = invK2 * invK2;
     const Axis ax = axis_per(ic, xi, g.nx), ay = axis_y(g, jc, eta), az = axis_clamp(kc, zeta, g.nz);
     const Cell c = cell_of(g, ax, ay, az);
+    float4 Gc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (GAM) Gc = tri4<1>(b.Gm, c, 0);
+    const float M2 = GAM ? m2 + Gc.x : m2;
+    const float K2 = kh2 + M2;
+    const float invK2 = rcp(K2);
+    const float invK4 = invK2 * invK2;
     const float f2c = row_lerp(b.f2, ay);
     float gk, gl, gm, N2c;
     {
@@ -562,13 +591,19 @@ __device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc,
         A0.z = TRI_COMP(KA, z, c);
         A0.w = TRI_COMP(KA, w, c);
         N2c = A0.z;
-        const float rom = rsq((N2c * kh2 + f2c * m2) * invK2);  // 1 / omega_hat
+        const float rom = rsq((N2c * kh2 + f2c * M2) * invK2);  // 1 / omega_hat
         const float h = 0.5f * invK2 * rom;
         const float q = kh2 * h;
-        const float qf = m2 * h;
+        const float qf = M2 * h;
         gk = k * A0.w;
         gl = qf * row_lerp(b.f2y, ay);
         gm = 0.0f;
+        if (GAM) {
+            const float qg = -(q * (N2c - f2c) * invK2);
+            gk += qg * Gc.y;
+            gl += qg * Gc.z;
+            gm += qg * Gc.w;
+        }
         // gradient records one at a time (bounded register use)
 #pragma unroll 1
         for (int r = 0; r < 2; r++) {
@@ -614,9 +649,12 @@ __device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc,
                                 useU ? K.e0.x : K.e0.y, useU ? K.e1.x : K.e1.y, f);
         const float N2f = TRI_COMP(K, z, f);
         const float f2f = axn == 1 ? row_lerp(b.f2, fy) : f2c;
-        const float romf = rsq((N2f * kh2 + f2f * m2) * invK2);
-        const float sc = (N2f - f2f) * invK4 * romf;
-        const float v = axn == 0 ? wnd + k * m2 * sc : (axn == 1 ? wnd + l * m2 * sc : -m * kh2 * sc);
+        const float M2f = GAM ? m2 + gam2(b, f) : M2;
+        const float invK2f = GAM ? rcp(kh2 + M2f) : invK2;
+        const float invK4f = GAM ? invK2f * invK2f : invK4;
+        const float romf = rsq((N2f * kh2 + f2f * M2f) * invK2f);
+        const float sc = (N2f - f2f) * invK4f * romf;
+        const float v = axn == 0 ? wnd + k * M2f * sc : (axn == 1 ? wnd + l * M2f * sc : -m * kh2 * sc);
         cxp = fc == 0 ? v : cxp;
         cxm = fc == 1 ? v : cxm;
         cyp = fc == 2 ? v : cyp;

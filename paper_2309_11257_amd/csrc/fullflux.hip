@@ -47,14 +47,14 @@ struct PayFull64 {
         const double f2 = d64::row_lerp(b.f2, ay);
         const double fs = d64::row_lerp(frow, ay);
         const double kh2 = k * k + l * l;
-        const double m2 = m * m;
-        const double K2 = kh2 + m2;
+        const double M2 = m * m + d64::gam2(b, c);
+        const double K2 = kh2 + M2;
         const double K4 = K2 * K2;
-        const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
+        const double om = d64::omega_hat(N2, f2, kh2, M2, K2);
         const double d = N2 - f2;
         const double dn = om * K4;
-        const double cx = ((k * m2) * d) / dn;
-        const double cy = ((l * m2) * d) / dn;
+        const double cx = ((k * M2) * d) / dn;
+        const double cy = ((l * M2) * d) / dn;
         const double cz = -(((m * kh2) * d) / dn);
         const double om2 = om * om;
         const double den = (kh2 * (N2 - f2)) / K2;
@@ -94,13 +94,13 @@ struct PayFull32 {
         f32::n2_f2(g, b, ic, jc, kc, st.xi[s], eta, zeta, N2, f2);
         const float fs = f32::row_lerp(frow, f32::axis_y(g, jc, eta));
         const float kh2 = k * k + l * l;
-        const float m2 = m * m;
-        const float K2 = kh2 + m2;
+        const float M2 = m * m + f32::gam2_at(g, b, ic, jc, kc, st.xi[s], eta, zeta);
+        const float K2 = kh2 + M2;
         const float invK2 = f32::rcp(K2);
-        const float rom = f32::rsq((N2 * kh2 + f2 * m2) * invK2);  // 1 / omega_hat
+        const float rom = f32::rsq((N2 * kh2 + f2 * M2) * invK2);  // 1 / omega_hat
         const float sc = (N2 - f2) * (invK2 * invK2) * rom;
-        const float cx = k * m2 * sc, cy = l * m2 * sc, cz = -m * kh2 * sc;
-        const float om2 = (N2 * kh2 + f2 * m2) * invK2;
+        const float cx = k * M2 * sc, cy = l * M2 * sc, cz = -m * kh2 * sc;
+        const float om2 = (N2 * kh2 + f2 * M2) * invK2;
         const float iden = K2 * f32::rcp(kh2 * (N2 - f2));  // 1 / (omega^2 - f^2)
         const float a1 = om2 * iden, a2 = f2 * iden;
         const float bf = cz * fs * N2 * iden;
@@ -139,15 +139,15 @@ struct PayBudget64 {
         const double U = TRI64(K, x, c), V = TRI64(K, y, c), N2 = TRI64(K, z, c);
         const double f2 = d64::row_lerp(b.f2, ay);
         const double kh2 = k * k + l * l;
-        const double m2 = m * m;
-        const double K2 = kh2 + m2;
-        const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
+        const double M2 = m * m + d64::gam2(b, c);
+        const double K2 = kh2 + M2;
+        const double om = d64::omega_hat(N2, f2, kh2, M2, K2);
         const double d = N2 - f2;
         const double dn = om * (K2 * K2);
         const double sW = W / Dz;
         bv[0] = 1.0 * sW;
-        bv[1] = (U + ((k * m2) * d) / dn) * sW;
-        bv[2] = (V + ((l * m2) * d) / dn) * sW;
+        bv[1] = (U + ((k * M2) * d) / dn) * sW;
+        bv[2] = (V + ((l * M2) * d) / dn) * sW;
         bv[3] = (-(((m * kh2) * d) / dn)) * sW;
         zb = z - 0.5 * Dz;
         zt = z + 0.5 * Dz;
@@ -175,14 +175,14 @@ struct PayBudget32 {
         const float U = TRI_COMP(K, x, c), V = TRI_COMP(K, y, c), N2 = TRI_COMP(K, z, c);
         const float f2 = f32::row_lerp(b.f2, ay);
         const float kh2 = k * k + l * l;
-        const float m2 = m * m;
-        const float invK2 = f32::rcp(kh2 + m2);
-        const float rom = f32::rsq((N2 * kh2 + f2 * m2) * invK2);
+        const float M2 = m * m + f32::gam2(b, c);
+        const float invK2 = f32::rcp(kh2 + M2);
+        const float rom = f32::rsq((N2 * kh2 + f2 * M2) * invK2);
         const float sc = (N2 - f2) * (invK2 * invK2) * rom;
         const double sW = st.W[s] * (double)f32::rcp(Dz);
         bv[0] = sW;
-        bv[1] = (double)(U + k * m2 * sc) * sW;
-        bv[2] = (double)(V + l * m2 * sc) * sW;
+        bv[1] = (double)(U + k * M2 * sc) * sW;
+        bv[2] = (double)(V + l * M2 * sc) * sW;
         bv[3] = (double)(-m * kh2 * sc) * sW;
         const double zc = ((double)kc + (double)zeta) * zdz;
         zb = zc - 0.5 * (double)Dz;

@@ -198,6 +198,8 @@ void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double 
 // deposition payload: single-precision dispersion at the carrier, wave action
 // and the flux densities in double
 // ---------------------------------------------------------------------------
+// GAM: with the scale-height correction (a separate instantiation)
+template <bool GAM>
 struct Pay32 {
     G32 g;
     Bg32P b;
@@ -220,12 +222,12 @@ struct Pay32 {
         // group velocity as in the step: one-rounding reciprocal and
         // reciprocal square root
         const float kh2 = k * k + l * l;
-        const float m2 = m * m;
-        const float invK2 = f32::rcp(kh2 + m2);
-        const float rom = f32::rsq((N2 * kh2 + f2 * m2) * invK2);  // 1 / omega_hat
+        const float M2 = m * m + (GAM ? f32::gam2_at(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta) : 0.0f);
+        const float invK2 = f32::rcp(kh2 + M2);
+        const float rom = f32::rsq((N2 * kh2 + f2 * M2) * invK2);  // 1 / omega_hat
         const float sc = (N2 - f2) * (invK2 * invK2) * rom;
-        const double cx = (double)(k * m2 * sc);
-        const double cy = (double)(l * m2 * sc);
+        const double cx = (double)(k * M2 * sc);
+        const double cy = (double)(l * M2 * sc);
         const double cz = (double)(-m * kh2 * sc);
         const double sW = st.W[s] * (double)f32::rcp(Dz);
         const double kd = k, ld = l;
@@ -249,9 +251,10 @@ struct Pay32 {
         f32::n2_f2(g, b, ic, jc, st.lev[s], st.xi[s], st.eta[s], st.zeta[s], N2, f2);
         const float k = st.k[s], l = st.l[s], m = (float)st.m[s];
         const float kh2 = k * k + l * l;
-        const float m2 = m * m;
-        const float K2 = kh2 + m2;
-        const float om = sqrtf((N2 * kh2 + f2 * m2) / K2);
+        const float M2 =
+            m * m + (GAM ? f32::gam2_at(g, b, ic, jc, st.lev[s], st.xi[s], st.eta[s], st.zeta[s]) : 0.0f);
+        const float K2 = kh2 + M2;
+        const float om = sqrtf((N2 * kh2 + f2 * M2) / K2);
         const float sc = (N2 - f2) / (K2 * K2) / om;
         kd = k;
         ld = l;
@@ -272,13 +275,22 @@ struct Pay32 {
 void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s)
 {
-    Pay32 p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
-    launch_deposit_k(g, p, perm, colstart, flux, s);
+    if (b.Gm) {
+        Pay32<true> p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
+        launch_deposit_k(g, p, perm, colstart, flux, s);
+    } else {
+        Pay32<false> p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
+        launch_deposit_k(g, p, perm, colstart, flux, s);
+    }
 }
 
 void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s)
 {
-    Pay32 p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
-    k_features<Pay32><<<(unsigned)((g.ncol + 3) / 4), 256, 0, s>>>(g, p, perm, colstart, X);
+    const unsigned nb = (unsigned)((g.ncol + 3) / 4);
+    const G32 h = f32::make_g32(g);
+    if (b.Gm)
+        k_features<Pay32<true>><<<nb, 256, 0, s>>>(g, Pay32<true>{h, b, st, g.dz, 1.0 / g.dz}, perm, colstart, X);
+    else
+        k_features<Pay32<false>><<<nb, 256, 0, s>>>(g, Pay32<false>{h, b, st, g.dz, 1.0 / g.dz}, perm, colstart, X);
 }

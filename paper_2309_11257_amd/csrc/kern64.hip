@@ -11,6 +11,37 @@
 // background: centred-difference gradients (periodic in x, and in y on the
 // box; one-sided at the vertical ends and the first/last latitude rows)
 // ---------------------------------------------------------------------------
+// the three gradients of field A at cell c = (i, j, k) of the [nz][ny][nx] layout
+__device__ inline void grad3(const Grid &g, const double *A, int64_t c, int i, int j, int k, double &gx, double &gy,
+                             double &gz)
+{
+    const int ip = (i + 1) % g.nx, im = (i + g.nx - 1) % g.nx;
+    const int64_t row = (int64_t)g.nx;
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    gx = (A[c - i + ip] - A[c - i + im]) / (2.0 * g.dx);
+    if (g.geometry == RT_CARTESIAN) {
+        const int jp = (j + 1) % g.ny, jm = (j + g.ny - 1) % g.ny;
+        gy = (A[c + (jp - j) * row] - A[c + (jm - j) * row]) / (2.0 * g.dy);
+    } else if (g.ny == 1) {
+        gy = 0.0;
+    } else if (j == 0) {
+        gy = (A[c + row] - A[c]) / g.dy;
+    } else if (j == g.ny - 1) {
+        gy = (A[c] - A[c - row]) / g.dy;
+    } else {
+        gy = (A[c + row] - A[c - row]) / (2.0 * g.dy);
+    }
+    if (g.nz == 1) {
+        gz = 0.0;
+    } else if (k == 0) {
+        gz = (A[c + plane] - A[c]) / g.dz;
+    } else if (k == g.nz - 1) {
+        gz = (A[c] - A[c - plane]) / g.dz;
+    } else {
+        gz = (A[c + plane] - A[c - plane]) / (2.0 * g.dz);
+    }
+}
+
 __global__ void k_gradients(Grid g, const double *U, const double *V, const double *N2, double *out)
 {
     const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
@@ -20,38 +51,44 @@ __global__ void k_gradients(Grid g, const double *U, const double *V, const doub
     const int j = (int)((c / g.nx) % g.ny);
     const int k = (int)(c / ((int64_t)g.nx * g.ny));
     const double *F[3] = {U, V, N2};
-    const int ip = (i + 1) % g.nx, im = (i + g.nx - 1) % g.nx;
-    const int64_t row = (int64_t)g.nx;
-    const int64_t plane = (int64_t)g.nx * g.ny;
     for (int f = 0; f < 3; f++) {
-        const double *A = F[f];
-        const double gx = (A[c - i + ip] - A[c - i + im]) / (2.0 * g.dx);
-        double gy, gz;
-        if (g.geometry == RT_CARTESIAN) {
-            const int jp = (j + 1) % g.ny, jm = (j + g.ny - 1) % g.ny;
-            gy = (A[c + (jp - j) * row] - A[c + (jm - j) * row]) / (2.0 * g.dy);
-        } else if (g.ny == 1) {
-            gy = 0.0;
-        } else if (j == 0) {
-            gy = (A[c + row] - A[c]) / g.dy;
-        } else if (j == g.ny - 1) {
-            gy = (A[c] - A[c - row]) / g.dy;
-        } else {
-            gy = (A[c + row] - A[c - row]) / (2.0 * g.dy);
-        }
-        if (g.nz == 1) {
-            gz = 0.0;
-        } else if (k == 0) {
-            gz = (A[c + plane] - A[c]) / g.dz;
-        } else if (k == g.nz - 1) {
-            gz = (A[c] - A[c - plane]) / g.dz;
-        } else {
-            gz = (A[c + plane] - A[c - plane]) / (2.0 * g.dz);
-        }
+        double gx, gy, gz;
+        grad3(g, F[f], c, i, j, k, gx, gy, gz);
         out[(3 * f + 0) * cells + c] = gx;
         out[(3 * f + 1) * cells + c] = gy;
         out[(3 * f + 2) * cells + c] = gz;
     }
+}
+
+// scale-height correction: records (Gamma^2, its x, y, z gradients) by cell,
+// column-major like the packed background (cell (column, level) at
+// column * nz + level), from the [nz][ny][nx] field; a single-precision
+// record rounds each double once
+template <class T4>
+__global__ void k_gamma_pack(Grid g, const double *G2, T4 *out)
+{
+    const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const int i = (int)(c % g.nx);
+    const int j = (int)((c / g.nx) % g.ny);
+    const int k = (int)(c / ((int64_t)g.nx * g.ny));
+    double gx, gy, gz;
+    grad3(g, G2, c, i, j, k, gx, gy, gz);
+    T4 r;
+    r.x = G2[c];
+    r.y = gx;
+    r.z = gy;
+    r.w = gz;
+    out[((int64_t)j * g.nx + i) * g.nz + k] = r;
+}
+
+void launch_gamma_pack(const Grid &g, const double *G2, double4 *out64, float4 *out32, hipStream_t s)
+{
+    const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+    const unsigned nb = (unsigned)((cells + 255) / 256);
+    k_gamma_pack<double4><<<nb, 256, 0, s>>>(g, G2, out64);
+    if (out32) k_gamma_pack<float4><<<nb, 256, 0, s>>>(g, G2, out32);
 }
 
 __global__ void k_f2(Grid g, const double *f, double *f2, double *f2y)
@@ -185,7 +222,7 @@ void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCount
 // the background stencil they use into LDS (dev64.h).
 #define STEP64_BLOCK 64
 
-template <bool SPH>
+template <bool SPH, bool GAM>
 __global__ __launch_bounds__(STEP64_BLOCK, 2) void k_step64(Grid g, Bg64P b, S64 src, S64 dst,
                                                             const uint32_t *__restrict__ perm,
                                                             uint32_t *__restrict__ key_out,
@@ -271,7 +308,7 @@ __global__ __launch_bounds__(STEP64_BLOCK, 2) void k_step64(Grid g, Bg64P b, S64
     const int nst = (frozen && frozen[skeys[i]]) ? 0 : 3;
 #pragma unroll 1
     for (int st = 0; st < nst; st++) {
-        d64::rhs<SPH>(g, b, Y, F, w);
+        d64::rhs<SPH, GAM>(g, b, Y, F, w);
 #pragma unroll
         for (int c = 0; c < 9; c++) {
             Q[c] = A[st] * Q[c] + dt * F[c];
@@ -306,10 +343,15 @@ void launch_step64(const Grid &g, const Bg64P &b, S64 src, S64 dst, const uint32
     if (bound <= 0) return;
     const unsigned nb = (unsigned)((bound + STEP64_BLOCK - 1) / STEP64_BLOCK);
     const size_t lds = (size_t)WB64_RECS * sizeof(double4);  // the wave's stencil box
-    if (g.geometry == RT_SPHERICAL)
-        k_step64<true><<<nb, STEP64_BLOCK, lds, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
+    const bool sph = g.geometry == RT_SPHERICAL, gam = b.Gm != nullptr;
+    if (sph && gam)
+        k_step64<true, true><<<nb, STEP64_BLOCK, lds, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
+    else if (sph)
+        k_step64<true, false><<<nb, STEP64_BLOCK, lds, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
+    else if (gam)
+        k_step64<false, true><<<nb, STEP64_BLOCK, lds, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
     else
-        k_step64<false><<<nb, STEP64_BLOCK, lds, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
+        k_step64<false, false><<<nb, STEP64_BLOCK, lds, s>>>(g, b, src, dst, perm, key_out, dc, dt, frozen, skeys);
 }
 
 // ---------------------------------------------------------------------------
@@ -411,6 +453,9 @@ void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double 
 // deposition payload: wave action W = N Px Py Pz, intrinsic group velocity at
 // the carrier from the dispersion relation (N^2 and f^2 interpolated there)
 // ---------------------------------------------------------------------------
+// GAM: with the scale-height correction (a separate instantiation, so that
+// the form without it carries no extra registers)
+template <bool GAM>
 struct Pay64 {
     Grid g;
     Bg64P b;
@@ -430,14 +475,14 @@ struct Pay64 {
         const double N2 = TRI64(K, z, c);
         const double f2 = d64::row_lerp(b.f2, ay);
         const double kh2 = k * k + l * l;
-        const double m2 = m * m;
-        const double K2 = kh2 + m2;
+        const double M2 = m * m + (GAM ? d64::gam2(b, c) : 0.0);
+        const double K2 = kh2 + M2;
         const double K4 = K2 * K2;
-        const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
+        const double om = d64::omega_hat(N2, f2, kh2, M2, K2);
         const double d = N2 - f2;
         const double den = om * K4;
-        const double cx = ((k * m2) * d) / den;
-        const double cy = ((l * m2) * d) / den;
+        const double cx = ((k * M2) * d) / den;
+        const double cy = ((l * M2) * d) / den;
         const double cz = -(((m * kh2) * d) / den);
         const double sW = W / Dz;
         bv[0] = (cx * k) * sW;
@@ -462,9 +507,9 @@ struct Pay64 {
         const d64::Corners<1> K(b.A, c, 0);
         const double N2 = TRI64(K, z, c), f2 = d64::row_lerp(b.f2, ay);
         const double kh2 = k * k + l * l;
-        const double m2 = m * m;
-        const double K2 = kh2 + m2;
-        const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
+        const double M2 = m * m + (GAM ? d64::gam2(b, c) : 0.0);
+        const double K2 = kh2 + M2;
+        const double om = d64::omega_hat(N2, f2, kh2, M2, K2);
         cgz = -(((m * kh2) * (N2 - f2)) / (om * (K2 * K2)));
         z = st.z[s];
     }
@@ -480,13 +525,21 @@ struct Pay64 {
 void launch_deposit64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s)
 {
-    Pay64 p{g, b, st, 0.0};
-    launch_deposit_k(g, p, perm, colstart, flux, s);
+    if (b.Gm) {
+        Pay64<true> p{g, b, st, 0.0};
+        launch_deposit_k(g, p, perm, colstart, flux, s);
+    } else {
+        Pay64<false> p{g, b, st, 0.0};
+        launch_deposit_k(g, p, perm, colstart, flux, s);
+    }
 }
 
 void launch_features64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                        float *X, hipStream_t s)
 {
-    Pay64 p{g, b, st, 0.0};
-    k_features<Pay64><<<(unsigned)((g.ncol + 3) / 4), 256, 0, s>>>(g, p, perm, colstart, X);
+    const unsigned nb = (unsigned)((g.ncol + 3) / 4);
+    if (b.Gm)
+        k_features<Pay64<true>><<<nb, 256, 0, s>>>(g, Pay64<true>{g, b, st, 0.0}, perm, colstart, X);
+    else
+        k_features<Pay64<false>><<<nb, 256, 0, s>>>(g, Pay64<false>{g, b, st, 0.0}, perm, colstart, X);
 }

@@ -34,6 +34,7 @@ struct Bg64P {
     const double4 *A;  // [ncol*nz]
     const double4 *G;  // [ncol*nz*2]
     const double *f2, *f2y;
+    const double4 *Gm;  // [ncol*nz] (Gamma^2, its x, y, z gradients); null when Gamma = 0
 };
 
 // Packed single-precision background for cell (column c, level k) at index
@@ -44,6 +45,7 @@ struct Bg32P {
     const float4 *A;  // [ncol*nz]
     const float4 *G;  // [ncol*nz*2]
     const float *f2, *f2y;
+    const float4 *Gm;  // [ncol*nz] (Gamma^2, its x, y, z gradients); null when Gamma = 0
 };
 
 // double-precision state: absolute coordinates, as the public interface
@@ -129,6 +131,11 @@ struct rt_ctx_s {
     uint32_t *lscr;
     int64_t lscr_len;
     double *lflux;
+    // scale-height correction (allocated on first use): the field as given and
+    // its packed records; bp64.Gm / bp32.Gm point at the records while it is on
+    double *g2raw;
+    double4 *gm64;
+    float4 *gm32;
     // per-column flags: 1 = the surrogate owns the column this step
     uint8_t *frozen;
     bool have_frozen;
@@ -225,6 +232,7 @@ void launch_gradients64(const Grid &g, const double *U, const double *V, const d
                         double *out12, double *f2, double *f2y, hipStream_t s);
 void launch_round32(const double *in, float *out, int64_t n, hipStream_t s);
 void launch_pack64(const Grid &g, const Bg<double> &b, double4 *A, double4 *G, hipStream_t s);
+void launch_gamma_pack(const Grid &g, const double *G2, double4 *out64, float4 *out32, hipStream_t s);
 void launch_pack32(const Grid &g, const Bg<double> &b, float4 *A, float4 *G, hipStream_t s);
 
 void launch_load64(const Grid &g, const rt_rays &in, int64_t n, S64 dst, uint32_t *key, hipStream_t s);

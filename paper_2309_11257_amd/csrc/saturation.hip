@@ -19,6 +19,7 @@
 #include "deposit_common.h"
 
 // (m^2 kh^2 / (omega_hat K^2)) W / Dz and the same times K^2, per unit height
+template <bool GAM>
 struct PaySat64 {
     Grid g;
     Bg64P b;
@@ -40,8 +41,9 @@ struct PaySat64 {
         const double f2 = d64::row_lerp(b.f2, ay);
         const double kh2 = k * k + l * l;
         const double m2 = m * m;
-        const double K2 = kh2 + m2;
-        const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
+        const double M2 = m2 + (GAM ? d64::gam2(b, c) : 0.0);
+        const double K2 = kh2 + M2;
+        const double om = d64::omega_hat(N2, f2, kh2, M2, K2);
         const double sw = (m2 * kh2) / (om * K2);
         const double a = W / Dz;
         bv[0] = sw * a;
@@ -51,6 +53,7 @@ struct PaySat64 {
     }
 };
 
+template <bool GAM>
 struct PaySat32 {
     G32 g;
     Bg32P b;
@@ -71,9 +74,10 @@ struct PaySat32 {
         f32::n2_f2(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta, N2, f2);
         const float kh2 = k * k + l * l;
         const float m2 = m * m;
-        const float K2 = kh2 + m2;
+        const float M2 = m2 + (GAM ? f32::gam2_at(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta) : 0.0f);
+        const float K2 = kh2 + M2;
         const float invK2 = f32::rcp(K2);
-        const float rom = f32::rsq((N2 * kh2 + f2 * m2) * invK2);  // 1 / omega_hat
+        const float rom = f32::rsq((N2 * kh2 + f2 * M2) * invK2);  // 1 / omega_hat
         const float sw = m2 * kh2 * rom * invK2;
         const double a = st.W[s] * (double)f32::rcp(Dz);
         bv[0] = (double)sw * a;
@@ -119,8 +123,9 @@ __device__ inline double sat_factor(const Grid &g, const double *__restrict__ ka
     return fac < 0.0 ? 0.0 : fac;
 }
 
-__global__ void k_damp64(Grid g, S64 st, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ skeys,
-                         const DevCounters *__restrict__ dc, const double *__restrict__ kappa, double dt)
+__global__ void k_damp64(Grid g, Bg64P b, S64 st, const uint32_t *__restrict__ perm,
+                         const uint32_t *__restrict__ skeys, const DevCounters *__restrict__ dc,
+                         const double *__restrict__ kappa, double dt)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= dc->n_active) return;
@@ -128,14 +133,15 @@ __global__ void k_damp64(Grid g, S64 st, const uint32_t *__restrict__ perm, cons
     const int c = (int)skeys[i];
     const double z = st.z[s], Dz = st.dz[s];
     const double k = st.k[s], l = st.l[s], m = st.m[s];
-    const double K2 = (k * k + l * l) + m * m;
+    // K^2 includes Gamma^2 at the carrier
+    const double K2 = (k * k + l * l) + (m * m + d64::gam2_at(g, b, st.x[s], st.y[s], z));
     const double fac = sat_factor(g, kappa, c, z - 0.5 * Dz, z + 0.5 * Dz, Dz, K2, dt, true, 0.0);
     if (fac != 1.0) st.n[s] = st.n[s] * fac;
 }
 
-__global__ void k_damp32(Grid g, S32 st, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ skeys,
-                         const DevCounters *__restrict__ dc, const double *__restrict__ kappa, double dt,
-                         double inv_dz)
+__global__ void k_damp32(Grid g, f32::G32 g32, Bg32P b, S32 st, const uint32_t *__restrict__ perm,
+                         const uint32_t *__restrict__ skeys, const DevCounters *__restrict__ dc,
+                         const double *__restrict__ kappa, double dt, double inv_dz)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= dc->n_active) return;
@@ -144,7 +150,9 @@ __global__ void k_damp32(Grid g, S32 st, const uint32_t *__restrict__ perm, cons
     const double zc = ((double)st.lev[s] + (double)st.zeta[s]) * g.dz;
     const double Dz = (double)st.dz[s];
     const float k = st.k[s], l = st.l[s], m = (float)st.m[s];
-    const double K2 = (double)(k * k + l * l + m * m);
+    const int jc = c / g.nx, ic = c - jc * g.nx;
+    const float G2 = f32::gam2_at(g32, b, ic, jc, st.lev[s], st.xi[s], st.eta[s], st.zeta[s]);
+    const double K2 = (double)(k * k + l * l + (m * m + G2));
     const double fac = sat_factor(g, kappa, c, zc - 0.5 * Dz, zc + 0.5 * Dz, Dz, K2, dt, false, inv_dz);
     if (fac != 1.0) st.W[s] = st.W[s] * fac;
 }
@@ -153,21 +161,32 @@ void launch_saturation64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *
                          const uint32_t *colstart, const DevCounters *dc, const double *rho, double dt, double *PQ,
                          double *kappa, int64_t bound, hipStream_t s)
 {
-    PaySat64 p{g, b, st, 1.0 / g.dz};
-    launch_deposit_k(g, p, perm, colstart, PQ, s);
+    if (b.Gm) {
+        PaySat64<true> p{g, b, st, 1.0 / g.dz};
+        launch_deposit_k(g, p, perm, colstart, PQ, s);
+    } else {
+        PaySat64<false> p{g, b, st, 1.0 / g.dz};
+        launch_deposit_k(g, p, perm, colstart, PQ, s);
+    }
     const int64_t cells = (int64_t)g.nz * g.ncol;
     k_kappa<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, PQ, rho, dt, kappa);
-    if (bound > 0) k_damp64<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(g, st, perm, skeys, dc, kappa, dt);
+    if (bound > 0) k_damp64<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(g, b, st, perm, skeys, dc, kappa, dt);
 }
 
 void launch_saturation32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *skeys,
                          const uint32_t *colstart, const DevCounters *dc, const double *rho, double dt, double *PQ,
                          double *kappa, int64_t bound, hipStream_t s)
 {
-    PaySat32 p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
-    launch_deposit_k(g, p, perm, colstart, PQ, s);
+    if (b.Gm) {
+        PaySat32<true> p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
+        launch_deposit_k(g, p, perm, colstart, PQ, s);
+    } else {
+        PaySat32<false> p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
+        launch_deposit_k(g, p, perm, colstart, PQ, s);
+    }
     const int64_t cells = (int64_t)g.nz * g.ncol;
     k_kappa<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, PQ, rho, dt, kappa);
     if (bound > 0)
-        k_damp32<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(g, st, perm, skeys, dc, kappa, dt, 1.0 / g.dz);
+        k_damp32<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(g, f32::make_g32(g), b, st, perm, skeys, dc, kappa, dt,
+                                                                 1.0 / g.dz);
 }

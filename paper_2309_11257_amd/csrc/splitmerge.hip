@@ -53,7 +53,8 @@ __device__ inline double metric_y(const Grid &g, double z, double D)
 // --- double-precision storage ----------------------------------------------
 struct IO64 {
     S64 s;
-    const double *f2r;  // f^2 by latitude row
+    const double *f2r;            // f^2 by latitude row
+    const double4 *Gm = nullptr;  // Gamma^2 records (wave energy), null when Gamma = 0
     __device__ RayD get(const Grid &g, uint32_t i) const
     {
         RayD r;
@@ -147,9 +148,9 @@ struct IO64 {
         const double N2 = TRI64(K, z, c), f2 = d64::row_lerp(f2r, ay);
         const double k = s.k[i], l = s.l[i], m = s.m[i];
         const double kh2 = k * k + l * l;
-        const double m2 = m * m;
-        const double K2 = kh2 + m2;
-        const double om = d64::omega_hat(N2, f2, kh2, m2, K2);
+        const double M2 = m * m + d64::gam2(Gm, c);
+        const double K2 = kh2 + M2;
+        const double om = d64::omega_hat(N2, f2, kh2, M2, K2);
         return om * (((s.n[i] * s.px[i]) * s.py[i]) * s.pz[i]);
     }
 };
@@ -157,7 +158,8 @@ struct IO64 {
 // --- single-precision storage (positions as cell + offset) -----------------
 struct IO32 {
     S32 s;
-    const float *f2r;  // f^2 by latitude row
+    const float *f2r;            // f^2 by latitude row
+    const float4 *Gm = nullptr;  // Gamma^2 records (wave energy), null when Gamma = 0
     __device__ RayD get(const Grid &g, uint32_t i) const
     {
         RayD r;
@@ -263,10 +265,16 @@ struct IO32 {
         A.z = tri(vz);
         const int j0 = (c.c00 / g.nz) / g.nx, j1 = (c.c10 / g.nz) / g.nx;
         A.w = (double)f2r[j0] + c.wy * ((double)f2r[j1] - (double)f2r[j0]);
+        double G2 = 0.0;
+        if (Gm) {
+            double vg[8];
+            for (int q = 0; q < 8; q++) vg[q] = Gm[o[q]].x;
+            G2 = tri(vg);
+        }
         const double kh2 = r.k * r.k + r.l * r.l;
-        const double m2 = r.m * r.m;
-        const double K2 = kh2 + m2;
-        return d64::omega_hat(A.z, A.w, kh2, m2, K2) * r.W;
+        const double M2 = r.m * r.m + G2;
+        const double K2 = kh2 + M2;
+        return d64::omega_hat(A.z, A.w, kh2, M2, K2) * r.W;
     }
 };
 
@@ -735,12 +743,12 @@ rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, r
     prof_begin(ctx, PC_SPLIT);
     rt_status r;
     if (ctx->precision == RT_FP64)
-        r = split_merge_impl<IO64, double4>(ctx, IO64{ctx->s64[ctx->cur], ctx->bp64.f2},
-                                            IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2}, ctx->bp64.A,
+        r = split_merge_impl<IO64, double4>(ctx, IO64{ctx->s64[ctx->cur], ctx->bp64.f2, ctx->bp64.Gm},
+                                            IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2, ctx->bp64.Gm}, ctx->bp64.A,
                                             alpha, nmax, mode);
     else
-        r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2},
-                                           IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2}, ctx->bp32.A,
+        r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2, ctx->bp32.Gm},
+                                           IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2, ctx->bp32.Gm}, ctx->bp32.A,
                                            alpha, nmax, mode);
     prof_end(ctx);  // profile groups do not nest: the regrouping times as a sort
     rt_status r2 = sort_current_ext(ctx);
@@ -764,6 +772,7 @@ struct LaunchD {
     const double *flux_col;  // device copy, or null
     const double *N2;        // [nz][ny][nx]
     const double *f2;        // [ny]
+    const double4 *Gm;       // packed Gamma^2 records, null when Gamma = 0
 };
 
 #define LAUNCH_PI 3.14159265358979323846
@@ -810,15 +819,19 @@ __device__ inline bool launch_bin(const Grid &g, const LaunchD &p, int c, int d,
                                  at(ay.i1, ax.i1, az.i0), at(ay.i0, ax.i0, az.i1), at(ay.i0, ax.i1, az.i1),
                                  at(ay.i1, ax.i0, az.i1), at(ay.i1, ax.i1, az.i1), cl);
     const double f2 = d64::row_lerp(p.f2, ay);
+    const double G2 = d64::gam2(p.Gm, d64::cell_of(g, ax, ay, az));
     const double om = p.kh * cb, om2 = om * om;
     if (!(om2 > f2 && om2 < N2) || !(Fb > 0.0)) return false;
     const double kh = p.kh;
-    const double m = -sqrt(((kh * kh) * (N2 - om2)) / (om2 - f2));
+    // m^2 + Gamma^2 from the dispersion relation; evanescent where not above Gamma^2
+    const double mm = ((kh * kh) * (N2 - om2)) / (om2 - f2) - G2;
+    if (!(mm > 0.0)) return false;
+    const double m = -sqrt(mm);
     const double k = d == 0 ? kh : (d == 2 ? -kh : 0.0);
     const double l = d == 1 ? kh : (d == 3 ? -kh : 0.0);
     // vertical group velocity of the dispersion relation (cancellation-free form)
-    const double kh2 = k * k + l * l, m2 = m * m, K2 = kh2 + m2;
-    const double omd = d64::omega_hat(N2, f2, kh2, m2, K2);
+    const double kh2 = k * k + l * l, M2 = m * m + G2, K2 = kh2 + M2;
+    const double omd = d64::omega_hat(N2, f2, kh2, M2, K2);
     const double cgz = -(((m * kh2) * (N2 - f2)) / (omd * (K2 * K2)));
     const double Dz = cgz * p.dt;
     const double z = p.z_launch + 0.5 * Dz;
@@ -955,6 +968,7 @@ rt_status do_launch(rt_ctx ctx, const rt_launch_params *lp, const double *flux_d
     p.flux_col = flux_dev;
     p.N2 = ctx->bg64.N2;
     p.f2 = ctx->bg64.f2;
+    p.Gm = ctx->bp64.Gm;
     // spectral weights normalised over the bins, summed in bin order as the
     // definition reads
     double sw = 0.0;

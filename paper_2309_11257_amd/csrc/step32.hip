@@ -12,8 +12,8 @@
 // soon as its wave ends, whatever the other waves' loads
 #define STEP_BLOCK 64
 
-template <bool SPH>
-__global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 src, S32 dst,
+template <bool SPH, bool GAM>
+__global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P b, S32 src, S32 dst,
                                                           const uint32_t *__restrict__ perm,
                                                           uint32_t *__restrict__ key_out,
                                                           const uint32_t *__restrict__ colstart,
@@ -137,11 +137,12 @@ __global__ __launch_bounds__(STEP_BLOCK, 5) void k_step32(G32 g, Bg32P b, S32 sr
 #pragma unroll 1
     for (int st = 0; st < nst; st++) {
         // a stage whose lookups all lie in the box, for every lane, runs the
-        // box-only form; otherwise each lookup tests the box itself
-        if (w.on && __ballot(!f32::box_stage_in(g, w, kc0, Y)) == 0ull)
+        // box-only form; otherwise each lookup tests the box itself (always
+        // with the scale-height correction, whose records are not staged)
+        if (!GAM && w.on && __ballot(!f32::box_stage_in(g, w, kc0, Y)) == 0ull)
             f32::rhs_box<SPH>(g, kc0, phi0, Y, F, w);
         else
-            f32::rhs<SPH>(g, b, ic, jc, kc0, phi0, Y, F, w);
+            f32::rhs<SPH, GAM>(g, b, ic, jc, kc0, phi0, Y, F, w);
 #pragma unroll
         for (int c = 0; c < 9; c++) {
             Q[c] = A[st] * Q[c] + dt * F[c];
@@ -241,10 +242,17 @@ void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32
     const unsigned nb = (unsigned)wave_table_len(bound, g.ncol);  // an upper bound of the waves
     const G32 h = f32::make_g32(g);
     const size_t lds = (size_t)WB_RECS * sizeof(float4);  // the wave's stencil box
-    if (g.geometry == RT_SPHERICAL)
-        k_step32<true><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, colstart, wcol, (float)dt,
-                                                   frozen, skeys);
+    const bool sph = g.geometry == RT_SPHERICAL, gam = b.Gm != nullptr;
+    if (sph && gam)
+        k_step32<true, true><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, colstart, wcol, (float)dt,
+                                                         frozen, skeys);
+    else if (sph)
+        k_step32<true, false><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, colstart, wcol, (float)dt,
+                                                          frozen, skeys);
+    else if (gam)
+        k_step32<false, true><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, colstart, wcol, (float)dt,
+                                                          frozen, skeys);
     else
-        k_step32<false><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, colstart, wcol, (float)dt,
-                                                    frozen, skeys);
+        k_step32<false, false><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, colstart, wcol,
+                                                           (float)dt, frozen, skeys);
 }

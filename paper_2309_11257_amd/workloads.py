@@ -64,6 +64,7 @@ class Workload:
     split_alpha: Optional[float] = None
     merge_nmax: Optional[int] = None
     meta: dict = field(default_factory=dict)
+    G2: Optional[np.ndarray] = None  # scale-height correction Gamma^2 [nz][ny][nx]; None: Gamma = 0
 
     @property
     def n_rays(self) -> int:
@@ -415,6 +416,30 @@ def analytic_sphere(nx=72, ny=36, nz=20, top=40.0e3, U=None, N2=None, rotating=T
                     ev(U, 0.0), np.zeros((nz, ny, nx)), ev(N2, 1.0e-4), f, _density(zc),
                     {f_: np.zeros(0) for f_ in RAY_FIELDS} | {"id": np.zeros(0, np.int64)},
                     dt=60.0, steps=1)
+
+
+def density_gamma2(w: Workload) -> np.ndarray:
+    """Scale-height correction Gamma^2 = 1 / (4 H_rho^2) of the reference
+    density, H_rho = -rho / (d rho / dz) by centred differences of the level
+    densities (one-sided at the ends), as a [nz][ny][nx] field: the usual
+    anelastic value (the paper names the density scale height but gives no
+    formula for Gamma)."""
+    rho = np.asarray(w.rho, dtype=np.float64)
+    drho = np.gradient(rho, w.dz) if w.nz > 1 else np.zeros(1)
+    g2 = (0.5 * drho / rho) ** 2
+    return np.ascontiguousarray(np.broadcast_to(g2[:, None, None], (w.nz, w.ny, w.nx)), dtype=np.float64)
+
+
+def varying_gamma2(w: Workload, amp: float) -> np.ndarray:
+    """A smooth, everywhere positive Gamma^2 field of size amp that varies in
+    all three directions (periodic in x, and in y on the box), for tests that
+    must see every Gamma term."""
+    xc = (np.arange(w.nx) + 0.5) / w.nx
+    yc = (np.arange(w.ny) + 0.5) / w.ny
+    zc = (np.arange(w.nz) + 0.5) / w.nz
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    return np.ascontiguousarray(amp * (1.0 + 0.5 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)) * np.exp(-Z),
+                                dtype=np.float64)
 
 
 def rays_from(x, y, z, k, l, m, dx, dy, dz, px, py, pz, n) -> Dict[str, np.ndarray]:

@@ -209,3 +209,32 @@ def test_saturation_and_deposit_are_gamma_free_at_shifted_m(orc):
     assert np.allclose(F[:4], F0[:4], rtol=1e-13, atol=0)
     assert np.allclose(F[4:], F0[4:] * (m / M), rtol=1e-13, atol=0)
     assert F[4:].any()
+
+
+def test_saturation_with_gamma_restores_the_threshold(orc):
+    """One cell filled by volumes sharing one wavevector, above the
+    instability threshold, in a uniform Gamma^2: the damping
+    N <- N (1 - 2 kappa K^2 dt) uses the same K^2 (with Gamma^2) as the sum
+    P_j K_j^2 in kappa, so the cell ends exactly on the threshold P = rho/2
+    and every density drops by the factor (rho/2) / P."""
+    G0 = 2e-7
+    w = _box(lambda X, Y, Z: 0 * X + G0)
+    k, l, m = 2 * math.pi / 50e3, 2 * math.pi / 80e3, -2 * math.pi / 4e3
+    kc, n = 6, 12
+    rng = np.random.default_rng(84)
+    z = (kc + 0.5) * w.dz + rng.uniform(-0.1, 0.1, n) * w.dz
+    ones = np.ones(n)
+    rays = W.rays_from((3.5 + rng.uniform(-0.3, 0.3, n)) * w.dx, (4.5 + rng.uniform(-0.3, 0.3, n)) * w.dx, z,
+                       k * ones, l * ones, m * ones, 2e3 * ones, 2e3 * ones, 0.2 * w.dz * ones,
+                       200.0 * ones, 300.0 * ones, 0.1 * abs(m) * 0.2 * w.dz * ones, ones)
+    bg = orc.Background.from_workload(w)
+    P1, _, _ = orc.saturation(bg, orc.RaySet(rays), 30.0)
+    scale = 3.0 * 0.5 * w.rho[kc] / P1[kc, 4, 3]
+    rays["n"] = rays["n"] * scale
+    rs = orc.RaySet(rays)
+    n0 = rs["n"].copy()
+    P, Q, kap = orc.saturation(bg, rs, 30.0)
+    assert P[kc, 4, 3] == pytest.approx(1.5 * w.rho[kc], rel=1e-12, abs=0) and kap[kc, 4, 3] > 0
+    assert np.allclose(rs["n"] / n0, 1.0 / 3.0, rtol=1e-12, atol=0)
+    P2, _, _ = orc.saturation(bg, rs, 30.0)
+    assert P2[kc, 4, 3] == pytest.approx(0.5 * w.rho[kc], rel=1e-12, abs=0)

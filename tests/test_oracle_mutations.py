@@ -51,6 +51,10 @@ MUTATIONS = [
      "g->G2x[c] = ddx(g, g->G2, i, j, k);",
      "g->G2x[c] = ddx(g, g->N2, i, j, k);",
      [G.test_gamma_fields_interpolate_and_differentiate_exactly]),
+    ("saturation damping with K^2 without Gamma^2",
+     "K2 = (r->k[i] * r->k[i] + r->l[i] * r->l[i]) + (r->m[i] * r->m[i] + G[0]);",
+     "K2 = (r->k[i] * r->k[i] + r->l[i] * r->l[i]) + r->m[i] * r->m[i];",
+     [G.test_saturation_with_gamma_restores_the_threshold]),
     ("saturation K^2 without Gamma^2",
      "K2 = kh2 + (m2 + G2);",
      "K2 = kh2 + m2;",
