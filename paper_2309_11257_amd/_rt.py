@@ -14,7 +14,9 @@ from typing import Dict, Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librt.so")
+# RT_LIBRARY may name another build of the same library (an A/B timing of two
+# versions of the kernels in one process tree)
+LIB_PATH = os.environ.get("RT_LIBRARY") or os.path.join(_HERE, "librt.so")
 
 RT_OK, RT_E_ARG, RT_E_STATE, RT_E_NOMEM, RT_E_CAPACITY, RT_E_DEVICE, RT_E_NUMERIC, RT_E_UNSUPPORTED = range(8)
 RT_CARTESIAN, RT_SPHERICAL = 0, 1

@@ -394,8 +394,9 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
         F[8] = czp - czm;
     } else {
         const double r = g.a + z;
-        const double cphi = cos(y);
-        const double tphi = tan(y);
+        double sphi, cphi;
+        sincos(y, &sphi, &cphi);
+        const double tphi = sphi / cphi;
         const double rc = r * cphi;
         const double uc = 0.5 * (cxp + cxm);
         const double vc = 0.5 * (cyp + cym);

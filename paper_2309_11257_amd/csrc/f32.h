@@ -259,19 +259,23 @@ __device__ inline float gam2_at(const G32 &g, const Bg32P &b, int ic, int jc, in
 
 // Per-wave stencil box in LDS.  When every volume of a wave lies in one
 // column and the wave's levels span at most WB_LMAX - 6, the wave stages the
-// A records of the 5 x 5 columns around it and the gradient records of the
-// 3 x 3 columns, for the levels kbase .. kbase + L - 1, plus f2 and (f2)_y of
-// the five rows, and interpolates from LDS; a lookup that falls outside the
-// box for any lane of the wave goes to global memory for the whole wave.
+// A records of the 5 x 5 columns around it for the levels kbase .. kbase +
+// L - 1 (the faces' reach), the gradient records of the 3 x 3 columns for
+// the narrower window kbase_g .. kbase_g + LG - 1 (the centre's nodes only),
+// plus f2 and (f2)_y of the five rows, and interpolates from LDS; a lookup
+// that falls outside the box for any lane of the wave goes to global memory
+// for the whole wave.  8 160 bytes a wave: 20 waves fit a compute unit's LDS.
 #define WB_LMAX 13
+#define WB_GMAX (WB_LMAX - 3)
 #define WB_A (25 * WB_LMAX)
-#define WB_F2 (WB_A + 18 * WB_LMAX)  // five rows of (f2, (f2)_y, 0, 0) after the records
+#define WB_F2 (WB_A + 18 * WB_GMAX)  // five rows of (f2, (f2)_y, 0, 0) after the records
 #define WB_RECS (WB_F2 + 5)
 extern __shared__ float4 wb_lds[];
 
 struct WBox {
     int on;  // wave-uniform
     int ic, jc, kbase, L, base;
+    int kbase_g, LG;  // level window of the gradient records
 };
 
 __device__ inline int wrapd(int d, int n)
@@ -286,38 +290,39 @@ __device__ inline int wrapd(int d, int n)
 // x node of a cell is always the next box column and the upper y and z nodes
 // the next row and level unless the axis clamps them; one base index and two
 // strides (0 or a row, 0 or a level) locate all eight corners.  Layout
-// [dy][dx][k] with a column stride of WB_LMAX records.
+// [dy][dx][k] with a column stride of LS records (WB_LMAX for the A records,
+// WB_GMAX for the gradient records), levels from kb, L of them.
 struct BCell {
     int base, sy, sz;
 };
 
-template <int RAD>
-__device__ inline bool box_of(const G32 &g, const WBox &w, const Axis &x, const Axis &y, const Axis &z, BCell &b)
+template <int RAD, int LS>
+__device__ inline bool box_of(const G32 &g, const WBox &w, int kb, int L, const Axis &x, const Axis &y, const Axis &z,
+                              BCell &b)
 {
     const int dx0 = wrapd(x.i0 - w.ic, g.nx);
     int dy0 = y.i0 - w.jc;
     if (g.geometry == RT_CARTESIAN) dy0 = wrapd(dy0, g.ny);
-    const int ey = y.i1 - y.i0, k0 = z.i0 - w.kbase;  // ey: 0 (clamped) or 1 (or 1 - ny, periodic wrap)
+    const int ey = y.i1 - y.i0, k0 = z.i0 - kb;  // ey: 0 (clamped) or 1 (or 1 - ny, periodic wrap)
     const int side = 2 * RAD + 1;
-    b.base = __mul24((dy0 + RAD) * side + (dx0 + RAD), WB_LMAX) + k0;
-    b.sy = ey != 0 ? side * WB_LMAX : 0;
+    b.base = __mul24((dy0 + RAD) * side + (dx0 + RAD), LS) + k0;
+    b.sy = ey != 0 ? side * LS : 0;
     b.sz = z.i1 - z.i0;
-    return dx0 >= -RAD && dx0 < RAD && dy0 >= -RAD && dy0 + (ey != 0 ? 1 : 0) <= RAD && k0 >= 0 &&
-           k0 + b.sz < w.L;
+    return dx0 >= -RAD && dx0 < RAD && dy0 >= -RAD && dy0 + (ey != 0 ? 1 : 0) <= RAD && k0 >= 0 && k0 + b.sz < L;
 }
 
-template <int R>
+template <int R, int LS>
 __device__ inline void fill_box(Corners<R> &K, int off, const BCell &b)
 {
     const int p = off + b.base;
     K.a0 = wb_lds[p];
-    K.a1 = wb_lds[p + WB_LMAX];
+    K.a1 = wb_lds[p + LS];
     K.b0 = wb_lds[p + b.sy];
-    K.b1 = wb_lds[p + b.sy + WB_LMAX];
+    K.b1 = wb_lds[p + b.sy + LS];
     K.d0 = wb_lds[p + b.sz];
-    K.d1 = wb_lds[p + b.sz + WB_LMAX];
+    K.d1 = wb_lds[p + b.sz + LS];
     K.e0 = wb_lds[p + b.sy + b.sz];
-    K.e1 = wb_lds[p + b.sy + b.sz + WB_LMAX];
+    K.e1 = wb_lds[p + b.sy + b.sz + LS];
 }
 
 // A corners of a cell: from the box when every lane of the wave is inside
@@ -325,9 +330,9 @@ __device__ inline void corners_A(const G32 &g, const WBox &w, const Bg32P &b, co
                                  const Axis &z, const Cell &c, Corners<1> &K)
 {
     BCell bc;
-    const bool in = w.on && box_of<2>(g, w, x, y, z, bc);
+    const bool in = w.on && box_of<2, WB_LMAX>(g, w, w.kbase, w.L, x, y, z, bc);
     if (__ballot(!in) == 0ull)
-        fill_box(K, w.base, bc);
+        fill_box<1, WB_LMAX>(K, w.base, bc);
     else
         K.fill(b.A, c, 0);
 }
@@ -336,9 +341,9 @@ __device__ inline void corners_G(const G32 &g, const WBox &w, const Bg32P &b, co
                                  const Axis &z, const Cell &c, int r, Corners<2> &K)
 {
     BCell bc;
-    const bool in = w.on && box_of<1>(g, w, x, y, z, bc);
+    const bool in = w.on && box_of<1, WB_GMAX>(g, w, w.kbase_g, w.LG, x, y, z, bc);
     if (__ballot(!in) == 0ull)
-        fill_box(K, w.base + WB_A + r * 9 * WB_LMAX, bc);
+        fill_box<2, WB_GMAX>(K, w.base + WB_A + r * 9 * WB_GMAX, bc);
     else
         K.fill(b.G, c, r);
 }
@@ -420,6 +425,7 @@ __device__ inline float face_t(float c, float sg, float ext) { return fmaf(sg, e
 
 // every lookup of the stage in the box: centre nodes at offsets -1 or 0 (the
 // 3 x 3 gradient box), face nodes at -2 .. 1 (the 5 x 5 box), levels inside
+// (the centre's in both level windows)
 __device__ inline bool box_stage_in(const G32 &g, const WBox &w, int kc, const float *Y)
 {
     // horizontal nodes: floor(t) in lo .. hi exactly when lo <= t < hi + 1
@@ -435,8 +441,9 @@ __device__ inline bool box_stage_in(const G32 &g, const WBox &w, int kc, const f
     const int k0 = blev(g, w, kc, Y[2] - 0.5f, s0, t);
     const int kp = blev(g, w, kc, face_t(Y[2], 0.5f, sdz), s1, t);
     const int km = blev(g, w, kc, face_t(Y[2], -0.5f, sdz), s2, t);
+    const int kg = k0 + (w.kbase - w.kbase_g);
     return hor && (uint32_t)k0 < (uint32_t)(w.L - s0) && (uint32_t)kp < (uint32_t)(w.L - s1) &&
-           (uint32_t)km < (uint32_t)(w.L - s2);
+           (uint32_t)km < (uint32_t)(w.L - s2) && (uint32_t)kg < (uint32_t)(w.LG - s0);
 }
 
 // eight corners from LDS: p the lower corner's record, sx/sy/sz the steps to
@@ -465,7 +472,7 @@ __device__ inline float box_row(int r, float wgt, int c)
 template <bool SPH>
 __device__ inline void rhs_box(const G32 &g, int kc, float phi0, const float *Y, float *F, const WBox &w)
 {
-    constexpr int SA = 5 * WB_LMAX, SG = 3 * WB_LMAX;  // row steps of the A and gradient boxes
+    constexpr int SA = 5 * WB_LMAX, SG = 3 * WB_GMAX;  // row steps of the A and gradient boxes
     const float k = Y[3], l = Y[4], m = Y[5];
     const float kh2 = k * k + l * l;
     const float m2 = m * m;
@@ -490,12 +497,12 @@ __device__ inline void rhs_box(const G32 &g, int kc, float phi0, const float *Y,
         gk = k * TRI_COMP(KA, w, c);
         gl = qf * box_row(dy + 2, c.wy, 1);
         gm = 0.0f;
-        const int pg = WB_A + (dy + 1) * SG + (dx + 1) * WB_LMAX + kb;
+        const int pg = WB_A + (dy + 1) * SG + (dx + 1) * WB_GMAX + kb + (w.kbase - w.kbase_g);
         // gradient records one at a time (bounded register use)
 #pragma unroll 1
         for (int r = 0; r < 2; r++) {
             Corners<2> KG;
-            box_corners(KG, pg + r * 9 * WB_LMAX, WB_LMAX, SG, sz);
+            box_corners(KG, pg + r * 9 * WB_GMAX, WB_GMAX, SG, sz);
             const float4 Gr = make_float4(TRI_COMP(KG, x, c), TRI_COMP(KG, y, c), TRI_COMP(KG, z, c), TRI_COMP(KG, w, c));
             if (r == 0) {  // Uy Uz Vx Vy
                 gl += k * Gr.x + l * Gr.w;

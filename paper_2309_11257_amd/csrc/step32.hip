@@ -67,8 +67,11 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
         // reads global memory)
         w.kbase = max(0, kmn - 2);
         w.L = min(g.nz - 1, kmx + 3) - w.kbase + 1;
+        // the gradient records serve the centre only: one level either side
+        w.kbase_g = max(0, kmn - 1);
+        w.LG = min(g.nz - 1, kmx + 1) - w.kbase_g + 1;
         // one wrap corrects a column or row index when the grid has at least two
-        w.on = w.L <= WB_LMAX && g.nx >= 2 && (g.geometry != RT_CARTESIAN || g.ny >= 2);
+        w.on = w.L <= WB_LMAX && w.LG <= WB_GMAX && g.nx >= 2 && (g.geometry != RT_CARTESIAN || g.ny >= 2);
         if (w.on) {
             // a lane keeps one box column (and gradient record) and a phase
             // of its levels: A records by 50 lanes (25 columns x 2 phases,
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
             // columns x 2 records x 3 phases, levels ph, ph + 3, ...); the
             // column is located once, the levels are constant offsets, and
             // all loads are issued before the LDS writes
-            constexpr int NA = (WB_LMAX + 1) / 2, NG = (WB_LMAX + 2) / 3;
+            constexpr int NA = (WB_LMAX + 1) / 2, NG = (WB_GMAX + 2) / 3;
             const int ca = lane % 25, pa = lane / 25;  // pa: 0, 1 (2 idle)
             const int gg = lane % 18, pg = lane / 18;  // pg: 0 .. 2 (3 idle)
             const int rg = gg / 9, cg = gg % 9;
@@ -96,20 +99,20 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
                 jg = min(max(jg, 0), g.ny - 1);
             }
             const uint32_t ka = f32::col_base(g, ja, ia) + (uint32_t)(w.kbase + pa);
-            const uint32_t kg = (f32::col_base(g, jg, ig) + (uint32_t)(w.kbase + pg)) * 2u + (uint32_t)rg;
+            const uint32_t kg = (f32::col_base(g, jg, ig) + (uint32_t)(w.kbase_g + pg)) * 2u + (uint32_t)rg;
             float4 va[NA], vg[NG];
 #pragma unroll
             for (int t = 0; t < NA; t++)
                 if (pa < 2 && pa + 2 * t < w.L) va[t] = f32::rec(b.A, ka + 2u * t);
 #pragma unroll
             for (int t = 0; t < NG; t++)
-                if (pg < 3 && pg + 3 * t < w.L) vg[t] = f32::rec(b.G, kg + 6u * t);
+                if (pg < 3 && pg + 3 * t < w.LG) vg[t] = f32::rec(b.G, kg + 6u * t);
 #pragma unroll
             for (int t = 0; t < NA; t++)
                 if (pa < 2 && pa + 2 * t < w.L) f32::wb_lds[ca * WB_LMAX + pa + 2 * t] = va[t];
 #pragma unroll
             for (int t = 0; t < NG; t++)
-                if (pg < 3 && pg + 3 * t < w.L) f32::wb_lds[WB_A + rg * 9 * WB_LMAX + cg * WB_LMAX + pg + 3 * t] = vg[t];
+                if (pg < 3 && pg + 3 * t < w.LG) f32::wb_lds[WB_A + rg * 9 * WB_GMAX + cg * WB_GMAX + pg + 3 * t] = vg[t];
             // f2 and (f2)_y of the five box rows
             if (lane < 5) {
                 int jj = w.jc + lane - 2;
