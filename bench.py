@@ -400,6 +400,46 @@ def rows_report():
         out.append(_row("f3-budget", wl, name, ms_bud, w3.n_rays * vb + (ncol * (w3.nz + 1)) * 4 * 8 * 2 + cells * 16,
                         t_bud, cores, f"oracle budget fields and terms ({t_bud:.2f} s)" if t_bud else "",
                         "A, cg_h A, cg_z A and the propagation terms"))
+    # f2: launch from the ghost layer (latitudinal background source, eight
+    # phase speeds, four directions) into the 20 M-volume set after one step:
+    # the set is compacted (read and written once), the new volumes written,
+    # the whole set regrouped
+    lp = dict(lambda_h=300e3, c_min=2.0, c_max=62.0, c_center=25.0, c_width=15.0, n_speeds=8)
+    z_launch = 9e3
+    for prec, name in ((_rt.RT_FP32, "f32"), (_rt.RT_FP64, "f64")):
+        vb = STEP_BYTES["fp32" if name == "f32" else "fp64"]
+        tr = _rt.Tracer.for_workload(w3, prec, capacity=w3.n_rays + 8 * 4 * 8 * ncol)
+        tr.init_background_from(w3)
+        tr.set_rays(w3.rays)
+        tr.step(w3.dt)
+        n0 = tr.stats()["n_active"]
+        ms = _ev_ms(lambda: tr.launch(z_launch, w3.dt, **lp), 5)
+        n_new = (tr.stats()["n_active"] - n0) // 6
+        tr.close()
+        t_l = 0.0
+        if name == "f32":
+            rs3 = oracle.RaySet(w3.rays, capacity=w3.n_rays + 4 * 8 * ncol)
+            t = time.perf_counter()
+            oracle.launch(bg3, rs3, oracle.launch_params(z_launch, w3.dt, **lp))
+            t_l = time.perf_counter() - t
+            del rs3
+        out.append(_row("f2", f"global {w3.nx}x{w3.ny}x{w3.nz}, {n0} ray volumes + {n_new} launched", name, ms,
+                        n0 * 2 * vb + n_new * vb, t_l, cores,
+                        f"oracle launch into the same set ({t_l:.2f} s)" if t_l else "",
+                        "candidates flagged, scanned and written after the compacted set, regrouping sort"))
+    # f4: a full step (RK3, regrouping, deposition, drag) with the
+    # scale-height correction Gamma^2 = 1/(4 H_rho^2) of the reference density
+    w3g = W.make_c3()
+    w3g.G2 = W.density_gamma2(w3g)
+    for prec, name in ((_rt.RT_FP32, "f32"), (_rt.RT_FP64, "f64")):
+        r = time_path(w3g, prec, 10, 3, late=False)
+        r0 = time_path(w3, prec, 10, 3, late=False)
+        vb = STEP_BYTES["fp32" if name == "f32" else "fp64"]
+        out.append(_row("f4", f"global {w3.nx}x{w3.ny}x{w3.nz}, {w3.n_rays} ray volumes, Gamma from the density "
+                        "scale height", name, r["ms_per_step"], w3.n_rays * vb, 0.0, cores, "",
+                        f"whole step with Gamma {r['ms_per_step']:.3f} ms, without {r0['ms_per_step']:.3f} ms; "
+                        f"step kernel {r['kernels'].get('step', {}).get('ms_avg', 0):.3f} ms with, "
+                        f"{r0['kernels'].get('step', {}).get('ms_avg', 0):.3f} ms without"))
     del bg3
     # a9 + a10: split (alpha = 2) and per-cell merge (64) on the jet box
     w2 = W.make_c2()
