@@ -351,7 +351,7 @@ __device__ inline void corners_G(const G32 &g, const WBox &w, const Bg32P &b, co
 // Right-hand side from the centre's refraction sums (gk, gl, gm) and the face
 // velocities of each axis (sum s and half-difference h of the + and - faces).
 template <bool SPH>
-__device__ inline void assemble(const G32 &g, int kc, float phi0, const float *Y, float gk, float gl, float gm,
+__device__ inline void assemble(const G32 &g, int kc, float2 lat, const float *Y, float gk, float gl, float gm,
                                 float sx, float hx, float sy, float hy, float sz, float hz, float *F)
 {
     const float k = Y[3], l = Y[4];
@@ -368,8 +368,14 @@ __device__ inline void assemble(const G32 &g, int kc, float phi0, const float *Y
     } else {
         const float r = g.a + ((float)kc + Y[2]) * g.dz;
         const float ir = rcp(r);
-        float sphi, cphi;
-        sincosf(phi0 + Y[1] * g.dyr, &sphi, &cphi);
+        // sin and cos of the latitude from those of the cell's southern edge
+        // (lat) and the Taylor series of the offset d = y dphi; up to half a
+        // radian the terms kept leave an error far below one ulp
+        const float d = Y[1] * g.dyr, d2 = d * d;
+        const float sd = d + d * d2 * (-1.0f / 6.0f + d2 * (1.0f / 120.0f + d2 * (-1.0f / 5040.0f + d2 * (1.0f / 362880.0f))));
+        const float cd = 1.0f + d2 * (-0.5f + d2 * (1.0f / 24.0f + d2 * (-1.0f / 720.0f + d2 * (1.0f / 40320.0f))));
+        const float sphi = lat.x * cd + lat.y * sd;
+        const float cphi = lat.y * cd - lat.x * sd;
         const float icphi = rcp(cphi);
         const float tphi = sphi * icphi;
         const float irc = ir * icphi;
@@ -470,7 +476,7 @@ __device__ inline float box_row(int r, float wgt, int c)
 }
 
 template <bool SPH>
-__device__ inline void rhs_box(const G32 &g, int kc, float phi0, const float *Y, float *F, const WBox &w)
+__device__ inline void rhs_box(const G32 &g, int kc, float2 lat, const float *Y, float *F, const WBox &w)
 {
     constexpr int SA = 5 * WB_LMAX, SG = 3 * WB_GMAX;  // row steps of the A and gradient boxes
     const float k = Y[3], l = Y[4], m = Y[5];
@@ -558,7 +564,7 @@ __device__ inline void rhs_box(const G32 &g, int kc, float phi0, const float *Y,
         szs += v;
         hz += sg * v;
     }
-    assemble<SPH>(g, kc, phi0, Y, gk, gl, gm, sx, hx, sy, hy, szs, hz, F);
+    assemble<SPH>(g, kc, lat, Y, gk, gl, gm, sx, hx, sy, hy, szs, hz, F);
 }
 
 // RK stage right-hand side in cell units: Y = (xi, eta, zeta, k, l, m, Dxi,
@@ -573,7 +579,7 @@ __device__ inline void rhs_box(const G32 &g, int kc, float phi0, const float *Y,
 // Gamma^2 gradients weighed by d omega_hat / d Gamma^2 =
 // -(kh^2 / (2 omega_hat K^2)) (N^2 - f^2) / K^2.
 template <bool SPH, bool GAM>
-__device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc, float phi0, const float *Y,
+__device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc, float2 lat, const float *Y,
                            float *F, const WBox &w)
 {
     const float xi = Y[0], eta = Y[1], zeta = Y[2], k = Y[3], l = Y[4], m = Y[5];
@@ -669,7 +675,7 @@ __device__ inline void rhs(const G32 &g, const Bg32P &b, int ic, int jc, int kc,
         czp = fc == 4 ? v : czp;
         czm = fc == 5 ? v : czm;
     }
-    assemble<SPH>(g, kc, phi0, Y, gk, gl, gm, cxp + cxm, 0.5f * (cxp - cxm), cyp + cym, 0.5f * (cyp - cym), czp + czm,
+    assemble<SPH>(g, kc, lat, Y, gk, gl, gm, cxp + cxm, 0.5f * (cxp - cxm), cyp + cym, 0.5f * (cyp - cym), czp + czm,
                   0.5f * (czp - czm), F);
 }
 

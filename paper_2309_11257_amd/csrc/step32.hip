@@ -135,6 +135,8 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
     const float A[3] = {0.0f, -5.0f / 9.0f, -153.0f / 128.0f};
     const float B[3] = {1.0f / 3.0f, 15.0f / 16.0f, 8.0f / 15.0f};
     const float phi0 = g.y0 + (float)jc * g.dyr;
+    float2 lat = make_float2(0.0f, 1.0f);
+    if (SPH) sincosf(phi0, &lat.x, &lat.y);
     // volumes in columns handed to the surrogate keep their state this step
     const int nst = (frozen && frozen[f32::at(skeys, i)]) ? 0 : 3;
 #pragma unroll 1
@@ -143,9 +145,9 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
         // box-only form; otherwise each lookup tests the box itself (always
         // with the scale-height correction, whose records are not staged)
         if (!GAM && w.on && __ballot(!f32::box_stage_in(g, w, kc0, Y)) == 0ull)
-            f32::rhs_box<SPH>(g, kc0, phi0, Y, F, w);
+            f32::rhs_box<SPH>(g, kc0, lat, Y, F, w);
         else
-            f32::rhs<SPH, GAM>(g, b, ic, jc, kc0, phi0, Y, F, w);
+            f32::rhs<SPH, GAM>(g, b, ic, jc, kc0, lat, Y, F, w);
 #pragma unroll
         for (int c = 0; c < 9; c++) {
             Q[c] = A[st] * Q[c] + dt * F[c];
