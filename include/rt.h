@@ -126,10 +126,10 @@ typedef struct {
 
 /* Create a context on the current HIP device.  The grid and precision are
    fixed for the context's lifetime.  Errors: RT_E_ARG for bad sizes;
-   RT_E_UNSUPPORTED for nz > 640 and, in single precision, for grids of
-   2^24 columns or more or nx*ny*nz >= 2^27 cells (32-bit offsets into the
-   packed background) and for a capacity of 2^30 ray volumes or more (32-bit
-   offsets into the ray fields). */
+   RT_E_UNSUPPORTED for nz > 640, for grids of 2^24 columns or more (24-bit
+   index products) and, in single precision, for nx*ny*nz >= 2^27 cells
+   (32-bit offsets into the packed background) and for a capacity of 2^30
+   ray volumes or more (32-bit offsets into the ray fields). */
 rt_status rt_create(const rt_config *cfg, rt_ctx *out);
 
 /* Release all device memory of the context (synchronises its stream). */

@@ -164,11 +164,12 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     if (!(cfg->dx > 0 && cfg->dy > 0 && cfg->dz > 0)) return RT_E_ARG;
     if (cfg->geometry == RT_SPHERICAL && !(cfg->a > 0)) return RT_E_ARG;
     if (cfg->capacity < 0 || cfg->capacity > (int64_t)0xffffff00) return RT_E_ARG;
+    // cell indices are formed with 24-bit products (fewer than 2^24 columns);
     // single-precision lookups address the packed background with 32-bit byte
-    // offsets (2 gradient records of 16 B per cell) and 24-bit index products;
-    // its step reads and writes 4-byte ray fields at 32-bit byte offsets
+    // offsets (2 gradient records of 16 B per cell) and its step reads and
+    // writes 4-byte ray fields at 32-bit byte offsets
+    if ((int64_t)cfg->nx * cfg->ny >= ((int64_t)1 << 24)) return RT_E_UNSUPPORTED;
     if (cfg->precision == RT_FP32 && ((int64_t)cfg->nx * cfg->ny * cfg->nz * 32 >= ((int64_t)1 << 32) ||
-                                      (int64_t)cfg->nx * cfg->ny >= ((int64_t)1 << 24) ||
                                       cfg->capacity >= ((int64_t)1 << 30)))
         return RT_E_UNSUPPORTED;
     if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return RT_E_ARG;

@@ -44,6 +44,76 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// sum of v over lane i and lane i + OFF (OFF = 16, 32: exactly lane i xor
+// OFF, by the half-row and half-wave swaps of CDNA4) or, within each row of
+// 16 lanes, lane (i + OFF) mod 16 (OFF = 2, 4, 8); every form keeps the lane
+// index modulo OFF, and the rounding of each lane's sum is fixed by the lane
+template <int OFF>
+__device__ inline double lane_pair_sum(double v)
+{
+    if constexpr (OFF >= 16) {
+        const uint32_t lo = (uint32_t)__double2loint(v), hi = (uint32_t)__double2hiint(v);
+        const auto a = OFF == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                                 : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto b = OFF == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                                 : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+    } else {
+        return v + __builtin_amdgcn_update_dpp(0.0, v, 0x120 + OFF, 0xf, 0xf, false);  // row_ror:OFF
+    }
+}
+
+// Level window of L levels (and interfaces) k0 .. k0 + L - 1 for a chunk of
+// 64 volumes staged at vd (zb, zt, then NF densities, each [64]): lane i takes
+// level k0 + s, s = (i - k0) mod L, for the volumes gi, gi + 64/L, ... of the
+// chunk (gi = i / L), so that the lane that keeps level k in its registers
+// (lane k mod 64) is one of the 64/L lanes summing it; the partial sums of
+// those lanes, L apart, are then added by a fixed tree of lane exchanges.
+template <class P, int L>
+__device__ inline void chunk_window(const Grid &g, const double *vd, int k0, int lane,
+                                    double (&preg)[P::NL + P::NI][2])
+{
+    constexpr int NL = P::NL, NF = P::NL + P::NI, G = 64 / L;
+    const int sl = (lane - k0) & (L - 1), gi = lane / L, k = k0 + sl;
+    const double lv = (double)k * g.dz, hv = (double)(k + 1) * g.dz;
+    double lv2 = ((double)k - 0.5) * g.dz, hv2 = ((double)k + 0.5) * g.dz;
+    if (lv2 < 0.0) lv2 = 0.0;
+    if (hv2 > g.Lz) hv2 = g.Lz;
+    const bool lev_ok = k <= g.nz - 1, itf_ok = k <= g.nz;
+    double sm[NF];
+#pragma unroll
+    for (int q = 0; q < NF; q++) sm[q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < L; i++) {
+        const int j = gi + G * i;
+        const double zbj = vd[j], ztj = vd[64 + j];
+        double o = fmin(ztj, hv) - fmax(zbj, lv);
+        double o2 = fmin(ztj, hv2) - fmax(zbj, lv2);
+        o = (lev_ok && o > 0.0) ? o : 0.0;
+        o2 = (itf_ok && o2 > 0.0) ? o2 : 0.0;
+#pragma unroll
+        for (int q = 0; q < NL; q++) sm[q] += vd[128 + 64 * q + j] * o;
+#pragma unroll
+        for (int q = NL; q < NF; q++) sm[q] += vd[128 + 64 * q + j] * o2;
+    }
+#pragma unroll
+    for (int q = 0; q < NF; q++) {
+        if (L <= 2) sm[q] = lane_pair_sum<2>(sm[q]);
+        if (L <= 4) sm[q] = lane_pair_sum<4>(sm[q]);
+        sm[q] = lane_pair_sum<8>(sm[q]);
+        sm[q] = lane_pair_sum<16>(sm[q]);
+        sm[q] = lane_pair_sum<32>(sm[q]);
+    }
+    // level k0 + s (s < L) is kept by lane (k0 + s) mod 64, in register slot
+    // (k0 + s) / 64
+    const bool take = ((lane - k0) & 63) < L, hi_slot = k >= 64;
+#pragma unroll
+    for (int q = 0; q < NF; q++) {
+        preg[q][0] += (take && !hi_slot) ? sm[q] : 0.0;
+        preg[q][1] += (take && hi_slot) ? sm[q] : 0.0;
+    }
+}
+
 // P::load(slot, column, zb, zt, bv[NF]) fills the vertical span of the volume
 // (in the column the sort grouped it in) and its NF densities per unit
 // height (for the fluxes: (cgx k, cgx l, cgy k, cgy l, cgz k, cgz l) * W / Dz).
@@ -121,54 +191,23 @@ __global__ __launch_bounds__(64 * CPW, RP ? P::WAVES : 2) void k_deposit(Grid g,
             }
             const int k0 = wave_min_i(min(lo, lo2)), k1 = wave_max_i(max(hi, hi2));
             if (RP && k1 - k0 < 8) {
-                // Chunk within eight levels (a column sorted by level): lane
-                // 8 g + s takes level (and interface) k0 + s for the volumes g,
-                // g + 8, ..., g + 56 of the chunk, read from the wave's LDS
-                // (its integer profile, zero between chunks), and the eight
-                // groups are added by a fixed butterfly: double sums in a
-                // fixed order, with no fixed-point scale.
+                // Chunk within eight levels (a column sorted by level): the
+                // chunk is staged in the wave's LDS (its integer profile, zero
+                // between chunks) and summed level by level in double, in a
+                // fixed order, with no fixed-point scale; the window is the
+                // narrowest of 2, 4 or 8 levels that holds the chunk
                 double *vd = (double *)acc;
                 vd[lane] = zb;
                 vd[64 + lane] = zt;
 #pragma unroll
                 for (int q = 0; q < NF; q++) vd[128 + 64 * q + lane] = bv[q];
                 wave_sync();
-                const int sl8 = lane & 7, gi = lane >> 3, k = k0 + sl8;
-                const double lv = (double)k * g.dz, hv = (double)(k + 1) * g.dz;
-                double lv2 = ((double)k - 0.5) * g.dz, hv2 = ((double)k + 0.5) * g.dz;
-                if (lv2 < 0.0) lv2 = 0.0;
-                if (hv2 > g.Lz) hv2 = g.Lz;
-                const bool lev_ok = k <= g.nz - 1, itf_ok = k <= g.nz;
-                double sm[NF];
-#pragma unroll
-                for (int q = 0; q < NF; q++) sm[q] = 0.0;
-#pragma unroll
-                for (int i = 0; i < 8; i++) {
-                    const int j = gi + 8 * i;
-                    const double zbj = vd[j], ztj = vd[64 + j];
-                    double o = fmin(ztj, hv) - fmax(zbj, lv);
-                    double o2 = fmin(ztj, hv2) - fmax(zbj, lv2);
-                    o = (lev_ok && o > 0.0) ? o : 0.0;
-                    o2 = (itf_ok && o2 > 0.0) ? o2 : 0.0;
-#pragma unroll
-                    for (int q = 0; q < NL; q++) sm[q] += vd[128 + 64 * q + j] * o;
-#pragma unroll
-                    for (int q = NL; q < NF; q++) sm[q] += vd[128 + 64 * q + j] * o2;
-                }
-#pragma unroll
-                for (int q = 0; q < NF; q++)
-#pragma unroll
-                    for (int off = 8; off < 64; off <<= 1) sm[q] += __shfl_xor(sm[q], off, 64);
-                // level k0 + s (held by lanes s < 8) to the lane that keeps it:
-                // lane (k0 + s) mod 64, register slot (k0 + s) / 64
-                const int src = (lane - k0) & 63;
-                const bool take = src < 8, hi_slot = k0 + src >= 64;
-#pragma unroll
-                for (int q = 0; q < NF; q++) {
-                    const double v = __shfl(sm[q], src, 64);
-                    preg[q][0] += (take && !hi_slot) ? v : 0.0;
-                    preg[q][1] += (take && hi_slot) ? v : 0.0;
-                }
+                if (k1 - k0 < 2)
+                    chunk_window<P, 2>(g, vd, k0, lane, preg);
+                else if (k1 - k0 < 4)
+                    chunk_window<P, 4>(g, vd, k0, lane, preg);
+                else
+                    chunk_window<P, 8>(g, vd, k0, lane, preg);
                 wave_sync();
 #pragma unroll
                 for (int t = 0; t < 2 + NF; t++) acc[64 * t + lane] = 0ull;

@@ -83,13 +83,18 @@ struct Cell {
     double wx, wy, wz;
 };
 
+// 24-bit products (full rate): a context has fewer than 2^24 columns and at
+// most 640 levels, and every product is a cell index below 2^31
+__device__ inline int mul24(int a, int b) { return (int)__umul24((uint32_t)a, (uint32_t)b); }
+__device__ inline int col_cells(const Grid &g, int j, int i) { return mul24(mul24(j, g.nx) + i, g.nz); }
+
 __device__ inline Cell cell_of(const Grid &g, const Axis &x, const Axis &y, const Axis &z)
 {
     Cell c;
-    c.c00 = (y.i0 * g.nx + x.i0) * g.nz;
-    c.c01 = (y.i0 * g.nx + x.i1) * g.nz;
-    c.c10 = (y.i1 * g.nx + x.i0) * g.nz;
-    c.c11 = (y.i1 * g.nx + x.i1) * g.nz;
+    c.c00 = col_cells(g, y.i0, x.i0);
+    c.c01 = col_cells(g, y.i0, x.i1);
+    c.c10 = col_cells(g, y.i1, x.i0);
+    c.c11 = col_cells(g, y.i1, x.i1);
     c.k0 = z.i0;
     c.k1 = z.i1;
     c.wx = x.w;
@@ -168,6 +173,7 @@ struct WBox {
 
 struct BCell {
     int r00, r01, r10, r11, k0, k1;
+    int on;  // faces: every lane's corners in the box (wave-uniform)
 };
 
 __device__ inline int wrapd(int d, int n)
@@ -271,6 +277,111 @@ __device__ inline double gam2_at(const Grid &g, const Bg64P &b, double x, double
     return gam2(b, c);
 }
 
+// Box offsets of the centre's nodes in the 5 x 5 A box ([dy][dx][k] layout):
+// the row and column parts of each node and whether the nodes of each axis
+// lie in the box (faces replace one axis)
+struct BOff {
+    int ry0, ry1, cx0, cx1, k0, k1;  // (dy + 2) * 5, dx + 2, level - kbase
+    bool inx, iny, inz;
+};
+
+__device__ inline void box_offsets(const Grid &g, const WBox &w, const Axis &x, const Axis &y, const Axis &z, BOff &o)
+{
+    const int dx0 = wrapd(x.i0 - w.ic, g.nx), dx1 = wrapd(x.i1 - w.ic, g.nx);
+    int dy0 = y.i0 - w.jc, dy1 = y.i1 - w.jc;
+    if (g.geometry == RT_CARTESIAN) {
+        dy0 = wrapd(dy0, g.ny);
+        dy1 = wrapd(dy1, g.ny);
+    }
+    o.cx0 = dx0 + 2;
+    o.cx1 = dx1 + 2;
+    o.ry0 = (dy0 + 2) * 5;
+    o.ry1 = (dy1 + 2) * 5;
+    o.k0 = z.i0 - w.kbase;
+    o.k1 = z.i1 - w.kbase;
+    o.inx = abs(dx0) <= 2 && abs(dx1) <= 2;
+    o.iny = abs(dy0) <= 2 && abs(dy1) <= 2;
+    o.inz = o.k0 >= 0 && o.k1 < w.L;
+}
+
+// the A box cell of a face (AX: the face's axis, a its nodes on that axis);
+// on = 0 when a node of any lane lies outside the box
+template <int AX>
+__device__ inline BCell face_box(const Grid &g, const WBox &w, const BOff &o, const Axis &a)
+{
+    BOff f = o;
+    if (AX == 0) {
+        const int d0 = wrapd(a.i0 - w.ic, g.nx), d1 = wrapd(a.i1 - w.ic, g.nx);
+        f.cx0 = d0 + 2;
+        f.cx1 = d1 + 2;
+        f.inx = abs(d0) <= 2 && abs(d1) <= 2;
+    } else if (AX == 1) {
+        int d0 = a.i0 - w.jc, d1 = a.i1 - w.jc;
+        if (g.geometry == RT_CARTESIAN) {
+            d0 = wrapd(d0, g.ny);
+            d1 = wrapd(d1, g.ny);
+        }
+        f.ry0 = (d0 + 2) * 5;
+        f.ry1 = (d1 + 2) * 5;
+        f.iny = abs(d0) <= 2 && abs(d1) <= 2;
+    } else {
+        f.k0 = a.i0 - w.kbase;
+        f.k1 = a.i1 - w.kbase;
+        f.inz = f.k0 >= 0 && f.k1 < w.L;
+    }
+    BCell b;
+    b.r00 = mul24(f.ry0 + f.cx0, w.L);
+    b.r01 = mul24(f.ry0 + f.cx1, w.L);
+    b.r10 = mul24(f.ry1 + f.cx0, w.L);
+    b.r11 = mul24(f.ry1 + f.cx1, w.L);
+    b.k0 = f.k0;
+    b.k1 = f.k1;
+    // a wave-uniform flag in the cell's spare field
+    b.on = (__ballot(!(w.on && f.inx && f.iny && f.inz)) == 0ull) ? 1 : 0;
+    return b;
+}
+
+// horizontal (AX = 0: U, AX = 1: V) or vertical (AX = 2) group velocity at
+// one face: the wind component along the axis (none vertically) plus the
+// intrinsic part, from the face's N^2 and f^2 (Section 3a, Appendix B)
+template <int AX, bool GAM>
+__device__ inline double face_v(const Grid &g, const WBox &w, const Bg64P &b, const Cell &f, const BCell &bc,
+                                double k, double l, double m, double kh2, double m2, double K2, double K4, double f2f)
+{
+    (void)g;
+    double c8[8], n8[8];
+    if (bc.on) {
+        const double *L = (const double *)wb64_lds;
+        const int rr[4] = {bc.r00, bc.r01, bc.r10, bc.r11};
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int rec = rr[t & 3] + ((t & 4) ? bc.k1 : bc.k0);
+            if (AX < 2) c8[t] = L[4 * rec + AX];
+            n8[t] = L[4 * rec + 2];
+        }
+    } else {
+        const double *A = (const double *)b.A;
+        const int cc[4] = {f.c00, f.c01, f.c10, f.c11};
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int rec = cc[t & 3] + ((t & 4) ? f.k1 : f.k0);
+            if (AX < 2) c8[t] = A[4 * (int64_t)rec + AX];
+            n8[t] = A[4 * (int64_t)rec + 2];
+        }
+    }
+    // corner order of lerp3: (j0,i0) (j0,i1) (j1,i0) (j1,i1) at k0, then at k1
+    const double N2f = lerp3(n8[0], n8[1], n8[2], n8[3], n8[4], n8[5], n8[6], n8[7], f);
+    const double M2f = GAM ? m2 + gam2(b, f) : m2;
+    const double K2f = GAM ? kh2 + M2f : K2;
+    const double K4f = GAM ? K2f * K2f : K4;
+    const double omf = omega_hat(N2f, f2f, kh2, M2f, K2f);
+    const double num = AX == 0 ? k * M2f : (AX == 1 ? l * M2f : m * kh2);
+    const double t = (num * (N2f - f2f)) / (omf * K4f);
+    if (AX == 2) return -t;
+    const double wnd = lerp3(c8[0], c8[1], c8[2], c8[3], c8[4], c8[5], c8[6], c8[7], f);
+    return wnd + t;
+}
+
 // Right-hand side of one RK stage.  Y = (x, y, z, k, l, m, Dx, Dy, Dz).
 // Carrier wavevector tendency from the centre fields and gradients
 // (eq. eikonal-sphere 1-3; flat limit on the box); carrier motion and extent
@@ -346,41 +457,57 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
         gm = gm + qg * Gc.w;
     }
 
-    // faces: +x, -x, +y, -y, +z, -z, one at a time (bounded register use)
+    // faces, one axis at a time and one face at a time (bounded register
+    // use): a face differs from the centre along its own axis only, so the
+    // centre's nodes of the other two axes (and their cell and box offsets)
+    // are kept
+    const int X0 = mul24(ax.i0, g.nz), X1 = mul24(ax.i1, g.nz);  // x nodes, in cells
+    const int R0 = c.c00 - X0, R1 = c.c10 - X0;                    // y rows, in cells
+    BOff bo;
+    box_offsets(g, w, ax, ay, az, bo);
     double cxp = 0.0, cxm = 0.0, cyp = 0.0, cym = 0.0, czp = 0.0, czm = 0.0;
 #pragma unroll 1
-    for (int fc = 0; fc < 6; fc++) {
-        const int axn = fc >> 1;
-        const double sg = (fc & 1) ? -0.5 : 0.5;
-        Axis fx = ax, fy = ay, fz = az;
-        if (axn == 0)
-            fx = axis_x(g, x + sg * Dx);
-        else if (axn == 1)
-            fy = axis_y(g, y + sg * Dy);
-        else
-            fz = axis_z(g, z + sg * Dz);
-        const Cell f = cell_of(g, fx, fy, fz);
-        Corners<1> K;
-        corners_A(g, w, b, fx, fy, fz, f, K);
-        const double N2f = TRI64(K, z, f);
-        const double f2f = axn == 1 ? row_lerp(b.f2, fy) : f2c;
-        const bool useU = axn == 0;
-        const double wnd = lerp3(useU ? K.a0.x : K.a0.y, useU ? K.a1.x : K.a1.y, useU ? K.b0.x : K.b0.y,
-                                 useU ? K.b1.x : K.b1.y, useU ? K.d0.x : K.d0.y, useU ? K.d1.x : K.d1.y,
-                                 useU ? K.e0.x : K.e0.y, useU ? K.e1.x : K.e1.y, f);
-        const double M2f = GAM ? m2 + gam2(b, f) : m2;
-        const double K2f = GAM ? kh2 + M2f : K2;
-        const double K4f = GAM ? K2f * K2f : K4;
-        const double omf = omega_hat(N2f, f2f, kh2, M2f, K2f);
-        const double num = axn == 0 ? k * M2f : (axn == 1 ? l * M2f : m * kh2);
-        const double t = (num * (N2f - f2f)) / (omf * K4f);
-        const double v = axn == 2 ? -t : wnd + t;
-        cxp = fc == 0 ? v : cxp;
-        cxm = fc == 1 ? v : cxm;
-        cyp = fc == 2 ? v : cyp;
-        cym = fc == 3 ? v : cym;
-        czp = fc == 4 ? v : czp;
-        czm = fc == 5 ? v : czm;
+    for (int sd = 0; sd < 2; sd++) {
+        const double sg = sd ? -0.5 : 0.5;
+        const Axis fx = axis_x(g, x + sg * Dx);
+        Cell f = c;
+        const int F0 = mul24(fx.i0, g.nz), F1 = mul24(fx.i1, g.nz);
+        f.c00 = R0 + F0;
+        f.c01 = R0 + F1;
+        f.c10 = R1 + F0;
+        f.c11 = R1 + F1;
+        f.wx = fx.w;
+        const double v = face_v<0, GAM>(g, w, b, f, face_box<0>(g, w, bo, fx), k, l, m, kh2, m2, K2, K4, f2c);
+        cxp = sd == 0 ? v : cxp;
+        cxm = sd == 1 ? v : cxm;
+    }
+#pragma unroll 1
+    for (int sd = 0; sd < 2; sd++) {
+        const double sg = sd ? -0.5 : 0.5;
+        const Axis fy = axis_y(g, y + sg * Dy);
+        Cell f = c;
+        const int Q0 = mul24(mul24(fy.i0, g.nx), g.nz), Q1 = mul24(mul24(fy.i1, g.nx), g.nz);
+        f.c00 = Q0 + X0;
+        f.c01 = Q0 + X1;
+        f.c10 = Q1 + X0;
+        f.c11 = Q1 + X1;
+        f.wy = fy.w;
+        const double v = face_v<1, GAM>(g, w, b, f, face_box<1>(g, w, bo, fy), k, l, m, kh2, m2, K2, K4,
+                                         row_lerp(b.f2, fy));
+        cyp = sd == 0 ? v : cyp;
+        cym = sd == 1 ? v : cym;
+    }
+#pragma unroll 1
+    for (int sd = 0; sd < 2; sd++) {
+        const double sg = sd ? -0.5 : 0.5;
+        const Axis fz = axis_z(g, z + sg * Dz);
+        Cell f = c;
+        f.k0 = fz.i0;
+        f.k1 = fz.i1;
+        f.wz = fz.w;
+        const double v = face_v<2, GAM>(g, w, b, f, face_box<2>(g, w, bo, fz), k, l, m, kh2, m2, K2, K4, f2c);
+        czp = sd == 0 ? v : czp;
+        czm = sd == 1 ? v : czm;
     }
     if (!SPH) {
         F[0] = 0.5 * (cxp + cxm);

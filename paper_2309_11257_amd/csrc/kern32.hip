@@ -208,7 +208,7 @@ struct Pay32 {
     double inv_dz;  // its reciprocal (level spans of the deposition)
     static constexpr bool EXACT_LEVELS = false;
     static constexpr int NL = 4, NI = 2;  // horizontal fluxes on levels, vertical on interfaces
-    static constexpr int WAVES = 6;
+    static constexpr int WAVES = 5;
     __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
         // the wave's column (the slot's own column, by the grouping)
