@@ -185,27 +185,6 @@ __device__ inline int wrapd(int d, int n)
     return d;
 }
 
-// box position of a stencil ([dy][dx][k] layout, RAD columns around the
-// wave's column); false if any node lies outside the box
-template <int RAD>
-__device__ inline bool box_of(const Grid &g, const WBox &w, const Axis &x, const Axis &y, const Axis &z, BCell &b)
-{
-    const int dx0 = wrapd(x.i0 - w.ic, g.nx), dx1 = wrapd(x.i1 - w.ic, g.nx);
-    int dy0 = y.i0 - w.jc, dy1 = y.i1 - w.jc;
-    if (g.geometry == RT_CARTESIAN) {
-        dy0 = wrapd(dy0, g.ny);
-        dy1 = wrapd(dy1, g.ny);
-    }
-    b.k0 = z.i0 - w.kbase;
-    b.k1 = z.i1 - w.kbase;
-    const int side = 2 * RAD + 1;
-    b.r00 = ((dy0 + RAD) * side + (dx0 + RAD)) * w.L;
-    b.r01 = ((dy0 + RAD) * side + (dx1 + RAD)) * w.L;
-    b.r10 = ((dy1 + RAD) * side + (dx0 + RAD)) * w.L;
-    b.r11 = ((dy1 + RAD) * side + (dx1 + RAD)) * w.L;
-    return abs(dx0) <= RAD && abs(dx1) <= RAD && abs(dy0) <= RAD && abs(dy1) <= RAD && b.k0 >= 0 && b.k1 < w.L;
-}
-
 template <int R>
 __device__ inline void fill_box(Corners<R> &K, int off, const BCell &b)
 {
@@ -217,29 +196,6 @@ __device__ inline void fill_box(Corners<R> &K, int off, const BCell &b)
     K.d1 = wb64_lds[off + b.r01 + b.k1];
     K.e0 = wb64_lds[off + b.r10 + b.k1];
     K.e1 = wb64_lds[off + b.r11 + b.k1];
-}
-
-// A corners of a cell: from the box when every lane of the wave is inside
-__device__ inline void corners_A(const Grid &g, const WBox &w, const Bg64P &b, const Axis &x, const Axis &y,
-                                 const Axis &z, const Cell &c, Corners<1> &K)
-{
-    BCell bc;
-    const bool in = w.on && box_of<2>(g, w, x, y, z, bc);
-    if (__ballot(!in) == 0ull)
-        fill_box(K, 0, bc);
-    else
-        K.fill(b.A, c, 0);
-}
-
-__device__ inline void corners_G(const Grid &g, const WBox &w, const Bg64P &b, const Axis &x, const Axis &y,
-                                 const Axis &z, const Cell &c, int r, Corners<2> &K)
-{
-    BCell bc;
-    const bool in = w.on && box_of<1>(g, w, x, y, z, bc);
-    if (__ballot(!in) == 0ull)
-        fill_box(K, WB64_A + r * 9 * WB64_LMAX, bc);
-    else
-        K.fill(b.G, c, r);
 }
 
 // f^2 (or its latitude derivative) between rows: equal, bit for bit, to the
@@ -277,68 +233,67 @@ __device__ inline double gam2_at(const Grid &g, const Bg64P &b, double x, double
     return gam2(b, c);
 }
 
-// Box offsets of the centre's nodes in the 5 x 5 A box ([dy][dx][k] layout):
-// the row and column parts of each node and whether the nodes of each axis
-// lie in the box (faces replace one axis)
+// Offsets of a lookup's nodes from the wave's column and lowest staged level
+// (the box position), and whether they lie in the 5 x 5 A box; faces replace
+// the offsets of one axis
 struct BOff {
-    int ry0, ry1, cx0, cx1, k0, k1;  // (dy + 2) * 5, dx + 2, level - kbase
-    bool inx, iny, inz;
+    int dx0, dx1, dy0, dy1, k0, k1;
 };
 
 __device__ inline void box_offsets(const Grid &g, const WBox &w, const Axis &x, const Axis &y, const Axis &z, BOff &o)
 {
-    const int dx0 = wrapd(x.i0 - w.ic, g.nx), dx1 = wrapd(x.i1 - w.ic, g.nx);
-    int dy0 = y.i0 - w.jc, dy1 = y.i1 - w.jc;
+    o.dx0 = wrapd(x.i0 - w.ic, g.nx);
+    o.dx1 = wrapd(x.i1 - w.ic, g.nx);
+    o.dy0 = y.i0 - w.jc;
+    o.dy1 = y.i1 - w.jc;
     if (g.geometry == RT_CARTESIAN) {
-        dy0 = wrapd(dy0, g.ny);
-        dy1 = wrapd(dy1, g.ny);
+        o.dy0 = wrapd(o.dy0, g.ny);
+        o.dy1 = wrapd(o.dy1, g.ny);
     }
-    o.cx0 = dx0 + 2;
-    o.cx1 = dx1 + 2;
-    o.ry0 = (dy0 + 2) * 5;
-    o.ry1 = (dy1 + 2) * 5;
     o.k0 = z.i0 - w.kbase;
     o.k1 = z.i1 - w.kbase;
-    o.inx = abs(dx0) <= 2 && abs(dx1) <= 2;
-    o.iny = abs(dy0) <= 2 && abs(dy1) <= 2;
-    o.inz = o.k0 >= 0 && o.k1 < w.L;
 }
 
-// the A box cell of a face (AX: the face's axis, a its nodes on that axis);
-// on = 0 when a node of any lane lies outside the box
+// box cell of a lookup in the box of radius RAD (2: A records, 5 x 5 columns;
+// 1: gradient records, 3 x 3); on = 1 when the nodes of every lane of the
+// wave lie in it (wave-uniform)
+template <int RAD>
+__device__ inline BCell box_cell(const WBox &w, const BOff &o)
+{
+    constexpr int side = 2 * RAD + 1;
+    BCell b;
+    b.r00 = mul24((o.dy0 + RAD) * side + (o.dx0 + RAD), w.L);
+    b.r01 = mul24((o.dy0 + RAD) * side + (o.dx1 + RAD), w.L);
+    b.r10 = mul24((o.dy1 + RAD) * side + (o.dx0 + RAD), w.L);
+    b.r11 = mul24((o.dy1 + RAD) * side + (o.dx1 + RAD), w.L);
+    b.k0 = o.k0;
+    b.k1 = o.k1;
+    const bool in = w.on && abs(o.dx0) <= RAD && abs(o.dx1) <= RAD && abs(o.dy0) <= RAD && abs(o.dy1) <= RAD &&
+                    o.k0 >= 0 && o.k1 < w.L;
+    b.on = __ballot(!in) == 0ull ? 1 : 0;
+    return b;
+}
+
+// the A box cell of a face (AX: the face's axis, a its nodes on that axis)
 template <int AX>
 __device__ inline BCell face_box(const Grid &g, const WBox &w, const BOff &o, const Axis &a)
 {
     BOff f = o;
     if (AX == 0) {
-        const int d0 = wrapd(a.i0 - w.ic, g.nx), d1 = wrapd(a.i1 - w.ic, g.nx);
-        f.cx0 = d0 + 2;
-        f.cx1 = d1 + 2;
-        f.inx = abs(d0) <= 2 && abs(d1) <= 2;
+        f.dx0 = wrapd(a.i0 - w.ic, g.nx);
+        f.dx1 = wrapd(a.i1 - w.ic, g.nx);
     } else if (AX == 1) {
-        int d0 = a.i0 - w.jc, d1 = a.i1 - w.jc;
+        f.dy0 = a.i0 - w.jc;
+        f.dy1 = a.i1 - w.jc;
         if (g.geometry == RT_CARTESIAN) {
-            d0 = wrapd(d0, g.ny);
-            d1 = wrapd(d1, g.ny);
+            f.dy0 = wrapd(f.dy0, g.ny);
+            f.dy1 = wrapd(f.dy1, g.ny);
         }
-        f.ry0 = (d0 + 2) * 5;
-        f.ry1 = (d1 + 2) * 5;
-        f.iny = abs(d0) <= 2 && abs(d1) <= 2;
     } else {
         f.k0 = a.i0 - w.kbase;
         f.k1 = a.i1 - w.kbase;
-        f.inz = f.k0 >= 0 && f.k1 < w.L;
     }
-    BCell b;
-    b.r00 = mul24(f.ry0 + f.cx0, w.L);
-    b.r01 = mul24(f.ry0 + f.cx1, w.L);
-    b.r10 = mul24(f.ry1 + f.cx0, w.L);
-    b.r11 = mul24(f.ry1 + f.cx1, w.L);
-    b.k0 = f.k0;
-    b.k1 = f.k1;
-    // a wave-uniform flag in the cell's spare field
-    b.on = (__ballot(!(w.on && f.inx && f.iny && f.inz)) == 0ull) ? 1 : 0;
-    return b;
+    return box_cell<2>(w, f);
 }
 
 // horizontal (AX = 0: U, AX = 1: V) or vertical (AX = 2) group velocity at
@@ -401,6 +356,8 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
     const double m2 = m * m;
     const Axis ax = axis_x(g, x), ay = axis_y(g, y), az = axis_z(g, z);
     const Cell c = cell_of(g, ax, ay, az);
+    BOff bo;
+    box_offsets(g, w, ax, ay, az, bo);
     double4 Gc = make_double4(0.0, 0.0, 0.0, 0.0);
     if (GAM) {
         const Corners<1> KG(b.Gm, c, 0);
@@ -412,46 +369,66 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
     const double M2 = GAM ? m2 + Gc.x : m2;
     const double K2 = kh2 + M2;
     const double K4 = K2 * K2;
-    double4 A0;  // U V N2 Ux
+    // centre: N2 and Ux, the last two components of the A records
+    double N2c, Ux;
     {
-        Corners<1> KA;
-        corners_A(g, w, b, ax, ay, az, c, KA);
-        A0.x = TRI64(KA, x, c);
-        A0.y = TRI64(KA, y, c);
-        A0.z = TRI64(KA, z, c);
-        A0.w = TRI64(KA, w, c);
+        const BCell bc = box_cell<2>(w, bo);
+        double n8[8], u8[8];
+        const double *src = bc.on ? (const double *)wb64_lds : (const double *)b.A;
+        const int rr[4] = {bc.on ? bc.r00 : c.c00, bc.on ? bc.r01 : c.c01, bc.on ? bc.r10 : c.c10,
+                           bc.on ? bc.r11 : c.c11};
+        const int kk0 = bc.on ? bc.k0 : c.k0, kk1 = bc.on ? bc.k1 : c.k1;
+        if (bc.on) {
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const int rec = rr[t & 3] + ((t & 4) ? kk1 : kk0);
+                n8[t] = src[4 * rec + 2];
+                u8[t] = src[4 * rec + 3];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const int64_t rec = rr[t & 3] + ((t & 4) ? kk1 : kk0);
+                n8[t] = src[4 * rec + 2];
+                u8[t] = src[4 * rec + 3];
+            }
+        }
+        N2c = lerp3(n8[0], n8[1], n8[2], n8[3], n8[4], n8[5], n8[6], n8[7], c);
+        Ux = lerp3(u8[0], u8[1], u8[2], u8[3], u8[4], u8[5], u8[6], u8[7], c);
     }
     const double f2c = row_lerp(b.f2, ay);
-    const double om = omega_hat(A0.z, f2c, kh2, M2, K2);
+    const double om = omega_hat(N2c, f2c, kh2, M2, K2);
     const double q = kh2 / ((2.0 * om) * K2);
     const double qf = M2 / ((2.0 * om) * K2);
-    // gradient records one at a time: (Uy Uz Vx Vy) (Vz N2x N2y N2z)
-    const double Ux = A0.w;
-    double Uy = 0, Uz = 0, Vx = 0, Vy = 0, Vz = 0, N2x = 0, N2y = 0, N2z = 0;
-#pragma unroll 1
-    for (int r = 0; r < 2; r++) {
-        Corners<2> KG;
-        corners_G(g, w, b, ax, ay, az, c, r, KG);
-        double4 Gr;
-        Gr.x = TRI64(KG, x, c);
-        Gr.y = TRI64(KG, y, c);
-        Gr.z = TRI64(KG, z, c);
-        Gr.w = TRI64(KG, w, c);
-        Uy = r == 0 ? Gr.x : Uy;
-        Uz = r == 0 ? Gr.y : Uz;
-        Vx = r == 0 ? Gr.z : Vx;
-        Vy = r == 0 ? Gr.w : Vy;
-        Vz = r == 1 ? Gr.x : Vz;
-        N2x = r == 1 ? Gr.y : N2x;
-        N2y = r == 1 ? Gr.z : N2y;
-        N2z = r == 1 ? Gr.w : N2z;
-    }
     const double f2y = row_lerp(b.f2y, ay);
-    double gk = (k * Ux + l * Vx) + q * N2x;
-    double gl = ((k * Uy + l * Vy) + q * N2y) + qf * f2y;
-    double gm = (k * Uz + l * Vz) + q * N2z;
+    // gradient records one at a time, (Uy Uz Vx Vy) then (Vz N2x N2y N2z),
+    // each folded into the refraction sums as soon as it is complete
+    double gk = 0.0, gl = 0.0, gm = 0.0;
+    {
+        const BCell bg = box_cell<1>(w, bo);
+        double gk0 = 0.0, gl0 = 0.0, kUz = 0.0;
+#pragma unroll 1
+        for (int r = 0; r < 2; r++) {
+            Corners<2> KG;
+            if (bg.on)
+                fill_box(KG, WB64_A + r * 9 * WB64_LMAX, bg);
+            else
+                KG.fill(b.G, c, r);
+            const double4 Gr =
+                make_double4(TRI64(KG, x, c), TRI64(KG, y, c), TRI64(KG, z, c), TRI64(KG, w, c));
+            if (r == 0) {
+                gk0 = k * Ux + l * Gr.z;     // k Ux + l Vx
+                gl0 = k * Gr.x + l * Gr.w;   // k Uy + l Vy
+                kUz = k * Gr.y;
+            } else {
+                gk = gk0 + q * Gr.y;                  // + q N2x
+                gl = (gl0 + q * Gr.z) + qf * f2y;     // + q N2y + qf (f2)_y
+                gm = (kUz + l * Gr.x) + q * Gr.w;     // k Uz + l Vz + q N2z
+            }
+        }
+    }
     if (GAM) {
-        const double qg = -((kh2 * (A0.z - f2c)) / (((2.0 * om) * K2) * K2));
+        const double qg = -((kh2 * (N2c - f2c)) / (((2.0 * om) * K2) * K2));
         gk = gk + qg * Gc.y;
         gl = gl + qg * Gc.z;
         gm = gm + qg * Gc.w;
@@ -463,8 +440,6 @@ __device__ inline void rhs(const Grid &g, const Bg64P &b, const double *Y, doubl
     // are kept
     const int X0 = mul24(ax.i0, g.nz), X1 = mul24(ax.i1, g.nz);  // x nodes, in cells
     const int R0 = c.c00 - X0, R1 = c.c10 - X0;                    // y rows, in cells
-    BOff bo;
-    box_offsets(g, w, ax, ay, az, bo);
     double cxp = 0.0, cxm = 0.0, cyp = 0.0, cym = 0.0, czp = 0.0, czm = 0.0;
 #pragma unroll 1
     for (int sd = 0; sd < 2; sd++) {
