@@ -292,6 +292,37 @@ def test_load_order(rt, orc, prec):
     assert np.array_equal(tr.get_columns(), np.sort(rs["col"]))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_regrouping_is_the_stable_sort_of_the_previous_order(rt, prec):
+    """Each step's regrouping is the stable sort of the previous sorted order
+    by the new column key (by column and level on every fourth), over a set
+    of several radix tiles with columns changing and volumes removed: the
+    step and the level-key pass count the first radix pass's digits as they
+    write the keys, and each pass counts the next one's as it scatters."""
+    w = c3_small(60_000)
+    tr = gpu_tracer(w, rt.RT_FP64 if prec == "fp64" else rt.RT_FP32)
+    prev = np.asarray(tr.get_rays()["id"])
+    moved = 0
+    for s in range(1, 10):
+        tr.step(w.dt * 40)
+        g = tr.get_rays()
+        ids = np.asarray(g["id"])
+        cols = tr.get_columns().astype(np.int64)
+        where = {int(v): j for j, v in enumerate(prev)}
+        pos = np.array([where[int(v)] for v in ids])
+        if s % 4 == 0:
+            lev = np.clip(np.floor(np.asarray(g["z"]) / w.dz), 0, w.nz).astype(np.int64)
+            key = cols * (w.nz + 1) + lev
+        else:
+            key = cols
+        expect = np.lexsort((pos, key))
+        assert np.array_equal(ids, ids[expect]), s
+        moved += int(np.count_nonzero(np.diff(pos) < 0))
+        prev = ids
+    assert moved > 0, "no volume changed its place (the test checks nothing)"
+    tr.close()
+
+
 def test_api_errors(rt):
     w = W.make_c1(n_rays=10)
     tr = rt.Tracer.for_workload(w, rt.RT_FP64, capacity=10)
