@@ -267,6 +267,11 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
             ALLOC(s.lev, int32_t, cap);
             ALLOC(s.W, double, cap);
             ALLOC(s.id, int64_t, cap);
+            float *c;
+            ALLOC(c, float, 3 * cap);
+            s.cn2 = c;
+            s.cf2 = c + cap;
+            s.cg2 = c + 2 * cap;
         }
         ALLOC(ctx->key[buf], uint32_t, cap);
     }
@@ -403,6 +408,7 @@ extern "C" rt_status rt_init_background(rt_ctx ctx, const double *U, const doubl
     HIP_OK(hipGetLastError());
     if (where == RT_HOST) HIP_OK(hipStreamSynchronize(ctx->stream));
     ctx->have_bg = true;
+    ctx->car_ok = false;  // the carrier background is that of the old fields
     return RT_OK;
 }
 
@@ -445,6 +451,7 @@ extern "C" rt_status rt_set_scale_height(rt_ctx ctx, const double *G2, int32_t w
     if (!G2) {
         ctx->bp64.Gm = nullptr;
         ctx->bp32.Gm = nullptr;
+        ctx->car_ok = false;
         return RT_OK;
     }
     if (where != RT_HOST && where != RT_DEVICE) return rt_fail(ctx, RT_E_ARG, "bad 'where'");
@@ -471,6 +478,7 @@ extern "C" rt_status rt_set_scale_height(rt_ctx ctx, const double *G2, int32_t w
     if (where == RT_HOST) HIP_OK(hipStreamSynchronize(ctx->stream));
     ctx->bp64.Gm = ctx->gm64;
     ctx->bp32.Gm = ctx->gm32;
+    ctx->car_ok = false;
     return RT_OK;
 }
 
@@ -519,6 +527,7 @@ extern "C" rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int
         unstage(ctx, staged);
     }
     ctx->have_rays = true;
+    ctx->car_ok = false;  // loaded volumes carry no carrier background
     return RT_OK;
 }
 
@@ -545,6 +554,8 @@ extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
     prof_end(ctx);
     launch_sorted_from_active(ctx->dc, ctx->stream);
     ctx->cur = nxt;
+    // the single-precision step wrote the carrier background of the state it produced
+    ctx->car_ok = ctx->precision == RT_FP32;
     rt_status st = sort_current(ctx);
     if (st) return st;
     if (flags & RT_STEP_SATURATE) {
@@ -636,7 +647,7 @@ extern "C" rt_status rt_deposit_flux(rt_ctx ctx, double *flux, double *drag, int
     if (ctx->precision == RT_FP64)
         launch_deposit64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
     else
-        launch_deposit32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
+        launch_deposit32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->car_ok, ctx->stream);
     prof_end(ctx);
     prof_begin(ctx, PC_DRAG);
     launch_drag(g, ctx->rho, ctx->coslat, fdst, ddst, ctx->stream);
@@ -872,11 +883,13 @@ extern "C" rt_status rt_split_merge(rt_ctx ctx, double alpha_split, int32_t n_ma
     if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
     if (mode != RT_MERGE && mode != RT_CAP && mode != RT_SPLIT_ONLY) return rt_fail(ctx, RT_E_ARG, "bad mode");
     if (mode != RT_SPLIT_ONLY && n_max_per_cell < 1) return rt_fail(ctx, RT_E_ARG, "n_max_per_cell must be >= 1");
+    ctx->car_ok = false;  // split pieces and merged volumes sit elsewhere
     return do_split_merge(ctx, alpha_split, n_max_per_cell, mode, out);
 }
 
 extern "C" rt_status rt_launch(rt_ctx ctx, const rt_launch_params *p, int64_t *n_launched)
 {
+    if (ctx) ctx->car_ok = false;  // launched volumes carry no carrier background
     if (!ctx) return RT_E_ARG;
     if (n_launched) *n_launched = 0;
     if (!ctx->have_bg || !ctx->have_rays) return rt_fail(ctx, RT_E_STATE, "background and rays are required");
@@ -1023,5 +1036,6 @@ extern "C" rt_status rt_set_rays_host_noalloc(rt_ctx ctx, const rt_rays *rays, i
     if (st) return st;
     HIP_OK(hipStreamSynchronize(ctx->stream));
     ctx->have_rays = true;
+    ctx->car_ok = false;  // loaded volumes carry no carrier background
     return RT_OK;
 }

@@ -567,6 +567,34 @@ __device__ inline void rhs_box(const G32 &g, int kc, float2 lat, const float *Y,
     assemble<SPH>(g, kc, lat, Y, gk, gl, gm, sx, hx, sy, hy, szs, hz, F);
 }
 
+// N^2 and f^2 at a volume's carrier (base cell ic, jc, kc and offsets in
+// cell and level units): from the wave's stencil box when every lane's nodes
+// lie in it (a volume that moved to a neighbouring column included), else
+// from global memory.  The box holds the wrapped columns and the clamped
+// rows (interpolating between two equal clamped rows returns that row), and
+// a clamped level has weight 0 in both forms; the two forms may still round
+// differently by an ulp where the compiler contracts them differently.
+__device__ inline void n2_f2_carrier(const G32 &g, const Bg32P &b, const WBox &w, int ic, int jc, int kc, float xi,
+                                     float eta, float zeta, float &N2, float &f2)
+{
+    constexpr int SA = 5 * WB_LMAX;
+    Cell c;
+    int sz;
+    int dy0 = jc - w.jc;
+    if (g.geometry == RT_CARTESIAN) dy0 = wrapd(dy0, g.ny);
+    const int dx = wrapd(ic - w.ic, g.nx) + bnode(xi - 0.5f, c.wx), dy = dy0 + bnode(eta - 0.5f, c.wy);
+    const int kb = blev(g, w, kc, zeta - 0.5f, sz, c.wz);
+    const bool in = w.on && dx >= -2 && dx <= 1 && dy >= -2 && dy <= 1 && kb >= 0 && kb + sz < w.L;
+    if (__ballot(!in) == 0ull) {
+        Corners<1> K;
+        box_corners(K, (dy + 2) * SA + (dx + 2) * WB_LMAX + kb, WB_LMAX, SA, sz);
+        N2 = TRI_COMP(K, z, c);
+        f2 = box_row(dy + 2, c.wy, 0);
+    } else {
+        n2_f2(g, b, ic, jc, kc, xi, eta, zeta, N2, f2);
+    }
+}
+
 // RK stage right-hand side in cell units: Y = (xi, eta, zeta, k, l, m, Dxi,
 // Deta, Dz), offsets relative to the base cell (ic, jc, kc), Dz in metres.
 // Centre: 12 fields from three records per corner (U V N2 Ux | Uy Uz Vx Vy |

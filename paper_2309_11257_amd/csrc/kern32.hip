@@ -199,7 +199,9 @@ void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double 
 // and the flux densities in double
 // ---------------------------------------------------------------------------
 // GAM: with the scale-height correction (a separate instantiation)
-template <bool GAM>
+// CAR: N^2, f^2 (and Gamma^2) at the carrier from the state's carrier arrays
+// (written by the step that produced the state) instead of interpolated here
+template <bool GAM, bool CAR = false>
 struct Pay32 {
     G32 g;
     Bg32P b;
@@ -217,12 +219,19 @@ struct Pay32 {
         const float zeta = st.zeta[s];
         const float k = st.k[s], l = st.l[s], m = (float)st.m[s];
         const float Dz = st.dz[s];
-        float N2, f2;
-        f32::n2_f2(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta, N2, f2);
+        float N2, f2, G2 = 0.0f;
+        if (CAR) {
+            N2 = st.cn2[s];
+            f2 = st.cf2[s];
+            if (GAM) G2 = st.cg2[s];
+        } else {
+            f32::n2_f2(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta, N2, f2);
+            if (GAM) G2 = f32::gam2_at(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta);
+        }
         // group velocity as in the step: one-rounding reciprocal and
         // reciprocal square root
         const float kh2 = k * k + l * l;
-        const float M2 = m * m + (GAM ? f32::gam2_at(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta) : 0.0f);
+        const float M2 = m * m + G2;
         const float invK2 = f32::rcp(kh2 + M2);
         const float rom = f32::rsq((N2 * kh2 + f2 * M2) * invK2);  // 1 / omega_hat
         const float sc = (N2 - f2) * (invK2 * invK2) * rom;
@@ -272,16 +281,23 @@ struct Pay32 {
     }
 };
 
-void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
-                      double *flux, hipStream_t s)
+template <bool GAM, bool CAR>
+static void deposit32_with(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+                           double *flux, hipStream_t s)
 {
-    if (b.Gm) {
-        Pay32<true> p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
-        launch_deposit_k(g, p, perm, colstart, flux, s);
-    } else {
-        Pay32<false> p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
-        launch_deposit_k(g, p, perm, colstart, flux, s);
-    }
+    Pay32<GAM, CAR> p{f32::make_g32(g), b, st, g.dz, 1.0 / g.dz};
+    launch_deposit_k(g, p, perm, colstart, flux, s);
+}
+
+void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
+                      double *flux, bool car, hipStream_t s)
+{
+    if (b.Gm)
+        car ? deposit32_with<true, true>(g, b, st, perm, colstart, flux, s)
+            : deposit32_with<true, false>(g, b, st, perm, colstart, flux, s);
+    else
+        car ? deposit32_with<false, true>(g, b, st, perm, colstart, flux, s)
+            : deposit32_with<false, false>(g, b, st, perm, colstart, flux, s);
 }
 
 void launch_features32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,

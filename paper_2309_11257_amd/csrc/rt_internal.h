@@ -68,6 +68,9 @@ struct S32 {
     double *m;
     double *W;
     int64_t *id;
+    // N^2, f^2 and Gamma^2 at the carrier, written by the step that produced
+    // the state (the deposition's background; valid while ctx->car_ok)
+    float *cn2, *cf2, *cg2;
 };
 
 // device-side counters (one instance per context)
@@ -109,6 +112,7 @@ struct rt_ctx_s {
     int64_t cap;
     int64_t n_bound;  // host-side upper bound of active count (the device holds the exact one)
     bool have_rays;
+    bool car_ok;  // single precision: the current buffer's carrier background is that of its state (set by rt_step)
     // sorted view of the current buffer
     uint32_t *perm, *skeys;
     uint32_t *colstart;  // [ncol + 1]
@@ -278,8 +282,10 @@ void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double 
 
 void launch_deposit64(const Grid &g, const Bg64P &b, S64 st, const uint32_t *perm, const uint32_t *colstart,
                       double *flux, hipStream_t s);
+// car: take N^2, f^2 (and Gamma^2) at the carrier from the state's carrier
+// arrays instead of interpolating them
 void launch_deposit32(const Grid &g, const Bg32P &b, S32 st, const uint32_t *perm, const uint32_t *colstart,
-                      double *flux, hipStream_t s);
+                      double *flux, bool car, hipStream_t s);
 void launch_drag(const Grid &g, const double *rho, const double *cosr, const double *flux, double *drag, hipStream_t s);
 void launch_coslat(const Grid &g, double *cosr, hipStream_t s);
 // full fluxes [8][nz+1][ncol], budget fields [4][nz+1][ncol], smoothing of

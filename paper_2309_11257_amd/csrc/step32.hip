@@ -220,6 +220,14 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
                 key = (uint32_t)(jc * g.nx + ic);
         }
     }
+    // the carrier background of the new state, for the deposition
+    if (key < (uint32_t)g.ncol) {
+        float cn2, cf2;
+        f32::n2_f2_carrier(g, b, w, ic, jc, kc, Y[0], Y[1], Y[2], cn2, cf2);
+        f32::put(dst.cn2, i, cn2);
+        f32::put(dst.cf2, i, cf2);
+        if (GAM) f32::put(dst.cg2, i, f32::gam2_at(g, b, ic, jc, kc, Y[0], Y[1], Y[2]));
+    }
     f32::put(dst.col, i, (uint32_t)(jc * g.nx + ic));
     f32::put(dst.lev, i, kc);
     f32::put(dst.xi, i, Y[0]);
