@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "rt_internal.h"
+#include <utility>
 
 rt_status rt_fail(rt_ctx c, rt_status s, const char *fmt, ...)
 {
@@ -282,6 +283,25 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     ctx->hist_len = radix_hist_len(cap);
     ALLOC(ctx->hist, uint32_t, ctx->hist_len);
     ALLOC(ctx->colstart, uint32_t, (int64_t)g.ncol + 1);
+    ALLOC(ctx->colstart_b, uint32_t, (int64_t)g.ncol + 1);
+    ALLOC(ctx->skeys_b, uint32_t, cap);
+    {
+        const int64_t nt = regroup_tiles(cap);
+        uint32_t *r;
+        ALLOC(r, uint32_t, 7 * (int64_t)g.ncol + 1 + (1 + RK_NREASON) * nt);
+        RegroupBufs &rb = ctx->rg;
+        rb.inc = r;
+        rb.inlow = r + g.ncol;
+        rb.outc = r + 2 * (int64_t)g.ncol;
+        rb.mfill = r + 3 * (int64_t)g.ncol;
+        rb.mstart = r + 4 * (int64_t)g.ncol;
+        rb.lpc = r + 5 * (int64_t)g.ncol;
+        rb.cnew = r + 6 * (int64_t)g.ncol;
+        rb.tmv = rb.cnew + g.ncol + 1;
+        rb.rtc = rb.tmv + nt;
+        ALLOC(rb.mbuf, uint32_t, cap);
+        ALLOC(rb.scratch, uint32_t, regroup_scratch_words(cap, g.ncol));
+    }
     if (cfg->precision == RT_FP32) ALLOC(ctx->wcol, uint32_t, wave_table_len(cap, g.ncol));
     ALLOC(ctx->flux, double, (int64_t)6 * (g.nz + 1) * g.ncol);
     ALLOC(ctx->drag, double, 2 * cells);
@@ -295,7 +315,8 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     ALLOC(ctx->ired, int64_t, 8 + 2 * cap);
     ALLOC(ctx->sm, uint32_t, 8 * cap + 16 + scan_tmp_len(cap));
     if (hipMemsetAsync(ctx->dc, 0, sizeof(DevCounters), ctx->stream) != hipSuccess ||
-        hipMemsetAsync(ctx->colstart, 0, sizeof(uint32_t) * ((size_t)g.ncol + 1), ctx->stream) != hipSuccess) {
+        hipMemsetAsync(ctx->colstart, 0, sizeof(uint32_t) * ((size_t)g.ncol + 1), ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->rg.inc, 0, sizeof(uint32_t) * 4 * (size_t)g.ncol, ctx->stream) != hipSuccess) {
         ctx_release(ctx);
         delete ctx;
         return RT_E_DEVICE;
@@ -339,7 +360,12 @@ static int bits_of(uint64_t maxkey)
 // turned back into column keys); the column sorts in between are stable, so
 // the level order persists except for volumes that moved.  The step's waves
 // then span few levels and share one stencil box.
-static rt_status sort_current(rt_ctx ctx)
+//
+// after_step: the keys were written by the step at the positions of the
+// previous regrouping, whose sorted keys and offsets are still current; a
+// column sort is then the regrouping that moves only the volumes that
+// changed column (the same permutation as the radix sort)
+static rt_status sort_current(rt_ctx ctx, bool after_step = false)
 {
     const int64_t bound = ctx->n_bound;
     const uint64_t nl = (uint64_t)ctx->g.nz + 1;
@@ -348,6 +374,19 @@ static rt_status sort_current(rt_ctx ctx)
                        ctx->n_sorts % LEVEL_REFINE_EVERY == 0;
     ctx->n_sorts++;
     prof_begin(ctx, PC_SORT);
+    if (after_step && !bylev) {
+        regroup_after_step(ctx->key[ctx->cur], ctx->skeys, ctx->colstart, &ctx->dc->n_sorted, bound, ctx->g.ncol,
+                           ctx->rg, ctx->perm, ctx->skeys_b, ctx->colstart_b, ctx->wcol, ctx->dc, ctx->stream);
+        std::swap(ctx->skeys, ctx->skeys_b);
+        std::swap(ctx->colstart, ctx->colstart_b);
+        if (ctx->precision == RT_FP64)
+            launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
+        else
+            launch_tally32(ctx->g, ctx->s32[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
+        prof_end(ctx);
+        HIP_OK(hipGetLastError());
+        return RT_OK;
+    }
     if (bylev) {
         if (ctx->precision == RT_FP64)
             launch_levkey64(ctx->g, ctx->s64[ctx->cur], ctx->key[ctx->cur], ctx->dc, bound, ctx->stream);
@@ -556,7 +595,7 @@ extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
     ctx->cur = nxt;
     // the single-precision step wrote the carrier background of the state it produced
     ctx->car_ok = ctx->precision == RT_FP32;
-    rt_status st = sort_current(ctx);
+    rt_status st = sort_current(ctx, true);
     if (st) return st;
     if (flags & RT_STEP_SATURATE) {
         st = rt_saturate(ctx, dt, nullptr, RT_DEVICE);

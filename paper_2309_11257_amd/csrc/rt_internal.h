@@ -89,6 +89,17 @@ struct DevCounters {
                          // last report (the largest complement), 0 if none
 };
 
+// Scratch of the regrouping after a step (sort.hip): per-column counters
+// (zero between regroupings), offsets, per-tile counts and arrival buckets
+struct RegroupBufs {
+    uint32_t *inc, *inlow, *outc, *mfill, *mstart, *lpc;  // [ncol]
+    uint32_t *cnew;                                       // [ncol + 1]
+    uint32_t *tmv;                                        // [tiles] changed keys per tile, then their prefix
+    uint32_t *rtc;                                        // [RK_NREASON][tiles] removed per tile, then prefix
+    uint32_t *mbuf;                                       // [capacity] arrivals, by destination column
+    uint32_t *scratch;                                    // [regroup_scratch_words] (8-byte aligned)
+};
+
 struct rt_ctx_s {
     rt_config cfg;
     Grid g;
@@ -120,6 +131,10 @@ struct rt_ctx_s {
     // sort scratch
     uint32_t *tk, *tv, *hist;
     int64_t hist_len;
+    // regrouping after a step: second sorted-key and offset arrays (swapped
+    // with skeys / colstart) and scratch
+    uint32_t *skeys_b, *colstart_b;
+    RegroupBufs rg;
     // flux scratch
     double *flux, *drag;
     // saturation: level sums P and sum P_j K_j^2 [2][nz+1][ncol], kappa [nz][ncol]
@@ -263,6 +278,16 @@ void radix_sort(const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out, 
                 uint32_t *tk, uint32_t *tv, uint32_t *hist, const int64_t *n_dev, int64_t bound, int nbits,
                 hipStream_t s);
 int64_t radix_hist_len(int64_t bound);
+
+// The stable sort by column of keys written at the positions of the previous
+// regrouping (sk_old, cs_old: its sorted keys and column offsets), for at
+// most bound keys (n_dev on the device): perm, sk_new, cs_new (and wcol,
+// nullable) as the radix sort and launch_colstart give them; dc->n_active set
+void regroup_after_step(const uint32_t *key, const uint32_t *sk_old, const uint32_t *cs_old, const int64_t *n_dev,
+                        int64_t bound, int ncol, RegroupBufs rb, uint32_t *perm, uint32_t *sk_new, uint32_t *cs_new,
+                        uint32_t *wcol, DevCounters *dc, hipStream_t s);
+int64_t regroup_tiles(int64_t bound);
+int64_t regroup_scratch_words(int64_t cap, int ncol);
 // in-place exclusive scan of t[0..len) (parts: scan_tmp_len(len) scratch)
 void scan_u32(uint32_t *t, int64_t len, uint32_t *parts, hipStream_t s);
 int64_t scan_tmp_len(int64_t len);

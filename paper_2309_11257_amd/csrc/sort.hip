@@ -13,7 +13,9 @@
 
 #define RS_THREADS 256
 #define RS_ITEMS 16
+#define RS_TILE_SHIFT 12
 #define RS_TILE (RS_THREADS * RS_ITEMS)
+static_assert(RS_TILE == (1 << RS_TILE_SHIFT), "tile size");
 #define SCAN_CHUNK 4096
 
 static int64_t rs_blocks(int64_t bound) { return bound > 0 ? (bound + RS_TILE - 1) / RS_TILE : 1; }
@@ -327,4 +329,377 @@ __global__ void k_copy_n(const uint32_t *src, uint32_t *dst, const DevCounters *
 void launch_copy_n(const uint32_t *src, uint32_t *dst, const DevCounters *dc, int64_t bound, hipStream_t s)
 {
     if (bound > 0) k_copy_n<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(src, dst, dc);
+}
+
+// ---------------------------------------------------------------------------
+// Regrouping after a step.  The step writes each volume's new key at the
+// volume's position in the previous regrouping, so the keys arrive in that
+// order, and the stable sort by the new key is known in advance for all but
+// the few volumes whose key changed: in each column the stayers (new key =
+// previous column) keep their previous order, preceded by the volumes that
+// moved in from earlier positions and followed by those that moved in from
+// later ones (each group by position); removed volumes follow all columns,
+// by reason and then position.  Stayers and removed volumes are placed by
+// counting (tile prefix sums of the volumes that changed key), the volumes
+// that changed column by a sort of each column's few arrivals.  The result
+// is the permutation the radix sort produces.
+
+// Per-tile counting in thread order: a tile's RS_ITEMS rounds of RS_THREADS
+// positions (round-major, position base + round * RS_THREADS + thread); each
+// wave's ballot count of a flag per round goes to LDS cnt[round][wave], after
+// which a lane's exclusive prefix over the tile in position order is
+// tile_prefix(): earlier rounds whole, then earlier waves of its round, then
+// its lower lanes.
+__device__ inline uint32_t tile_prefix(const uint32_t (*cnt)[4], int it, unsigned long long ball)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t pre = (uint32_t)__popcll(ball & ((1ull << lane) - 1ull));
+    for (int r = 0; r < it; r++) pre += cnt[r][0] + cnt[r][1] + cnt[r][2] + cnt[r][3];
+    for (int w = 0; w < wave; w++) pre += cnt[it][w];
+    return pre;
+}
+
+// counts: volumes leaving each column, arriving in each column (and those
+// arriving from earlier positions), changed keys per tile, removed volumes
+// per tile and reason, and the tile prefix of changed keys at each column's
+// first position
+__global__ __launch_bounds__(RS_THREADS) void k_rg_classify(const uint32_t *__restrict__ key,
+                                                            const uint32_t *__restrict__ sk_old,
+                                                            const uint32_t *__restrict__ cs_old,
+                                                            const int64_t *n_dev, uint32_t ncol, int64_t nb,
+                                                            RegroupBufs rb)
+{
+    __shared__ uint32_t cnt[RS_ITEMS][4];
+    __shared__ uint32_t rc[RK_NREASON];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < RK_NREASON) rc[tid] = 0u;
+    const int64_t n = *n_dev;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    // every round's keys in flight at once: new key, previous key, and the
+    // previous key of the position before (a column's first position)
+    uint32_t kt[RS_ITEMS], ot[RS_ITEMS], pt[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; it++) {
+        const int64_t p = base + (int64_t)it * RS_THREADS + tid;
+        kt[it] = p < n ? key[p] : 0u;
+        ot[it] = p < n ? sk_old[p] : 0u;
+        pt[it] = (p < n && p > 0) ? sk_old[p - 1] : 0xffffffffu;
+    }
+    unsigned long long bl[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; it++) {
+        const int64_t p = base + (int64_t)it * RS_THREADS + tid;
+        bl[it] = __ballot(p < n && kt[it] != ot[it]);
+        if (lane == 0) cnt[it][wave] = (uint32_t)__popcll(bl[it]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; it++) {
+        const int64_t p = base + (int64_t)it * RS_THREADS + tid;
+        if (p >= n) continue;
+        const uint32_t k = kt[it], o = ot[it];
+        if (o != pt[it]) rb.lpc[o] = tile_prefix(cnt, it, bl[it]);
+        if (k != o) {
+            atomicAdd(&rb.outc[o], 1u);
+            if (k < ncol) {
+                atomicAdd(&rb.inc[k], 1u);
+                if ((uint32_t)p < cs_old[k]) atomicAdd(&rb.inlow[k], 1u);
+            } else {
+                atomicAdd(&rc[k - ncol], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (int r = 0; r < RS_ITEMS; r++) t += cnt[r][0] + cnt[r][1] + cnt[r][2] + cnt[r][3];
+        rb.tmv[blockIdx.x] = t;
+    }
+    if (tid < RK_NREASON) rb.rtc[(int64_t)tid * nb + blockIdx.x] = rc[tid];
+}
+
+// Exclusive scans of three sequences in one pair of launches, in chunks of
+// RG_CHUNK values: the columns' (new count, arrivals) packed in one word
+// (both sums stay below 2^32) -> (column offset, arrival bucket offset); the
+// changed keys per tile; the removed volumes per tile, reason-major.  The
+// first launch sums each chunk, the second adds the sums of the chunks
+// before it (a few dozen) and scans its own.
+#define RG_CHUNK 4096
+struct RgScan {
+    const uint32_t *cs_old;
+    uint32_t ncol;
+    int64_t nb;
+    RegroupBufs rb;
+    int64_t b1, b2;  // first chunk of the tile and removed sequences
+    __device__ int64_t seg_len(int sg) const { return sg == 0 ? ncol : (sg == 1 ? nb : RK_NREASON * nb); }
+    __device__ uint64_t get(int sg, int64_t i) const
+    {
+        if (sg == 0) {
+            const uint32_t stay = (cs_old[i + 1] - cs_old[i]) - rb.outc[i];
+            return ((uint64_t)(stay + rb.inc[i]) << 32) | (uint64_t)rb.inc[i];
+        }
+        return sg == 1 ? rb.tmv[i] : rb.rtc[i];
+    }
+    __device__ void put(int sg, int64_t i, uint64_t v) const
+    {
+        if (sg == 0) {
+            rb.cnew[i] = (uint32_t)(v >> 32);
+            rb.mstart[i] = (uint32_t)v;
+        } else if (sg == 1) {
+            rb.tmv[i] = (uint32_t)v;
+        } else {
+            rb.rtc[i] = (uint32_t)v;
+        }
+    }
+    __device__ void locate(int64_t b, int &sg, int64_t &c0, int64_t &first) const
+    {
+        sg = b < b1 ? 0 : (b < b2 ? 1 : 2);
+        first = sg == 0 ? 0 : (sg == 1 ? b1 : b2);
+        c0 = (b - first) * RG_CHUNK;
+    }
+};
+
+__global__ __launch_bounds__(256) void k_rg_sreduce(RgScan sc, uint64_t *btot)
+{
+    __shared__ uint64_t sh[256];
+    int sg;
+    int64_t c0, first;
+    sc.locate(blockIdx.x, sg, c0, first);
+    const int64_t len = sc.seg_len(sg);
+    uint64_t s = 0;
+    for (int q = threadIdx.x; q < RG_CHUNK; q += 256)
+        if (c0 + q < len) s += sc.get(sg, c0 + q);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) btot[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_rg_sapply(RgScan sc, const uint64_t *__restrict__ btot, DevCounters *dc)
+{
+    __shared__ uint64_t sh[256];
+    int sg;
+    int64_t c0, first;
+    sc.locate(blockIdx.x, sg, c0, first);
+    const int64_t len = sc.seg_len(sg);
+    const int tid = threadIdx.x;
+    uint64_t pre = 0;
+    for (int64_t b = first; b < (int64_t)blockIdx.x; b++) pre += btot[b];
+    // 16 consecutive values a thread
+    constexpr int PER = RG_CHUNK / 256;
+    uint64_t v[PER];
+    uint64_t s = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int64_t i = c0 + (int64_t)tid * PER + q;
+        v[q] = i < len ? sc.get(sg, i) : 0ull;
+        s += v[q];
+    }
+    sh[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint64_t t = tid >= off ? sh[tid - off] : 0ull;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    uint64_t run = pre + sh[tid] - s;
+    const uint64_t chunk_total = sh[255];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int64_t i = c0 + (int64_t)tid * PER + q;
+        if (i < len) sc.put(sg, i, run);
+        run += v[q];
+    }
+    // the last column chunk ends the column sequence: the active count
+    if (sg == 0 && tid == 0 && c0 + RG_CHUNK >= len) {
+        const uint32_t tot = (uint32_t)((pre + chunk_total) >> 32);
+        sc.rb.cnew[sc.ncol] = tot;
+        dc->n_active = (int64_t)tot;
+    }
+}
+
+// per column: where its first stayer goes, less that stayer's count of
+// changed keys before it (so that a stayer at p goes to base + p - (changed
+// keys before p)); the leaving counts are cleared for the next regrouping
+__global__ void k_rg_base(const uint32_t *__restrict__ cs_old, uint32_t ncol, RegroupBufs rb, uint32_t *base)
+{
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    const uint32_t x = cs_old[c];
+    uint32_t bs = 0;
+    if (cs_old[c + 1] > x) bs = rb.cnew[c] + rb.inlow[c] - x + rb.tmv[x >> RS_TILE_SHIFT] + rb.lpc[c];
+    base[c] = bs;
+    rb.outc[c] = 0u;
+}
+
+// stayers and removed volumes to their places, arrivals into their column's
+// bucket (in no particular order)
+__global__ __launch_bounds__(RS_THREADS) void k_rg_place(const uint32_t *__restrict__ key,
+                                                         const uint32_t *__restrict__ sk_old,
+                                                         const uint32_t *__restrict__ cbase,
+                                                         const int64_t *n_dev, uint32_t ncol, int64_t nb,
+                                                         RegroupBufs rb, uint32_t *__restrict__ perm,
+                                                         uint32_t *__restrict__ sk_new)
+{
+    __shared__ uint32_t cnt[RS_ITEMS][4];
+    __shared__ uint32_t rcnt[RK_NREASON][RS_ITEMS][4];
+    __shared__ int anyrem;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) anyrem = 0;
+    const int64_t n = *n_dev;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const uint32_t tpre = rb.tmv[blockIdx.x];  // changed keys before this tile
+    uint32_t kt[RS_ITEMS], ot[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; it++) {
+        const int64_t p = base + (int64_t)it * RS_THREADS + tid;
+        kt[it] = p < n ? key[p] : 0u;
+        ot[it] = p < n ? sk_old[p] : 0u;
+    }
+    uint32_t bt[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; it++) bt[it] = cbase[ot[it]];
+    unsigned long long bl[RS_ITEMS];
+    bool rem_here = false;
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; it++) {
+        const int64_t p = base + (int64_t)it * RS_THREADS + tid;
+        bl[it] = __ballot(p < n && kt[it] != ot[it]);
+        if (lane == 0) cnt[it][wave] = (uint32_t)__popcll(bl[it]);
+        rem_here = rem_here || (p < n && kt[it] >= ncol);
+    }
+    if (__ballot(rem_here) != 0ull && lane == 0) anyrem = 1;
+    __syncthreads();
+    const bool rem_tile = anyrem != 0;
+    if (rem_tile) {
+        // removed volumes per reason, round and wave
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; it++) {
+            const int64_t p = base + (int64_t)it * RS_THREADS + tid;
+            for (int r = 0; r < RK_NREASON; r++) {
+                const unsigned long long bm = __ballot(p < n && kt[it] == ncol + (uint32_t)r);
+                if (lane == 0) rcnt[r][it][wave] = (uint32_t)__popcll(bm);
+            }
+        }
+        __syncthreads();
+    }
+    const uint32_t nact = rb.cnew[ncol];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; it++) {
+        const int64_t p = base + (int64_t)it * RS_THREADS + tid;
+        if (p >= n) continue;
+        const uint32_t k = kt[it], o = ot[it];
+        if (k == o) {
+            const uint32_t q = bt[it] + (uint32_t)p - (tpre + tile_prefix(cnt, it, bl[it]));
+            perm[q] = (uint32_t)p;
+            sk_new[q] = o;
+        } else if (k < ncol) {
+            const uint32_t slot = atomicAdd(&rb.mfill[k], 1u);
+            rb.mbuf[rb.mstart[k] + slot] = (uint32_t)p;
+        } else {
+            // removed: after the active volumes, by reason, then position
+            // (the lanes here are this round's removed volumes of the wave)
+            const uint32_t r = k - ncol;
+            const unsigned long long below = (1ull << lane) - 1ull;
+            uint32_t q = 0;
+            for (int rr = 0; rr < RK_NREASON; rr++) {
+                const unsigned long long bm = __ballot(r == (uint32_t)rr);
+                if (r == (uint32_t)rr) q = (uint32_t)__popcll(bm & below);
+            }
+            q += nact + rb.rtc[(int64_t)r * nb + blockIdx.x];
+            for (int rr = 0; rr < it; rr++) q += rcnt[r][rr][0] + rcnt[r][rr][1] + rcnt[r][rr][2] + rcnt[r][rr][3];
+            for (int w = 0; w < wave; w++) q += rcnt[r][it][w];
+            perm[q] = (uint32_t)p;
+            sk_new[q] = k;
+        }
+    }
+}
+
+// each column's arrivals by position (low ones before its stayers, high ones
+// after), its offset and its waves in the single-precision wave table; one
+// wave per column, the counters cleared for the next regrouping
+__global__ __launch_bounds__(256) void k_rg_arrivals(const uint32_t *__restrict__ cs_old, uint32_t ncol, RegroupBufs rb,
+                                                     uint32_t *__restrict__ perm, uint32_t *__restrict__ sk_new,
+                                                     uint32_t *__restrict__ colstart, uint32_t *__restrict__ wcol)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t c = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (c > ncol) return;
+    if (c == ncol) {
+        if (lane == 0) colstart[ncol] = rb.cnew[ncol];
+        return;
+    }
+    const uint32_t m = rb.inc[c], low = rb.inlow[c], s = rb.cnew[c], e = rb.cnew[c + 1];
+    const uint32_t stay = e - s - m;
+    const uint32_t *bk = rb.mbuf + rb.mstart[c];
+    if (m > 0 && m <= 64) {
+        // bitonic sort of the arrivals' positions across the wave
+        uint32_t v = (uint32_t)lane < m ? bk[lane] : 0xffffffffu;
+        for (int kk = 2; kk <= 64; kk <<= 1)
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                const uint32_t w = (uint32_t)__shfl_xor((int)v, j, 64);
+                const bool asc = (lane & kk) == 0, lower = (lane & j) == 0;
+                v = (lower == asc) ? min(v, w) : max(v, w);
+            }
+        if ((uint32_t)lane < m) {
+            const uint32_t t = (uint32_t)lane, q = t < low ? s + t : s + stay + t;
+            perm[q] = v;
+            sk_new[q] = c;
+        }
+    } else if (m > 64) {
+        // rank by counting (a column rarely receives more than a wave's worth)
+        for (uint32_t a = lane; a < m; a += 64) {
+            const uint32_t v = bk[a];
+            uint32_t t = 0;
+            for (uint32_t b = 0; b < m; b++) t += bk[b] < v ? 1u : 0u;
+            const uint32_t q = t < low ? s + t : s + stay + t;
+            perm[q] = v;
+            sk_new[q] = c;
+        }
+    }
+    if (lane == 0) {
+        colstart[c] = s;
+        rb.inc[c] = 0u;
+        rb.inlow[c] = 0u;
+        rb.mfill[c] = 0u;
+    }
+    if (wcol) {
+        const int64_t w0 = (int64_t)c + s / 64, w1 = w0 + (e - s + 63) / 64, wn = (int64_t)c + 1 + e / 64;
+        for (int64_t w = w0 + lane; w < w1; w += 64) wcol[w] = c;
+        for (int64_t w = w1 + lane; w < wn; w += 64) wcol[w] = 0xffffffffu;
+    }
+}
+
+int64_t regroup_tiles(int64_t bound) { return rs_blocks(bound); }
+
+// chunk sums of the three scans and the per-column stayer bases
+int64_t regroup_scratch_words(int64_t cap, int ncol)
+{
+    const int64_t nb = rs_blocks(cap);
+    const int64_t chunks = (ncol + RG_CHUNK - 1) / RG_CHUNK + (nb + RG_CHUNK - 1) / RG_CHUNK +
+                           (RK_NREASON * nb + RG_CHUNK - 1) / RG_CHUNK;
+    return 2 * chunks + ncol;
+}
+
+void regroup_after_step(const uint32_t *key, const uint32_t *sk_old, const uint32_t *cs_old, const int64_t *n_dev,
+                        int64_t bound, int ncol, RegroupBufs rb, uint32_t *perm, uint32_t *sk_new, uint32_t *cs_new,
+                        uint32_t *wcol, DevCounters *dc, hipStream_t s)
+{
+    const int64_t nb = rs_blocks(bound);
+    const int64_t c1 = (ncol + RG_CHUNK - 1) / RG_CHUNK, c2 = (nb + RG_CHUNK - 1) / RG_CHUNK,
+                  c3 = (RK_NREASON * nb + RG_CHUNK - 1) / RG_CHUNK;
+    RgScan sc{cs_old, (uint32_t)ncol, nb, rb, c1, c1 + c2};
+    uint64_t *btot = (uint64_t *)rb.scratch;
+    uint32_t *cbase = (uint32_t *)(btot + c1 + c2 + c3);
+    k_rg_classify<<<(unsigned)nb, RS_THREADS, 0, s>>>(key, sk_old, cs_old, n_dev, (uint32_t)ncol, nb, rb);
+    k_rg_sreduce<<<(unsigned)(c1 + c2 + c3), 256, 0, s>>>(sc, btot);
+    k_rg_sapply<<<(unsigned)(c1 + c2 + c3), 256, 0, s>>>(sc, btot, dc);
+    k_rg_base<<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(cs_old, (uint32_t)ncol, rb, cbase);
+    k_rg_place<<<(unsigned)nb, RS_THREADS, 0, s>>>(key, sk_old, cbase, n_dev, (uint32_t)ncol, nb, rb, perm, sk_new);
+    k_rg_arrivals<<<(unsigned)((ncol + 1 + 3) / 4), 256, 0, s>>>(cs_old, (uint32_t)ncol, rb, perm, sk_new, cs_new,
+                                                                wcol);
 }
