@@ -285,6 +285,7 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
     ALLOC(ctx->colstart, uint32_t, (int64_t)g.ncol + 1);
     ALLOC(ctx->colstart_b, uint32_t, (int64_t)g.ncol + 1);
     ALLOC(ctx->skeys_b, uint32_t, cap);
+    ALLOC(ctx->perm_b, uint32_t, cap);
     {
         const int64_t nt = regroup_tiles(cap);
         uint32_t *r;
@@ -374,11 +375,21 @@ static rt_status sort_current(rt_ctx ctx, bool after_step = false)
                        ctx->n_sorts % LEVEL_REFINE_EVERY == 0;
     ctx->n_sorts++;
     prof_begin(ctx, PC_SORT);
-    if (after_step && !bylev) {
+    if (after_step) {
+        // a refining sort: the regrouping, then each column by level (ties
+        // keep the regrouping's position order, as in the radix sort of the
+        // level-refined key)
         regroup_after_step(ctx->key[ctx->cur], ctx->skeys, ctx->colstart, &ctx->dc->n_sorted, bound, ctx->g.ncol,
-                           ctx->rg, ctx->perm, ctx->skeys_b, ctx->colstart_b, ctx->wcol, ctx->dc, ctx->stream);
+                           ctx->rg, bylev ? ctx->perm_b : ctx->perm, ctx->skeys_b, ctx->colstart_b, ctx->wcol,
+                           ctx->dc, ctx->stream);
         std::swap(ctx->skeys, ctx->skeys_b);
         std::swap(ctx->colstart, ctx->colstart_b);
+        if (bylev) {
+            const bool f64 = ctx->precision == RT_FP64;
+            regroup_levels(ctx->perm_b, ctx->perm, ctx->colstart, ctx->g.ncol, f64 ? nullptr : ctx->s32[ctx->cur].lev,
+                           f64 ? ctx->s64[ctx->cur].z : nullptr, ctx->g.dz, ctx->g.nz, ctx->stream);
+            copy_removed(ctx->perm_b, ctx->perm, ctx->colstart + ctx->g.ncol, &ctx->dc->n_sorted, ctx->stream);
+        }
         if (ctx->precision == RT_FP64)
             launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
         else

@@ -133,7 +133,7 @@ struct rt_ctx_s {
     int64_t hist_len;
     // regrouping after a step: second sorted-key and offset arrays (swapped
     // with skeys / colstart) and scratch
-    uint32_t *skeys_b, *colstart_b;
+    uint32_t *skeys_b, *colstart_b, *perm_b;
     RegroupBufs rg;
     // flux scratch
     double *flux, *drag;
@@ -287,6 +287,12 @@ void regroup_after_step(const uint32_t *key, const uint32_t *sk_old, const uint3
                         int64_t bound, int ncol, RegroupBufs rb, uint32_t *perm, uint32_t *sk_new, uint32_t *cs_new,
                         uint32_t *wcol, DevCounters *dc, hipStream_t s);
 int64_t regroup_tiles(int64_t bound);
+// each column's range of pin, stably sorted by level (lev: single-precision
+// stored levels, or z and dz: floor(z / dz) clamped to 0 .. nz), into pout
+void regroup_levels(const uint32_t *pin, uint32_t *pout, const uint32_t *colstart, int ncol, const int32_t *lev,
+                    const double *z, double dz, int nz, hipStream_t s);
+// pout[j] = pin[j] for j in [*cs_end, *n_dev) (the removed volumes)
+void copy_removed(const uint32_t *pin, uint32_t *pout, const uint32_t *cs_end, const int64_t *n_dev, hipStream_t s);
 int64_t regroup_scratch_words(int64_t cap, int ncol);
 // in-place exclusive scan of t[0..len) (parts: scan_tmp_len(len) scratch)
 void scan_u32(uint32_t *t, int64_t len, uint32_t *parts, hipStream_t s);

@@ -703,3 +703,131 @@ void regroup_after_step(const uint32_t *key, const uint32_t *sk_old, const uint3
     k_rg_arrivals<<<(unsigned)((ncol + 1 + 3) / 4), 256, 0, s>>>(cs_old, (uint32_t)ncol, rb, perm, sk_new, cs_new,
                                                                 wcol);
 }
+
+// Level refinement of a regrouping: each column's volumes, in position order
+// after the regrouping, stably sorted by level index (the radix sort's order
+// for the key column x (nz + 1) + level, whose ties keep position order);
+// one wave per column, a counting sort over the column's levels in LDS.  The
+// level of a volume is its stored level (single precision) or floor(z / dz)
+// clamped to 0 .. nz (double precision), as in the level keys.
+#define RG_LVL_WAVES 4
+__device__ inline uint32_t rg_level(uint32_t slot, const int32_t *lev, const double *z, double dz, int nz)
+{
+    if (lev) return (uint32_t)min(max(lev[slot], 0), nz);
+    const double q = floor(z[slot] / dz);
+    return q > (double)nz ? (uint32_t)nz : (q >= 0.0 ? (uint32_t)q : 0u);  // NaN gives 0
+}
+
+// lanes of the wave holding the same level as this lane, valid lanes a prefix:
+// runs of neighbours when the levels do not decrease (one shuffle, one
+// ballot), else a match on the level's bits
+__device__ inline unsigned long long level_peers(uint32_t d, bool valid, int lane, int nbits)
+{
+    const uint32_t prev = (uint32_t)__shfl_up((int)d, 1, 64);
+    if (__ballot(valid && lane > 0 && d < prev) == 0ull) {
+        const unsigned long long vm = __ballot(valid);
+        const unsigned long long heads = __ballot(valid && (lane == 0 || d != prev));
+        const unsigned long long upto = (2ull << lane) - 1ull;
+        const int h = 63 - __clzll(heads & upto);
+        const unsigned long long above = heads & ~upto;
+        const int e = above ? __ffsll(above) - 1 : __popcll(vm);
+        const unsigned long long lo = h > 0 ? (1ull << h) - 1ull : 0ull;
+        const unsigned long long hi = e == 64 ? ~0ull : (1ull << e) - 1ull;
+        return valid ? (hi & ~lo) : 0ull;
+    }
+    unsigned long long peers = __ballot(valid);
+    for (int bit = 0; bit < nbits; bit++) {
+        const bool b = (d >> bit) & 1u;
+        const unsigned long long m = __ballot(b);
+        peers &= b ? m : ~m;
+    }
+    return valid ? peers : 0ull;
+}
+
+__global__ __launch_bounds__(64 * RG_LVL_WAVES) void k_rg_levels(const uint32_t *__restrict__ pin,
+                                                                 uint32_t *__restrict__ pout,
+                                                                 const uint32_t *__restrict__ colstart, uint32_t ncol,
+                                                                 const int32_t *__restrict__ lev,
+                                                                 const double *__restrict__ z, double dz, int nz)
+{
+    extern __shared__ uint32_t lvl_bins[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nzp = nz + 1;
+    uint32_t *bins = lvl_bins + wave * nzp;
+    const uint32_t c = blockIdx.x * RG_LVL_WAVES + wave;
+    if (c >= ncol) return;
+    const uint32_t s = colstart[c], e = colstart[c + 1];
+    if (e - s <= 1) {
+        if (e > s && lane == 0) pout[s] = pin[s];
+        return;
+    }
+    int nbits = 1;
+    while ((1 << nbits) <= nz) nbits++;
+    for (int q = lane; q < nzp; q += 64) bins[q] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // counts per level
+    for (uint32_t j0 = s; j0 < e; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        if (j < e) atomicAdd(&bins[rg_level(pin[j], lev, z, dz, nz)], 1u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // exclusive prefix over the levels, 64 at a time
+    uint32_t carry = 0;
+    for (int q0 = 0; q0 < nzp; q0 += 64) {
+        const int q = q0 + lane;
+        const uint32_t v = q < nzp ? bins[q] : 0u;
+        uint32_t incl = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)incl, off, 64);
+            if (lane >= off) incl += t;
+        }
+        if (q < nzp) bins[q] = carry + incl - v;
+        carry += (uint32_t)__shfl((int)incl, 63, 64);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // place in position order: the rank among the chunk's lanes of the same
+    // level, after the earlier chunks' (the bins advance by the run head)
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (uint32_t j0 = s; j0 < e; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        const bool valid = j < e;
+        const uint32_t slot = valid ? pin[j] : 0u;
+        const uint32_t d = valid ? rg_level(slot, lev, z, dz, nz) : 0u;
+        const unsigned long long peers = level_peers(d, valid, lane, nbits);
+        const uint32_t base = valid ? bins[d] : 0u;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (valid) {
+            pout[s + base + (uint32_t)__popcll(peers & below)] = slot;
+            if (lane == __ffsll((long long)peers) - 1) bins[d] = base + (uint32_t)__popcll(peers);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+void regroup_levels(const uint32_t *pin, uint32_t *pout, const uint32_t *colstart, int ncol, const int32_t *lev,
+                    const double *z, double dz, int nz, hipStream_t s)
+{
+    const size_t smem = sizeof(uint32_t) * (size_t)RG_LVL_WAVES * (size_t)(nz + 1);
+    k_rg_levels<<<(unsigned)((ncol + RG_LVL_WAVES - 1) / RG_LVL_WAVES), 64 * RG_LVL_WAVES, smem, s>>>(
+        pin, pout, colstart, (uint32_t)ncol, lev, z, dz, nz);
+}
+
+// the removed volumes' range [colstart[ncol], n) unchanged from pin to pout
+__global__ void k_copy_removed(const uint32_t *__restrict__ pin, uint32_t *__restrict__ pout,
+                               const uint32_t *__restrict__ cs_end, const int64_t *__restrict__ n_dev)
+{
+    const int64_t n = *n_dev;
+    for (int64_t j = (int64_t)*cs_end + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        pout[j] = pin[j];
+}
+
+void copy_removed(const uint32_t *pin, uint32_t *pout, const uint32_t *cs_end, const int64_t *n_dev, hipStream_t s)
+{
+    k_copy_removed<<<256, 256, 0, s>>>(pin, pout, cs_end, n_dev);
+}
