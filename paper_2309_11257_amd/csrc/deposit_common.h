@@ -23,6 +23,7 @@
 // vertical pseudo-momentum fluxes; the saturation sums: 2 level fields).
 #pragma once
 #include "rt_internal.h"
+#include <type_traits>
 
 // round x * 2^e (|x * 2^e| <= 2^51) to the nearest
 // integer, ties to even: adding 1.5 * 2^52 puts the integer part in the low
@@ -114,6 +115,29 @@ __device__ inline void chunk_window(const Grid &g, const double *vd, int k0, int
     }
 }
 
+// A payload may split its per-volume work into fetch(slot, raw), the loads,
+// and cook(raw, column, zb, zt, bv), the arithmetic, so that the deposition
+// can issue a chunk's loads one chunk ahead; any other payload is fetched as
+// its slot and cooked by load().
+template <class P, class = void>
+struct DepSplit {
+    using Raw = uint32_t;
+    __device__ static void fetch(const P &, uint32_t s, Raw &r) { r = s; }
+    __device__ static void cook(const P &p, const Raw &r, int c, double &zb, double &zt, double *bv)
+    {
+        p.load(r, c, zb, zt, bv);
+    }
+};
+template <class P>
+struct DepSplit<P, std::void_t<typename P::Raw>> {
+    using Raw = typename P::Raw;
+    __device__ static void fetch(const P &p, uint32_t s, Raw &r) { p.fetch(s, r); }
+    __device__ static void cook(const P &p, const Raw &r, int c, double &zb, double &zt, double *bv)
+    {
+        p.cook(r, c, zb, zt, bv);
+    }
+};
+
 // P::load(slot, column, zb, zt, bv[NF]) fills the vertical span of the volume
 // (in the column the sort grouped it in) and its NF densities per unit
 // height (for the fluxes: (cgx k, cgx l, cgy k, cgy l, cgz k, cgz l) * W / Dz).
@@ -165,13 +189,22 @@ __global__ __launch_bounds__(64 * CPW, RP ? P::WAVES : 2) void k_deposit(Grid g,
     if (wave < ncols) {
         const int c = c_first + wave;
         const uint32_t s0 = colstart[c], s1 = colstart[c + 1];
+        // loads run ahead of the arithmetic: the state of the next chunk and
+        // the slots of the one after are in flight while a chunk is summed
+        using Split = DepSplit<P>;
+        typename Split::Raw raw{};
+        uint32_t pn = s0 + 64u + (uint32_t)lane < s1 ? perm[s0 + 64u + (uint32_t)lane] : 0u;
+        if (s0 + (uint32_t)lane < s1) Split::fetch(pl, perm[s0 + (uint32_t)lane], raw);
         for (uint32_t base = s0; base < s1; base += 64) {
             const uint32_t r = base + (uint32_t)lane;
             const bool valid = r < s1;
+            const typename Split::Raw cur = raw;
+            if (r + 64u < s1) Split::fetch(pl, pn, raw);
+            pn = r + 128u < s1 ? perm[r + 128u] : 0u;
             double zb = 0.0, zt = 0.0, bv[NF];
 #pragma unroll
             for (int q = 0; q < NF; q++) bv[q] = 0.0;
-            if (valid) pl.load(perm[r], c, zb, zt, bv);
+            if (valid) Split::cook(pl, cur, c, zb, zt, bv);
             // the levels (lo .. hi) and interfaces (lo2 .. hi2) the volume
             // overlaps, in level units: the double-precision payload divides
             // (so it visits the same levels as a plain division); the

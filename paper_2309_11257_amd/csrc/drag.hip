@@ -20,19 +20,22 @@ void launch_coslat(const Grid &g, double *cosr, hipStream_t s)
     k_coslat<<<(unsigned)((g.ny + 255) / 256), 256, 0, s>>>(g, cosr);
 }
 
+// grid: x over the columns of a level, y over the levels (32-bit column
+// arithmetic: a context has fewer than 2^24 columns)
 __global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__ rho, const double *__restrict__ cosr,
                                               const double *__restrict__ flux, double *__restrict__ drag)
 {
     const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cells) return;
-    const int i = (int)(c % g.nx);
-    const int j = (int)((c / g.nx) % g.ny);
-    const int k = (int)(c / ((int64_t)g.nx * g.ny));
+    const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= (uint32_t)g.ncol) return;
+    const int k = (int)blockIdx.y;
+    const int j = (int)(col / (uint32_t)g.nx);
+    const int i = (int)col - j * g.nx;
+    const int64_t c = (int64_t)k * g.ncol + col;
     const int64_t plane = (int64_t)(g.nz + 1) * g.ncol;
     const int64_t row = g.nx;
     const int64_t at = (int64_t)k * g.ncol + (int64_t)j * g.nx + i;
-    const int ip = (i + 1) % g.nx, im = (i + g.nx - 1) % g.nx;
+    const int ip = i + 1 == g.nx ? 0 : i + 1, im = i == 0 ? g.nx - 1 : i - 1;
     for (int comp = 0; comp < 2; comp++) {
         const double *Fx = flux + (int64_t)(0 + comp) * plane;
         const double *Fy = flux + (int64_t)(2 + comp) * plane;
@@ -40,7 +43,7 @@ __global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__
         const double divz = (Fz[at + g.ncol] - Fz[at]) / g.dz;
         double divx, divy;
         if (g.geometry == RT_CARTESIAN) {
-            const int jp = (j + 1) % g.ny, jm = (j + g.ny - 1) % g.ny;
+            const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
             divx = (Fx[at - i + ip] - Fx[at - i + im]) / (2.0 * g.dx);
             divy = (Fy[at + (jp - j) * row] - Fy[at + (jm - j) * row]) / (2.0 * g.dy);
         } else {
@@ -70,6 +73,6 @@ __global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__
 
 void launch_drag(const Grid &g, const double *rho, const double *cosr, const double *flux, double *drag, hipStream_t s)
 {
-    const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
-    k_drag<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(g, rho, cosr, flux, drag);
+    if (g.nz <= 0 || g.ncol <= 0) return;
+    k_drag<<<dim3((unsigned)((g.ncol + 255) / 256), (unsigned)g.nz), 256, 0, s>>>(g, rho, cosr, flux, drag);
 }

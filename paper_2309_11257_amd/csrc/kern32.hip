@@ -210,23 +210,53 @@ struct Pay32 {
     double inv_dz;  // its reciprocal (level spans of the deposition)
     static constexpr bool EXACT_LEVELS = false;
     static constexpr int NL = 4, NI = 2;  // horizontal fluxes on levels, vertical on interfaces
-    static constexpr int WAVES = 5;
+    static constexpr int WAVES = 4;
+    // a volume's fields as loaded (fetch) and its densities from them (cook)
+    struct Raw {
+        int kc;
+        float zeta, k, l, Dz, xi, eta, N2, f2, G2;
+        double m, W;
+    };
+    __device__ void fetch(uint32_t s, Raw &r) const
+    {
+        r.kc = st.lev[s];
+        r.zeta = st.zeta[s];
+        r.k = st.k[s];
+        r.l = st.l[s];
+        r.Dz = st.dz[s];
+        r.m = st.m[s];
+        r.W = st.W[s];
+        if (CAR) {
+            r.N2 = st.cn2[s];
+            r.f2 = st.cf2[s];
+            if (GAM) r.G2 = st.cg2[s];
+        } else {
+            r.xi = st.xi[s];
+            r.eta = st.eta[s];
+        }
+    }
     __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
+    {
+        Raw r;
+        fetch(s, r);
+        cook(r, col, zb, zt, bv);
+    }
+    __device__ void cook(const Raw &r, int col, double &zb, double &zt, double *bv) const
     {
         // the wave's column (the slot's own column, by the grouping)
         const int jc = (int)((uint32_t)col / (uint32_t)g.nx), ic = col - jc * g.nx;
-        const int kc = st.lev[s];
-        const float zeta = st.zeta[s];
-        const float k = st.k[s], l = st.l[s], m = (float)st.m[s];
-        const float Dz = st.dz[s];
+        const int kc = r.kc;
+        const float zeta = r.zeta;
+        const float k = r.k, l = r.l, m = (float)r.m;
+        const float Dz = r.Dz;
         float N2, f2, G2 = 0.0f;
         if (CAR) {
-            N2 = st.cn2[s];
-            f2 = st.cf2[s];
-            if (GAM) G2 = st.cg2[s];
+            N2 = r.N2;
+            f2 = r.f2;
+            if (GAM) G2 = r.G2;
         } else {
-            f32::n2_f2(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta, N2, f2);
-            if (GAM) G2 = f32::gam2_at(g, b, ic, jc, kc, st.xi[s], st.eta[s], zeta);
+            f32::n2_f2(g, b, ic, jc, kc, r.xi, r.eta, zeta, N2, f2);
+            if (GAM) G2 = f32::gam2_at(g, b, ic, jc, kc, r.xi, r.eta, zeta);
         }
         // group velocity as in the step: one-rounding reciprocal and
         // reciprocal square root
@@ -238,7 +268,7 @@ struct Pay32 {
         const double cx = (double)(k * M2 * sc);
         const double cy = (double)(l * M2 * sc);
         const double cz = (double)(-m * kh2 * sc);
-        const double sW = st.W[s] * (double)f32::rcp(Dz);
+        const double sW = r.W * (double)f32::rcp(Dz);
         const double kd = k, ld = l;
         bv[0] = (cx * kd) * sW;
         bv[1] = (cx * ld) * sW;
