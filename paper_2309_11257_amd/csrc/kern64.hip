@@ -463,12 +463,37 @@ struct Pay64 {
     double inv_dz;  // unused: the double-precision deposition divides
     static constexpr bool EXACT_LEVELS = true;
     static constexpr int NL = 4, NI = 2;  // horizontal fluxes on levels, vertical on interfaces
-    static constexpr int WAVES = 6;
+    static constexpr int WAVES = 3;
+    // a volume's fields as loaded (fetch) and its densities from them (cook)
+    struct Raw {
+        double x, y, z, k, l, m, Dz, n, px, py, pz;
+    };
+    __device__ void fetch(uint32_t s, Raw &r) const
+    {
+        r.x = st.x[s];
+        r.y = st.y[s];
+        r.z = st.z[s];
+        r.k = st.k[s];
+        r.l = st.l[s];
+        r.m = st.m[s];
+        r.Dz = st.dz[s];
+        r.n = st.n[s];
+        r.px = st.px[s];
+        r.py = st.py[s];
+        r.pz = st.pz[s];
+    }
     __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
-        const double x = st.x[s], y = st.y[s], z = st.z[s];
-        const double k = st.k[s], l = st.l[s], m = st.m[s], Dz = st.dz[s];
-        const double W = W64(st, s);
+        Raw r;
+        fetch(s, r);
+        cook(r, col, zb, zt, bv);
+    }
+    __device__ void cook(const Raw &r, int col, double &zb, double &zt, double *bv) const
+    {
+        (void)col;
+        const double x = r.x, y = r.y, z = r.z;
+        const double k = r.k, l = r.l, m = r.m, Dz = r.Dz;
+        const double W = ((r.n * r.px) * r.py) * r.pz;  // as W64
         const d64::Axis ay = d64::axis_y(g, y);
         const d64::Cell c = d64::cell_of(g, d64::axis_x(g, x), ay, d64::axis_z(g, z));
         const d64::Corners<1> K(b.A, c, 0);
