@@ -270,6 +270,10 @@ __device__ inline float gam2_at(const G32 &g, const Bg32P &b, int ic, int jc, in
 #define WB_A (25 * WB_LMAX)
 #define WB_F2 (WB_A + 18 * WB_GMAX)  // five rows of (f2, (f2)_y, 0, 0) after the records
 #define WB_RECS (WB_F2 + 5)
+// with the scale-height correction the Gamma^2 records of the 5 x 5 columns
+// follow, in the A records' layout (13 424 bytes a wave)
+#define WB_GM WB_RECS
+#define WB_RECS_GAM (WB_RECS + 25 * WB_LMAX)
 extern __shared__ float4 wb_lds[];
 
 struct WBox {
@@ -475,34 +479,49 @@ __device__ inline float box_row(int r, float wgt, int c)
     return a + wgt * (b - a);
 }
 
-template <bool SPH>
+template <bool SPH, bool GAM>
 __device__ inline void rhs_box(const G32 &g, int kc, float2 lat, const float *Y, float *F, const WBox &w)
 {
     constexpr int SA = 5 * WB_LMAX, SG = 3 * WB_GMAX;  // row steps of the A and gradient boxes
     const float k = Y[3], l = Y[4], m = Y[5];
     const float kh2 = k * k + l * l;
     const float m2 = m * m;
-    const float K2 = kh2 + m2;
-    const float invK2 = rcp(K2);
-    const float invK4 = invK2 * invK2;
     Cell c;
     int sz;
     const int dx = bnode(Y[0] - 0.5f, c.wx), dy = bnode(Y[1] - 0.5f, c.wy);
     const int kb = blev(g, w, kc, Y[2] - 0.5f, sz, c.wz);
     const int pyz = (dy + 2) * SA + kb;  // A box: row and level of the centre
+    // GAM: Gamma^2 and its gradients at the centre (the Gamma^2 records sit
+    // in the A records' layout)
+    float4 Gc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (GAM) {
+        Corners<1> KM;
+        box_corners(KM, WB_GM + pyz + (dx + 2) * WB_LMAX, WB_LMAX, SA, sz);
+        Gc = make_float4(TRI_COMP(KM, x, c), TRI_COMP(KM, y, c), TRI_COMP(KM, z, c), TRI_COMP(KM, w, c));
+    }
+    const float M2 = GAM ? m2 + Gc.x : m2;
+    const float K2 = kh2 + M2;
+    const float invK2 = rcp(K2);
+    const float invK4 = invK2 * invK2;
     const float f2c = box_row(dy + 2, c.wy, 0);
     float gk, gl, gm;
     {
         Corners<1> KA;
         box_corners(KA, pyz + (dx + 2) * WB_LMAX, WB_LMAX, SA, sz);
         const float N2c = TRI_COMP(KA, z, c);
-        const float rom = rsq((N2c * kh2 + f2c * m2) * invK2);  // 1 / omega_hat
+        const float rom = rsq((N2c * kh2 + f2c * M2) * invK2);  // 1 / omega_hat
         const float h = 0.5f * invK2 * rom;
         const float q = kh2 * h;
-        const float qf = m2 * h;
+        const float qf = M2 * h;
         gk = k * TRI_COMP(KA, w, c);
         gl = qf * box_row(dy + 2, c.wy, 1);
         gm = 0.0f;
+        if (GAM) {
+            const float qg = -(q * (N2c - f2c) * invK2);
+            gk += qg * Gc.y;
+            gl += qg * Gc.z;
+            gm += qg * Gc.w;
+        }
         const int pg = WB_A + (dy + 1) * SG + (dx + 1) * WB_GMAX + kb + (w.kbase - w.kbase_g);
         // gradient records one at a time (bounded register use)
 #pragma unroll 1
@@ -521,6 +540,21 @@ __device__ inline void rhs_box(const G32 &g, int kc, float2 lat, const float *Y,
             }
         }
     }
+    // a face's M2 = m^2 + Gamma^2 and 1/K^4 (the centre's without Gamma);
+    // p: the face's lower corner in the A layout, sxs/szs its steps
+    auto face_m2 = [&](int p, int sys, int szs, const Cell &f, float &M2f, float &invK4f) {
+        if (GAM) {
+            const float4 *G = wb_lds + WB_GM + p;
+            const float g2 = lerp3(G[0].x, G[WB_LMAX].x, G[sys].x, G[sys + WB_LMAX].x, G[szs].x, G[szs + WB_LMAX].x,
+                                   G[szs + sys].x, G[szs + sys + WB_LMAX].x, f);
+            M2f = m2 + g2;
+            const float iK2 = rcp(kh2 + M2f);
+            invK4f = iK2 * iK2;
+        } else {
+            M2f = M2;
+            invK4f = invK4;
+        }
+    };
     const float sdz = Y[8] * g.inv_dz;
     float sx = 0.0f, hx = 0.0f, sy = 0.0f, hy = 0.0f, szs = 0.0f, hz = 0.0f;
 #pragma unroll 1
@@ -528,11 +562,14 @@ __device__ inline void rhs_box(const G32 &g, int kc, float2 lat, const float *Y,
         const float sg = sd ? -0.5f : 0.5f;
         Cell f = c;
         const int d = bnode(face_t(Y[0], sg, Y[6]), f.wx);
+        const int p = pyz + (d + 2) * WB_LMAX;
         Corners<1> K;
-        box_corners(K, pyz + (d + 2) * WB_LMAX, WB_LMAX, SA, sz);
+        box_corners(K, p, WB_LMAX, SA, sz);
+        float M2f, invK4f;
+        face_m2(p, SA, sz, f, M2f, invK4f);
         const float N2f = TRI_COMP(K, z, f);
-        const float romf = rsq((N2f * kh2 + f2c * m2) * invK2);
-        const float v = TRI_COMP(K, x, f) + k * m2 * ((N2f - f2c) * invK4 * romf);
+        const float romf = rsq((N2f * kh2 + f2c * M2f) * (GAM ? rcp(kh2 + M2f) : invK2));
+        const float v = TRI_COMP(K, x, f) + k * M2f * ((N2f - f2c) * invK4f * romf);
         sx += v;
         hx += sg * v;
     }
@@ -541,12 +578,15 @@ __device__ inline void rhs_box(const G32 &g, int kc, float2 lat, const float *Y,
         const float sg = sd ? -0.5f : 0.5f;
         Cell f = c;
         const int d = bnode(face_t(Y[1], sg, Y[7]), f.wy);
+        const int p = (d + 2) * SA + (dx + 2) * WB_LMAX + kb;
         Corners<1> K;
-        box_corners(K, (d + 2) * SA + (dx + 2) * WB_LMAX + kb, WB_LMAX, SA, sz);
+        box_corners(K, p, WB_LMAX, SA, sz);
+        float M2f, invK4f;
+        face_m2(p, SA, sz, f, M2f, invK4f);
         const float N2f = TRI_COMP(K, z, f);
         const float f2f = box_row(d + 2, f.wy, 0);
-        const float romf = rsq((N2f * kh2 + f2f * m2) * invK2);
-        const float v = TRI_COMP(K, y, f) + l * m2 * ((N2f - f2f) * invK4 * romf);
+        const float romf = rsq((N2f * kh2 + f2f * M2f) * (GAM ? rcp(kh2 + M2f) : invK2));
+        const float v = TRI_COMP(K, y, f) + l * M2f * ((N2f - f2f) * invK4f * romf);
         sy += v;
         hy += sg * v;
     }
@@ -556,11 +596,14 @@ __device__ inline void rhs_box(const G32 &g, int kc, float2 lat, const float *Y,
         Cell f = c;
         int szf;
         const int kf = blev(g, w, kc, face_t(Y[2], sg, sdz), szf, f.wz);
+        const int p = (dy + 2) * SA + (dx + 2) * WB_LMAX + kf;
         Corners<1> K;
-        box_corners(K, (dy + 2) * SA + (dx + 2) * WB_LMAX + kf, WB_LMAX, SA, szf);
+        box_corners(K, p, WB_LMAX, SA, szf);
+        float M2f, invK4f;
+        face_m2(p, SA, szf, f, M2f, invK4f);
         const float N2f = TRI_COMP(K, z, f);
-        const float romf = rsq((N2f * kh2 + f2c * m2) * invK2);
-        const float v = -m * kh2 * ((N2f - f2c) * invK4 * romf);
+        const float romf = rsq((N2f * kh2 + f2c * M2f) * (GAM ? rcp(kh2 + M2f) : invK2));
+        const float v = -m * kh2 * ((N2f - f2c) * invK4f * romf);
         szs += v;
         hz += sg * v;
     }

@@ -110,6 +110,16 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
 #pragma unroll
             for (int t = 0; t < NA; t++)
                 if (pa < 2 && pa + 2 * t < w.L) f32::wb_lds[ca * WB_LMAX + pa + 2 * t] = va[t];
+            if (GAM) {
+                // the Gamma^2 records of the same cells, in the same layout
+                float4 vm[NA];
+#pragma unroll
+                for (int t = 0; t < NA; t++)
+                    if (pa < 2 && pa + 2 * t < w.L) vm[t] = f32::rec(b.Gm, ka + 2u * t);
+#pragma unroll
+                for (int t = 0; t < NA; t++)
+                    if (pa < 2 && pa + 2 * t < w.L) f32::wb_lds[WB_GM + ca * WB_LMAX + pa + 2 * t] = vm[t];
+            }
 #pragma unroll
             for (int t = 0; t < NG; t++)
                 if (pg < 3 && pg + 3 * t < w.LG) f32::wb_lds[WB_A + rg * 9 * WB_GMAX + cg * WB_GMAX + pg + 3 * t] = vg[t];
@@ -142,10 +152,9 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
 #pragma unroll 1
     for (int st = 0; st < nst; st++) {
         // a stage whose lookups all lie in the box, for every lane, runs the
-        // box-only form; otherwise each lookup tests the box itself (always
-        // with the scale-height correction, whose records are not staged)
-        if (!GAM && w.on && __ballot(!f32::box_stage_in(g, w, kc0, Y)) == 0ull)
-            f32::rhs_box<SPH>(g, kc0, lat, Y, F, w);
+        // box-only form; otherwise each lookup tests the box itself
+        if (w.on && __ballot(!f32::box_stage_in(g, w, kc0, Y)) == 0ull)
+            f32::rhs_box<SPH, GAM>(g, kc0, lat, Y, F, w);
         else
             f32::rhs<SPH, GAM>(g, b, ic, jc, kc0, lat, Y, F, w);
 #pragma unroll
@@ -254,8 +263,8 @@ void launch_step32(const Grid &g, const Bg32P &b, S32 src, S32 dst, const uint32
     if (bound <= 0) return;
     const unsigned nb = (unsigned)wave_table_len(bound, g.ncol);  // an upper bound of the waves
     const G32 h = f32::make_g32(g);
-    const size_t lds = (size_t)WB_RECS * sizeof(float4);  // the wave's stencil box
     const bool sph = g.geometry == RT_SPHERICAL, gam = b.Gm != nullptr;
+    const size_t lds = (size_t)(gam ? WB_RECS_GAM : WB_RECS) * sizeof(float4);  // the wave's stencil box
     if (sph && gam)
         k_step32<true, true><<<nb, STEP_BLOCK, lds, s>>>(h, b, src, dst, perm, key_out, colstart, wcol, (float)dt,
                                                          frozen, skeys);
