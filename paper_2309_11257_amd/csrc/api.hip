@@ -273,6 +273,8 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
             s.cn2 = c;
             s.cf2 = c + cap;
             s.cg2 = c + 2 * cap;
+            ALLOC(ctx->hm_b[buf], uint32_t, cap);
+            s.hm = nullptr;
         }
         ALLOC(ctx->key[buf], uint32_t, cap);
     }
@@ -329,6 +331,8 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
         return RT_E_DEVICE;
     }
     ctx->cur = 0;
+    ctx->hm_on = false;
+    ctx->home = 0;
     *out = ctx;
     return RT_OK;
 }
@@ -354,6 +358,45 @@ static int bits_of(uint64_t maxkey)
 // every this many regrouping sorts (and the first after a load) the column
 // key is refined by the level
 #define LEVEL_REFINE_EVERY 4
+
+// The single-precision state of buffer b as kernels see it: while a run of
+// steps leaves px, py, pz and id at their home slots, they are those of the
+// home buffer, read through b's hm.
+S32 view32(const rt_ctx_s *ctx, int b)
+{
+    S32 v = ctx->s32[b];
+    if (ctx->hm_on) {
+        const S32 &h = ctx->s32[ctx->home];
+        v.px = h.px;
+        v.py = h.py;
+        v.pz = h.pz;
+        v.id = h.id;
+        v.hm = ctx->hm_b[b];
+    } else {
+        v.hm = nullptr;
+    }
+    return v;
+}
+
+// Gathers px, py, pz and id back to the current buffer's slots (before an
+// operation that rewrites the state or adds volumes); afterwards the
+// current buffer holds them itself.
+void materialize32(rt_ctx_s *ctx)
+{
+    if (ctx->precision != RT_FP32 || !ctx->hm_on) return;
+    const int cur = ctx->cur, h = ctx->home, t = 1 - h;
+    launch_gather_carried(ctx->s32[h], ctx->s32[t], ctx->hm_b[cur], ctx->perm, &ctx->dc->n_sorted, ctx->n_bound,
+                          ctx->stream);
+    if (t != cur) {
+        // the gathered arrays become the current buffer's
+        std::swap(ctx->s32[0].px, ctx->s32[1].px);
+        std::swap(ctx->s32[0].py, ctx->s32[1].py);
+        std::swap(ctx->s32[0].pz, ctx->s32[1].pz);
+        std::swap(ctx->s32[0].id, ctx->s32[1].id);
+    }
+    ctx->hm_on = false;
+    ctx->home = cur;
+}
 
 // sort the current buffer's keys -> skeys/perm, column offsets, removal
 // tallies.  A refining sort orders each column's volumes by level (sort key
@@ -393,7 +436,7 @@ static rt_status sort_current(rt_ctx ctx, bool after_step = false)
         if (ctx->precision == RT_FP64)
             launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
         else
-            launch_tally32(ctx->g, ctx->s32[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
+            launch_tally32(ctx->g, view32(ctx, ctx->cur), ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
         prof_end(ctx);
         HIP_OK(hipGetLastError());
         return RT_OK;
@@ -411,7 +454,7 @@ static rt_status sort_current(rt_ctx ctx, bool after_step = false)
     if (ctx->precision == RT_FP64)
         launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
     else
-        launch_tally32(ctx->g, ctx->s32[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
+        launch_tally32(ctx->g, view32(ctx, ctx->cur), ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
     prof_end(ctx);
     HIP_OK(hipGetLastError());
     return RT_OK;
@@ -562,6 +605,8 @@ extern "C" rt_status rt_set_rays(rt_ctx ctx, const rt_rays *rays, int64_t n, int
     }
     HIP_OK(hipMemsetAsync(ctx->dc, 0, sizeof(DevCounters), ctx->stream));
     ctx->cur = 0;
+    ctx->hm_on = false;
+    ctx->home = 0;
     if (ctx->precision == RT_FP64)
         launch_load64(ctx->g, src, n, ctx->s64[0], ctx->key[0], ctx->stream);
     else
@@ -598,9 +643,17 @@ extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
     if (ctx->precision == RT_FP64)
         launch_step64(ctx->g, ctx->bp64, ctx->s64[ctx->cur], ctx->s64[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
                       ctx->n_bound, dt, frozen, ctx->skeys, ctx->stream);
-    else
-        launch_step32(ctx->g, ctx->bp32, ctx->s32[ctx->cur], ctx->s32[nxt], ctx->perm, ctx->key[nxt], ctx->colstart,
+    else {
+        // px, py, pz and id stay where they are; the step passes on their slots
+        S32 dst = ctx->s32[nxt];
+        dst.hm = ctx->hm_b[nxt];
+        launch_step32(ctx->g, ctx->bp32, view32(ctx, ctx->cur), dst, ctx->perm, ctx->key[nxt], ctx->colstart,
                       ctx->wcol, ctx->n_bound, dt, frozen, ctx->skeys, ctx->stream);
+        if (!ctx->hm_on) {
+            ctx->home = ctx->cur;
+            ctx->hm_on = true;
+        }
+    }
     prof_end(ctx);
     launch_sorted_from_active(ctx->dc, ctx->stream);
     ctx->cur = nxt;
@@ -835,7 +888,7 @@ extern "C" rt_status rt_get_rays(rt_ctx ctx, rt_rays *rays, int64_t *n_inout, in
     if (ctx->precision == RT_FP64)
         launch_store64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->dc, dst, n, ctx->stream);
     else
-        launch_store32(ctx->g, ctx->s32[ctx->cur], ctx->perm, ctx->dc, dst, n, ctx->stream);
+        launch_store32(ctx->g, view32(ctx, ctx->cur), ctx->perm, ctx->dc, dst, n, ctx->stream);
     HIP_OK(hipGetLastError());
     if (where == RT_HOST) {
         double *hs[13] = {rays->x, rays->y, rays->z, rays->k, rays->l, rays->m, rays->dx,
@@ -1056,6 +1109,8 @@ extern "C" rt_status rt_set_rays_host_noalloc(rt_ctx ctx, const rt_rays *rays, i
     if (st) return st;
     HIP_OK(hipMemsetAsync(ctx->dc, 0, sizeof(DevCounters), ctx->stream));
     ctx->cur = 0;
+    ctx->hm_on = false;
+    ctx->home = 0;
     for (int64_t off = 0; off < n; off += RT_NOALLOC_CHUNK) {
         const int64_t c = n - off < (int64_t)RT_NOALLOC_CHUNK ? n - off : (int64_t)RT_NOALLOC_CHUNK;
         // chunk layout in the scratch array: 13 fields of c doubles, then c ids

@@ -96,12 +96,13 @@ __global__ void k_store32(Grid g, S32 st, const uint32_t *perm, const DevCounter
     o.dx[i] = (double)st.dxi[s] * g.dx;
     o.dy[i] = (double)st.deta[s] * g.dy;
     o.dz[i] = st.dz[s];
-    const double px = st.px[s], py = st.py[s], pz = st.pz[s];
+    const uint32_t h = st.hm ? st.hm[s] : s;  // the slot that holds px, py, pz and id
+    const double px = st.px[h], py = st.py[h], pz = st.pz[h];
     o.px[i] = px;
     o.py[i] = py;
     o.pz[i] = pz;
     o.n[i] = st.W[s] / ((px * py) * pz);
-    o.id[i] = st.id[s];
+    o.id[i] = st.id[h];
 }
 
 void launch_store32(const Grid &g, S32 src, const uint32_t *perm, const DevCounters *dc, rt_rays out, int64_t bound,
@@ -135,14 +136,39 @@ void launch_levkey32(const Grid &g, S32 st, uint32_t *key, const DevCounters *dc
 struct W32 {
     const double *w;
     const int64_t *ids;
+    const uint32_t *hm;  // home slots of the ids (null: the slot itself)
     __device__ double W(uint32_t slot) const { return w[slot]; }
-    __device__ int64_t id(uint32_t slot) const { return ids[slot]; }
+    __device__ int64_t id(uint32_t slot) const { return ids[hm ? hm[slot] : slot]; }
 };
 
 void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc, double *red,
                     hipStream_t s)
 {
-    launch_tally_k(g, W32{st.W, st.id}, perm, skeys, dc, red, s);
+    launch_tally_k(g, W32{st.W, st.id, st.hm}, perm, skeys, dc, red, s);
+}
+
+// the carried fields back at the slots: for every sorted position j,
+// to.f[perm[j]] = from.f[hm[perm[j]]] (the slots the positions name are
+// distinct, and every one of them was written by the step that wrote hm)
+__global__ void k_gather_carried(S32 from, S32 to, const uint32_t *__restrict__ hm, const uint32_t *__restrict__ perm,
+                                 const int64_t *__restrict__ n_dev)
+{
+    const int64_t n = *n_dev;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = perm[j], h = hm[s];
+        to.px[s] = from.px[h];
+        to.py[s] = from.py[h];
+        to.pz[s] = from.pz[h];
+        to.id[s] = from.id[h];
+    }
+}
+
+void launch_gather_carried(S32 from, S32 to, const uint32_t *hm, const uint32_t *perm, const int64_t *n_dev,
+                           int64_t bound, hipStream_t s)
+{
+    if (bound <= 0) return;
+    const int64_t nb = std::min<int64_t>((bound + 255) / 256, 4096);
+    k_gather_carried<<<(unsigned)nb, 256, 0, s>>>(from, to, hm, perm, n_dev);
 }
 
 __global__ void k_stats32_part(S32 st, const uint32_t *perm, const DevCounters *dc, double *part)

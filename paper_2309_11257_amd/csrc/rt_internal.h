@@ -71,6 +71,10 @@ struct S32 {
     // N^2, f^2 and Gamma^2 at the carrier, written by the step that produced
     // the state (the deposition's background; valid while ctx->car_ok)
     float *cn2, *cf2, *cg2;
+    // the fields a step does not change (px, py, pz, id) stay where they
+    // were when the steps began: hm[slot] is the slot that holds them, or
+    // hm is null when they are stored at the slot itself
+    uint32_t *hm;
 };
 
 // device-side counters (one instance per context)
@@ -119,6 +123,13 @@ struct rt_ctx_s {
     S32 s32[2];
     uint32_t *key[2];
     int cur;
+    // single precision: hm arrays of the two buffers; while hm_on the
+    // current buffer's px, py, pz and id are those of buffer `home` at the
+    // slots its hm names (rt_step leaves them in place; anything that reads
+    // or rewrites them first gathers them back, see materialize32)
+    uint32_t *hm_b[2];
+    bool hm_on;
+    int home;
     int64_t n_sorts;  // regrouping sorts since the last load (some refine by level)
     int64_t cap;
     int64_t n_bound;  // host-side upper bound of active count (the device holds the exact one)
@@ -308,6 +319,10 @@ void launch_tally64(const Grid &g, S64 st, const uint32_t *perm, const uint32_t 
                     double *red, hipStream_t s);
 void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t *skeys, DevCounters *dc,
                     double *red, hipStream_t s);
+void launch_gather_carried(S32 from, S32 to, const uint32_t *hm, const uint32_t *perm, const int64_t *n_dev,
+                           int64_t bound, hipStream_t s);
+S32 view32(const rt_ctx_s *ctx, int b);
+void materialize32(rt_ctx_s *ctx);
 void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 

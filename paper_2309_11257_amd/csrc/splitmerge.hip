@@ -746,10 +746,12 @@ rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, r
         r = split_merge_impl<IO64, double4>(ctx, IO64{ctx->s64[ctx->cur], ctx->bp64.f2, ctx->bp64.Gm},
                                             IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2, ctx->bp64.Gm}, ctx->bp64.A,
                                             alpha, nmax, mode);
-    else
+    else {
+        materialize32(ctx);  // the compaction copies px, py, pz and id by slot
         r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2, ctx->bp32.Gm},
                                            IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2, ctx->bp32.Gm}, ctx->bp32.A,
                                            alpha, nmax, mode);
+    }
     prof_end(ctx);  // profile groups do not nest: the regrouping times as a sort
     rt_status r2 = sort_current_ext(ctx);
     if (r == RT_OK) r = r2;
@@ -985,9 +987,11 @@ rt_status do_launch(rt_ctx ctx, const rt_launch_params *lp, const double *flux_d
     if (ctx->precision == RT_FP64)
         r = launch_impl<IO64>(ctx, IO64{ctx->s64[ctx->cur], ctx->bp64.f2}, IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2},
                               p, flag, offs, parts, n_launched);
-    else
+    else {
+        materialize32(ctx);  // the compaction copies px, py, pz and id by slot
         r = launch_impl<IO32>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2}, IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2},
                               p, flag, offs, parts, n_launched);
+    }
     prof_end(ctx);
     if (r != RT_OK) return r;
     return sort_current_ext(ctx);

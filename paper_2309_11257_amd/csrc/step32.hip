@@ -171,10 +171,10 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
             }
         }
     }
-    // the fields carried unchanged are read while the post-step runs
-    const float cpx = f32::at(src.px, s), cpy = f32::at(src.py, s), cpz = f32::at(src.pz, s);
+    // the wave action is carried with the state (the deposition streams it);
+    // px, py, pz and id stay at their home slot, which is passed on
     const double cW = src.W[s];
-    const int64_t cid = src.id[s];
+    const uint32_t chm = src.hm ? f32::at(src.hm, s) : s;
     // post-step: validity, wrap, removal, column key
     uint32_t key;
     int kc = kc0;
@@ -248,11 +248,8 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
     f32::put(dst.dxi, i, Y[6]);
     f32::put(dst.deta, i, Y[7]);
     f32::put(dst.dz, i, Y[8]);
-    f32::put(dst.px, i, cpx);
-    f32::put(dst.py, i, cpy);
-    f32::put(dst.pz, i, cpz);
     dst.W[i] = cW;
-    dst.id[i] = cid;
+    f32::put(dst.hm, i, chm);
     f32::put(key_out, i, key);
 }
 
