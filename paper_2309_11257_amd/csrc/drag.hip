@@ -21,9 +21,18 @@ void launch_coslat(const Grid &g, double *cosr, hipStream_t s)
 }
 
 // grid: x over the columns of a level, y over the levels (32-bit column
-// arithmetic: a context has fewer than 2^24 columns)
-__global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__ rho, const double *__restrict__ cosr,
-                                              const double *__restrict__ flux, double *__restrict__ drag)
+// arithmetic: a context has fewer than 2^24 columns).  The grid spacings'
+// reciprocals come from the host, and each thread forms 1/rho and 1/(r cos
+// phi) once for both components: products instead of twelve correctly
+// rounded divisions per cell (a few units in the last place from the
+// oracle's quotients, far below the deposition's own rounding).
+struct DragInv {
+    double dz, dx2, dy2, dy;  // 1/dz, 1/(2 dx), 1/(2 dy), 1/dy
+};
+
+__global__ __launch_bounds__(256) void k_drag(Grid g, DragInv inv, const double *__restrict__ rho,
+                                              const double *__restrict__ cosr, const double *__restrict__ flux,
+                                              double *__restrict__ drag)
 {
     const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
     const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;
@@ -36,43 +45,45 @@ __global__ __launch_bounds__(256) void k_drag(Grid g, const double *__restrict__
     const int64_t row = g.nx;
     const int64_t at = (int64_t)k * g.ncol + (int64_t)j * g.nx + i;
     const int ip = i + 1 == g.nx ? 0 : i + 1, im = i == 0 ? g.nx - 1 : i - 1;
+    const double irho = 1.0 / rho[k];
+    const bool sph = g.geometry != RT_CARTESIAN;
+    double irc = 1.0, cj = 1.0, cp = 1.0, cm = 1.0;
+    if (sph) {
+        const double r = g.a + ((double)k + 0.5) * g.dz;
+        cj = cosr[j];
+        irc = 1.0 / (r * cj);
+        cp = j + 1 < g.ny ? cosr[j + 1] : 0.0;
+        cm = j > 0 ? cosr[j - 1] : 0.0;
+    }
     for (int comp = 0; comp < 2; comp++) {
         const double *Fx = flux + (int64_t)(0 + comp) * plane;
         const double *Fy = flux + (int64_t)(2 + comp) * plane;
         const double *Fz = flux + (int64_t)(4 + comp) * plane;
-        const double divz = (Fz[at + g.ncol] - Fz[at]) / g.dz;
-        double divx, divy;
-        if (g.geometry == RT_CARTESIAN) {
+        const double divz = (Fz[at + g.ncol] - Fz[at]) * inv.dz;
+        const double dlam = (Fx[at - i + ip] - Fx[at - i + im]) * inv.dx2;
+        double hdiv;
+        if (!sph) {
             const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
-            divx = (Fx[at - i + ip] - Fx[at - i + im]) / (2.0 * g.dx);
-            divy = (Fy[at + (jp - j) * row] - Fy[at + (jm - j) * row]) / (2.0 * g.dy);
+            hdiv = dlam + (Fy[at + (jp - j) * row] - Fy[at + (jm - j) * row]) * inv.dy2;
         } else {
-            const double r = g.a + ((double)k + 0.5) * g.dz;
-            const double cj = cosr[j];
-            const double rc = r * cj;
             double dphi;
-            divx = ((Fx[at - i + ip] - Fx[at - i + im]) / (2.0 * g.dx)) / rc;
-            if (g.ny == 1) {
+            if (g.ny == 1)
                 dphi = 0.0;
-            } else if (j == 0) {
-                const double c1 = cosr[1];
-                dphi = (c1 * Fy[at + row] - cj * Fy[at]) / g.dy;
-            } else if (j == g.ny - 1) {
-                const double cm = cosr[j - 1];
-                dphi = (cj * Fy[at] - cm * Fy[at - row]) / g.dy;
-            } else {
-                const double cp = cosr[j + 1];
-                const double cm = cosr[j - 1];
-                dphi = (cp * Fy[at + row] - cm * Fy[at - row]) / (2.0 * g.dy);
-            }
-            divy = dphi / rc;
+            else if (j == 0)
+                dphi = (cp * Fy[at + row] - cj * Fy[at]) * inv.dy;
+            else if (j == g.ny - 1)
+                dphi = (cj * Fy[at] - cm * Fy[at - row]) * inv.dy;
+            else
+                dphi = (cp * Fy[at + row] - cm * Fy[at - row]) * inv.dy2;
+            hdiv = (dlam + dphi) * irc;
         }
-        drag[(int64_t)comp * cells + c] = -((divx + divy) + divz) / rho[k];
+        drag[(int64_t)comp * cells + c] = -(hdiv + divz) * irho;
     }
 }
 
 void launch_drag(const Grid &g, const double *rho, const double *cosr, const double *flux, double *drag, hipStream_t s)
 {
     if (g.nz <= 0 || g.ncol <= 0) return;
-    k_drag<<<dim3((unsigned)((g.ncol + 255) / 256), (unsigned)g.nz), 256, 0, s>>>(g, rho, cosr, flux, drag);
+    const DragInv inv{1.0 / g.dz, 1.0 / (2.0 * g.dx), 1.0 / (2.0 * g.dy), 1.0 / g.dy};
+    k_drag<<<dim3((unsigned)((g.ncol + 255) / 256), (unsigned)g.nz), 256, 0, s>>>(g, inv, rho, cosr, flux, drag);
 }
