@@ -361,11 +361,13 @@ static int bits_of(uint64_t maxkey)
 
 // The single-precision state of buffer b as kernels see it: while a run of
 // steps leaves px, py, pz and id at their home slots, they are those of the
-// home buffer, read through b's hm.
+// home buffer, read through b's hm, and the column of each active volume is
+// its key (the step writes no separate column word).
 S32 view32(const rt_ctx_s *ctx, int b)
 {
     S32 v = ctx->s32[b];
     if (ctx->hm_on) {
+        v.col = ctx->key[b];
         const S32 &h = ctx->s32[ctx->home];
         v.px = h.px;
         v.py = h.py;
@@ -378,13 +380,17 @@ S32 view32(const rt_ctx_s *ctx, int b)
     return v;
 }
 
-// Gathers px, py, pz and id back to the current buffer's slots (before an
-// operation that rewrites the state or adds volumes); afterwards the
-// current buffer holds them itself.
-void materialize32(rt_ctx_s *ctx)
+// Gathers px, py, pz and id back to the current buffer's slots and copies
+// the columns of the active volumes from their keys (before an operation
+// that rewrites the state or adds volumes); afterwards the current buffer
+// holds them itself.
+rt_status materialize32(rt_ctx_s *ctx)
 {
-    if (ctx->precision != RT_FP32 || !ctx->hm_on) return;
+    if (ctx->precision != RT_FP32 || !ctx->hm_on) return RT_OK;
     const int cur = ctx->cur, h = ctx->home, t = 1 - h;
+    if (ctx->n_bound > 0)
+        HIP_OK(hipMemcpyAsync(ctx->s32[cur].col, ctx->key[cur], sizeof(uint32_t) * (size_t)ctx->n_bound,
+                              hipMemcpyDeviceToDevice, ctx->stream));
     launch_gather_carried(ctx->s32[h], ctx->s32[t], ctx->hm_b[cur], ctx->perm, &ctx->dc->n_sorted, ctx->n_bound,
                           ctx->stream);
     if (t != cur) {
@@ -396,6 +402,8 @@ void materialize32(rt_ctx_s *ctx)
     }
     ctx->hm_on = false;
     ctx->home = cur;
+    HIP_OK(hipGetLastError());
+    return RT_OK;
 }
 
 // sort the current buffer's keys -> skeys/perm, column offsets, removal
@@ -712,7 +720,7 @@ extern "C" rt_status rt_features(rt_ctx ctx, float *X, int32_t where)
     if (ctx->precision == RT_FP64)
         launch_features64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, dst, ctx->stream);
     else
-        launch_features32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, dst, ctx->stream);
+        launch_features32(g, ctx->bp32, view32(ctx, ctx->cur), ctx->perm, ctx->colstart, dst, ctx->stream);
     HIP_OK(hipGetLastError());
     if (staged) {
         HIP_OK(hipMemcpyAsync(X, dst, sizeof(float) * n, hipMemcpyDeviceToHost, ctx->stream));

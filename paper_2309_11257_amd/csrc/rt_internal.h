@@ -322,7 +322,7 @@ void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t 
 void launch_gather_carried(S32 from, S32 to, const uint32_t *hm, const uint32_t *perm, const int64_t *n_dev,
                            int64_t bound, hipStream_t s);
 S32 view32(const rt_ctx_s *ctx, int b);
-void materialize32(rt_ctx_s *ctx);
+rt_status materialize32(rt_ctx_s *ctx);
 void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 

@@ -747,8 +747,9 @@ rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, r
                                             IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2, ctx->bp64.Gm}, ctx->bp64.A,
                                             alpha, nmax, mode);
     else {
-        materialize32(ctx);  // the compaction copies px, py, pz and id by slot
-        r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2, ctx->bp32.Gm},
+        r = materialize32(ctx);  // the compaction copies px, py, pz, id and the column by slot
+        if (r == RT_OK)
+            r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2, ctx->bp32.Gm},
                                            IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2, ctx->bp32.Gm}, ctx->bp32.A,
                                            alpha, nmax, mode);
     }
@@ -988,8 +989,9 @@ rt_status do_launch(rt_ctx ctx, const rt_launch_params *lp, const double *flux_d
         r = launch_impl<IO64>(ctx, IO64{ctx->s64[ctx->cur], ctx->bp64.f2}, IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2},
                               p, flag, offs, parts, n_launched);
     else {
-        materialize32(ctx);  // the compaction copies px, py, pz and id by slot
-        r = launch_impl<IO32>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2}, IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2},
+        r = materialize32(ctx);  // the compaction copies px, py, pz, id and the column by slot
+        if (r == RT_OK)
+            r = launch_impl<IO32>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2}, IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2},
                               p, flag, offs, parts, n_launched);
     }
     prof_end(ctx);

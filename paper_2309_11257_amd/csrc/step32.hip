@@ -172,7 +172,8 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
         }
     }
     // the wave action is carried with the state (the deposition streams it);
-    // px, py, pz and id stay at their home slot, which is passed on
+    // px, py, pz and id stay at their home slot, which is passed on; the
+    // column of an active volume is its key
     const double cW = src.W[s];
     const uint32_t chm = src.hm ? f32::at(src.hm, s) : s;
     // post-step: validity, wrap, removal, column key
@@ -237,7 +238,6 @@ __global__ __launch_bounds__(STEP_BLOCK, GAM ? 4 : 5) void k_step32(G32 g, Bg32P
         f32::put(dst.cf2, i, cf2);
         if (GAM) f32::put(dst.cg2, i, f32::gam2_at(g, b, ic, jc, kc, Y[0], Y[1], Y[2]));
     }
-    f32::put(dst.col, i, (uint32_t)(jc * g.nx + ic));
     f32::put(dst.lev, i, kc);
     f32::put(dst.xi, i, Y[0]);
     f32::put(dst.eta, i, Y[1]);
