@@ -257,6 +257,9 @@ extern "C" rt_status rt_create(const rt_config *cfg, rt_ctx *out)
             double **f[13] = {&s.x, &s.y, &s.z, &s.k, &s.l, &s.m, &s.dx, &s.dy, &s.dz, &s.px, &s.py, &s.pz, &s.n};
             for (int q = 0; q < 13; q++) *f[q] = m + q * cap;
             ALLOC(s.id, int64_t, cap);
+            ALLOC(s.W, double, cap);
+            ALLOC(ctx->hm_b[buf], uint32_t, cap);
+            s.hm = nullptr;
         } else {
             float *m;
             ALLOC(m, float, 11 * cap);
@@ -380,25 +383,57 @@ S32 view32(const rt_ctx_s *ctx, int b)
     return v;
 }
 
-// Gathers px, py, pz and id back to the current buffer's slots and copies
-// the columns of the active volumes from their keys (before an operation
-// that rewrites the state or adds volumes); afterwards the current buffer
-// holds them itself.
-rt_status materialize32(rt_ctx_s *ctx)
+// The double-precision state of buffer b as kernels see it: while a run of
+// steps leaves px, py, pz, n and id at their home slots, they are those of
+// the home buffer, read through b's hm.
+S64 view64(const rt_ctx_s *ctx, int b)
 {
-    if (ctx->precision != RT_FP32 || !ctx->hm_on) return RT_OK;
+    S64 v = ctx->s64[b];
+    if (ctx->hm_on) {
+        const S64 &h = ctx->s64[ctx->home];
+        v.px = h.px;
+        v.py = h.py;
+        v.pz = h.pz;
+        v.n = h.n;
+        v.id = h.id;
+        v.hm = ctx->hm_b[b];
+    } else {
+        v.hm = nullptr;
+    }
+    return v;
+}
+
+// Gathers the carried fields back to the current buffer's slots (and, in
+// single precision, copies the active volumes' columns from their keys)
+// before an operation that rewrites the state or adds volumes; afterwards the
+// current buffer holds them itself.
+rt_status materialize_carried(rt_ctx_s *ctx)
+{
+    if (!ctx->hm_on) return RT_OK;
     const int cur = ctx->cur, h = ctx->home, t = 1 - h;
-    if (ctx->n_bound > 0)
-        HIP_OK(hipMemcpyAsync(ctx->s32[cur].col, ctx->key[cur], sizeof(uint32_t) * (size_t)ctx->n_bound,
-                              hipMemcpyDeviceToDevice, ctx->stream));
-    launch_gather_carried(ctx->s32[h], ctx->s32[t], ctx->hm_b[cur], ctx->perm, &ctx->dc->n_sorted, ctx->n_bound,
-                          ctx->stream);
-    if (t != cur) {
-        // the gathered arrays become the current buffer's
-        std::swap(ctx->s32[0].px, ctx->s32[1].px);
-        std::swap(ctx->s32[0].py, ctx->s32[1].py);
-        std::swap(ctx->s32[0].pz, ctx->s32[1].pz);
-        std::swap(ctx->s32[0].id, ctx->s32[1].id);
+    if (ctx->precision == RT_FP32) {
+        if (ctx->n_bound > 0)
+            HIP_OK(hipMemcpyAsync(ctx->s32[cur].col, ctx->key[cur], sizeof(uint32_t) * (size_t)ctx->n_bound,
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+        launch_gather_carried(ctx->s32[h], ctx->s32[t], ctx->hm_b[cur], ctx->perm, &ctx->dc->n_sorted, ctx->n_bound,
+                              ctx->stream);
+        if (t != cur) {
+            // the gathered arrays become the current buffer's
+            std::swap(ctx->s32[0].px, ctx->s32[1].px);
+            std::swap(ctx->s32[0].py, ctx->s32[1].py);
+            std::swap(ctx->s32[0].pz, ctx->s32[1].pz);
+            std::swap(ctx->s32[0].id, ctx->s32[1].id);
+        }
+    } else {
+        launch_gather_carried64(ctx->s64[h], ctx->s64[t], ctx->hm_b[cur], ctx->perm, &ctx->dc->n_sorted,
+                                ctx->n_bound, ctx->stream);
+        if (t != cur) {
+            std::swap(ctx->s64[0].px, ctx->s64[1].px);
+            std::swap(ctx->s64[0].py, ctx->s64[1].py);
+            std::swap(ctx->s64[0].pz, ctx->s64[1].pz);
+            std::swap(ctx->s64[0].n, ctx->s64[1].n);
+            std::swap(ctx->s64[0].id, ctx->s64[1].id);
+        }
     }
     ctx->hm_on = false;
     ctx->home = cur;
@@ -442,7 +477,7 @@ static rt_status sort_current(rt_ctx ctx, bool after_step = false)
             copy_removed(ctx->perm_b, ctx->perm, ctx->colstart + ctx->g.ncol, &ctx->dc->n_sorted, ctx->stream);
         }
         if (ctx->precision == RT_FP64)
-            launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
+            launch_tally64(ctx->g, view64(ctx, ctx->cur), ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
         else
             launch_tally32(ctx->g, view32(ctx, ctx->cur), ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
         prof_end(ctx);
@@ -460,7 +495,7 @@ static rt_status sort_current(rt_ctx ctx, bool after_step = false)
     if (bylev) launch_colkey(ctx->skeys, ctx->dc, (uint32_t)nl, bound, ctx->stream);
     launch_colstart(ctx->skeys, ctx->dc, ctx->colstart, ctx->wcol, ctx->g.ncol, ctx->stream);
     if (ctx->precision == RT_FP64)
-        launch_tally64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
+        launch_tally64(ctx->g, view64(ctx, ctx->cur), ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
     else
         launch_tally32(ctx->g, view32(ctx, ctx->cur), ctx->perm, ctx->skeys, ctx->dc, ctx->tred, ctx->stream);
     prof_end(ctx);
@@ -648,19 +683,22 @@ extern "C" rt_status rt_step(rt_ctx ctx, double dt, int32_t flags)
     const uint8_t *frozen = (flags & RT_STEP_SURROGATE) ? ctx->frozen : nullptr;
     const int nxt = 1 - ctx->cur;
     prof_begin(ctx, PC_STEP);
-    if (ctx->precision == RT_FP64)
-        launch_step64(ctx->g, ctx->bp64, ctx->s64[ctx->cur], ctx->s64[nxt], ctx->perm, ctx->key[nxt], ctx->dc,
+    // the fields a step does not change stay where they are; the step passes
+    // on their slots
+    if (ctx->precision == RT_FP64) {
+        S64 dst = ctx->s64[nxt];
+        dst.hm = ctx->hm_b[nxt];
+        launch_step64(ctx->g, ctx->bp64, view64(ctx, ctx->cur), dst, ctx->perm, ctx->key[nxt], ctx->dc,
                       ctx->n_bound, dt, frozen, ctx->skeys, ctx->stream);
-    else {
-        // px, py, pz and id stay where they are; the step passes on their slots
+    } else {
         S32 dst = ctx->s32[nxt];
         dst.hm = ctx->hm_b[nxt];
         launch_step32(ctx->g, ctx->bp32, view32(ctx, ctx->cur), dst, ctx->perm, ctx->key[nxt], ctx->colstart,
                       ctx->wcol, ctx->n_bound, dt, frozen, ctx->skeys, ctx->stream);
-        if (!ctx->hm_on) {
-            ctx->home = ctx->cur;
-            ctx->hm_on = true;
-        }
+    }
+    if (!ctx->hm_on) {
+        ctx->home = ctx->cur;
+        ctx->hm_on = true;
     }
     prof_end(ctx);
     launch_sorted_from_active(ctx->dc, ctx->stream);
@@ -686,7 +724,7 @@ extern "C" rt_status rt_saturate(rt_ctx ctx, double dt, double *kappa, int32_t w
     const Grid &g = ctx->g;
     prof_begin(ctx, PC_SAT);
     if (ctx->precision == RT_FP64)
-        launch_saturation64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->skeys, ctx->colstart, ctx->dc, ctx->rho,
+        launch_saturation64(g, ctx->bp64, view64(ctx, ctx->cur), ctx->perm, ctx->skeys, ctx->colstart, ctx->dc, ctx->rho,
                             dt, ctx->satpq, ctx->kappa, ctx->n_bound, ctx->stream);
     else
         launch_saturation32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->skeys, ctx->colstart, ctx->dc, ctx->rho,
@@ -718,7 +756,7 @@ extern "C" rt_status rt_features(rt_ctx ctx, float *X, int32_t where)
         dst = (float *)staged;
     }
     if (ctx->precision == RT_FP64)
-        launch_features64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, dst, ctx->stream);
+        launch_features64(g, ctx->bp64, view64(ctx, ctx->cur), ctx->perm, ctx->colstart, dst, ctx->stream);
     else
         launch_features32(g, ctx->bp32, view32(ctx, ctx->cur), ctx->perm, ctx->colstart, dst, ctx->stream);
     HIP_OK(hipGetLastError());
@@ -756,7 +794,7 @@ extern "C" rt_status rt_deposit_flux(rt_ctx ctx, double *flux, double *drag, int
     double *ddst = (where == RT_DEVICE && drag) ? drag : ctx->drag;
     prof_begin(ctx, PC_DEPOSIT);
     if (ctx->precision == RT_FP64)
-        launch_deposit64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->stream);
+        launch_deposit64(g, ctx->bp64, view64(ctx, ctx->cur), ctx->perm, ctx->colstart, fdst, ctx->stream);
     else
         launch_deposit32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, fdst, ctx->car_ok, ctx->stream);
     prof_end(ctx);
@@ -806,7 +844,7 @@ extern "C" rt_status rt_full_fluxes(rt_ctx ctx, double *flux, double *tend, int3
     if (st) return st;
     prof_begin(ctx, PC_DEPOSIT);
     if (ctx->precision == RT_FP64)
-        launch_full_fluxes64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->frow, ctx->perm, ctx->colstart, ctx->rho,
+        launch_full_fluxes64(g, ctx->bp64, view64(ctx, ctx->cur), ctx->frow, ctx->perm, ctx->colstart, ctx->rho,
                              ctx->full, ctx->stream);
     else
         launch_full_fluxes32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->frow32, ctx->perm, ctx->colstart, ctx->rho,
@@ -841,7 +879,7 @@ extern "C" rt_status rt_budget(rt_ctx ctx, double *fields, double *terms, int32_
     if (st) return st;
     prof_begin(ctx, PC_DEPOSIT);
     if (ctx->precision == RT_FP64)
-        launch_budget64(g, ctx->bp64, ctx->s64[ctx->cur], ctx->perm, ctx->colstart, ctx->bud, ctx->stream);
+        launch_budget64(g, ctx->bp64, view64(ctx, ctx->cur), ctx->perm, ctx->colstart, ctx->bud, ctx->stream);
     else
         launch_budget32(g, ctx->bp32, ctx->s32[ctx->cur], ctx->perm, ctx->colstart, ctx->bud, ctx->stream);
     const double *F = ctx->bud;
@@ -894,7 +932,7 @@ extern "C" rt_status rt_get_rays(rt_ctx ctx, rt_rays *rays, int64_t *n_inout, in
         staged = dst.x;
     }
     if (ctx->precision == RT_FP64)
-        launch_store64(ctx->g, ctx->s64[ctx->cur], ctx->perm, ctx->dc, dst, n, ctx->stream);
+        launch_store64(ctx->g, view64(ctx, ctx->cur), ctx->perm, ctx->dc, dst, n, ctx->stream);
     else
         launch_store32(ctx->g, view32(ctx, ctx->cur), ctx->perm, ctx->dc, dst, n, ctx->stream);
     HIP_OK(hipGetLastError());
@@ -942,7 +980,7 @@ rt_status fill_stats(rt_ctx ctx, rt_stats *out)
     out->first_bad_id = -1;
     if (ctx->have_rays) {
         if (ctx->precision == RT_FP64)
-            launch_stats64(ctx->s64[ctx->cur], ctx->perm, ctx->dc, ctx->red, ctx->n_bound, ctx->stream);
+            launch_stats64(view64(ctx, ctx->cur), ctx->perm, ctx->dc, ctx->red, ctx->n_bound, ctx->stream);
         else
             launch_stats32(ctx->s32[ctx->cur], ctx->perm, ctx->dc, ctx->red, ctx->n_bound, ctx->stream);
         HIP_OK(hipGetLastError());
@@ -1087,6 +1125,7 @@ static S64 state_at(S64 s, int64_t off)
     double **f[13] = {&s.x, &s.y, &s.z, &s.k, &s.l, &s.m, &s.dx, &s.dy, &s.dz, &s.px, &s.py, &s.pz, &s.n};
     for (int q = 0; q < 13; q++) *f[q] += off;
     s.id += off;
+    s.W += off;
     return s;
 }
 

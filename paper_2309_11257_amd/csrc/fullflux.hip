@@ -39,7 +39,7 @@ struct PayFull64 {
         (void)col;
         const double x = st.x[s], y = st.y[s], z = st.z[s];
         const double k = st.k[s], l = st.l[s], m = st.m[s], Dz = st.dz[s];
-        const double W = ((st.n[s] * st.px[s]) * st.py[s]) * st.pz[s];
+        const double W = st.W[s];
         const d64::Axis ay = d64::axis_y(g, y);
         const d64::Cell c = d64::cell_of(g, d64::axis_x(g, x), ay, d64::axis_z(g, z));
         const d64::Corners<1> K(b.A, c, 0);
@@ -132,7 +132,7 @@ struct PayBudget64 {
         (void)col;
         const double x = st.x[s], y = st.y[s], z = st.z[s];
         const double k = st.k[s], l = st.l[s], m = st.m[s], Dz = st.dz[s];
-        const double W = ((st.n[s] * st.px[s]) * st.py[s]) * st.pz[s];
+        const double W = st.W[s];
         const d64::Axis ay = d64::axis_y(g, y);
         const d64::Cell c = d64::cell_of(g, d64::axis_x(g, x), ay, d64::axis_z(g, z));
         const d64::Corners<1> K(b.A, c, 0);

@@ -152,6 +152,7 @@ __global__ void k_load64(Grid g, rt_rays in, int64_t n, S64 d, uint32_t *key)
     d.pz[i] = in.pz[i];
     d.n[i] = in.n[i];
     d.id[i] = in.id[i];
+    d.W[i] = ((in.n[i] * in.px[i]) * in.py[i]) * in.pz[i];
     key[i] = kk;
 }
 
@@ -198,11 +199,12 @@ __global__ void k_store64(S64 st, const uint32_t *perm, const DevCounters *dc, r
     o.dx[i] = st.dx[s];
     o.dy[i] = st.dy[s];
     o.dz[i] = st.dz[s];
-    o.px[i] = st.px[s];
-    o.py[i] = st.py[s];
-    o.pz[i] = st.pz[s];
-    o.n[i] = st.n[s];
-    o.id[i] = st.id[s];
+    const uint32_t h = st.home(s);  // the slot that holds px, py, pz, n and id
+    o.px[i] = st.px[h];
+    o.py[i] = st.py[h];
+    o.pz[i] = st.pz[h];
+    o.n[i] = st.n[h];
+    o.id[i] = st.id[h];
 }
 
 void launch_store64(const Grid &g, S64 src, const uint32_t *perm, const DevCounters *dc, rt_rays out, int64_t bound,
@@ -315,9 +317,10 @@ __global__ __launch_bounds__(STEP64_BLOCK, 2) void k_step64(Grid g, Bg64P b, S64
             Y[c] = Y[c] + B[st] * Q[c];
         }
     }
-    // the fields carried unchanged are read while the post-step runs
-    const double cpx = src.px[s], cpy = src.py[s], cpz = src.pz[s], cn = src.n[s];
-    const int64_t cid = src.id[s];
+    // px, py, pz, n and id stay at their home slot, which is passed on; the
+    // wave action is carried with the state (the deposition streams it)
+    const uint32_t chm = src.home(s);
+    const double cW = src.W[s];
     const uint32_t key = d64::post_step(g, Y);
     dst.x[i] = Y[0];
     dst.y[i] = Y[1];
@@ -328,11 +331,8 @@ __global__ __launch_bounds__(STEP64_BLOCK, 2) void k_step64(Grid g, Bg64P b, S64
     dst.dx[i] = Y[6];
     dst.dy[i] = Y[7];
     dst.dz[i] = Y[8];
-    dst.px[i] = cpx;
-    dst.py[i] = cpy;
-    dst.pz[i] = cpz;
-    dst.n[i] = cn;
-    dst.id[i] = cid;
+    dst.hm[i] = chm;
+    dst.W[i] = cW;
     key_out[i] = key;
 }
 
@@ -359,16 +359,52 @@ void launch_step64(const Grid &g, const Bg64P &b, S64 src, S64 dst, const uint32
 // ncol + reason) and diagnostics.  One block, fixed assignment and a fixed
 // reduction tree: deterministic.
 // ---------------------------------------------------------------------------
-__device__ inline double W64(const S64 &st, uint32_t s)
+__device__ inline double W64(const S64 &st, uint32_t s) { return st.W[s]; }
+
+// the wave action of slots 0 .. n - 1 from their n and extents (after an
+// operation that rewrote the set; the carried fields are at their slots then)
+__global__ void k_refresh_w64(S64 st, int64_t n)
 {
-    return ((st.n[s] * st.px[s]) * st.py[s]) * st.pz[s];
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    st.W[s] = ((st.n[s] * st.px[s]) * st.py[s]) * st.pz[s];
+}
+
+void launch_refresh_w64(S64 st, int64_t n, hipStream_t s)
+{
+    if (n > 0) k_refresh_w64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(st, n);
 }
 
 struct W64s {
     S64 st;
     __device__ double W(uint32_t slot) const { return W64(st, slot); }
-    __device__ int64_t id(uint32_t slot) const { return st.id[slot]; }
+    __device__ int64_t id(uint32_t slot) const { return st.id[st.home(slot)]; }
 };
+
+// the carried fields back at the slots: for every sorted position j,
+// to.f[perm[j]] = from.f[hm[perm[j]]] (the slots the positions name are
+// distinct, and every one of them was written by the step that wrote hm)
+__global__ void k_gather_carried64(S64 from, S64 to, const uint32_t *__restrict__ hm,
+                                   const uint32_t *__restrict__ perm, const int64_t *__restrict__ n_dev)
+{
+    const int64_t n = *n_dev;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = perm[j], h = hm[s];
+        to.px[s] = from.px[h];
+        to.py[s] = from.py[h];
+        to.pz[s] = from.pz[h];
+        to.n[s] = from.n[h];
+        to.id[s] = from.id[h];
+    }
+}
+
+void launch_gather_carried64(S64 from, S64 to, const uint32_t *hm, const uint32_t *perm, const int64_t *n_dev,
+                             int64_t bound, hipStream_t s)
+{
+    if (bound <= 0) return;
+    const int64_t nb = std::min<int64_t>((bound + 255) / 256, 4096);
+    k_gather_carried64<<<(unsigned)nb, 256, 0, s>>>(from, to, hm, perm, n_dev);
+}
 
 // sort key refined by the level (as in single precision): column key *
 // (nz + 1) + floor(z / dz), clamped to 0 .. nz
@@ -466,7 +502,7 @@ struct Pay64 {
     static constexpr int WAVES = 3;
     // a volume's fields as loaded (fetch) and its densities from them (cook)
     struct Raw {
-        double x, y, z, k, l, m, Dz, n, px, py, pz;
+        double x, y, z, k, l, m, Dz, W;
     };
     __device__ void fetch(uint32_t s, Raw &r) const
     {
@@ -477,10 +513,7 @@ struct Pay64 {
         r.l = st.l[s];
         r.m = st.m[s];
         r.Dz = st.dz[s];
-        r.n = st.n[s];
-        r.px = st.px[s];
-        r.py = st.py[s];
-        r.pz = st.pz[s];
+        r.W = st.W[s];
     }
     __device__ void load(uint32_t s, int col, double &zb, double &zt, double *bv) const
     {
@@ -493,7 +526,7 @@ struct Pay64 {
         (void)col;
         const double x = r.x, y = r.y, z = r.z;
         const double k = r.k, l = r.l, m = r.m, Dz = r.Dz;
-        const double W = ((r.n * r.px) * r.py) * r.pz;  // as W64
+        const double W = r.W;
         const d64::Axis ay = d64::axis_y(g, y);
         const d64::Cell c = d64::cell_of(g, d64::axis_x(g, x), ay, d64::axis_z(g, z));
         const d64::Corners<1> K(b.A, c, 0);

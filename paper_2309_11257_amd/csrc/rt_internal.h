@@ -52,6 +52,15 @@ struct Bg32P {
 struct S64 {
     double *x, *y, *z, *k, *l, *m, *dx, *dy, *dz, *px, *py, *pz, *n;
     int64_t *id;
+    // the wave action ((n px) py) pz of each slot, carried with the state
+    // and refreshed wherever n or an extent changes (load, saturation,
+    // split/merge, launch)
+    double *W;
+    // the fields a step does not change (px, py, pz, n, id) stay where they
+    // were when the steps began: hm[slot] is the slot that holds them, or hm
+    // is null when they are stored at the slot itself
+    uint32_t *hm;
+    __host__ __device__ uint32_t home(uint32_t s) const { return hm ? hm[s] : s; }
 };
 
 // single-precision state: horizontal position as column index + offset in
@@ -123,10 +132,10 @@ struct rt_ctx_s {
     S32 s32[2];
     uint32_t *key[2];
     int cur;
-    // single precision: hm arrays of the two buffers; while hm_on the
-    // current buffer's px, py, pz and id are those of buffer `home` at the
-    // slots its hm names (rt_step leaves them in place; anything that reads
-    // or rewrites them first gathers them back, see materialize32)
+    // hm arrays of the two buffers; while hm_on the current buffer's px,
+    // py, pz and id (and n in double precision) are those of buffer `home` at
+    // the slots its hm names (rt_step leaves them in place; an operation that
+    // rewrites the set first gathers them back, see materialize_carried)
     uint32_t *hm_b[2];
     bool hm_on;
     int home;
@@ -322,7 +331,11 @@ void launch_tally32(const Grid &g, S32 st, const uint32_t *perm, const uint32_t 
 void launch_gather_carried(S32 from, S32 to, const uint32_t *hm, const uint32_t *perm, const int64_t *n_dev,
                            int64_t bound, hipStream_t s);
 S32 view32(const rt_ctx_s *ctx, int b);
-rt_status materialize32(rt_ctx_s *ctx);
+S64 view64(const rt_ctx_s *ctx, int b);
+void launch_refresh_w64(S64 st, int64_t n, hipStream_t s);
+rt_status materialize_carried(rt_ctx_s *ctx);
+void launch_gather_carried64(S64 from, S64 to, const uint32_t *hm, const uint32_t *perm, const int64_t *n_dev,
+                             int64_t bound, hipStream_t s);
 void launch_stats64(S64 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 void launch_stats32(S32 st, const uint32_t *perm, const DevCounters *dc, double *red, int64_t bound, hipStream_t s);
 

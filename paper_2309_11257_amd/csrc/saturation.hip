@@ -33,7 +33,7 @@ struct PaySat64 {
         (void)col;
         const double x = st.x[s], y = st.y[s], z = st.z[s];
         const double k = st.k[s], l = st.l[s], m = st.m[s], Dz = st.dz[s];
-        const double W = ((st.n[s] * st.px[s]) * st.py[s]) * st.pz[s];
+        const double W = st.W[s];
         const d64::Axis ay = d64::axis_y(g, y);
         const d64::Cell c = d64::cell_of(g, d64::axis_x(g, x), ay, d64::axis_z(g, z));
         const d64::Corners<1> K(b.A, c, 0);
@@ -136,7 +136,11 @@ __global__ void k_damp64(Grid g, Bg64P b, S64 st, const uint32_t *__restrict__ p
     // K^2 includes Gamma^2 at the carrier
     const double K2 = (k * k + l * l) + (m * m + d64::gam2_at(g, b, st.x[s], st.y[s], z));
     const double fac = sat_factor(g, kappa, c, z - 0.5 * Dz, z + 0.5 * Dz, Dz, K2, dt, true, 0.0);
-    if (fac != 1.0) st.n[s] = st.n[s] * fac;
+    const uint32_t h = st.home(s);
+    if (fac != 1.0) {
+        st.n[h] = st.n[h] * fac;
+        st.W[s] = ((st.n[h] * st.px[h]) * st.py[h]) * st.pz[h];
+    }
 }
 
 __global__ void k_damp32(Grid g, f32::G32 g32, Bg32P b, S32 st, const uint32_t *__restrict__ perm,

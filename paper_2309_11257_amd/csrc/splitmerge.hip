@@ -742,17 +742,20 @@ rt_status do_split_merge(rt_ctx ctx, double alpha, int32_t nmax, int32_t mode, r
 {
     prof_begin(ctx, PC_SPLIT);
     rt_status r;
-    if (ctx->precision == RT_FP64)
+    // the compaction copies every field by slot: the carried ones first come
+    // back from their home slots
+    r = materialize_carried(ctx);
+    if (r == RT_OK && ctx->precision == RT_FP64) {
         r = split_merge_impl<IO64, double4>(ctx, IO64{ctx->s64[ctx->cur], ctx->bp64.f2, ctx->bp64.Gm},
                                             IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2, ctx->bp64.Gm}, ctx->bp64.A,
                                             alpha, nmax, mode);
-    else {
-        r = materialize32(ctx);  // the compaction copies px, py, pz, id and the column by slot
-        if (r == RT_OK)
-            r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2, ctx->bp32.Gm},
+        // the state's wave action from the n and extents the pass wrote
+        launch_refresh_w64(ctx->s64[ctx->cur], ctx->n_bound, ctx->stream);
+    }
+    else if (r == RT_OK)
+        r = split_merge_impl<IO32, float4>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2, ctx->bp32.Gm},
                                            IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2, ctx->bp32.Gm}, ctx->bp32.A,
                                            alpha, nmax, mode);
-    }
     prof_end(ctx);  // profile groups do not nest: the regrouping times as a sort
     rt_status r2 = sort_current_ext(ctx);
     if (r == RT_OK) r = r2;
@@ -985,15 +988,17 @@ rt_status do_launch(rt_ctx ctx, const rt_launch_params *lp, const double *flux_d
     uint32_t *flag = scratch, *offs = scratch + M, *parts = offs + M;
     prof_begin(ctx, PC_SPLIT);
     rt_status r;
-    if (ctx->precision == RT_FP64)
+    // the compaction copies every field by slot: the carried ones first come
+    // back from their home slots
+    r = materialize_carried(ctx);
+    if (r == RT_OK && ctx->precision == RT_FP64) {
         r = launch_impl<IO64>(ctx, IO64{ctx->s64[ctx->cur], ctx->bp64.f2}, IO64{ctx->s64[1 - ctx->cur], ctx->bp64.f2},
                               p, flag, offs, parts, n_launched);
-    else {
-        r = materialize32(ctx);  // the compaction copies px, py, pz, id and the column by slot
-        if (r == RT_OK)
-            r = launch_impl<IO32>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2}, IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2},
-                              p, flag, offs, parts, n_launched);
+        launch_refresh_w64(ctx->s64[ctx->cur], ctx->n_bound, ctx->stream);
     }
+    else if (r == RT_OK)
+        r = launch_impl<IO32>(ctx, IO32{ctx->s32[ctx->cur], ctx->bp32.f2}, IO32{ctx->s32[1 - ctx->cur], ctx->bp32.f2},
+                              p, flag, offs, parts, n_launched);
     prof_end(ctx);
     if (r != RT_OK) return r;
     return sort_current_ext(ctx);

@@ -1,5 +1,6 @@
-"""The single-precision step leaves each volume's px, py, pz and id in the
-slot they were loaded into and passes that slot on with the evolving state.
+"""The step leaves each volume's px, py, pz and id (and, in double precision,
+its wave-action density) in the slot they were loaded into and passes that
+slot on with the evolving state.
 After any number of steps every reader (rt_get_rays, the removal tallies and
 their first invalid id) must still see each volume's own values, and every
 operation that rewrites the set (split/merge, launch, a new load) must start
@@ -43,13 +44,14 @@ def check_own_values(got, loaded):
     return idx
 
 
-def test_carried_fields_after_steps(rt):
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_carried_fields_after_steps(rt, prec):
     """Nine steps over several radix tiles with volumes changing column and
     leaving through the top (removal tallies read the ids through the home
     slots); the wave action of every remaining volume is its own."""
     w = W.make_c3(n_rays=60_000)
     rays = distinct_extents(w.rays, 5)
-    tr = gpu_tracer(w, rt.RT_FP32, rays=rays)
+    tr = gpu_tracer(w, rt.RT_FP32 if prec == "fp32" else rt.RT_FP64, rays=rays)
     W0 = rays["n"] * rays["px"] * rays["py"] * rays["pz"]
     n0 = rays["x"].size
     for s in range(1, 10):
@@ -115,7 +117,8 @@ def test_split_merge_after_steps_matches_oracle(rt, orc):
     tr.close()
 
 
-def test_launch_and_reload_after_steps(rt):
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_launch_and_reload_after_steps(rt, prec):
     """A launch after steps keeps every stepped volume's own px, py, pz; a new
     load after steps starts from the loaded values."""
     cols = np.sort(np.random.default_rng(65).choice(128 * 128, 300, replace=False))
@@ -125,7 +128,7 @@ def test_launch_and_reload_after_steps(rt):
     flux[cols] = np.random.default_rng(66).uniform(1e-3, 4e-3, cols.size)
     prm = dict(lambda_h=150e3, c_min=2.0, c_max=34.0, c_center=15.0, c_width=10.0, n_speeds=8)
     cap = rays["x"].size + 4 * 4 * prm["n_speeds"] * cols.size
-    tr = gpu_tracer(w, rt.RT_FP32, rays=rays, capacity=cap)
+    tr = gpu_tracer(w, rt.RT_FP32 if prec == "fp32" else rt.RT_FP64, rays=rays, capacity=cap)
     for s in range(2):
         tr.step(w.dt)
     before = by_id(tr.get_rays())
