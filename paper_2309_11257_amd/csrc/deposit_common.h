@@ -179,7 +179,10 @@ __global__ __launch_bounds__(64 * CPW, RP ? P::WAVES : 2) void k_deposit(Grid g,
     double preg[NF][2];
 #pragma unroll
     for (int q = 0; q < NF; q++) preg[q][0] = preg[q][1] = 0.0;
-    const int c_first = blockIdx.x * CPW;
+    // runs of consecutive workgroups stay on one XCD, so that neighbouring
+    // columns share its L2 (the state lines at column boundaries, the flux
+    // rows written 32 bytes per workgroup)
+    const int c_first = (int)xcd_block(gridDim.x) * CPW;
     const int ncols = min(CPW, g.ncol - c_first);
     for (int e = lane; e < WR; e += 64) {
         acc[e] = 0ull;

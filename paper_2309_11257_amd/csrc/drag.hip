@@ -35,9 +35,12 @@ __global__ __launch_bounds__(256) void k_drag(Grid g, DragInv inv, const double 
                                               double *__restrict__ drag)
 {
     const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
-    const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;
+    // runs of consecutive blocks of a level stay on one XCD (the flux rows of
+    // neighbouring columns share its L2)
+    const int64_t lb = xcd_lin((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
+    const uint32_t col = (uint32_t)(lb % gridDim.x) * blockDim.x + threadIdx.x;
     if (col >= (uint32_t)g.ncol) return;
-    const int k = (int)blockIdx.y;
+    const int k = (int)(lb / gridDim.x);
     const int j = (int)(col / (uint32_t)g.nx);
     const int i = (int)col - j * g.nx;
     const int64_t c = (int64_t)k * g.ncol + col;

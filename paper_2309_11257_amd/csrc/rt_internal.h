@@ -248,14 +248,15 @@ __device__ inline int wave_min_i(int v) { return wave_reduce_i<false>(v); }
 // one contiguous eighth per XCD left the slowest XCD half as busy again as
 // the mean).  The ragged tail beyond whole rounds keeps the plain order.
 #define XCD_CHUNK 16
-__device__ inline int64_t xcd_block(int64_t nb)
+__device__ inline int64_t xcd_lin(int64_t b, int64_t nb)
 {
-    const int64_t b = blockIdx.x;
     const int64_t full = nb / (8 * XCD_CHUNK) * (8 * XCD_CHUNK);
     if (b >= full) return b;
     const int64_t x = b & 7, q = b >> 3;  // XCD, and the block's turn on it
     return (q / XCD_CHUNK) * (8 * XCD_CHUNK) + x * XCD_CHUNK + q % XCD_CHUNK;
 }
+// the same for the block of a one-dimensional grid of nb blocks
+__device__ inline int64_t xcd_block(int64_t nb) { return xcd_lin(blockIdx.x, nb); }
 
 // error helpers
 rt_status rt_fail(rt_ctx c, rt_status s, const char *fmt, ...);
