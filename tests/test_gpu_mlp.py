@@ -39,6 +39,16 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def max_err_over_rms(a, b):
+    """Largest element error over the RMS of the reference block.  The
+    kernels sum in single precision in another order than the reference;
+    where that moves an activation across a bfloat16 rounding boundary
+    (one unit is 2^-8 relative) the layers after it carry the difference,
+    so single elements differ by a few thousandths of the block's scale."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / np.sqrt(np.mean(b * b)))
+
+
 def make(sgmod, members=2, max_batch=4096, **kw):
     sh = dict(SHAPE, **kw)
     return sgmod.Surrogate(sh["n_in"], sh["n_hidden"], sh["n_layers"], sh["n_out"], n_members=members,
@@ -74,6 +84,7 @@ def test_forward_matches_reference(sgmod, mlp, B):
     Y = net.forward(X, member=0).cpu().numpy()
     ref, _ = mlp.forward(p.astype(np.float64), shape, X, emulate=True)
     assert rel_l2(Y, ref) <= 2e-2
+    assert max_err_over_rms(Y, ref) <= 2e-2  # element by element
     Yall = net.forward(X, member=-1).cpu().numpy()
     assert np.array_equal(Yall[0], Y)
     net.close()
@@ -83,7 +94,8 @@ def test_forward_matches_reference(sgmod, mlp, B):
 def test_gradient_matches_reference(sgmod, mlp, B):
     """B = 2500 takes the split-K weight-gradient path with a ragged last
     chunk; B = 300 the single-pass one.  Every layer's weight and bias block
-    within 2e-2 relative L2."""
+    within 2e-2 relative L2, and every element within 2e-2 of its block's
+    RMS."""
     net = make(sgmod)
     shape = mlp.Shape(**SHAPE)
     p = he_params(mlp, shape, 4)
@@ -97,6 +109,7 @@ def test_gradient_matches_reference(sgmod, mlp, B):
     blocks = [(i * o) for i, o in shape.layers()] + [o for _, o in shape.layers()]
     for n in blocks:
         assert rel_l2(g[off:off + n], gref[off:off + n]) <= 2e-2, (off, n)
+        assert max_err_over_rms(g[off:off + n], gref[off:off + n]) <= 2e-2, (off, n)
         off += n
     assert off == g.size
     g2 = net.gradient(0, X, T)
